@@ -1,0 +1,130 @@
+"""Brute-force set-definition checker for tiny universes.
+
+TEST INFRASTRUCTURE ONLY.  A second, independent formulation of the transfer
+check, written with Python sets over absolute addresses instead of the C
+oracle's per-index loop, so that a slip in either one shows up when the two
+are compared over every small case.
+
+The model (Cudagrind, arXiv 1310.0901): host memory carries A (addressable)
+and V (defined) shadow (Sec. 1.1); device memory is a set of live linear
+allocations kept per context (Sec. 2, Fig. 2 caption); a copy is checked for
+unallocated or too-small device ranges and for non-addressable or undefined
+source bytes (Sec. 2's error list); V is carried along host/device copies in
+all three directions (Sec. 5).
+"""
+from __future__ import annotations
+
+NONE = (1 << 64) - 1
+SRC_UNADDR, SRC_UNDEF, SRC_UNALLOC, SRC_OVERRUN = 1, 2, 4, 8
+DST_UNADDR, DST_UNALLOC, DST_OVERRUN, OVERLAP, BAD_KIND = 16, 32, 64, 128, 256
+
+
+class World:
+    """hb: host base; hv: dict addr->V byte for every host byte of the region;
+    haddr: set of addressable host addresses; allocs: dict base -> list of V."""
+
+    def __init__(self, hb, hv_list, a_list, allocs):
+        self.hv = {hb + x: int(b) for x, b in enumerate(hv_list)}
+        self.haddr = {hb + x for x, a in enumerate(a_list) if a}
+        self.allocs = {int(b): [int(x) for x in v] for b, v in allocs.items()}
+
+    def copy(self):
+        w = World.__new__(World)
+        w.hv = dict(self.hv)
+        w.haddr = set(self.haddr)
+        w.allocs = {b: list(v) for b, v in self.allocs.items()}
+        return w
+
+    def dev_bytes(self):
+        """address -> (base of its allocation)"""
+        return {b + k: b for b, v in self.allocs.items() for k in range(len(v))}
+
+
+def verdict(world: World, kind, src, dst, n):
+    """Verdict of one record plus the dict of destination writes it implies."""
+    if kind not in (0, 1, 2):
+        return (BAD_KIND, NONE, 0, 0), {}
+    if n == 0:
+        return (0, NONE, 0, 0), {}
+    owner = world.dev_bytes()
+    idx = range(n)
+    src_host, dst_host = kind == 0, kind == 1
+    flags = 0
+
+    def side(p, is_host, unalloc_flag, overrun_flag):
+        nonlocal flags
+        if is_host:
+            good = {i for i in idx if p + i in world.haddr}
+            return good, None
+        base = owner.get(p)
+        if base is None:
+            flags |= unalloc_flag
+            return set(), 0
+        # bytes of the same allocation, contiguous from p
+        good = {i for i in idx if owner.get(p + i) == base}
+        av = base + len(world.allocs[base]) - p
+        if len(good) < n:
+            flags |= overrun_flag
+        return good, av
+
+    ok_s, av_s = side(src, src_host, SRC_UNALLOC, SRC_OVERRUN)
+    ok_d, av_d = side(dst, dst_host, DST_UNALLOC, DST_OVERRUN)
+
+    def vsrc(i):
+        if src_host:
+            return world.hv[src + i]
+        base = owner[src + i]
+        return world.allocs[base][src + i - base]
+
+    undef = {i for i in ok_s if vsrc(i) != 0}
+    bad = (set(idx) - ok_s) | (set(idx) - ok_d) | undef
+    if src_host and ok_s != set(idx):
+        flags |= SRC_UNADDR
+    if dst_host and ok_d != set(idx):
+        flags |= DST_UNADDR
+    if undef:
+        flags |= SRC_UNDEF
+    if kind == 2 and set(range(src, src + n)) & set(range(dst, dst + n)):
+        flags |= OVERLAP
+    avail = min([a for a in (av_s, av_d) if a is not None])
+    writes = {}
+    if not flags & OVERLAP:
+        for i in ok_d:
+            writes[dst + i] = vsrc(i) if i in ok_s else 0xFF
+    return (flags, min(bad) if bad else NONE, len(undef), avail), writes
+
+
+def apply_writes(world: World, writes: dict, dst_host: bool):
+    owner = world.dev_bytes()
+    for addr, val in writes.items():
+        if dst_host:
+            world.hv[addr] = val
+        else:
+            b = owner[addr]
+            world.allocs[b][addr - b] = val
+
+
+def run_snapshot(world: World, records, propagate=False):
+    """All records read the state before the call; writes land afterwards."""
+    out, pending = [], []
+    for kind, src, dst, n in records:
+        v, w = verdict(world, kind, src, dst, n)
+        out.append(v)
+        pending.append((w, kind == 1))
+    after = world.copy()
+    if propagate:
+        for w, dh in pending:
+            apply_writes(after, w, dh)
+    return out, after
+
+
+def run_sequential(world: World, records, propagate=False):
+    """Records applied one after another, each seeing the previous writes."""
+    cur = world.copy()
+    out = []
+    for kind, src, dst, n in records:
+        v, w = verdict(cur, kind, src, dst, n)
+        out.append(v)
+        if propagate:
+            apply_writes(cur, w, kind == 1)
+    return out, cur

@@ -1,0 +1,113 @@
+"""ctypes front-end of the byte-by-byte C oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path (the HIP library and its
+binding) never imports this module, and this module imports nothing from it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+# flag bits, record and verdict layouts -- declared here independently
+SRC_UNADDR, SRC_UNDEF, SRC_UNALLOC, SRC_OVERRUN = 1, 2, 4, 8
+DST_UNADDR, DST_UNALLOC, DST_OVERRUN, OVERLAP, BAD_KIND = 16, 32, 64, 128, 256
+NONE = 0xFFFF_FFFF_FFFF_FFFF
+MODE_CHECK, MODE_PROPAGATE = 1, 2
+REC = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("reserved", "<u4")])
+VER = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
+                ("undef_bytes", "<u8"), ("avail", "<u8")])
+
+
+def build(cc: str = "gcc", out: str = LIB, src: str = SRC, extra=()) -> str:
+    """Compile the oracle: plain C, -O2, no vector intrinsics."""
+    cmd = [cc, "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", *extra, "-o", out, src]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str = LIB):
+    global _lib
+    with _lock:
+        if _lib is None or path != LIB:
+            if not os.path.exists(path):
+                build(out=path)
+            lib = ctypes.CDLL(path)
+            lib.oracle_run.restype = ctypes.c_int
+            lib.oracle_run.argtypes = [
+                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+            if path != LIB:
+                return lib
+            _lib = lib
+    return _lib
+
+
+class OracleState:
+    """Host region plus live allocations, all as numpy arrays owned here.
+
+    hv: uint8[hl]; ha: uint64[ceil(hl/64)]; allocs: list of (base, size, V)."""
+
+    def __init__(self, hb, hl, hv, ha, bases, sizes, vs, lib=None):
+        self.hb, self.hl = int(hb), int(hl)
+        self.hv = np.ascontiguousarray(hv, np.uint8)
+        self.ha = np.ascontiguousarray(ha, np.uint64)
+        assert self.hv.size == self.hl and self.ha.size >= (self.hl + 63) // 64
+        self.bases = np.ascontiguousarray(bases, np.uint64)
+        self.sizes = np.ascontiguousarray(sizes, np.uint64)
+        self.vs = [np.ascontiguousarray(v, np.uint8) for v in vs]
+        assert len(self.vs) == self.bases.size == self.sizes.size
+        for v, s in zip(self.vs, self.sizes):
+            assert v.size == int(s)
+        self._ptrs = (ctypes.c_void_p * max(1, len(self.vs)))(*[v.ctypes.data for v in self.vs])
+        self.lib = lib or load()
+
+    def alloc_index(self, base) -> int:
+        return int(np.flatnonzero(self.bases == np.uint64(base))[0])
+
+    def run(self, records, check=True, propagate=False) -> np.ndarray:
+        recs = np.ascontiguousarray(records, REC)
+        out = np.zeros(recs.size, VER)
+        mode = (MODE_CHECK if check else 0) | (MODE_PROPAGATE if propagate else 0)
+        rc = self.lib.oracle_run(self.hb, self.hl, self.hv.ctypes.data, self.ha.ctypes.data,
+                                 len(self.vs), self.bases.ctypes.data, self.sizes.ctypes.data,
+                                 ctypes.cast(self._ptrs, ctypes.c_void_p),
+                                 recs.size, recs.ctypes.data, out.ctypes.data, mode)
+        if rc != 0:
+            raise MemoryError("oracle snapshot allocation failed")
+        return out
+
+    def run_threads(self, records, threads: int) -> np.ndarray:
+        """Check-only evaluation split over contiguous record ranges on
+        `threads` host threads (ctypes releases the GIL during the call)."""
+        recs = np.ascontiguousarray(records, REC)
+        out = np.zeros(recs.size, VER)
+        bounds = np.linspace(0, recs.size, threads + 1).astype(np.int64)
+
+        def work(a, b):
+            if b > a:
+                self.lib.oracle_run(self.hb, self.hl, self.hv.ctypes.data, self.ha.ctypes.data,
+                                    len(self.vs), self.bases.ctypes.data, self.sizes.ctypes.data,
+                                    ctypes.cast(self._ptrs, ctypes.c_void_p), b - a,
+                                    recs[a:b].ctypes.data, out[a:b].ctypes.data, MODE_CHECK)
+
+        ts = [threading.Thread(target=work, args=(int(bounds[i]), int(bounds[i + 1])))
+              for i in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        return out

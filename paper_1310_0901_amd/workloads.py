@@ -1,0 +1,459 @@
+"""Seeded synthetic workloads for the transfer checker.
+
+This module only *describes* inputs: a host region (its V bytes and A
+bitmap), a set of device allocations with their initial shadow contents, and
+a list of transfer records with the labels the generator injected.  It holds
+none of the checking arithmetic.  Both the CPU oracle (through the numpy
+materialisers below) and the GPU path (through the library's own
+allocation / shadow-set calls plus a plain upload of the host arrays) build
+their state from the same description.
+
+Shapes follow the workloads of the method: host-to-device, device-to-host and
+device-to-device copies (Summary, Sec. 5), checked against a per-context list
+of linear device allocations (Sec. 2, Fig. 2 caption) and against host
+addressability / definedness shadow with one V byte per data byte where a set
+bit means "undefined" and one A bit per byte where 1 means "addressable"
+(Sec. 1.1).  Sizes, densities and mixes are those of the five benchmark
+configurations; where those are silent the reading is stated next to the code.
+
+Conventions
+-----------
+* A bitmap: the byte at region offset x is bit (x & 63) of little-endian u64
+  word x >> 6.
+* Record kinds: 0 = host->device, 1 = device->host, 2 = device->device.
+* Labels: 0 clean, 1 overrun injected, 2 use-after-free injected.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HOST_BASE = 0x7F00_0000_0000
+DEV_BASE = 0x7000_0000_0000
+KIND_H2D, KIND_D2H, KIND_D2D = 0, 1, 2
+SEED0 = 13100900
+KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
+
+LABEL_CLEAN, LABEL_OVERRUN, LABEL_UAF = 0, 1, 2
+
+# numpy layout of one transfer record and one verdict (32 bytes each)
+RECORD_DTYPE = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"),
+                         ("kind", "<u4"), ("reserved", "<u4")])
+VERDICT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"),
+                          ("first_bad", "<u8"), ("undef_bytes", "<u8"),
+                          ("avail", "<u8")])
+
+
+@dataclass
+class HostSpec:
+    """Host region [base, base+length) with its V bytes and A bitmap.
+
+    V = tile(pattern) then runs (start, len, value) then points (index, value);
+    A = all ones except holes (start, len).
+    """
+    base: int
+    length: int
+    pattern: np.ndarray = field(default_factory=lambda: np.zeros(1, np.uint8))
+    runs: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int64))
+    points: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int64))
+    holes: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int64))
+
+
+@dataclass
+class DeviceSpec:
+    """Device allocations (ascending base); only `live` ones are registered.
+
+    A live allocation's shadow starts at `init[j]` (0xFF = nothing defined
+    yet, 0 = fully written), then runs (alloc, offset, len, value) are set.
+    """
+    base: np.ndarray
+    size: np.ndarray
+    live: np.ndarray
+    init: np.ndarray
+    runs: np.ndarray = field(default_factory=lambda: np.zeros((0, 4), np.int64))
+
+    @property
+    def live_idx(self) -> np.ndarray:
+        return np.flatnonzero(self.live)
+
+    @property
+    def freed_idx(self) -> np.ndarray:
+        return np.flatnonzero(~self.live)
+
+
+@dataclass
+class Workload:
+    name: str
+    host: HostSpec
+    dev: DeviceSpec
+    records: np.ndarray            # RECORD_DTYPE
+    label: np.ndarray              # per record
+    propagate: bool = False
+    stages: list = field(default_factory=list)  # extra record batches (chains)
+    note: str = ""
+
+    @property
+    def count(self) -> int:
+        return int(self.records.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# materialisers (plain data construction, used by the oracle side and for the
+# upload of the host region to device memory)
+# ---------------------------------------------------------------------------
+
+def host_v(spec: HostSpec) -> np.ndarray:
+    p = np.asarray(spec.pattern, np.uint8)
+    if p.size == 1:
+        v = np.full(spec.length, p[0], np.uint8) if p[0] else np.zeros(spec.length, np.uint8)
+    else:
+        reps = -(-spec.length // p.size)
+        v = np.tile(p, reps)[: spec.length].copy()
+    for s, ln, val in np.asarray(spec.runs, np.int64).reshape(-1, 3):
+        v[s:s + ln] = val
+    pts = np.asarray(spec.points, np.int64).reshape(-1, 2)
+    if pts.shape[0]:
+        v[pts[:, 0]] = pts[:, 1].astype(np.uint8)
+    return v
+
+
+def host_a(spec: HostSpec) -> np.ndarray:
+    """A bitmap as little-endian u64 words (padded with zero bits)."""
+    nwords = -(-spec.length // 64)
+    a = np.full(nwords, np.uint64(0xFFFF_FFFF_FFFF_FFFF), np.uint64)
+    tail = spec.length & 63
+    if tail:
+        a[-1] = np.uint64((1 << tail) - 1)
+    full = np.uint64(0xFFFF_FFFF_FFFF_FFFF)
+    for s, ln in np.asarray(spec.holes, np.int64).reshape(-1, 2):
+        e = min(int(s + ln), spec.length)
+        s = int(s)
+        while s < e:
+            w, b = s >> 6, s & 63
+            take = min(64 - b, e - s)
+            m = full if take == 64 else np.uint64(((1 << take) - 1) << b)
+            if take == 64 and b == 0:
+                # clear whole words in one slice
+                wend = e >> 6
+                a[w:wend] = 0
+                s = wend << 6
+                continue
+            a[w] &= ~m
+            s += take
+    return a
+
+
+def alloc_v(dev: DeviceSpec, j: int) -> np.ndarray:
+    v = np.full(int(dev.size[j]), np.uint8(dev.init[j]), np.uint8)
+    r = np.asarray(dev.runs, np.int64).reshape(-1, 4)
+    for _, off, ln, val in r[r[:, 0] == j]:
+        v[off:off + ln] = val
+    return v
+
+
+def make_records(kind, src, dst, n) -> np.ndarray:
+    r = np.zeros(len(n), RECORD_DTYPE)
+    r["src"], r["dst"], r["n"], r["kind"] = src, dst, n, kind
+    return r
+
+
+# ---------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------
+
+def _round_up(x, a):
+    return (x + a - 1) // a * a
+
+
+def place_allocations(rng, sizes, align=256, gap_units=16) -> np.ndarray:
+    """Ascending bases: each base = round_up(prev_end, align) + align*U{0..gap_units}."""
+    sizes = np.asarray(sizes, np.int64)
+    gaps = rng.integers(0, gap_units + 1, size=sizes.size) * align
+    bases = np.empty(sizes.size, np.int64)
+    cur = 0
+    for j in range(sizes.size):
+        cur = _round_up(cur, align) + int(gaps[j])
+        bases[j] = cur
+        cur += int(sizes[j])
+    return (bases + DEV_BASE).astype(np.uint64)
+
+
+def log_uniform_int(rng, lo, hi, size) -> np.ndarray:
+    """floor(exp(U(ln lo, ln hi))), as int64 in [lo, hi)."""
+    x = np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))).astype(np.int64)
+    return np.clip(x, lo, hi - 1)
+
+
+def zipf_weights(m, s):
+    w = np.arange(1, m + 1, dtype=np.float64) ** (-s)
+    return w / w.sum()
+
+
+class ConditionalZipf:
+    """Draw an allocation by Zipf(s) rank over a seeded permutation, conditioned
+    on its size being >= a required length.
+
+    This is the same law as re-drawing until the size fits, computed directly
+    by restricting the cumulative Zipf mass to the allocations that fit."""
+
+    def __init__(self, rng, sizes, s):
+        m = sizes.size
+        perm = rng.permutation(m)           # rank r -> allocation perm[r]
+        w = np.empty(m)
+        w[perm] = zipf_weights(m, s)        # weight of each allocation
+        order = np.argsort(-sizes, kind="stable")   # largest first
+        self.order = order
+        self.sorted_sizes_desc = sizes[order]
+        self.cum = np.cumsum(w[order])
+
+    def draw(self, rng, need) -> np.ndarray:
+        need = np.asarray(need, np.int64)
+        # number of allocations with size >= need (prefix of the descending order)
+        m = np.searchsorted(-self.sorted_sizes_desc, -need, side="right")
+        if np.any(m == 0):
+            raise ValueError("no allocation large enough")
+        u = rng.uniform(0.0, 1.0, size=need.size) * self.cum[m - 1]
+        k = np.minimum(np.searchsorted(self.cum, u, side="right"), m - 1)
+        return self.order[k]
+
+
+def _sparse_runs(rng, total, density, max_len=64):
+    """Undefined runs at a byte density: count = round(density*total/mean_len),
+    run length U{1..max_len}."""
+    mean_len = (1 + max_len) / 2.0
+    cnt = int(round(density * total / mean_len))
+    lens = rng.integers(1, max_len + 1, size=cnt)
+    return cnt, lens
+
+
+# ---------------------------------------------------------------------------
+# configuration 1: plain, tiny
+# ---------------------------------------------------------------------------
+
+def config1(seed=SEED0 + 1, n_transfers=64, host_len=1 * MiB, n_alloc=20,
+            n_freed=4, max_n=64 * KiB) -> Workload:
+    rng = np.random.default_rng(seed)
+    hl = host_len
+    n_undef = int(round(1e-4 * hl))
+    pos = rng.choice(hl, size=n_undef, replace=False)
+    host = HostSpec(HOST_BASE, hl,
+                    points=np.stack([np.sort(pos), np.full(n_undef, 0xFF)], 1).astype(np.int64))
+    sizes = rng.integers(4 * KiB, 256 * KiB + 1, size=n_alloc)
+    bases = place_allocations(rng, sizes)
+    live = np.ones(n_alloc, bool)
+    live[rng.choice(n_alloc, size=n_freed, replace=False)] = False
+    dev = DeviceSpec(bases, sizes.astype(np.uint64), live, np.full(n_alloc, 0xFF, np.uint8))
+
+    T = n_transfers
+    n_over, n_uaf = int(round(0.10 * T)), int(round(0.05 * T))
+    cls = np.zeros(T, np.int64)
+    p = rng.permutation(T)
+    cls[p[:n_over]] = LABEL_OVERRUN
+    cls[p[n_over:n_over + n_uaf]] = LABEL_UAF
+    liv, fre = dev.live_idx, dev.freed_idx
+    src = np.zeros(T, np.uint64); dst = np.zeros(T, np.uint64); n = np.zeros(T, np.uint64)
+    for t in range(T):
+        if cls[t] == LABEL_OVERRUN:
+            d = int(rng.integers(1, 65))
+            nn = int(rng.integers(d + 1, max_n + 1))
+            cand = liv[sizes[liv] >= nn - d]
+            j = int(rng.choice(cand))
+            o = int(sizes[j]) - (nn - d)
+        elif cls[t] == LABEL_UAF:
+            nn = int(rng.integers(1, max_n + 1))
+            cand = fre[sizes[fre] >= nn]
+            j = int(rng.choice(cand if cand.size else fre))
+            o = int(rng.integers(0, max(int(sizes[j]) - nn, 0) + 1))
+        else:
+            nn = int(rng.integers(1, max_n + 1))
+            cand = liv[sizes[liv] >= nn]
+            j = int(rng.choice(cand))
+            o = int(rng.integers(0, int(sizes[j]) - nn + 1))
+        n[t] = nn
+        dst[t] = int(bases[j]) + o
+        src[t] = HOST_BASE + int(rng.integers(0, hl - nn + 1))
+    rec = make_records(np.full(T, KIND_H2D), src, dst, n)
+    return Workload("plain-tiny", host, dev, rec, cls,
+                    note="64 H2D over a 1 MiB host region, 16 live allocations")
+
+
+# ---------------------------------------------------------------------------
+# configuration 2: plain at scale
+# ---------------------------------------------------------------------------
+
+def config2(seed=SEED0 + 2, host_len=4 * GiB, n_alloc=4096, min_size=256,
+            max_size=64 * MiB, density=1e-6, hole_p=1e-5) -> Workload:
+    rng = np.random.default_rng(seed)
+    hl = host_len
+    cnt, lens = _sparse_runs(rng, hl, density)
+    starts = rng.integers(0, hl - lens + 1)
+    runs = np.stack([starts, lens, np.full(cnt, 0xFF)], 1).astype(np.int64)
+    npages = hl // 4096
+    hole_pages = np.flatnonzero(rng.random(npages) < hole_p) if npages < (1 << 22) else \
+        np.unique(rng.integers(0, npages, size=rng.binomial(npages, hole_p)))
+    holes = np.stack([hole_pages * 4096, np.full(hole_pages.size, 4096)], 1).astype(np.int64)
+    host = HostSpec(HOST_BASE, hl, runs=runs, holes=holes)
+    sizes = log_uniform_int(rng, min_size, max_size, n_alloc)
+    bases = place_allocations(rng, sizes)
+    dev = DeviceSpec(bases, sizes.astype(np.uint64), np.ones(n_alloc, bool),
+                     np.full(n_alloc, 0xFF, np.uint8))
+    n = sizes.astype(np.uint64)
+    src = (HOST_BASE + rng.integers(0, hl - sizes + 1)).astype(np.uint64)
+    rec = make_records(np.full(n_alloc, KIND_H2D), src, bases, n)
+    return Workload("plain-at-scale", host, dev, rec, np.zeros(n_alloc, np.int64),
+                    note="one full-size H2D per allocation")
+
+
+# ---------------------------------------------------------------------------
+# configuration 3: batched, Zipf over live allocations, mixed kinds
+# ---------------------------------------------------------------------------
+
+def config3(seed=SEED0 + 3, n_transfers=1_000_000, n_alloc=65536,
+            host_len=4 * GiB, min_size=8, max_size=16 * MiB,
+            zipf_s=1.1, p_over=0.02, p_uaf=0.01, density=1e-6,
+            hole_p=1e-5, freed_frac=0.01) -> Workload:
+    rng = np.random.default_rng(seed)
+    hl = host_len
+    # host region as in configuration 2
+    cnt, lens = _sparse_runs(rng, hl, density)
+    starts = rng.integers(0, hl - lens + 1)
+    runs = np.stack([starts, lens, np.full(cnt, 0xFF)], 1).astype(np.int64)
+    npages = hl // 4096
+    nh = rng.binomial(npages, hole_p)
+    hole_pages = np.unique(rng.integers(0, npages, size=nh))
+    holes = np.stack([hole_pages * 4096, np.full(hole_pages.size, 4096)], 1).astype(np.int64)
+    host = HostSpec(HOST_BASE, hl, runs=runs, holes=holes)
+
+    # device: live + freed allocations, interleaved in address order
+    n_freed = max(1, int(round(freed_frac * n_alloc)))
+    n_all = n_alloc + n_freed
+    sizes_all = log_uniform_int(rng, min_size, max_size, n_all)
+    bases = place_allocations(rng, sizes_all)
+    live = np.ones(n_all, bool)
+    live[rng.choice(n_all, size=n_freed, replace=False)] = False
+    init = np.zeros(n_all, np.uint8)           # device data written (defined)
+    liv = np.flatnonzero(live)
+    fre = np.flatnonzero(~live)
+    live_sizes = sizes_all[liv]
+    # undefined runs over the concatenated live shadow, at the byte density
+    tot = int(live_sizes.sum())
+    rcnt, rlens = _sparse_runs(rng, tot, density)
+    which = rng.choice(liv.size, size=rcnt, p=live_sizes / tot)
+    rl = np.minimum(rlens, live_sizes[which])
+    roff = (rng.random(rcnt) * (live_sizes[which] - rl + 1)).astype(np.int64)
+    druns = np.stack([liv[which], roff, rl, np.full(rcnt, 0xFF)], 1).astype(np.int64)
+    dev = DeviceSpec(bases, sizes_all.astype(np.uint64), live, init, druns)
+
+    T = n_transfers
+    kind = rng.choice(3, size=T, p=[0.6, 0.1, 0.3]).astype(np.int64)  # H2D, D2H, D2D
+    n = log_uniform_int(rng, min_size, max_size, T)
+    # transfers longer than the largest live allocation cannot be placed: redraw
+    # (device->device needs two distinct allocations that fit: second largest)
+    srt = np.sort(live_sizes)
+    mx = np.where(kind == KIND_D2D, int(srt[-2]), int(srt[-1]))
+    bad = n > mx
+    while bad.any():
+        n[bad] = log_uniform_int(rng, min_size, max_size, int(bad.sum()))
+        bad = n > mx
+    u = rng.random(T)
+    label = np.where(u < p_over, LABEL_OVERRUN, np.where(u < p_over + p_uaf, LABEL_UAF, LABEL_CLEAN))
+    delta = rng.integers(1, 65, size=T)
+    # overruns need n > delta
+    label[(label == LABEL_OVERRUN) & (n <= delta)] = LABEL_CLEAN
+
+    cz = ConditionalZipf(rng, live_sizes, zipf_s)
+    need = np.where(label == LABEL_OVERRUN, n - delta, n)
+    # the "device side" that carries an injection: dst for H2D/D2D, src for D2H
+    inj = liv[cz.draw(rng, need)]
+    o_inj = np.where(label == LABEL_OVERRUN, sizes_all[inj] - (n - delta),
+                     (rng.random(T) * (sizes_all[inj] - n + 1)).astype(np.int64))
+    # use-after-free: into a freed allocation
+    uaf = np.flatnonzero(label == LABEL_UAF)
+    fj = fre[rng.integers(0, fre.size, size=uaf.size)]
+    inj[uaf] = fj
+    o_inj[uaf] = (rng.random(uaf.size) * np.maximum(sizes_all[fj] - n[uaf] + 1, 1)).astype(np.int64)
+    side_inj = bases[inj].astype(np.int64) + o_inj
+
+    # the other device side of D2D (a clean draw, different allocation)
+    d2d = np.flatnonzero(kind == KIND_D2D)
+    other = liv[cz.draw(rng, n[d2d])]
+    same = other == inj[d2d]
+    while same.any():
+        other[same] = liv[cz.draw(rng, n[d2d][same])]
+        same = other == inj[d2d]
+    o_oth = (rng.random(d2d.size) * (sizes_all[other] - n[d2d] + 1)).astype(np.int64)
+    host_off = (rng.random(T) * (hl - n + 1)).astype(np.int64)
+    hostp = HOST_BASE + host_off
+
+    src = np.where(kind == KIND_H2D, hostp, side_inj)
+    dst = np.where(kind == KIND_D2H, hostp, side_inj)
+    src[d2d] = bases[other].astype(np.int64) + o_oth
+    rec = make_records(kind, src.astype(np.uint64), dst.astype(np.uint64), n.astype(np.uint64))
+    return Workload("batched-1M", host, dev, rec, label,
+                    note="Zipf(1.1) device sides, 60/30/10 H2D/D2D/D2H, 2% overrun, 1% UAF")
+
+
+# ---------------------------------------------------------------------------
+# configuration 4: partial definedness (16-byte records) plus propagation
+# ---------------------------------------------------------------------------
+
+def config4(seed=SEED0 + 4, host_len=2 * GiB, pieces=1, hops=4) -> Workload:
+    rng = np.random.default_rng(seed)
+    hl = host_len
+    R = hl // 16
+    pattern = np.array([0] * 13 + [0xFF] * 3, np.uint8)
+    P = int(math.floor(0.01 * R))
+    recs = np.sort(rng.choice(R, size=P, replace=False))
+    b = rng.integers(0, 13, size=P)
+    k = rng.integers(0, 8, size=P)
+    points = np.stack([recs * 16 + b, (1 << k)], 1).astype(np.int64)
+    host = HostSpec(HOST_BASE, hl, pattern=pattern, points=points)
+    nA = hops + 1
+    sizes = np.full(nA, hl, np.int64)
+    bases = place_allocations(rng, sizes)
+    dev = DeviceSpec(bases, sizes.astype(np.uint64), np.ones(nA, bool), np.full(nA, 0xFF, np.uint8))
+
+    def cuts():
+        if pieces == 1:
+            return np.array([0, hl], np.int64)
+        c = np.sort(rng.choice(np.arange(1, hl), size=pieces - 1, replace=False))
+        return np.concatenate([[0], c, [hl]]).astype(np.int64)
+
+    stages = []
+    c = cuts()
+    off, ln = c[:-1], np.diff(c)
+    stages.append(make_records(np.full(off.size, KIND_H2D), (HOST_BASE + off).astype(np.uint64),
+                               (bases[0].astype(np.int64) + off).astype(np.uint64), ln.astype(np.uint64)))
+    for h in range(1, nA):
+        c = cuts()
+        off, ln = c[:-1], np.diff(c)
+        stages.append(make_records(np.full(off.size, KIND_D2D),
+                                   (int(bases[h - 1]) + off).astype(np.uint64),
+                                   (int(bases[h]) + off).astype(np.uint64), ln.astype(np.uint64)))
+    w = Workload("partial-definedness", host, dev, stages[0], np.zeros(stages[0].size, np.int64),
+                 propagate=True, stages=stages,
+                 note=f"{R} 16-byte records, 3 padding bytes each, {P} payload bits; H2D then {hops} D2D hops")
+    w.R, w.P = R, P
+    w.payload_records, w.payload_byte, w.payload_bit = recs, b, k
+    return w
+
+
+# sizes used by the parity tests: several tiles and a ragged tail, oracle in seconds
+def small_config(k: int) -> Workload:
+    if k == 1:
+        return config1()
+    if k == 2:
+        return config2(host_len=64 * MiB + 4093, n_alloc=96, max_size=2 * MiB,
+                       density=2e-4, hole_p=2e-3)
+    if k == 3:
+        return config3(n_transfers=6000, n_alloc=2048, host_len=96 * MiB + 77,
+                       max_size=1 * MiB, density=2e-5, hole_p=1e-3)
+    if k == 4:
+        return config4(host_len=4 * MiB, pieces=37, hops=4)
+    raise ValueError(k)
+
+
+def full_config(k: int) -> Workload:
+    return {1: config1, 2: config2, 3: config3, 4: config4}[k]()
