@@ -1,0 +1,261 @@
+/*
+ * xfercheck.h -- C ABI of the MI355X (gfx950) transfer checker.
+ *
+ * Memcheck-style validation of host->device, device->host and device->device
+ * copies, after Baumann & Gracia, "Cudagrind: A Valgrind Extension for CUDA"
+ * (arXiv 1310.0901):
+ *   - every copy is cross-checked against the context's list of live device
+ *     allocations {pointer, size} (Sec. 2 and the Fig. 2 caption);
+ *   - host source data must be addressable and defined, with bitwise shadow
+ *     precision (Sec. 1.1, Sec. 1.2, the error list of Sec. 2);
+ *   - the report names the bytes the copy needs and the bytes the allocation
+ *     actually offers (Sec. 4.5, Listing 6);
+ *   - definedness follows the data through all three copy directions (Sec. 5).
+ *
+ * Shadow conventions.  One V byte per data byte: 0 = defined, any set bit =
+ * undefined (a byte counts as undefined when its V byte is non-zero; the bits
+ * themselves are carried unchanged by propagation).  Host addressability is
+ * one A bit per byte, 1 = addressable; the byte at region offset x is bit
+ * (x & 63) of the little-endian 64-bit word x >> 6.  Bits of the last word
+ * beyond the region are ignored.
+ *
+ * Threading and ordering.  A context is not thread-safe: call it from one
+ * host thread.  Device work is stream ordered: check_transfers and
+ * propagate_shadow run on the caller's stream; shadow_* calls run on the
+ * context's own stream.  The library orders the two: a check sees every
+ * shadow_* call made before it, and a shadow_* call waits for every check
+ * issued before it.  Results in device memory are valid once the caller's
+ * stream has been synchronised.
+ *
+ * Errors.  Every function returns an int status: CG_OK (0) or a negative
+ * CG_E* code; cg_last_error() gives the detailed text of the last failure on
+ * a context.  Faults found in the transfers themselves are never call
+ * errors: they are reported in the verdicts.
+ */
+#ifndef XFERCHECK_H
+#define XFERCHECK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CG_OK          0
+#define CG_EINVAL     -1   /* bad argument (null pointer, bad mode, misaligned buffer, size 0) */
+#define CG_ENOMEM     -2   /* shadow pool or device memory exhausted */
+#define CG_EOVERLAP   -3   /* shadow_alloc range intersects a live allocation */
+#define CG_ENOTFOUND  -4   /* shadow_free / shadow_set / shadow_ptr: not a live allocation */
+#define CG_ECONFLICT  -5   /* CG_DEBUG_CONFLICTS: a destination overlaps another record's shadow */
+#define CG_ECAPACITY  -6   /* more live allocations than max_allocs */
+#define CG_EHIP       -7   /* a HIP runtime call failed (text in cg_last_error) */
+#define CG_ESTATE     -8   /* call not valid in the current state (e.g. no host region) */
+
+/* ---- record kinds (the three copy directions of Sec. 5) ----------------- */
+#define CG_H2D 0u
+#define CG_D2H 1u
+#define CG_D2D 2u
+
+/* ---- verdict flags ------------------------------------------------------ */
+#define CG_SRC_UNADDR   0x001u  /* a host source byte is outside the region or has A = 0 */
+#define CG_SRC_UNDEF    0x002u  /* at least one valid source byte has V != 0 */
+#define CG_SRC_UNALLOC  0x004u  /* device source pointer is in no live allocation */
+#define CG_SRC_OVERRUN  0x008u  /* n exceeds the bytes left in the source allocation */
+#define CG_DST_UNADDR   0x010u  /* a host destination byte is outside the region or has A = 0 */
+#define CG_DST_UNALLOC  0x020u  /* device destination pointer is in no live allocation */
+#define CG_DST_OVERRUN  0x040u  /* n exceeds the bytes left in the destination allocation */
+#define CG_OVERLAP      0x080u  /* device->device copy whose ranges intersect (not propagated) */
+#define CG_BAD_KIND     0x100u  /* kind is not 0, 1 or 2 */
+#define CG_NONE 0xFFFFFFFFFFFFFFFFull /* first_bad when the transfer is clean */
+
+/* ---- modes of check_transfers ------------------------------------------ */
+#define CG_CHECK           0x01u  /* write verdicts */
+#define CG_PROPAGATE       0x02u  /* copy V bytes into the destination shadow */
+#define CG_PLAIN           0x04u  /* one kernel launch per transfer (baseline path) */
+#define CG_DEBUG_CONFLICTS 0x08u  /* host-side verification of the no-conflict rule (synchronous) */
+#define CG_EAGER           0x10u  /* batched path without graph capture */
+
+/*
+ * One transfer record, 32 bytes, in device memory (the parameters of a
+ * copy call: destination, source, byte count and direction; Sec. 2, Listing 2).
+ * src / dst are the application's addresses: host addresses for the host
+ * side, device addresses for the device side.  `reserved` is ignored.
+ */
+typedef struct cg_transfer {
+    uint64_t src, dst, n;
+    uint32_t kind, reserved;
+} cg_transfer;
+
+/*
+ * One verdict, 32 bytes, in device memory.
+ *   flags       OR of CG_* flags above.
+ *   first_bad   smallest byte index i in [0, n) that is bad: a source byte
+ *               that is not valid (host: outside the region or A = 0;
+ *               device: beyond the allocation), a destination byte that is
+ *               not valid, or a valid source byte with V != 0; CG_NONE if
+ *               none.  An unallocated device side makes it 0; an overrun
+ *               makes it at most `avail`.
+ *   undef_bytes number of valid source bytes with V != 0.
+ *   avail       bytes from the device pointer to the end of its allocation
+ *               (0 if unallocated), minimum over the device sides; this is
+ *               the "found" count of the report in Sec. 4.5.
+ * BAD_KIND gives {CG_BAD_KIND, CG_NONE, 0, 0}; n == 0 gives {0, CG_NONE, 0, 0}.
+ */
+typedef struct cg_verdict {
+    uint32_t flags, reserved;
+    uint64_t first_bad, undef_bytes, avail;
+} cg_verdict;
+
+typedef struct cg_ctx cg_ctx;   /* one per device context (Fig. 2 caption) */
+
+/*
+ * Create a context on HIP device `hip_device`.  The library allocates a
+ * device shadow pool of `shadow_pool_bytes` (V bytes of all live device
+ * allocations are sub-allocated from it, 256-byte aligned) and a table for
+ * up to `max_allocs` live allocations.  *out receives the context.
+ * Errors: CG_EINVAL (null out, zero sizes), CG_EHIP / CG_ENOMEM.
+ */
+int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t max_allocs);
+
+/* Destroy a context after synchronising its work; frees pool and tables. */
+int cg_destroy(cg_ctx *ctx);
+
+/*
+ * Register the host region [host_base, host_base + len) whose shadow lives
+ * in caller-owned device memory (Sec. 1.1: the host side's A and V shadow):
+ *   v_dev       V bytes, 16-byte aligned, at least round_up(len, 16) bytes
+ *               (bytes past len are never used but may be read);
+ *   a_bits_dev  A bitmap, 8-byte aligned, ceil(len / 64) words.
+ * The caller keeps both alive and unchanged while checks that use them are
+ * in flight.  Host bytes outside the region are unaddressable.  Replaces any
+ * earlier registration.  Errors: CG_EINVAL (null/misaligned pointer, len 0).
+ */
+int cg_host_register(cg_ctx *ctx, uint64_t host_base, uint64_t len, uint8_t *v_dev,
+                     uint64_t *a_bits_dev);
+
+/*
+ * Record a device allocation [dev_addr, dev_addr + size), as the wrapper of
+ * an allocation call does (Sec. 1.2, Sec. 2).  Its shadow is set to 0xFF:
+ * nothing is defined yet.  Errors: CG_EINVAL (size 0 or address wrap),
+ * CG_EOVERLAP (intersects a live allocation), CG_ECAPACITY, CG_ENOMEM
+ * (shadow pool full).
+ */
+int shadow_alloc(cg_ctx *ctx, uint64_t dev_addr, uint64_t size);
+
+/*
+ * Forget the live allocation whose base is dev_addr (the free wrapper).
+ * Later copies that touch it report UNALLOC.  Errors: CG_ENOTFOUND when
+ * dev_addr is not the base of a live allocation (double or wild free).
+ */
+int shadow_free(cg_ctx *ctx, uint64_t dev_addr);
+
+/* k allocations / frees at once; host arrays.  Stops at the first error and
+ * returns it; the calls before it have taken effect. */
+int shadow_alloc_batch(cg_ctx *ctx, const uint64_t *addr, const uint64_t *size, uint64_t k);
+int shadow_free_batch(cg_ctx *ctx, const uint64_t *addr, uint64_t k);
+
+/*
+ * Set the V bytes of [dev_addr, dev_addr + n) to v: a memset, or a kernel
+ * having written the bytes (kernels themselves are not instrumented; Sec. 5.1).
+ * The range must lie inside one live allocation.  Errors: CG_ENOTFOUND,
+ * CG_EINVAL (range leaves the allocation).
+ */
+int shadow_set(cg_ctx *ctx, uint64_t dev_addr, uint64_t n, uint8_t v);
+
+/* k shadow_set calls at once (host arrays), issued as one kernel launch. */
+int shadow_set_batch(cg_ctx *ctx, const uint64_t *addr, const uint64_t *n, const uint8_t *v,
+                     uint64_t k);
+
+/*
+ * Device pointer of the V byte that shadows dev_addr (any address inside a
+ * live allocation).  The pointer stays valid until the allocation is freed.
+ * Errors: CG_ENOTFOUND.
+ */
+int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
+
+/*
+ * Check `count` records at recs_dev (device memory) and write one verdict
+ * per record to out_dev (device memory, 32 bytes each), on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).
+ *   mode: CG_CHECK and/or CG_PROPAGATE, optionally with CG_PLAIN (one launch
+ *   per record), CG_EAGER (no graph capture) or CG_DEBUG_CONFLICTS.
+ * With CG_PROPAGATE every valid destination byte receives the source's V
+ * byte, or 0xFF where the source byte is not valid; overlapping D2D records
+ * are not propagated.  All records read the shadow as it was before the
+ * call.  Precondition for CG_PROPAGATE: no record's destination shadow
+ * intersects another record's source or destination shadow (checked, with
+ * CG_ECONFLICT, under CG_DEBUG_CONFLICTS).
+ * The caller keeps recs_dev and out_dev alive until the stream has synced.
+ * out_dev may be NULL when CG_CHECK is not set.
+ * Errors: CG_EINVAL (null pointers, mode without CHECK/PROPAGATE),
+ * CG_ESTATE (a host-side record but no host region registered), CG_EHIP.
+ */
+int check_transfers(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count,
+                    cg_verdict *out_dev, uint32_t mode, void *hip_stream);
+
+/* Propagation only: check_transfers(ctx, recs, count, NULL, CG_PROPAGATE, stream). */
+int propagate_shadow(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, void *hip_stream);
+
+/*
+ * Paper-style text for one verdict (the report of Sec. 4.5, Listing 6), for
+ * host copies of a record and its verdict.  Writes at most len bytes,
+ * NUL-terminated; returns the length of the full text (like snprintf), or a
+ * negative status.  A clean verdict gives an empty string.
+ */
+int cg_format_verdict(const cg_transfer *rec, const cg_verdict *v, char *buf, uint64_t len);
+
+/* Static text of a status code. */
+const char *cg_strerror(int status);
+
+/* Detailed text of the last failing call on ctx ("" if none). */
+const char *cg_last_error(cg_ctx *ctx);
+
+/* Block until all of the context's own stream work is done. */
+int cg_sync(cg_ctx *ctx);
+
+/* Number of live allocations and bytes of shadow pool in use. */
+int cg_stats(cg_ctx *ctx, uint64_t *live_allocs, uint64_t *pool_used);
+
+/* ---- tuning (the batched kernel's launch shape) -------------------------- */
+typedef struct cg_tuning {
+    uint32_t block;          /* threads per block: 256 or 512 */
+    uint32_t unroll;         /* 16-byte chunks in flight per lane: 1, 2, 4 or 8 */
+    uint32_t blocks_per_cu;  /* persistent blocks per compute unit */
+    uint32_t tile_units;     /* 16-byte units per work tile (power of two, >= 4096) */
+    uint32_t nontemporal;    /* 1: stream V with non-temporal loads */
+    uint32_t reserved[3];
+} cg_tuning;
+
+int cg_get_tuning(cg_ctx *ctx, cg_tuning *t);
+int cg_set_tuning(cg_ctx *ctx, const cg_tuning *t);
+
+/*
+ * Time candidate launch shapes of the batched check on these records (each
+ * run is a full check; out_dev is overwritten) and keep the fastest; *best
+ * (may be NULL) receives it.  If cache_path is non-NULL the choice is read
+ * from / appended to that JSON-lines file, keyed by device, CU count and a
+ * workload signature.  Synchronous.
+ */
+int cg_autotune(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, cg_verdict *out_dev,
+                uint32_t mode, void *hip_stream, const char *cache_path, cg_tuning *best);
+
+/*
+ * Kernel timing: when enabled, each batched or plain check records HIP events
+ * around its scan kernel(s) on the caller's stream; cg_kernel_ms returns the
+ * summed milliseconds of the scan kernels of the last finished check and the
+ * number of scan launches it made (waits for them).
+ */
+int cg_timing(cg_ctx *ctx, int enable);
+int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
+
+/* ---- bandwidth probes (roofline reference) -------------------------------- */
+/* Read `bytes` (multiple of 16) at dev and fold them into *sink_dev (u64). */
+int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip_stream);
+/* Copy `bytes` (multiple of 16) from src to dst. */
+int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XFERCHECK_H */

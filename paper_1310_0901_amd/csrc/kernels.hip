@@ -1,0 +1,876 @@
+// HIP kernels of the transfer checker, written for gfx950 (CDNA4, wave64).
+//
+// The method (Cudagrind, arXiv 1310.0901): every copy is cross-checked
+// against the context's list of live device allocations (Sec. 2, Fig. 2
+// caption); host source bytes must be addressable and defined, tracked with
+// bitwise shadow precision (Sec. 1.1); the report gives the bytes the copy
+// needs against the bytes the allocation holds (Sec. 4.5); definedness is
+// carried through host/device, device/host and device/device copies (Sec. 5).
+//
+// Pipeline of one batched check (all integer, bit-exact):
+//   k_classify     one lane per record: decode, interval lookup in the
+//                  sorted allocation table (top level staged in LDS),
+//                  range-derived verdict fields, scan descriptor, work weight,
+//                  block-local exclusive scan of the weights;
+//   k_scan_sums    one block: exclusive scan of the per-block sums, tile size;
+//   k_prefix_tiles global prefix and first record of every work tile;
+//   k_batched      persistent kernel: tiles of the flattened 16-byte unit space
+//                  taken from a device counter; 16-byte V loads and aligned
+//                  16-bit A loads, SWAR non-zero masks, popcount / ctz for the
+//                  undefined count and first fault, DPP wave reductions, rare
+//                  global atomics; optional realigned V store to the
+//                  destination shadow.
+// The plain path runs k_classify once, then k_plain once per record.
+#include <hip/hip_runtime.h>
+
+#include "xc_internal.h"
+
+namespace xc {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint64_t NONE = CG_NONE;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// Bits j of a 16-byte chunk with lo <= j < hi (offsets relative to the chunk).
+__device__ __forceinline__ uint32_t rmask(int64_t lo, int64_t hi)
+{
+    int64_t l = lo < 0 ? 0 : (lo > 16 ? 16 : lo);
+    int64_t h = hi < 0 ? 0 : (hi > 16 ? 16 : hi);
+    return h > l ? ((1u << (uint32_t)h) - (1u << (uint32_t)l)) : 0u;
+}
+
+// One bit per byte of w: set where the byte is non-zero (SWAR, no carries
+// cross byte lanes because every byte sum stays below 0x100).
+__device__ __forceinline__ uint32_t nz4(uint32_t w)
+{
+    uint32_t t = (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
+    return ((t >> 7) | (t >> 14) | (t >> 21) | (t >> 28)) & 0xFu;
+}
+
+__device__ __forceinline__ uint32_t nz16(u32x4 v)
+{
+    return nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+}
+
+// 4-bit mask -> byte mask (0x00 / 0xFF per byte); the shifted copies of m do
+// not overlap, so the multiply has no carries.
+__device__ __forceinline__ uint32_t expand4(uint32_t m)
+{
+    return ((m * 0x00204081u) & 0x01010101u) * 0xFFu;
+}
+
+// Value a source chunk contributes to propagation: its V byte where the
+// source byte is valid, 0xFF where it is not.
+__device__ __forceinline__ u32x4 prop_val(u32x4 v, uint32_t ok)
+{
+    if (ok == 0xFFFFu) return v;
+    u32x4 r;
+    r.x = v.x | ~expand4(ok & 0xFu);
+    r.y = v.y | ~expand4((ok >> 4) & 0xFu);
+    r.z = v.z | ~expand4((ok >> 8) & 0xFu);
+    r.w = v.w | ~expand4((ok >> 12) & 0xFu);
+    return r;
+}
+
+// Bytes [s, s + 16) of the 32-byte concatenation a || b.
+__device__ __forceinline__ u32x4 window(u32x4 a, u32x4 b, uint32_t s)
+{
+    const uint32_t q = s >> 2, r = s & 3u;
+    uint32_t w0, w1, w2, w3, w4;
+    switch (q) {
+    case 0: w0 = a.x; w1 = a.y; w2 = a.z; w3 = a.w; w4 = b.x; break;
+    case 1: w0 = a.y; w1 = a.z; w2 = a.w; w3 = b.x; w4 = b.y; break;
+    case 2: w0 = a.z; w1 = a.w; w2 = b.x; w3 = b.y; w4 = b.z; break;
+    default: w0 = a.w; w1 = b.x; w2 = b.y; w3 = b.z; w4 = b.w; break;
+    }
+    u32x4 o;
+    o.x = __builtin_amdgcn_alignbyte(w1, w0, r);
+    o.y = __builtin_amdgcn_alignbyte(w2, w1, r);
+    o.z = __builtin_amdgcn_alignbyte(w3, w2, r);
+    o.w = __builtin_amdgcn_alignbyte(w4, w3, r);
+    return o;
+}
+
+__device__ __forceinline__ void store_word_masked(uint8_t *p, uint32_t w, uint32_t m)
+{
+    if (m == 0xFu) { *reinterpret_cast<uint32_t *>(p) = w; return; }
+    if (m & 1u) p[0] = (uint8_t)w;
+    if (m & 2u) p[1] = (uint8_t)(w >> 8);
+    if (m & 4u) p[2] = (uint8_t)(w >> 16);
+    if (m & 8u) p[3] = (uint8_t)(w >> 24);
+}
+
+// Store the bytes of v selected by m at the 16-byte aligned address p.
+__device__ __forceinline__ void store_masked(uint8_t *p, u32x4 v, uint32_t m)
+{
+    if (m == 0xFFFFu) { *reinterpret_cast<u32x4 *>(p) = v; return; }
+    if (m & 0x000Fu) store_word_masked(p, v.x, m & 0xFu);
+    if (m & 0x00F0u) store_word_masked(p + 4, v.y, (m >> 4) & 0xFu);
+    if (m & 0x0F00u) store_word_masked(p + 8, v.z, (m >> 8) & 0xFu);
+    if (m & 0xF000u) store_word_masked(p + 12, v.w, (m >> 12) & 0xFu);
+}
+
+template <bool NT>
+__device__ __forceinline__ u32x4 ld16(uint64_t addr)
+{
+    const u32x4 *p = reinterpret_cast<const u32x4 *>(addr);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// ---- DPP wave reductions (every lane of the wave must be active) --------
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x)
+{
+    uint32_t lo = dpp32<CTRL>((uint32_t)x), hi = dpp32<CTRL>((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror =
+// 0x141, row_mirror = 0x140: after the four steps every lane holds its
+// 16-lane row's total; the four rows are combined from lanes 0/16/32/48.
+__device__ __forceinline__ uint64_t wave_min64(uint64_t x)
+{
+    uint64_t y;
+    y = dpp64<0xB1>(x); x = y < x ? y : x;
+    y = dpp64<0x4E>(x); x = y < x ? y : x;
+    y = dpp64<0x141>(x); x = y < x ? y : x;
+    y = dpp64<0x140>(x); x = y < x ? y : x;
+    uint64_t a = readlane64(x, 0), b = readlane64(x, 16), c = readlane64(x, 32), d = readlane64(x, 48);
+    a = b < a ? b : a;
+    c = d < c ? d : c;
+    return c < a ? c : a;
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x)
+{
+    x += dpp64<0xB1>(x);
+    x += dpp64<0x4E>(x);
+    x += dpp64<0x141>(x);
+    x += dpp64<0x140>(x);
+    return readlane64(x, 0) + readlane64(x, 16) + readlane64(x, 32) + readlane64(x, 48);
+}
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x)
+{
+    x |= dpp32<0xB1>(x);
+    x |= dpp32<0x4E>(x);
+    x |= dpp32<0x141>(x);
+    x |= dpp32<0x140>(x);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 0) | (uint32_t)__builtin_amdgcn_readlane((int)x, 16) |
+           (uint32_t)__builtin_amdgcn_readlane((int)x, 32) | (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// descriptor in registers
+// ---------------------------------------------------------------------------
+struct DV {
+    uint64_t src_sh, dst_sh;
+    int64_t v_lo, v_hi, d_lo, d_hi, a_src, a_dst;
+    uint64_t e0, units;
+    uint32_t ctl, phi, psi, delta, s;
+};
+
+__device__ __forceinline__ DV load_desc(const Desc *D, uint64_t t)
+{
+    const Desc &x = D[t];
+    DV d;
+    d.src_sh = x.src_sh; d.dst_sh = x.dst_sh;
+    d.v_lo = x.v_lo; d.v_hi = x.v_hi; d.d_lo = x.d_lo; d.d_hi = x.d_hi;
+    d.a_src = x.a_src; d.a_dst = x.a_dst; d.e0 = x.e0; d.units = x.units;
+    d.ctl = x.ctl;
+    d.phi = (d.ctl >> CTL_PHI_SHIFT) & 15u;
+    d.psi = (d.ctl >> CTL_PSI_SHIFT) & 15u;
+    d.delta = (d.ctl & CTL_DELTA) ? 1u : 0u;
+    d.s = (d.phi - d.psi) & 15u;
+    return d;
+}
+
+// Source chunk c: V bytes, valid-byte mask, and (host source) the in-range
+// bytes whose A bit is 0.  Nothing is read outside the valid byte range.
+template <bool NT>
+__device__ __forceinline__ void src_chunk(const DV &d, const Region &R, int64_t c, u32x4 &v,
+                                          uint32_t &ok, uint32_t &unaddr)
+{
+    const int64_t i0 = 16 * c - (int64_t)d.phi;
+    const uint32_t m = rmask(d.v_lo - i0, d.v_hi - i0);
+    v = u32x4{0u, 0u, 0u, 0u};
+    ok = 0u;
+    unaddr = 0u;
+    if (m) {
+        v = ld16<NT>(d.src_sh + (uint64_t)(16 * c));
+        if (d.ctl & CTL_SRC_HOST) {
+            const uint32_t a = R.a16[(d.a_src + 16 * c) >> 4];
+            ok = m & a;
+            unaddr = m & ~a;
+        } else {
+            ok = m;
+        }
+    }
+}
+
+struct Acc {
+    uint64_t first, undef;
+    uint32_t flags;
+};
+
+__device__ __forceinline__ void acc_reset(Acc &a) { a.first = NONE; a.undef = 0; a.flags = 0; }
+
+__device__ __forceinline__ void acc_min(Acc &a, int64_t i) { a.first = (uint64_t)i < a.first ? (uint64_t)i : a.first; }
+
+// Findings of source chunk c (checking only).
+__device__ __forceinline__ void src_findings(Acc &a, int64_t i0, u32x4 v, uint32_t ok, uint32_t unaddr)
+{
+    const uint32_t any = v.x | v.y | v.z | v.w;
+    if (unaddr) {
+        a.flags |= CG_SRC_UNADDR;
+        acc_min(a, i0 + __builtin_ctz(unaddr));
+    }
+    if (any) {
+        const uint32_t und = nz16(v) & ok;
+        if (und) {
+            a.flags |= CG_SRC_UNDEF;
+            a.undef += (uint64_t)__builtin_popcount(und);
+            acc_min(a, i0 + __builtin_ctz(und));
+        }
+    }
+}
+
+// Wave-wide flush of uniform-mode accumulators for record t (all lanes active).
+__device__ __forceinline__ void flush_wave(Acc &a, cg_verdict *out, uint64_t t)
+{
+    if (__ballot(a.flags != 0u)) {
+        const uint64_t first = wave_min64(a.first);
+        const uint64_t und = wave_sum64(a.undef);
+        const uint32_t fl = wave_or32(a.flags);
+        if (lane_id() == 0) {
+            atomicOr(&out[t].flags, fl);
+            if (first != NONE) atomicMin((unsigned long long *)&out[t].first_bad, (unsigned long long)first);
+            if (und) atomicAdd((unsigned long long *)&out[t].undef_bytes, (unsigned long long)und);
+        }
+    }
+    acc_reset(a);
+}
+
+// ---------------------------------------------------------------------------
+// uniform mode: the whole wave works on units [k_begin, k_end) of one record
+// ---------------------------------------------------------------------------
+template <int U, bool NT>
+__device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64_t k_begin, uint64_t k_end,
+                                            Acc &acc)
+{
+    const uint32_t lane = lane_id();
+    const bool check = (d.ctl & CTL_CHECK) != 0;
+    const bool prop = (d.ctl & CTL_PROP) != 0;
+    const bool dsta = (d.ctl & CTL_DST_A) != 0;
+    const bool dst_host = (d.ctl & CTL_DST_HOST) != 0;
+
+    for (uint64_t kb = k_begin; kb < k_end; kb += 64u * U) {
+        u32x4 v[U];
+        uint32_t ok[U], un[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t k = kb + 64u * j + lane;
+            const int64_t c = (int64_t)(d.e0 + k) - (int64_t)d.delta;
+            if (k < k_end) {
+                src_chunk<NT>(d, R, c, v[j], ok[j], un[j]);
+            } else {
+                v[j] = u32x4{0u, 0u, 0u, 0u};
+                ok[j] = 0u;
+                un[j] = 0u;
+            }
+        }
+        if (check) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint64_t k = kb + 64u * j + lane;
+                const int64_t c = (int64_t)(d.e0 + k) - (int64_t)d.delta;
+                src_findings(acc, 16 * c - (int64_t)d.phi, v[j], ok[j], un[j]);
+            }
+        }
+        if (dsta || prop) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint64_t k = kb + 64u * j + lane;
+                const bool act = k < k_end;
+                const int64_t e = (int64_t)(d.e0 + k);
+                const int64_t i0d = 16 * e - (int64_t)d.psi;
+                const uint32_t md = act ? rmask(d.d_lo - i0d, d.d_hi - i0d) : 0u;
+                uint32_t wm = md;
+                if (dst_host && md) {
+                    const uint32_t a = R.a16[(d.a_dst + 16 * e) >> 4];
+                    wm = md & a;
+                    const uint32_t ud = md & ~a;
+                    if (check && ud) {
+                        acc.flags |= CG_DST_UNADDR;
+                        acc_min(acc, i0d + __builtin_ctz(ud));
+                    }
+                }
+                if (prop) {
+                    const u32x4 own = prop_val(v[j], ok[j]);
+                    u32x4 nxt;
+                    nxt.x = __shfl_down(own.x, 1);
+                    nxt.y = __shfl_down(own.y, 1);
+                    nxt.z = __shfl_down(own.z, 1);
+                    nxt.w = __shfl_down(own.w, 1);
+                    if (j + 1 < U) {
+                        const u32x4 g = prop_val(v[j + 1 < U ? j + 1 : j], ok[j + 1 < U ? j + 1 : j]);
+                        const uint32_t gx = __shfl(g.x, 0), gy = __shfl(g.y, 0), gz = __shfl(g.z, 0),
+                                       gw = __shfl(g.w, 0);
+                        if (lane == 63u) nxt = u32x4{gx, gy, gz, gw};
+                    }
+                    const bool self = act && ((lane == 63u && j == U - 1) || k + 1 >= k_end);
+                    if (self) {
+                        u32x4 vn;
+                        uint32_t okn, unn;
+                        src_chunk<NT>(d, R, e - (int64_t)d.delta + 1, vn, okn, unn);
+                        nxt = prop_val(vn, okn);
+                    }
+                    if (wm) store_masked(reinterpret_cast<uint8_t *>(d.dst_sh + (uint64_t)(16 * e)),
+                                         window(own, nxt, d.s), wm);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one unit handled by one lane (small records, tile boundaries)
+// ---------------------------------------------------------------------------
+template <bool NT>
+__device__ __forceinline__ void run_unit(const DV &d, const Region &R, uint64_t k, Acc &acc)
+{
+    const bool check = (d.ctl & CTL_CHECK) != 0;
+    const int64_t e = (int64_t)(d.e0 + k);
+    const int64_t c = e - (int64_t)d.delta;
+    u32x4 v;
+    uint32_t ok, un;
+    src_chunk<NT>(d, R, c, v, ok, un);
+    if (check) src_findings(acc, 16 * c - (int64_t)d.phi, v, ok, un);
+    if (d.ctl & (CTL_DST_A | CTL_PROP)) {
+        const int64_t i0d = 16 * e - (int64_t)d.psi;
+        const uint32_t md = rmask(d.d_lo - i0d, d.d_hi - i0d);
+        uint32_t wm = md;
+        if ((d.ctl & CTL_DST_HOST) && md) {
+            const uint32_t a = R.a16[(d.a_dst + 16 * e) >> 4];
+            wm = md & a;
+            const uint32_t ud = md & ~a;
+            if (check && ud) {
+                acc.flags |= CG_DST_UNADDR;
+                acc_min(acc, i0d + __builtin_ctz(ud));
+            }
+        }
+        if ((d.ctl & CTL_PROP) && wm) {
+            u32x4 vn;
+            uint32_t okn, unn;
+            src_chunk<NT>(d, R, c + 1, vn, okn, unn);
+            store_masked(reinterpret_cast<uint8_t *>(d.dst_sh + (uint64_t)(16 * e)),
+                         window(prop_val(v, ok), prop_val(vn, okn), d.s), wm);
+        }
+    }
+}
+
+// Segmented flush: lanes hold findings for records `rec` (contiguous runs of
+// equal values; inactive lanes carry rec = ~0).  Only called when some lane
+// found something.
+__device__ __forceinline__ void flush_segmented(Acc &a, uint64_t rec, cg_verdict *out)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t prev = __shfl_up(rec, 1);
+    const bool head = lane == 0u || prev != rec;
+    const uint64_t heads = __ballot(head);
+    const uint64_t below = heads & (lane == 63u ? ~0ull : ((2ull << lane) - 1ull));
+    const uint32_t start = 63u - (uint32_t)__builtin_clzll(below);
+    for (uint32_t dd = 1; dd < 64u; dd <<= 1) {
+        const uint64_t of = __shfl_up(a.first, dd);
+        const uint64_t ou = __shfl_up(a.undef, dd);
+        const uint32_t ofl = __shfl_up(a.flags, dd);
+        if (lane >= dd && lane - dd >= start) {
+            a.first = of < a.first ? of : a.first;
+            a.undef += ou;
+            a.flags |= ofl;
+        }
+    }
+    const uint64_t next = __shfl_down(rec, 1);
+    const bool tail = lane == 63u || next != rec;
+    if (tail && rec != ~0ull && a.flags) {
+        atomicOr(&out[rec].flags, a.flags);
+        if (a.first != NONE) atomicMin((unsigned long long *)&out[rec].first_bad, (unsigned long long)a.first);
+        if (a.undef) atomicAdd((unsigned long long *)&out[rec].undef_bytes, (unsigned long long)a.undef);
+    }
+    acc_reset(a);
+}
+
+// ---------------------------------------------------------------------------
+// k_classify
+// ---------------------------------------------------------------------------
+
+// Largest index j with base[j] <= p among live allocations, if p < end[j].
+__device__ __forceinline__ int64_t table_lookup(const TableView &tb, const uint64_t *top, uint64_t p)
+{
+    if (tb.n == 0 || top[0] > p) return -1;
+    uint32_t lo = 0, hi = tb.ntop - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (top[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    uint64_t a = (uint64_t)lo << tb.top_shift;
+    uint64_t b = a + (1ull << tb.top_shift);
+    b = (b < tb.n ? b : tb.n) - 1;
+    while (a < b) {
+        const uint64_t mid = (a + b + 1) >> 1;
+        if (tb.base[mid] <= p) a = mid; else b = mid - 1;
+    }
+    return p < tb.end[a] ? (int64_t)a : -1;
+}
+
+// Byte indices i in [0, n) with hb <= p + i < hb + hl, as [lo, hi) (empty: 0, 0).
+__device__ __forceinline__ void region_clip(uint64_t p, uint64_t n, uint64_t hb, uint64_t hl,
+                                            uint64_t &lo, uint64_t &hi)
+{
+    lo = hi = 0;
+    if (hl == 0) return;
+    if (p >= hb) {
+        const uint64_t off = p - hb;
+        if (off >= hl) return;
+        lo = 0;
+        hi = (n < hl - off) ? n : hl - off;
+    } else {
+        const uint64_t gap = hb - p;
+        if (gap >= n) return;
+        lo = gap;
+        hi = (n - gap > hl) ? gap + hl : n;
+    }
+}
+
+__device__ __forceinline__ uint64_t clamp_scan(uint64_t x) { return x < kScanLimit ? x : kScanLimit; }
+
+// Decode record t; write its verdict's range-derived fields and its
+// descriptor; return its number of units.
+__device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
+{
+    const cg_transfer r = a.recs[t];
+    const uint64_t n = r.n;
+    Desc ds = {};
+    uint32_t flags = 0;
+    uint64_t first = NONE, avail = 0;
+    const bool check = (a.mode & CG_CHECK) != 0;
+    uint64_t units = 0;
+
+    if (r.kind > CG_D2D) {
+        flags = CG_BAD_KIND;
+    } else if (n != 0) {
+        const bool src_host = r.kind == CG_H2D;
+        const bool dst_host = r.kind == CG_D2H;
+        const Region &R = st.region;
+        uint64_t vlo = 0, vhi = 0, dlo = 0, dhi = 0, avail_s = 0, avail_d = 0;
+        uint32_t phi = 0, psi = 0;
+        uint64_t src0 = 0, dst0 = 0;   // shadow address of byte 0 (when valid)
+        bool src_ok = false, dst_ok = false;
+        if (src_host) {
+            region_clip(r.src, n, R.hb, R.hl, vlo, vhi);
+            if (vhi <= vlo || vlo > 0) { flags |= CG_SRC_UNADDR; first = 0; }
+            else if (vhi < n) { flags |= CG_SRC_UNADDR; first = first < vhi ? first : vhi; }
+            src_ok = vhi > vlo;
+            src0 = (uint64_t)R.v + (r.src - R.hb);
+            phi = (uint32_t)((r.src - R.hb) & 15u);
+            ds.a_src = (int64_t)((r.src - R.hb) - phi);
+        } else {
+            const int64_t j = table_lookup(st.table, top, r.src);
+            if (j < 0) { flags |= CG_SRC_UNALLOC; first = 0; }
+            else {
+                avail_s = st.table.end[j] - r.src;
+                if (n > avail_s) { flags |= CG_SRC_OVERRUN; first = first < avail_s ? first : avail_s; }
+                vlo = 0;
+                vhi = n < avail_s ? n : avail_s;
+                src0 = st.pool + st.table.off[j] + (r.src - st.table.base[j]);
+                phi = (uint32_t)(src0 & 15u);
+                src_ok = true;
+            }
+        }
+        if (dst_host) {
+            region_clip(r.dst, n, R.hb, R.hl, dlo, dhi);
+            if (dhi <= dlo || dlo > 0) { flags |= CG_DST_UNADDR; first = 0; }
+            else if (dhi < n) { flags |= CG_DST_UNADDR; first = first < dhi ? first : dhi; }
+            dst_ok = dhi > dlo;
+            dst0 = (uint64_t)R.v + (r.dst - R.hb);
+            psi = (uint32_t)((r.dst - R.hb) & 15u);
+            ds.a_dst = (int64_t)((r.dst - R.hb) - psi);
+        } else {
+            const int64_t j = table_lookup(st.table, top, r.dst);
+            if (j < 0) { flags |= CG_DST_UNALLOC; first = 0; }
+            else {
+                avail_d = st.table.end[j] - r.dst;
+                if (n > avail_d) { flags |= CG_DST_OVERRUN; first = first < avail_d ? first : avail_d; }
+                dlo = 0;
+                dhi = n < avail_d ? n : avail_d;
+                dst0 = st.pool + st.table.off[j] + (r.dst - st.table.base[j]);
+                psi = (uint32_t)(dst0 & 15u);
+                dst_ok = true;
+            }
+        }
+        bool overlap = false;
+        if (r.kind == CG_D2D) {
+            overlap = (r.src < r.dst) ? (r.dst - r.src < n) : (r.src - r.dst < n);
+            if (overlap) flags |= CG_OVERLAP;
+        }
+        avail = src_host ? avail_d : (dst_host ? avail_s : (avail_s < avail_d ? avail_s : avail_d));
+
+        const bool prop = (a.mode & CG_PROPAGATE) && !overlap;
+        const bool dsta = check && dst_host;
+        const bool dstwork = (prop || dsta) && dst_ok;
+        vlo = clamp_scan(vlo); vhi = clamp_scan(vhi);
+        dlo = clamp_scan(dlo); dhi = clamp_scan(dhi);
+        const uint32_t delta = (dstwork && phi < psi) ? 1u : 0u;
+        // unit ranges of the source and destination sides
+        uint64_t e_lo = ~0ull, e_hi = 0;
+        if (src_ok && vhi > vlo) {
+            const uint64_t c_lo = (vlo + phi) >> 4, c_hi = ((vhi - 1 + phi) >> 4) + 1;
+            e_lo = c_lo + delta;
+            e_hi = c_hi + delta;
+            // propagation needs every destination chunk, including those whose
+            // bytes come only from invalid source bytes (written as 0xFF)
+        }
+        if (dstwork && dhi > dlo) {
+            const uint64_t f_lo = (dlo + psi) >> 4, f_hi = ((dhi - 1 + psi) >> 4) + 1;
+            e_lo = f_lo < e_lo ? f_lo : e_lo;
+            e_hi = f_hi > e_hi ? f_hi : e_hi;
+        }
+        if (e_hi > e_lo) units = e_hi - e_lo; else e_lo = 0;
+        ds.src_sh = src0 - phi;
+        ds.dst_sh = dst0 - psi;
+        ds.v_lo = (int64_t)vlo; ds.v_hi = (int64_t)vhi;
+        ds.d_lo = (int64_t)dlo; ds.d_hi = (int64_t)dhi;
+        ds.e0 = e_lo;
+        ds.units = units;
+        ds.ctl = (src_host ? CTL_SRC_HOST : 0u) | (dst_host ? CTL_DST_HOST : 0u) | (check ? CTL_CHECK : 0u) |
+                 (prop && dst_ok ? CTL_PROP : 0u) | (dsta && dst_ok ? CTL_DST_A : 0u) |
+                 (phi << CTL_PHI_SHIFT) | (psi << CTL_PSI_SHIFT) | (delta ? CTL_DELTA : 0u);
+        if (!src_ok) { ds.v_lo = 0; ds.v_hi = 0; }
+    }
+    a.desc[t] = ds;
+    a.weight[t] = units;
+    if (a.out && check) {
+        cg_verdict v;
+        v.flags = flags;
+        v.reserved = 0;
+        v.first_bad = first;
+        v.undef_bytes = 0;
+        v.avail = avail;
+        a.out[t] = v;
+    }
+    return units;
+}
+
+__global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
+{
+    __shared__ uint64_t top[kMaxTop];
+    __shared__ uint64_t wsum[kClassifyBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    const DevState st = *a.st;
+    for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
+    uint64_t w = 0;
+    if (t < a.count) {
+        const uint64_t u = classify_one(a, st, t, top);
+        w = u ? u : 1;
+    }
+    // block exclusive scan of w
+    const uint32_t lane = lane_id(), wid = tid >> 6;
+    uint64_t x = w;
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63u) wsum[wid] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
+    if (t < a.count) a.local[t] = off + x - w;
+    if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
+}
+
+// ---------------------------------------------------------------------------
+// k_scan_sums: one block, exclusive scan of the classify-block sums
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_units)
+{
+    __shared__ uint64_t wsum[16];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const uint64_t nb = (a.count + kClassifyBlock - 1) / kClassifyBlock;
+    const uint64_t per = (nb + 1023) / 1024;
+    const uint64_t b0 = tid * per, b1 = (b0 + per < nb) ? b0 + per : nb;
+    uint64_t s = 0;
+    for (uint64_t b = b0; b < b1; ++b) s += a.bsum[b];
+    uint64_t x = s;
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63u) wsum[wid] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
+    uint64_t run = off + x - s;
+    for (uint64_t b = b0; b < b1; ++b) {
+        a.boff[b] = run;
+        run += a.bsum[b];
+    }
+    if (tid == 1023) {
+        const uint64_t total = off + x;
+        uint64_t tu = tile_units;
+        while ((total + tu - 1) / tu > a.tiles_cap) tu <<= 1;
+        a.ctl->total_units = total;
+        a.ctl->tile_units = tu;
+        a.ctl->ntiles = (total + tu - 1) / tu;
+        a.ctl->counter = 0;
+        a.prefix[a.count] = total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_prefix_tiles: global prefix and the first record of every tile
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_prefix_tiles(BatchArgs a)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= a.count) return;
+    const uint64_t p = a.local[t] + a.boff[t / kClassifyBlock];
+    a.prefix[t] = p;
+    const uint64_t w = a.weight[t] ? a.weight[t] : 1;
+    const uint64_t tu = a.ctl->tile_units;
+    const uint64_t j0 = (p + tu - 1) / tu, j1 = (p + w + tu - 1) / tu;
+    for (uint64_t j = j0; j < j1; ++j) a.tile_start[j] = (uint32_t)t;
+}
+
+// ---------------------------------------------------------------------------
+// k_batched: persistent kernel over the tiles of the flattened unit space
+// ---------------------------------------------------------------------------
+template <int U, bool NT>
+__global__ void __launch_bounds__(512) k_batched(BatchArgs a)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t ntiles = a.ctl->ntiles;
+    const uint64_t tu = a.ctl->tile_units;
+    const uint64_t total = a.ctl->total_units;
+    const uint64_t T = a.count;
+    const Region R = a.st->region;
+    Acc acc;
+    acc_reset(acc);
+    for (;;) {
+        uint32_t j = 0;
+        if (lane == 0) j = atomicAdd(&a.ctl->counter, 1u);
+        j = __shfl(j, 0);
+        if (j >= ntiles) break;
+        uint64_t u = (uint64_t)j * tu;
+        const uint64_t u_end = (u + tu < total) ? u + tu : total;
+        uint64_t t = a.tile_start[j];
+        while (u < u_end) {
+            const uint64_t pt = a.prefix[t], pt1 = a.prefix[t + 1];
+            const uint64_t seg_end = pt1 < u_end ? pt1 : u_end;
+            const uint64_t nfull = (seg_end - u) & ~63ull;
+            if (nfull) {
+                const DV d = load_desc(a.desc, t);
+                run_uniform<U, NT>(d, R, u - pt, u - pt + nfull, acc);
+                if (a.out) flush_wave(acc, a.out, t);
+                u += nfull;
+                if (u == pt1) ++t;
+                continue;
+            }
+            // up to 64 units, one per lane, possibly of several records
+            const uint64_t g_end = (u + 64 < u_end) ? u + 64 : u_end;
+            const uint64_t ul = u + lane;
+            const bool act = ul < g_end;
+            uint64_t lo = t, hi = (t + 64 < T - 1) ? t + 64 : T - 1;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi + 1) >> 1;
+                if (a.prefix[mid] <= ul) lo = mid; else hi = mid - 1;
+            }
+            const uint64_t tl = lo;
+            if (act) {
+                const DV d = load_desc(a.desc, tl);
+                const uint64_t k = ul - a.prefix[tl];
+                if (k < d.units) run_unit<NT>(d, R, k, acc);
+            }
+            if (a.out && __ballot(acc.flags != 0u)) flush_segmented(acc, act ? tl : ~0ull, a.out);
+            else acc_reset(acc);
+            if (g_end < u_end) {
+                const uint64_t t63 = __shfl(tl, 63);
+                t = (a.prefix[t63 + 1] <= g_end) ? t63 + 1 : t63;
+            }
+            u = g_end;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_plain: one record per launch, waves split its units evenly
+// ---------------------------------------------------------------------------
+template <int U, bool NT>
+__global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t units)
+{
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    uint64_t span = (units + waves - 1) / waves;
+    span = (span + 63) & ~63ull;
+    const uint64_t k0 = w * span;
+    if (k0 >= units) return;
+    const uint64_t k1 = (k0 + span < units) ? k0 + span : units;
+    const DV d = load_desc(a.desc, t);
+    Acc acc;
+    acc_reset(acc);
+    run_uniform<U, NT>(d, a.st->region, k0, k1, acc);
+    if (a.out) flush_wave(acc, a.out, t);
+}
+
+// ---------------------------------------------------------------------------
+// shadow fills and bandwidth probes
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fill(const FillRange *ranges, uint64_t k)
+{
+    for (uint64_t i = blockIdx.x; i < k; i += gridDim.x) {
+        const FillRange fr = ranges[i];
+        uint8_t *p = reinterpret_cast<uint8_t *>(fr.ptr);
+        const uint8_t v = (uint8_t)fr.val;
+        const uint64_t len = fr.len;
+        uint64_t head = (16u - (fr.ptr & 15u)) & 15u;
+        head = head < len ? head : len;
+        if (threadIdx.x < head) p[threadIdx.x] = v;
+        const uint64_t body = (len - head) & ~15ull;
+        const uint32_t w = 0x01010101u * v;
+        const u32x4 vv{w, w, w, w};
+        for (uint64_t o = head + 16ull * threadIdx.x; o < head + body; o += 16ull * blockDim.x)
+            *reinterpret_cast<u32x4 *>(p + o) = vv;
+        const uint64_t tail = len - head - body;
+        if (threadIdx.x < tail) p[head + body + threadIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_probe_read(const u32x4 *p, uint64_t n16, uint64_t *sink)
+{
+    u32x4 acc{0u, 0u, 0u, 0u};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(p + i);
+        const u32x4 b = __builtin_nontemporal_load(p + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(p + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(p + i + 3 * stride);
+        acc ^= a ^ b ^ c ^ d;
+    }
+    for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(p + i);
+    const uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+    if (x == 0x9E3779B9u) atomicXor((unsigned long long *)sink, (unsigned long long)x);
+}
+
+__global__ void __launch_bounds__(256) k_probe_copy(u32x4 *d, const u32x4 *p, uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        d[i] = __builtin_nontemporal_load(p + i);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_classify(const BatchArgs &a, hipStream_t s)
+{
+    const uint64_t blocks = (a.count + kClassifyBlock - 1) / kClassifyBlock;
+    hipLaunchKernelGGL(k_classify, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, a, tile_units);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s)
+{
+    const uint64_t blocks = (a.count + 255) / 256;
+    hipLaunchKernelGGL(k_prefix_tiles, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int U, bool NT>
+static void launch_batched_t(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batched<U, NT>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+}
+
+template <int U, bool NT>
+static void launch_plain_t(const BatchArgs &a, uint64_t t, uint64_t units, uint32_t grid, uint32_t block,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((k_plain<U, NT>), dim3(grid), dim3(block), 0, s, a, t, units);
+}
+
+#define XC_DISPATCH(FN, ...)                                                   \
+    do {                                                                       \
+        const bool nt_ = sh.nontemporal != 0;                                  \
+        switch (sh.unroll) {                                                   \
+        case 1: nt_ ? FN<1, true>(__VA_ARGS__) : FN<1, false>(__VA_ARGS__); break; \
+        case 2: nt_ ? FN<2, true>(__VA_ARGS__) : FN<2, false>(__VA_ARGS__); break; \
+        case 8: nt_ ? FN<8, true>(__VA_ARGS__) : FN<8, false>(__VA_ARGS__); break; \
+        default: nt_ ? FN<4, true>(__VA_ARGS__) : FN<4, false>(__VA_ARGS__); break; \
+        }                                                                      \
+    } while (0)
+
+hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
+{
+    XC_DISPATCH(launch_batched_t, a, sh, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh, hipStream_t s)
+{
+    const uint64_t per_block = (uint64_t)(sh.block / 64) * 64u * sh.unroll * 4u;
+    uint64_t grid = (units + per_block - 1) / per_block;
+    if (grid > sh.grid) grid = sh.grid;
+    if (grid == 0) grid = 1;
+    XC_DISPATCH(launch_plain_t, a, rec, units, (uint32_t)grid, sh.block, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s)
+{
+    if (k == 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)(k < 65536 ? k : 65536);
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, ranges_dev, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_read(const void *p, uint64_t bytes, uint64_t *sink, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_probe_read, dim3(8192), dim3(256), 0, s, reinterpret_cast<const u32x4 *>(p), bytes / 16,
+                       sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(void *d, const void *p, uint64_t bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_probe_copy, dim3(8192), dim3(256), 0, s, reinterpret_cast<u32x4 *>(d),
+                       reinterpret_cast<const u32x4 *>(p), bytes / 16);
+    return hipGetLastError();
+}
+
+}  // namespace xc

@@ -1,0 +1,904 @@
+// Host runtime of the transfer checker: context, allocation table and its
+// device mirror, shadow pool, per-stream workspaces, graph cache, plain and
+// batched check paths, autotuner and the C ABI declared in xfercheck.h.
+//
+// Method: Cudagrind (arXiv 1310.0901).  The wrappers of Sec. 1.2 / Sec. 2 keep
+// a per-context list of device allocations, updated on every allocation and
+// free, and cross-check each copy against it and against host shadow memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "host_logic.h"
+#include "xc_internal.h"
+
+using namespace xc;
+
+namespace {
+
+constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
+constexpr uint64_t kFillCap = 1ull << 16;     // ranges per fill launch
+constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
+constexpr size_t kGraphsPerWs = 8;
+
+// A captured batched check.  With kernel timing on, the scan kernel is kept in
+// a graph of its own so that events on the caller's stream bracket exactly it.
+struct GraphEntry {
+    const void *recs;
+    void *out;
+    uint64_t count;
+    uint32_t mode;
+    cg_tuning tun;
+    bool split;
+    hipGraph_t graph, graph2;
+    hipGraphExec_t exec, exec2;
+};
+
+void destroy_graph(GraphEntry &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.exec2) (void)hipGraphExecDestroy(g.exec2);
+    if (g.graph2) (void)hipGraphDestroy(g.graph2);
+}
+
+struct Workspace {
+    uint64_t cap = 0;
+    Desc *desc = nullptr;
+    uint64_t *weight = nullptr, *local = nullptr, *bsum = nullptr, *boff = nullptr, *prefix = nullptr;
+    uint32_t *tile_start = nullptr;
+    Ctl *ctl = nullptr;
+    uint64_t *h_weight = nullptr;   // pinned copy of weights (plain path)
+    hipEvent_t done = nullptr;      // recorded after every check issued on this stream
+    bool used = false;
+    std::vector<GraphEntry> graphs;
+};
+
+struct TimingPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+bool same_tuning(const cg_tuning &x, const cg_tuning &y)
+{
+    return x.block == y.block && x.unroll == y.unroll && x.blocks_per_cu == y.blocks_per_cu &&
+           x.tile_units == y.tile_units && x.nontemporal == y.nontemporal;
+}
+
+}  // namespace
+
+struct cg_ctx {
+    int dev = 0;
+    int cu_count = 0;
+    std::string arch;
+    hipStream_t s = nullptr;     // the context's own stream (table and shadow updates)
+    hipStream_t cap = nullptr;   // graph capture stream
+    uint8_t *pool = nullptr;
+    uint64_t pool_bytes = 0;
+    PoolAllocator *palloc = nullptr;
+    AllocTable table;
+    uint64_t max_allocs = 0;
+    // device mirror of the table and state
+    uint64_t *d_tab = nullptr;   // base | end | off | top, contiguous
+    DevState *d_state = nullptr;
+    uint64_t *h_stage = nullptr;   // pinned staging for the table upload
+    DevState *h_state = nullptr;
+    hipEvent_t ev_stage = nullptr;
+    bool stage_busy = false;
+    bool dirty = true;
+    Region region{0, 0, nullptr, nullptr};
+    // fills
+    FillRange *d_fill = nullptr, *h_fill = nullptr;
+    hipEvent_t ev_fill = nullptr;
+    bool fill_busy = false;
+    // ordering
+    hipEvent_t ev_ctx = nullptr;
+    std::map<hipStream_t, Workspace *> ws;
+    cg_tuning tuning{};
+    // timing
+    bool timing = false;
+    std::vector<TimingPair> tpairs;   // pairs of the last check
+    size_t tused = 0;
+    std::string last_error;
+};
+
+namespace {
+
+int fail(cg_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->last_error = msg;
+    return code;
+}
+
+int hip_fail(cg_ctx *c, const char *what, hipError_t e)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, CG_EHIP, m);
+}
+
+#define HIPTRY(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, #call, e_); \
+    } while (0)
+
+// ctx stream waits for every check issued so far
+int ctx_begin(cg_ctx *c)
+{
+    for (auto &kv : c->ws)
+        if (kv.second->used) HIPTRY(c, hipStreamWaitEvent(c->s, kv.second->done, 0));
+    return CG_OK;
+}
+
+int ctx_end(cg_ctx *c)
+{
+    HIPTRY(c, hipEventRecord(c->ev_ctx, c->s));
+    return CG_OK;
+}
+
+// Upload the table and state if they changed (on the context stream).
+int upload(cg_ctx *c)
+{
+    if (!c->dirty) return CG_OK;
+    if (c->stage_busy) {
+        HIPTRY(c, hipEventSynchronize(c->ev_stage));
+        c->stage_busy = false;
+    }
+    const uint64_t n = c->table.size();
+    const uint64_t M = c->max_allocs;
+    uint64_t *hb = c->h_stage, *he = hb + M, *ho = he + M, *ht = ho + M;
+    c->table.export_sorted(hb, he, ho);
+    uint32_t shift = 0;
+    while (((n + (1ull << shift) - 1) >> shift) > (uint64_t)kMaxTop) ++shift;
+    const uint32_t ntop = (uint32_t)((n + (1ull << shift) - 1) >> shift);
+    for (uint32_t k = 0; k < ntop; ++k) ht[k] = hb[(uint64_t)k << shift];
+    DevState &st = *c->h_state;
+    st.table.base = c->d_tab;
+    st.table.end = c->d_tab + M;
+    st.table.off = c->d_tab + 2 * M;
+    st.table.top = c->d_tab + 3 * M;
+    st.table.n = n;
+    st.table.top_shift = shift;
+    st.table.ntop = ntop;
+    st.region = c->region;
+    st.pool = (uint64_t)c->pool;
+    int rc = ctx_begin(c);
+    if (rc) return rc;
+    if (n) {
+        HIPTRY(c, hipMemcpyAsync(c->d_tab, hb, n * 8, hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, hipMemcpyAsync(c->d_tab + M, he, n * 8, hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, hipMemcpyAsync(c->d_tab + 2 * M, ho, n * 8, hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, hipMemcpyAsync(c->d_tab + 3 * M, ht, ntop * 8ull, hipMemcpyHostToDevice, c->s));
+    }
+    HIPTRY(c, hipMemcpyAsync(c->d_state, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
+    HIPTRY(c, hipEventRecord(c->ev_stage, c->s));
+    c->stage_busy = true;
+    c->dirty = false;
+    return ctx_end(c);
+}
+
+// Issue fills of [ptr, ptr + len) with v on the context stream.
+int issue_fills(cg_ctx *c, const std::vector<FillRange> &rs)
+{
+    size_t i = 0;
+    int rc = ctx_begin(c);
+    if (rc) return rc;
+    while (i < rs.size()) {
+        if (c->fill_busy) {
+            HIPTRY(c, hipEventSynchronize(c->ev_fill));
+            c->fill_busy = false;
+        }
+        size_t k = 0;
+        for (; i < rs.size() && k < kFillCap; ++i) c->h_fill[k++] = rs[i];
+        HIPTRY(c, hipMemcpyAsync(c->d_fill, c->h_fill, k * sizeof(FillRange), hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, launch_fill(c->d_fill, k, c->s));
+        HIPTRY(c, hipEventRecord(c->ev_fill, c->s));
+        c->fill_busy = true;
+    }
+    return ctx_end(c);
+}
+
+void add_fill(std::vector<FillRange> &rs, uint64_t ptr, uint64_t len, uint8_t v)
+{
+    while (len) {
+        const uint64_t take = len < kFillPiece ? len : kFillPiece;
+        rs.push_back(FillRange{ptr, take, v, 0});
+        ptr += take;
+        len -= take;
+    }
+}
+
+void free_ws(Workspace *w)
+{
+    for (auto &g : w->graphs) destroy_graph(g);
+    w->graphs.clear();
+    (void)hipFree(w->desc);
+    (void)hipFree(w->weight);
+    (void)hipFree(w->local);
+    (void)hipFree(w->bsum);
+    (void)hipFree(w->boff);
+    (void)hipFree(w->prefix);
+    (void)hipFree(w->tile_start);
+    (void)hipFree(w->ctl);
+    if (w->h_weight) (void)hipHostFree(w->h_weight);
+    w->desc = nullptr;
+    w->weight = w->local = w->bsum = w->boff = w->prefix = nullptr;
+    w->tile_start = nullptr;
+    w->ctl = nullptr;
+    w->h_weight = nullptr;
+    w->cap = 0;
+}
+
+int get_ws(cg_ctx *c, hipStream_t s, uint64_t count, Workspace **out)
+{
+    Workspace *w;
+    auto it = c->ws.find(s);
+    if (it == c->ws.end()) {
+        w = new Workspace();
+        HIPTRY(c, hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+        c->ws[s] = w;
+    } else {
+        w = it->second;
+    }
+    if (w->cap < count) {
+        // buffers may be in use by earlier checks on this stream
+        HIPTRY(c, hipStreamSynchronize(s));
+        free_ws(w);
+        uint64_t cap = 1024;
+        while (cap < count) cap <<= 1;
+        const uint64_t nb = (cap + kClassifyBlock - 1) / kClassifyBlock;
+        HIPTRY(c, hipMalloc(&w->desc, cap * sizeof(Desc)));
+        HIPTRY(c, hipMalloc(&w->weight, cap * 8));
+        HIPTRY(c, hipMalloc(&w->local, cap * 8));
+        HIPTRY(c, hipMalloc(&w->bsum, nb * 8));
+        HIPTRY(c, hipMalloc(&w->boff, nb * 8));
+        HIPTRY(c, hipMalloc(&w->prefix, (cap + 1) * 8));
+        HIPTRY(c, hipMalloc(&w->tile_start, kTilesCap * 4));
+        HIPTRY(c, hipMalloc(&w->ctl, sizeof(Ctl)));
+        HIPTRY(c, hipHostMalloc(&w->h_weight, cap * 8, hipHostMallocDefault));
+        w->cap = cap;
+    }
+    *out = w;
+    return CG_OK;
+}
+
+BatchArgs make_args(cg_ctx *c, Workspace *w, const cg_transfer *recs, uint64_t count, cg_verdict *out,
+                    uint32_t mode)
+{
+    BatchArgs a{};
+    a.recs = recs;
+    a.count = count;
+    a.out = (mode & CG_CHECK) ? out : nullptr;
+    a.mode = mode & (CG_CHECK | CG_PROPAGATE);
+    a.st = c->d_state;
+    a.desc = w->desc;
+    a.weight = w->weight;
+    a.local = w->local;
+    a.bsum = w->bsum;
+    a.boff = w->boff;
+    a.prefix = w->prefix;
+    a.tile_start = w->tile_start;
+    a.tiles_cap = kTilesCap;
+    a.ctl = w->ctl;
+    return a;
+}
+
+LaunchShape shape_of(cg_ctx *c, const cg_tuning &t)
+{
+    LaunchShape sh;
+    sh.block = t.block;
+    sh.unroll = t.unroll;
+    sh.grid = (uint32_t)c->cu_count * t.blocks_per_cu;
+    sh.nontemporal = t.nontemporal;
+    sh.tile_units = t.tile_units;
+    return sh;
+}
+
+hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_classify(a, s)) != hipSuccess) return e;
+    if ((e = launch_scan_sums(a, sh.tile_units, s)) != hipSuccess) return e;
+    return launch_prefix_tiles(a, s);
+}
+
+hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp)
+{
+    hipError_t e;
+    if ((e = enqueue_prepare(a, sh, s)) != hipSuccess) return e;
+    if (tp && (e = hipEventRecord(tp->a, s)) != hipSuccess) return e;
+    if ((e = launch_batched(a, sh, s)) != hipSuccess) return e;
+    if (tp && (e = hipEventRecord(tp->b, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part);
+
+TimingPair *next_pair(cg_ctx *c)
+{
+    if (c->tused == c->tpairs.size()) {
+        TimingPair p;
+        (void)hipEventCreate(&p.a);
+        (void)hipEventCreate(&p.b);
+        c->tpairs.push_back(p);
+    }
+    return &c->tpairs[c->tused++];
+}
+
+int valid_tuning(const cg_tuning &t)
+{
+    const bool u_ok = t.unroll == 1 || t.unroll == 2 || t.unroll == 4 || t.unroll == 8;
+    const bool b_ok = t.block == 256 || t.block == 512;
+    const bool tu_ok = t.tile_units >= 4096 && (t.tile_units & (t.tile_units - 1)) == 0;
+    return u_ok && b_ok && tu_ok && t.blocks_per_cu >= 1 && t.blocks_per_cu <= 16;
+}
+
+// Host-side verification of the no-conflict rule for propagation: no
+// record's destination shadow bytes may meet another record's source or
+// destination shadow bytes.
+int debug_conflicts(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, hipStream_t s)
+{
+    std::vector<cg_transfer> h(count);
+    HIPTRY(c, hipMemcpyAsync(h.data(), recs_dev, count * sizeof(cg_transfer), hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    struct Iv {
+        uint64_t a, b;   // shadow byte interval in a unified space
+        uint64_t rec;
+        bool write;
+    };
+    std::vector<Iv> iv;
+    // unified shadow space: host region at [0, hl), pool at [2^63, 2^63 + pool)
+    const uint64_t POOL = 1ull << 63;
+    auto host_iv = [&](uint64_t p, uint64_t n, uint64_t *a, uint64_t *b) {
+        const uint64_t hb = c->region.hb, hl = c->region.hl;
+        uint64_t lo = std::max<uint64_t>(p, hb), hi = std::min<uint64_t>(p + n < p ? ~0ull : p + n, hb + hl);
+        if (hi <= lo) return false;
+        *a = lo - hb;
+        *b = hi - hb;
+        return true;
+    };
+    auto dev_iv = [&](uint64_t p, uint64_t n, uint64_t *a, uint64_t *b) {
+        uint64_t base;
+        const AllocEntry *e = c->table.find(p, &base);
+        if (!e) return false;
+        const uint64_t avail = base + e->size - p;
+        *a = POOL + e->off + (p - base);
+        *b = *a + std::min(n, avail);
+        return true;
+    };
+    for (uint64_t t = 0; t < count; ++t) {
+        const cg_transfer &r = h[t];
+        if (r.kind > CG_D2D || r.n == 0) continue;
+        if (r.kind == CG_D2D) {
+            const bool ov = (r.src < r.dst) ? (r.dst - r.src < r.n) : (r.src - r.dst < r.n);
+            if (ov) {
+                uint64_t a, b;
+                if (dev_iv(r.src, r.n, &a, &b)) iv.push_back({a, b, t, false});
+                continue;   // not propagated
+            }
+        }
+        uint64_t a, b;
+        const bool sh = r.kind == CG_H2D, dh = r.kind == CG_D2H;
+        if (sh ? host_iv(r.src, r.n, &a, &b) : dev_iv(r.src, r.n, &a, &b)) iv.push_back({a, b, t, false});
+        if (dh ? host_iv(r.dst, r.n, &a, &b) : dev_iv(r.dst, r.n, &a, &b)) iv.push_back({a, b, t, true});
+    }
+    std::sort(iv.begin(), iv.end(), [](const Iv &x, const Iv &y) { return x.a < y.a; });
+    // sweep by start: keep, for reads and for writes separately, the two
+    // furthest-reaching intervals of distinct records seen so far
+    struct Best {
+        uint64_t end1 = 0, rec1 = ~0ull, end2 = 0;
+        uint64_t reach_other(uint64_t rec) const { return rec1 != rec ? end1 : end2; }
+        void add(uint64_t end, uint64_t rec)
+        {
+            if (rec == rec1) { end1 = std::max(end1, end); return; }
+            if (end > end1) { end2 = end1; end1 = end; rec1 = rec; }
+            else if (end > end2) end2 = end;
+        }
+    } rd, wr;
+    for (const Iv &x : iv) {
+        if (x.a < wr.reach_other(x.rec) || (x.write && x.a < rd.reach_other(x.rec)))
+            return fail(c, CG_ECONFLICT, "record " + std::to_string(x.rec) +
+                                             " touches shadow bytes another record of the batch writes or reads");
+        (x.write ? wr : rd).add(x.b, x.rec);
+    }
+    return CG_OK;
+}
+
+int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *out, uint32_t mode,
+              hipStream_t s, const cg_tuning &tun)
+{
+    Workspace *w;
+    int rc = get_ws(c, s, count, &w);
+    if (rc) return rc;
+    rc = upload(c);
+    if (rc) return rc;
+    HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+    if ((mode & CG_DEBUG_CONFLICTS) && (mode & CG_PROPAGATE)) {
+        rc = debug_conflicts(c, recs, count, s);
+        if (rc) return rc;
+    }
+    const BatchArgs a = make_args(c, w, recs, count, out, mode);
+    const LaunchShape sh = shape_of(c, tun);
+    c->tused = 0;
+    if (mode & CG_PLAIN) {
+        HIPTRY(c, launch_classify(a, s));
+        HIPTRY(c, hipMemcpyAsync(w->h_weight, w->weight, count * 8, hipMemcpyDeviceToHost, s));
+        HIPTRY(c, hipStreamSynchronize(s));
+        TimingPair *tp = c->timing ? next_pair(c) : nullptr;
+        if (tp) HIPTRY(c, hipEventRecord(tp->a, s));
+        for (uint64_t t = 0; t < count; ++t) {
+            const uint64_t u = w->h_weight[t];
+            if (u) HIPTRY(c, launch_plain(a, t, u, sh, s));
+        }
+        if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
+    } else if (mode & CG_EAGER) {
+        TimingPair *tp = c->timing ? next_pair(c) : nullptr;
+        HIPTRY(c, enqueue_batched(a, sh, s, tp));
+    } else {
+        const bool split = c->timing;
+        GraphEntry *ge = nullptr;
+        for (auto &g : w->graphs)
+            if (g.recs == recs && g.out == out && g.count == count && g.mode == (mode & 3u) &&
+                same_tuning(g.tun, tun) && g.split == split)
+                ge = &g;
+        if (!ge) {
+            if (w->graphs.size() >= kGraphsPerWs) {
+                HIPTRY(c, hipStreamSynchronize(s));
+                destroy_graph(w->graphs.front());
+                w->graphs.erase(w->graphs.begin());
+            }
+            GraphEntry g{recs, out, count, mode & 3u, tun, split, nullptr, nullptr, nullptr, nullptr};
+            rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0);
+            if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2);
+            if (rc) { destroy_graph(g); return rc; }
+            w->graphs.push_back(g);
+            ge = &w->graphs.back();
+        }
+        if (split) {
+            TimingPair *tp = next_pair(c);
+            HIPTRY(c, hipGraphLaunch(ge->exec, s));
+            HIPTRY(c, hipEventRecord(tp->a, s));
+            HIPTRY(c, hipGraphLaunch(ge->exec2, s));
+            HIPTRY(c, hipEventRecord(tp->b, s));
+        } else {
+            HIPTRY(c, hipGraphLaunch(ge->exec, s));
+        }
+    }
+    HIPTRY(c, hipEventRecord(w->done, s));
+    w->used = true;
+    return CG_OK;
+}
+
+// Capture part 0 (the whole batched check), 1 (the preparation kernels) or
+// 2 (the scan kernel) into an executable graph.
+int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part)
+{
+    HIPTRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr)
+                 : part == 1 ? enqueue_prepare(a, sh, c->cap)
+                             : launch_batched(a, sh, c->cap);
+    hipError_t e2 = hipStreamEndCapture(c->cap, g);
+    if (e != hipSuccess) return hip_fail(c, "graph capture", e);
+    if (e2 != hipSuccess) return hip_fail(c, "hipStreamEndCapture", e2);
+    HIPTRY(c, hipGraphInstantiate(x, *g, nullptr, nullptr, 0));
+    return CG_OK;
+}
+
+std::string tuning_json(const cg_tuning &t)
+{
+    std::ostringstream o;
+    o << "\"block\": " << t.block << ", \"unroll\": " << t.unroll << ", \"blocks_per_cu\": " << t.blocks_per_cu
+      << ", \"tile_units\": " << t.tile_units << ", \"nontemporal\": " << t.nontemporal;
+    return o.str();
+}
+
+bool parse_field(const std::string &line, const char *name, uint32_t *v)
+{
+    const std::string key = std::string("\"") + name + "\": ";
+    const size_t p = line.find(key);
+    if (p == std::string::npos) return false;
+    *v = (uint32_t)std::stoul(line.substr(p + key.size()));
+    return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *cg_strerror(int status)
+{
+    switch (status) {
+    case CG_OK: return "ok";
+    case CG_EINVAL: return "invalid argument";
+    case CG_ENOMEM: return "out of shadow or device memory";
+    case CG_EOVERLAP: return "allocation overlaps a live allocation";
+    case CG_ENOTFOUND: return "not a live device allocation";
+    case CG_ECONFLICT: return "records of one batch touch the same shadow bytes";
+    case CG_ECAPACITY: return "allocation table is full";
+    case CG_EHIP: return "HIP runtime error";
+    case CG_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+const char *cg_last_error(cg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t max_allocs)
+{
+    if (!out || shadow_pool_bytes == 0 || max_allocs == 0) return CG_EINVAL;
+    *out = nullptr;
+    cg_ctx *c = new cg_ctx();
+    c->dev = hip_device;
+    c->max_allocs = max_allocs;
+    auto bail = [&](int rc) {
+        cg_destroy(c);
+        return rc;
+    };
+    if (hipSetDevice(hip_device) != hipSuccess) return bail(CG_EHIP);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return bail(CG_EHIP);
+    c->cu_count = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return bail(CG_EHIP);
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) return bail(CG_EHIP);
+    const uint64_t pool = (shadow_pool_bytes + 255) / 256 * 256;
+    if (hipMalloc(&c->pool, pool) != hipSuccess) return bail(CG_ENOMEM);
+    c->pool_bytes = pool;
+    c->palloc = new PoolAllocator(pool, 256);
+    if (hipMalloc(&c->d_tab, (3 * max_allocs + kMaxTop) * 8) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->d_state, sizeof(DevState)) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipHostMalloc(&c->h_stage, (3 * max_allocs + kMaxTop) * 8, hipHostMallocDefault) != hipSuccess)
+        return bail(CG_ENOMEM);
+    if (hipHostMalloc(&c->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->d_fill, kFillCap * sizeof(FillRange)) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipHostMalloc(&c->h_fill, kFillCap * sizeof(FillRange), hipHostMallocDefault) != hipSuccess)
+        return bail(CG_ENOMEM);
+    if (hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+    if (hipEventCreateWithFlags(&c->ev_fill, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+    if (hipEventCreateWithFlags(&c->ev_ctx, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+    c->tuning.block = 256;
+    c->tuning.unroll = 4;
+    c->tuning.blocks_per_cu = 4;
+    c->tuning.tile_units = 1u << 16;
+    c->tuning.nontemporal = 1;
+    if (const char *e = getenv("XC_UNROLL")) c->tuning.unroll = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_BLOCK")) c->tuning.block = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_BLOCKS_PER_CU")) c->tuning.blocks_per_cu = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
+    if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
+    // an empty table and region, so that checks before any allocation work
+    if (upload(c) != CG_OK) return bail(CG_EHIP);
+    if (hipStreamSynchronize(c->s) != hipSuccess) return bail(CG_EHIP);
+    *out = c;
+    return CG_OK;
+}
+
+int cg_destroy(cg_ctx *c)
+{
+    if (!c) return CG_EINVAL;
+    (void)hipSetDevice(c->dev);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->ws) {
+        free_ws(kv.second);
+        if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+        delete kv.second;
+    }
+    for (auto &p : c->tpairs) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    if (c->s) (void)hipStreamDestroy(c->s);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    (void)hipFree(c->pool);
+    (void)hipFree(c->d_tab);
+    (void)hipFree(c->d_state);
+    (void)hipFree(c->d_fill);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_fill) (void)hipHostFree(c->h_fill);
+    if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
+    if (c->ev_fill) (void)hipEventDestroy(c->ev_fill);
+    if (c->ev_ctx) (void)hipEventDestroy(c->ev_ctx);
+    delete c->palloc;
+    delete c;
+    return CG_OK;
+}
+
+int cg_host_register(cg_ctx *c, uint64_t host_base, uint64_t len, uint8_t *v_dev, uint64_t *a_bits_dev)
+{
+    if (!c) return CG_EINVAL;
+    if (len == 0 || !v_dev || !a_bits_dev) return fail(c, CG_EINVAL, "host region: null buffer or zero length");
+    if (((uint64_t)v_dev & 15u) || ((uint64_t)a_bits_dev & 7u))
+        return fail(c, CG_EINVAL, "host region: V must be 16-byte and A 8-byte aligned");
+    if (host_base + len < host_base) return fail(c, CG_EINVAL, "host region wraps the address space");
+    c->region.hb = host_base;
+    c->region.hl = len;
+    c->region.v = v_dev;
+    c->region.a16 = reinterpret_cast<const uint16_t *>(a_bits_dev);
+    c->dirty = true;
+    return CG_OK;
+}
+
+static int alloc_one(cg_ctx *c, uint64_t addr, uint64_t size, std::vector<FillRange> &fills)
+{
+    int rc = c->table.check_insert(addr, size);
+    if (rc == CG_EINVAL) return fail(c, rc, "shadow_alloc: size 0 or range wraps");
+    if (rc == CG_EOVERLAP) return fail(c, rc, "shadow_alloc: range intersects a live allocation");
+    if (c->table.size() >= c->max_allocs) return fail(c, CG_ECAPACITY, "shadow_alloc: table full");
+    uint64_t off;
+    if (!c->palloc->alloc(size, &off)) return fail(c, CG_ENOMEM, "shadow_alloc: shadow pool exhausted");
+    c->table.insert(addr, size, off);
+    add_fill(fills, (uint64_t)c->pool + off, size, 0xFF);
+    c->dirty = true;
+    return CG_OK;
+}
+
+int shadow_alloc(cg_ctx *c, uint64_t dev_addr, uint64_t size)
+{
+    if (!c) return CG_EINVAL;
+    std::vector<FillRange> fills;
+    int rc = alloc_one(c, dev_addr, size, fills);
+    if (rc) return rc;
+    return issue_fills(c, fills);
+}
+
+int shadow_alloc_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *size, uint64_t k)
+{
+    if (!c || (k && (!addr || !size))) return CG_EINVAL;
+    std::vector<FillRange> fills;
+    int rc = CG_OK;
+    for (uint64_t i = 0; i < k && rc == CG_OK; ++i) rc = alloc_one(c, addr[i], size[i], fills);
+    int rc2 = issue_fills(c, fills);
+    return rc ? rc : rc2;
+}
+
+static int free_one(cg_ctx *c, uint64_t addr)
+{
+    AllocEntry e;
+    if (c->table.erase(addr, &e) != CG_OK) return fail(c, CG_ENOTFOUND, "shadow_free: not the base of a live allocation");
+    c->palloc->release(e.off, e.size);
+    c->dirty = true;
+    return CG_OK;
+}
+
+int shadow_free(cg_ctx *c, uint64_t dev_addr)
+{
+    if (!c) return CG_EINVAL;
+    return free_one(c, dev_addr);
+}
+
+int shadow_free_batch(cg_ctx *c, const uint64_t *addr, uint64_t k)
+{
+    if (!c || (k && !addr)) return CG_EINVAL;
+    for (uint64_t i = 0; i < k; ++i) {
+        int rc = free_one(c, addr[i]);
+        if (rc) return rc;
+    }
+    return CG_OK;
+}
+
+static int set_one(cg_ctx *c, uint64_t addr, uint64_t n, uint8_t v, std::vector<FillRange> &fills)
+{
+    if (n == 0) return CG_OK;
+    uint64_t base;
+    const AllocEntry *e = c->table.find(addr, &base);
+    if (!e) return fail(c, CG_ENOTFOUND, "shadow_set: address is in no live allocation");
+    if (n > base + e->size - addr) return fail(c, CG_EINVAL, "shadow_set: range leaves the allocation");
+    add_fill(fills, (uint64_t)c->pool + e->off + (addr - base), n, v);
+    return CG_OK;
+}
+
+int shadow_set(cg_ctx *c, uint64_t dev_addr, uint64_t n, uint8_t v)
+{
+    if (!c) return CG_EINVAL;
+    std::vector<FillRange> fills;
+    int rc = set_one(c, dev_addr, n, v, fills);
+    if (rc) return rc;
+    return issue_fills(c, fills);
+}
+
+int shadow_set_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *n, const uint8_t *v, uint64_t k)
+{
+    if (!c || (k && (!addr || !n || !v))) return CG_EINVAL;
+    std::vector<FillRange> fills;
+    int rc = CG_OK;
+    for (uint64_t i = 0; i < k && rc == CG_OK; ++i) rc = set_one(c, addr[i], n[i], v[i], fills);
+    int rc2 = issue_fills(c, fills);
+    return rc ? rc : rc2;
+}
+
+int shadow_ptr(cg_ctx *c, uint64_t dev_addr, uint8_t **v_dev)
+{
+    if (!c || !v_dev) return CG_EINVAL;
+    uint64_t base;
+    const AllocEntry *e = c->table.find(dev_addr, &base);
+    if (!e) return fail(c, CG_ENOTFOUND, "shadow_ptr: address is in no live allocation");
+    *v_dev = c->pool + e->off + (dev_addr - base);
+    return CG_OK;
+}
+
+int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdict *out_dev, uint32_t mode,
+                    void *hip_stream)
+{
+    if (!c) return CG_EINVAL;
+    if (!(mode & (CG_CHECK | CG_PROPAGATE))) return fail(c, CG_EINVAL, "mode needs CG_CHECK or CG_PROPAGATE");
+    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER))
+        return fail(c, CG_EINVAL, "unknown mode bits");
+    if (count == 0) return CG_OK;
+    if (!recs_dev) return fail(c, CG_EINVAL, "null records");
+    if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
+    if (count >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 records per call");
+    if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+    return run_check(c, recs_dev, count, out_dev, mode, (hipStream_t)hip_stream, c->tuning);
+}
+
+int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)
+{
+    return check_transfers(c, recs_dev, count, nullptr, CG_PROPAGATE, hip_stream);
+}
+
+int cg_sync(cg_ctx *c)
+{
+    if (!c) return CG_EINVAL;
+    HIPTRY(c, hipStreamSynchronize(c->s));
+    return CG_OK;
+}
+
+int cg_stats(cg_ctx *c, uint64_t *live, uint64_t *used)
+{
+    if (!c) return CG_EINVAL;
+    if (live) *live = c->table.size();
+    if (used) *used = c->palloc->used();
+    return CG_OK;
+}
+
+int cg_get_tuning(cg_ctx *c, cg_tuning *t)
+{
+    if (!c || !t) return CG_EINVAL;
+    *t = c->tuning;
+    return CG_OK;
+}
+
+int cg_set_tuning(cg_ctx *c, const cg_tuning *t)
+{
+    if (!c || !t) return CG_EINVAL;
+    if (!valid_tuning(*t)) return fail(c, CG_EINVAL, "tuning out of range");
+    c->tuning = *t;
+    return CG_OK;
+}
+
+int cg_timing(cg_ctx *c, int enable)
+{
+    if (!c) return CG_EINVAL;
+    c->timing = enable != 0;
+    return CG_OK;
+}
+
+int cg_kernel_ms(cg_ctx *c, double *ms, uint64_t *launches)
+{
+    if (!c || !ms) return CG_EINVAL;
+    double sum = 0;
+    for (size_t i = 0; i < c->tused; ++i) {
+        HIPTRY(c, hipEventSynchronize(c->tpairs[i].b));
+        float x = 0;
+        HIPTRY(c, hipEventElapsedTime(&x, c->tpairs[i].a, c->tpairs[i].b));
+        sum += x;
+    }
+    *ms = sum;
+    if (launches) *launches = c->tused;
+    return CG_OK;
+}
+
+int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdict *out_dev, uint32_t mode,
+                void *hip_stream, const char *cache_path, cg_tuning *best)
+{
+    if (!c || !recs_dev || !count) return CG_EINVAL;
+    if ((mode & CG_CHECK) && !out_dev) return CG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    mode &= (CG_CHECK | CG_PROPAGATE);
+    if (!mode) return CG_EINVAL;
+    // workload signature: count and log2 of the total units, from a first run
+    const bool was_timing = c->timing;
+    c->timing = true;
+    int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, c->tuning);
+    if (rc) { c->timing = was_timing; return rc; }
+    HIPTRY(c, hipStreamSynchronize(s));
+    Ctl ctl;
+    HIPTRY(c, hipMemcpy(&ctl, c->ws[s]->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    uint32_t lg = 0;
+    while ((1ull << lg) < ctl.total_units) ++lg;
+    std::ostringstream key;
+    key << c->arch << "/cu" << c->cu_count << "/n" << count << "/u2^" << lg << "/m" << mode;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            if (line.find("\"key\": \"" + key.str() + "\"") == std::string::npos) continue;
+            cg_tuning t = c->tuning;
+            if (parse_field(line, "block", &t.block) && parse_field(line, "unroll", &t.unroll) &&
+                parse_field(line, "blocks_per_cu", &t.blocks_per_cu) && parse_field(line, "tile_units", &t.tile_units) &&
+                parse_field(line, "nontemporal", &t.nontemporal) && valid_tuning(t)) {
+                c->tuning = t;
+                c->timing = was_timing;
+                if (best) *best = t;
+                return CG_OK;
+            }
+        }
+    }
+    auto measure = [&](const cg_tuning &t, double *ms) -> int {
+        double sum = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+            int r = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, t);
+            if (r) return r;
+            double x;
+            uint64_t l;
+            r = cg_kernel_ms(c, &x, &l);
+            if (r) return r;
+            if (rep) sum += x;   // first run warms caches / code
+        }
+        *ms = sum / 2;
+        return CG_OK;
+    };
+    cg_tuning cur = c->tuning;
+    double cur_ms;
+    rc = measure(cur, &cur_ms);
+    if (rc) { c->timing = was_timing; return rc; }
+    auto try_set = [&](std::vector<cg_tuning> cands) -> int {
+        for (const auto &t : cands) {
+            if (!valid_tuning(t) || same_tuning(t, cur)) continue;
+            double ms;
+            int r = measure(t, &ms);
+            if (r) return r;
+            if (ms < cur_ms) { cur = t; cur_ms = ms; }
+        }
+        return CG_OK;
+    };
+    std::vector<cg_tuning> cands;
+    for (uint32_t u : {2u, 4u, 8u})
+        for (uint32_t nt : {0u, 1u}) { cg_tuning t = cur; t.unroll = u; t.nontemporal = nt; cands.push_back(t); }
+    rc = try_set(cands);
+    if (!rc) {
+        cands.clear();
+        for (uint32_t b : {256u, 512u})
+            for (uint32_t bpc : {1u, 2u, 4u, 8u}) { cg_tuning t = cur; t.block = b; t.blocks_per_cu = bpc; cands.push_back(t); }
+        rc = try_set(cands);
+    }
+    if (!rc) {
+        cands.clear();
+        for (uint32_t tu : {1u << 14, 1u << 16, 1u << 18}) { cg_tuning t = cur; t.tile_units = tu; cands.push_back(t); }
+        rc = try_set(cands);
+    }
+    c->timing = was_timing;
+    if (rc) return rc;
+    c->tuning = cur;
+    if (best) *best = cur;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << "{\"key\": \"" << key.str() << "\", " << tuning_json(cur) << ", \"ms\": " << cur_ms << "}\n";
+    }
+    return CG_OK;
+}
+
+int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip_stream)
+{
+    if (!dev || !sink_dev || (bytes & 15u) || ((uint64_t)dev & 15u)) return CG_EINVAL;
+    return launch_probe_read(dev, bytes, sink_dev, (hipStream_t)hip_stream) == hipSuccess ? CG_OK : CG_EHIP;
+}
+
+int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream)
+{
+    if (!dst || !src || (bytes & 15u) || ((uint64_t)dst & 15u) || ((uint64_t)src & 15u)) return CG_EINVAL;
+    return launch_probe_copy(dst, src, bytes, (hipStream_t)hip_stream) == hipSuccess ? CG_OK : CG_EHIP;
+}
+
+}  // extern "C"

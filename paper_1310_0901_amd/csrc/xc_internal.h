@@ -1,0 +1,120 @@
+// Internal types shared by the HIP kernels (kernels.hip) and the host runtime
+// (runtime.cpp).  Not part of the public C ABI.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/xfercheck.h"
+
+namespace xc {
+
+// Per-record scan descriptor written by the classify kernel.
+//
+// A record's byte index i runs over [0, n).  The source side is read in
+// 16-byte "chunks" aligned in shadow memory: source chunk c covers byte
+// indices [16c - phi, 16c - phi + 16), destination chunk e covers
+// [16e - psi, 16e - psi + 16).  One unit of work handles destination chunk
+// e = e0 + k together with source chunk c = e - delta; delta is 1 when the
+// source phase is behind the destination phase, so that destination chunk e
+// is byte window [s, s + 16) of source chunks c and c + 1, s = (phi - psi) mod 16.
+struct alignas(16) Desc {
+    uint64_t src_sh;   // device address of source chunk 0 (16-byte aligned)
+    uint64_t dst_sh;   // device address of destination chunk 0 (16-byte aligned)
+    int64_t v_lo, v_hi;  // source bytes that are valid to read: [v_lo, v_hi)
+    int64_t d_lo, d_hi;  // destination bytes inside the region / allocation
+    int64_t a_src;     // A-bit index of source chunk 0 (host source only)
+    int64_t a_dst;     // A-bit index of destination chunk 0 (host destination only)
+    uint64_t e0;       // first unit's destination-chunk index
+    uint64_t units;    // number of units
+    uint32_t ctl;      // CTL_* bits, phase fields
+    uint32_t pad[3];
+};
+static_assert(sizeof(Desc) == 96, "descriptor layout");
+
+enum : uint32_t {
+    CTL_SRC_HOST = 1u << 0,
+    CTL_DST_HOST = 1u << 1,
+    CTL_CHECK = 1u << 2,      // accumulate findings
+    CTL_PROP = 1u << 3,       // write destination shadow
+    CTL_DST_A = 1u << 4,      // scan destination A bits (host destination, checking)
+    CTL_PHI_SHIFT = 8,        // 4 bits
+    CTL_PSI_SHIFT = 12,       // 4 bits
+    CTL_DELTA = 1u << 16,
+};
+
+// Device-resident control block of one batched check.
+struct alignas(64) Ctl {
+    uint64_t total_units;   // sum of max(units, 1)
+    uint64_t ntiles;
+    uint64_t tile_units;    // units per tile actually used
+    uint32_t counter;       // dynamic tile counter
+    uint32_t pad0;
+    uint64_t pad[4];
+};
+
+struct Region {
+    uint64_t hb, hl;
+    const uint8_t *v;
+    const uint16_t *a16;   // A bitmap viewed as 16-bit words
+};
+
+struct TableView {
+    const uint64_t *base, *end, *off;
+    const uint64_t *top;   // base[k << top_shift], k < ntop
+    uint64_t n;
+    uint32_t top_shift, ntop;
+};
+
+// Device-resident view of the context (allocation table, host region, pool);
+// kernels read it through a pointer so that captured graphs stay valid when
+// the table changes.
+struct DevState {
+    TableView table;
+    Region region;
+    uint64_t pool;          // device address of the shadow pool
+};
+
+struct FillRange {
+    uint64_t ptr, len;
+    uint32_t val, pad;
+};
+
+constexpr int kMaxTop = 1024;        // LDS-staged top level of the table
+constexpr int kClassifyBlock = 256;  // records per classify block
+constexpr uint64_t kScanLimit = 1ull << 62;  // byte indices scanned per record
+
+struct BatchArgs {
+    const cg_transfer *recs;
+    uint64_t count;
+    cg_verdict *out;        // may be null (propagation only)
+    uint32_t mode;          // CG_CHECK | CG_PROPAGATE
+    const DevState *st;
+    Desc *desc;
+    uint64_t *weight;       // units per record
+    uint64_t *local;        // block-local exclusive prefix of max(units, 1)
+    uint64_t *bsum;         // per classify block sums
+    uint64_t *boff;         // exclusive prefix of bsum
+    uint64_t *prefix;       // global exclusive prefix, count + 1 entries
+    uint32_t *tile_start;   // first record of each tile
+    uint64_t tiles_cap;
+    Ctl *ctl;
+};
+
+struct LaunchShape {
+    uint32_t block, unroll, grid, nontemporal;
+    uint32_t tile_units;
+};
+
+// kernel launchers (kernels.hip); all asynchronous on `s`
+hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
+hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, hipStream_t s);
+hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);
+hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s);
+hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
+                        hipStream_t s);
+hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
+hipError_t launch_probe_read(const void *p, uint64_t bytes, uint64_t *sink, hipStream_t s);
+hipError_t launch_probe_copy(void *d, const void *p, uint64_t bytes, hipStream_t s);
+
+}  // namespace xc

@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element, on
+seeded inputs (needs an MI355X; run with -m gpu)."""
+import numpy as np
+import pytest
+
+from paper_1310_0901_amd import workloads as W
+from tests import util
+from tests.test_oracle_pins import all_records, HB, HV, HA, ALLOCS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_1310_0901_amd import xfercheck
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    xfercheck.lib()
+    return xfercheck
+
+
+@pytest.fixture(scope="module")
+def H(X):
+    from paper_1310_0901_amd import harness
+    return harness
+
+
+def modes(X):
+    return [("graph", X.CG_CHECK), ("eager", X.CG_CHECK | X.CG_EAGER), ("plain", X.CG_CHECK | X.CG_PLAIN)]
+
+
+def tiny_workload(records):
+    bases = sorted(ALLOCS)
+    return util.workload_from_arrays(HB, HV, HA, bases, [len(ALLOCS[b]) for b in bases],
+                                     [ALLOCS[b] for b in bases], records)
+
+
+def test_tiny_universe_every_case(X, H):
+    rows = all_records()
+    recs = np.array([(s, d, n, k, 0) for k, s, d, n in rows], W.RECORD_DTYPE)
+    w = tiny_workload(recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for name, mode in modes(X):
+            util.assert_verdicts_equal(dw.check(recs, mode), want, name)
+    finally:
+        dw.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_small_config_parity(X, H, k):
+    w = W.small_config(k)
+    want = util.oracle_for(w).run(w.records)
+    dw = H.DeviceWorld(w)
+    try:
+        for name, mode in modes(X):
+            util.assert_verdicts_equal(dw.check(w.records, mode), want, f"config {k} {name}")
+    finally:
+        dw.close()
+
+
+def test_small_tiles_and_ragged_tails(X, H):
+    """Minimum tile size, so that records straddle many tiles and every
+    tile / wave boundary; random alignments and ragged lengths."""
+    rng = np.random.default_rng(7)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=400_000, nalloc=9, max_size=300_000, dens=0.003)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 400, max_n=200_000)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for unroll in (1, 2, 4, 8):
+            t = X.cg_get_tuning(dw.ctx)
+            t.tile_units, t.unroll = 4096, unroll
+            X.cg_set_tuning(dw.ctx, t)
+            for name, mode in modes(X):
+                util.assert_verdicts_equal(dw.check(recs, mode), want, f"unroll {unroll} {name}")
+    finally:
+        dw.close()
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14, 15])
+def test_random_worlds_check(X, H, seed):
+    rng = np.random.default_rng(seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 300)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for name, mode in modes(X):
+            util.assert_verdicts_equal(dw.check(recs, mode), want, f"seed {seed} {name}")
+    finally:
+        dw.close()
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23, 24])
+@pytest.mark.parametrize("path", ["graph", "plain"])
+def test_random_worlds_propagation(X, H, seed, path):
+    """Check + propagate on conflict-free batches: verdicts and every shadow
+    byte (device allocations and host region) equal the oracle's."""
+    rng = np.random.default_rng(seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, dens=0.02)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 200, max_n=30_000)
+    recs = util.conflict_free(recs, W.HOST_BASE, hl, bases, sizes)
+    assert len(recs) >= 3
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    o = util.oracle_for(w)
+    want = o.run(recs, propagate=True)
+    dw = H.DeviceWorld(w)
+    try:
+        mode = X.CG_CHECK | X.CG_PROPAGATE | X.CG_DEBUG_CONFLICTS
+        if path == "plain":
+            mode |= X.CG_PLAIN
+        util.assert_verdicts_equal(dw.check(recs, mode), want, f"seed {seed}")
+        for j in range(bases.size):
+            assert np.array_equal(dw.alloc_shadow(bases[j], sizes[j]), o.vs[j]), f"allocation {j}"
+        assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
+    finally:
+        dw.close()
+
+
+def test_config4_small_chain(X, H):
+    """Struct padding and single payload bits, H2D then D2D hops with
+    propagation: verdicts and shadows bit-exact after every hop."""
+    w = W.small_config(4)
+    o = util.oracle_for(w)
+    dw = H.DeviceWorld(w)
+    live = w.dev.live_idx
+    try:
+        for h, stage in enumerate(w.stages):
+            want = o.run(stage, propagate=True)
+            got = dw.check(stage, X.CG_CHECK | X.CG_PROPAGATE | X.CG_DEBUG_CONFLICTS)
+            util.assert_verdicts_equal(got, want, f"hop {h}")
+            for k, j in enumerate(live):
+                assert np.array_equal(dw.alloc_shadow(w.dev.base[j], w.dev.size[j]), o.vs[k]), (h, k)
+    finally:
+        dw.close()
+
+
+def test_conflicting_batch_is_refused(X, H):
+    w = tiny_workload(np.zeros(0, W.RECORD_DTYPE))
+    dw = H.DeviceWorld(w)
+    try:
+        b = sorted(ALLOCS)
+        recs = np.array([(HB, b[0], 4, 0, 0), (HB + 8, b[0] + 2, 4, 0, 0)], W.RECORD_DTYPE)
+        with pytest.raises(X.CgError) as e:
+            dw.check(recs, X.CG_CHECK | X.CG_PROPAGATE | X.CG_DEBUG_CONFLICTS)
+        assert e.value.status == X.CG_ECONFLICT
+    finally:
+        dw.close()
