@@ -241,10 +241,12 @@ int cg_autotune(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, cg_ver
                 uint32_t mode, void *hip_stream, const char *cache_path, cg_tuning *best);
 
 /*
- * Kernel timing: when enabled, each batched or plain check records HIP events
- * around its scan kernel(s) on the caller's stream; cg_kernel_ms returns the
- * summed milliseconds of the scan kernels of the last finished check and the
- * number of scan launches it made (waits for them).
+ * Kernel timing: when enabled, each check records a pair of HIP events on the
+ * caller's stream around its scan work: around the persistent scan kernel
+ * (batched path; in graph mode the scan kernel then runs as a graph of its
+ * own after the graph of the preparation kernels), or around the whole
+ * per-record launch loop (plain path).  cg_kernel_ms waits for the pending
+ * pairs, returns their summed milliseconds and their number, and forgets them.
  */
 int cg_timing(cg_ctx *ctx, int enable);
 int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);

@@ -96,19 +96,25 @@ __device__ __forceinline__ u32x4 window(u32x4 a, u32x4 b, uint32_t s)
     return o;
 }
 
-__device__ __forceinline__ void store_word_masked(uint8_t *p, uint32_t w, uint32_t m)
+// Global (address space 1) views of device addresses, so that the compiler
+// emits global_load / global_store rather than flat accesses.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> using gcptr = const __attribute__((address_space(1))) T *;
+
+__device__ __forceinline__ void store_word_masked(uint64_t p, uint32_t w, uint32_t m)
 {
-    if (m == 0xFu) { *reinterpret_cast<uint32_t *>(p) = w; return; }
-    if (m & 1u) p[0] = (uint8_t)w;
-    if (m & 2u) p[1] = (uint8_t)(w >> 8);
-    if (m & 4u) p[2] = (uint8_t)(w >> 16);
-    if (m & 8u) p[3] = (uint8_t)(w >> 24);
+    if (m == 0xFu) { *reinterpret_cast<gptr<uint32_t>>(p) = w; return; }
+    gptr<uint8_t> b = reinterpret_cast<gptr<uint8_t>>(p);
+    if (m & 1u) b[0] = (uint8_t)w;
+    if (m & 2u) b[1] = (uint8_t)(w >> 8);
+    if (m & 4u) b[2] = (uint8_t)(w >> 16);
+    if (m & 8u) b[3] = (uint8_t)(w >> 24);
 }
 
 // Store the bytes of v selected by m at the 16-byte aligned address p.
-__device__ __forceinline__ void store_masked(uint8_t *p, u32x4 v, uint32_t m)
+__device__ __forceinline__ void store_masked(uint64_t p, u32x4 v, uint32_t m)
 {
-    if (m == 0xFFFFu) { *reinterpret_cast<u32x4 *>(p) = v; return; }
+    if (m == 0xFFFFu) { *reinterpret_cast<gptr<u32x4>>(p) = v; return; }
     if (m & 0x000Fu) store_word_masked(p, v.x, m & 0xFu);
     if (m & 0x00F0u) store_word_masked(p + 4, v.y, (m >> 4) & 0xFu);
     if (m & 0x0F00u) store_word_masked(p + 8, v.z, (m >> 8) & 0xFu);
@@ -118,9 +124,33 @@ __device__ __forceinline__ void store_masked(uint8_t *p, u32x4 v, uint32_t m)
 template <bool NT>
 __device__ __forceinline__ u32x4 ld16(uint64_t addr)
 {
-    const u32x4 *p = reinterpret_cast<const u32x4 *>(addr);
+    gcptr<u32x4> p = reinterpret_cast<gcptr<u32x4>>(addr);
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
+}
+
+__device__ __forceinline__ uint32_t ld_u16(uint64_t addr)
+{
+    return *reinterpret_cast<gcptr<uint16_t>>(addr);
+}
+
+__device__ __forceinline__ int32_t clamp32(int64_t x)
+{
+    return x < -(1ll << 30) ? -(1 << 30) : (x > (1ll << 30) ? (1 << 30) : (int32_t)x);
+}
+
+// rmask for offsets already clamped to 32 bits
+__device__ __forceinline__ uint32_t rmask32(int32_t lo, int32_t hi)
+{
+    const int32_t l = lo < 0 ? 0 : (lo > 16 ? 16 : lo);
+    const int32_t h = hi < 0 ? 0 : (hi > 16 ? 16 : hi);
+    return h > l ? ((1u << h) - (1u << l)) : 0u;
+}
+
+__device__ __forceinline__ uint32_t ufl32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t ufl64(uint64_t x)
+{
+    return ((uint64_t)ufl32((uint32_t)(x >> 32)) << 32) | ufl32((uint32_t)x);
 }
 
 // ---- DPP wave reductions (every lane of the wave must be active) --------
@@ -186,9 +216,8 @@ struct DV {
     uint32_t ctl, phi, psi, delta, s;
 };
 
-__device__ __forceinline__ DV load_desc(const Desc *D, uint64_t t)
+__device__ __forceinline__ DV make_dv(const Desc &x)
 {
-    const Desc &x = D[t];
     DV d;
     d.src_sh = x.src_sh; d.dst_sh = x.dst_sh;
     d.v_lo = x.v_lo; d.v_hi = x.v_hi; d.d_lo = x.d_lo; d.d_hi = x.d_hi;
@@ -199,6 +228,22 @@ __device__ __forceinline__ DV load_desc(const Desc *D, uint64_t t)
     d.delta = (d.ctl & CTL_DELTA) ? 1u : 0u;
     d.s = (d.phi - d.psi) & 15u;
     return d;
+}
+
+// Per-lane descriptor (lanes may work on different records).
+__device__ __forceinline__ DV load_desc(const Desc *D, uint64_t t) { return make_dv(D[t]); }
+
+// Wave-uniform descriptor: every field forced into scalar registers.
+__device__ __forceinline__ DV load_desc_uniform(const Desc *D, uint64_t t)
+{
+    const Desc &x = D[t];
+    Desc u;
+    u.src_sh = ufl64(x.src_sh); u.dst_sh = ufl64(x.dst_sh);
+    u.v_lo = (int64_t)ufl64((uint64_t)x.v_lo); u.v_hi = (int64_t)ufl64((uint64_t)x.v_hi);
+    u.d_lo = (int64_t)ufl64((uint64_t)x.d_lo); u.d_hi = (int64_t)ufl64((uint64_t)x.d_hi);
+    u.a_src = (int64_t)ufl64((uint64_t)x.a_src); u.a_dst = (int64_t)ufl64((uint64_t)x.a_dst);
+    u.e0 = ufl64(x.e0); u.units = ufl64(x.units); u.ctl = ufl32(x.ctl);
+    return make_dv(u);
 }
 
 // Source chunk c: V bytes, valid-byte mask, and (host source) the in-range
@@ -215,7 +260,7 @@ __device__ __forceinline__ void src_chunk(const DV &d, const Region &R, int64_t 
     if (m) {
         v = ld16<NT>(d.src_sh + (uint64_t)(16 * c));
         if (d.ctl & CTL_SRC_HOST) {
-            const uint32_t a = R.a16[(d.a_src + 16 * c) >> 4];
+            const uint32_t a = ld_u16((uint64_t)R.a16 + (uint64_t)((d.a_src + 16 * c) >> 3));
             ok = m & a;
             unaddr = m & ~a;
         } else {
@@ -270,55 +315,94 @@ __device__ __forceinline__ void flush_wave(Acc &a, cg_verdict *out, uint64_t t)
 // ---------------------------------------------------------------------------
 // uniform mode: the whole wave works on units [k_begin, k_end) of one record
 // ---------------------------------------------------------------------------
-template <int U, bool NT>
+template <int U, bool NT, bool PROP>
 __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64_t k_begin, uint64_t k_end,
                                             Acc &acc)
 {
-    const uint32_t lane = lane_id();
+    // Lane l of sub-iteration j handles unit kb + 64 j + l: destination chunk
+    // e = e0 + kb + 64 j + l and source chunk c = e - delta.  Per iteration all
+    // offsets are taken relative to the first unit, in 32 bits.  Loads are
+    // issued for every lane with the chunk index clamped into the range of
+    // chunks that hold valid bytes, so that all U loads go out back to back
+    // without branches; lanes whose own chunk has no valid byte ignore the data.
+    const int32_t lane = (int32_t)lane_id();
     const bool check = (d.ctl & CTL_CHECK) != 0;
-    const bool prop = (d.ctl & CTL_PROP) != 0;
+    const bool prop = PROP && (d.ctl & CTL_PROP) != 0;
     const bool dsta = (d.ctl & CTL_DST_A) != 0;
+    const bool src_host = (d.ctl & CTL_SRC_HOST) != 0;
     const bool dst_host = (d.ctl & CTL_DST_HOST) != 0;
+    const uint64_t a16b = (uint64_t)R.a16;
 
     for (uint64_t kb = k_begin; kb < k_end; kb += 64u * U) {
+        const int64_t cb = (int64_t)(d.e0 + kb) - (int64_t)d.delta;
+        const int64_t i0b = 16 * cb - (int64_t)d.phi;
+        const int32_t vlo = clamp32(d.v_lo - i0b), vhi = clamp32(d.v_hi - i0b);
+        const int32_t kend = clamp32((int64_t)(k_end - kb));
+        const int32_t clo = (vlo >> 4) > 0 ? (vlo >> 4) : 0;
+        const int32_t chi = ((vhi + 15) >> 4) < 64 * U ? ((vhi + 15) >> 4) : 64 * U;
+        const uint64_t vbase = d.src_sh + (uint64_t)(16 * cb);
+        const uint64_t abase = a16b + (uint64_t)((d.a_src + 16 * cb) >> 3);
+
         u32x4 v[U];
         uint32_t ok[U], un[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            const uint64_t k = kb + 64u * j + lane;
-            const int64_t c = (int64_t)(d.e0 + k) - (int64_t)d.delta;
-            if (k < k_end) {
-                src_chunk<NT>(d, R, c, v[j], ok[j], un[j]);
-            } else {
-                v[j] = u32x4{0u, 0u, 0u, 0u};
-                ok[j] = 0u;
-                un[j] = 0u;
+            v[j] = u32x4{0u, 0u, 0u, 0u};
+            ok[j] = 0u;
+            un[j] = 0u;
+        }
+        if (chi > clo) {
+            uint32_t av[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int32_t cr = 64 * j + lane;
+                const int32_t cc = cr < clo ? clo : (cr >= chi ? chi - 1 : cr);
+                v[j] = ld16<NT>(vbase + (uint32_t)(16 * cc));
+                if (src_host) av[j] = ld_u16(abase + (uint32_t)(2 * cc));
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int32_t cr = 64 * j + lane;
+                const uint32_t m = cr < kend ? rmask32(vlo - 16 * cr, vhi - 16 * cr) : 0u;
+                if (src_host) {
+                    ok[j] = m & av[j];
+                    un[j] = m & ~av[j];
+                } else {
+                    ok[j] = m;
+                }
             }
         }
         if (check) {
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const uint64_t k = kb + 64u * j + lane;
-                const int64_t c = (int64_t)(d.e0 + k) - (int64_t)d.delta;
-                src_findings(acc, 16 * c - (int64_t)d.phi, v[j], ok[j], un[j]);
-            }
+            for (int j = 0; j < U; ++j) src_findings(acc, i0b + 16 * (64 * j + lane), v[j], ok[j], un[j]);
         }
         if (dsta || prop) {
+            const int64_t eb = (int64_t)(d.e0 + kb);
+            const int64_t i0db = 16 * eb - (int64_t)d.psi;
+            const int32_t dlo = clamp32(d.d_lo - i0db), dhi = clamp32(d.d_hi - i0db);
+            const int32_t dclo = (dlo >> 4) > 0 ? (dlo >> 4) : 0;
+            const int32_t dchi = ((dhi + 15) >> 4) < 64 * U ? ((dhi + 15) >> 4) : 64 * U;
+            uint32_t ad[U];
+            if (dst_host && dchi > dclo) {
+                const uint64_t dbase = a16b + (uint64_t)((d.a_dst + 16 * eb) >> 3);
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int32_t cr = 64 * j + lane;
+                    const int32_t cc = cr < dclo ? dclo : (cr >= dchi ? dchi - 1 : cr);
+                    ad[j] = ld_u16(dbase + (uint32_t)(2 * cc));
+                }
+            }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                const uint64_t k = kb + 64u * j + lane;
-                const bool act = k < k_end;
-                const int64_t e = (int64_t)(d.e0 + k);
-                const int64_t i0d = 16 * e - (int64_t)d.psi;
-                const uint32_t md = act ? rmask(d.d_lo - i0d, d.d_hi - i0d) : 0u;
+                const int32_t cr = 64 * j + lane;
+                const uint32_t md = (cr < kend && dchi > dclo) ? rmask32(dlo - 16 * cr, dhi - 16 * cr) : 0u;
                 uint32_t wm = md;
-                if (dst_host && md) {
-                    const uint32_t a = R.a16[(d.a_dst + 16 * e) >> 4];
-                    wm = md & a;
-                    const uint32_t ud = md & ~a;
+                if (dst_host) {
+                    wm = md & ad[j];
+                    const uint32_t ud = md & ~ad[j];
                     if (check && ud) {
                         acc.flags |= CG_DST_UNADDR;
-                        acc_min(acc, i0d + __builtin_ctz(ud));
+                        acc_min(acc, i0db + 16 * cr + __builtin_ctz(ud));
                     }
                 }
                 if (prop) {
@@ -329,20 +413,20 @@ __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64
                     nxt.z = __shfl_down(own.z, 1);
                     nxt.w = __shfl_down(own.w, 1);
                     if (j + 1 < U) {
-                        const u32x4 g = prop_val(v[j + 1 < U ? j + 1 : j], ok[j + 1 < U ? j + 1 : j]);
+                        const int jn = j + 1 < U ? j + 1 : j;
+                        const u32x4 g = prop_val(v[jn], ok[jn]);
                         const uint32_t gx = __shfl(g.x, 0), gy = __shfl(g.y, 0), gz = __shfl(g.z, 0),
                                        gw = __shfl(g.w, 0);
-                        if (lane == 63u) nxt = u32x4{gx, gy, gz, gw};
+                        if (lane == 63) nxt = u32x4{gx, gy, gz, gw};
                     }
-                    const bool self = act && ((lane == 63u && j == U - 1) || k + 1 >= k_end);
+                    const bool self = cr < kend && ((lane == 63 && j == U - 1) || cr + 1 >= kend);
                     if (self) {
                         u32x4 vn;
                         uint32_t okn, unn;
-                        src_chunk<NT>(d, R, e - (int64_t)d.delta + 1, vn, okn, unn);
+                        src_chunk<NT>(d, R, cb + cr + 1, vn, okn, unn);
                         nxt = prop_val(vn, okn);
                     }
-                    if (wm) store_masked(reinterpret_cast<uint8_t *>(d.dst_sh + (uint64_t)(16 * e)),
-                                         window(own, nxt, d.s), wm);
+                    if (wm) store_masked(d.dst_sh + (uint64_t)(16 * eb) + (uint32_t)(16 * cr), window(own, nxt, d.s), wm);
                 }
             }
         }
@@ -352,7 +436,7 @@ __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64
 // ---------------------------------------------------------------------------
 // one unit handled by one lane (small records, tile boundaries)
 // ---------------------------------------------------------------------------
-template <bool NT>
+template <bool NT, bool PROP>
 __device__ __forceinline__ void run_unit(const DV &d, const Region &R, uint64_t k, Acc &acc)
 {
     const bool check = (d.ctl & CTL_CHECK) != 0;
@@ -367,7 +451,7 @@ __device__ __forceinline__ void run_unit(const DV &d, const Region &R, uint64_t 
         const uint32_t md = rmask(d.d_lo - i0d, d.d_hi - i0d);
         uint32_t wm = md;
         if ((d.ctl & CTL_DST_HOST) && md) {
-            const uint32_t a = R.a16[(d.a_dst + 16 * e) >> 4];
+            const uint32_t a = ld_u16((uint64_t)R.a16 + (uint64_t)((d.a_dst + 16 * e) >> 3));
             wm = md & a;
             const uint32_t ud = md & ~a;
             if (check && ud) {
@@ -375,12 +459,11 @@ __device__ __forceinline__ void run_unit(const DV &d, const Region &R, uint64_t 
                 acc_min(acc, i0d + __builtin_ctz(ud));
             }
         }
-        if ((d.ctl & CTL_PROP) && wm) {
+        if (PROP && (d.ctl & CTL_PROP) && wm) {
             u32x4 vn;
             uint32_t okn, unn;
             src_chunk<NT>(d, R, c + 1, vn, okn, unn);
-            store_masked(reinterpret_cast<uint8_t *>(d.dst_sh + (uint64_t)(16 * e)),
-                         window(prop_val(v, ok), prop_val(vn, okn), d.s), wm);
+            store_masked(d.dst_sh + (uint64_t)(16 * e), window(prop_val(v, ok), prop_val(vn, okn), d.s), wm);
         }
     }
 }
@@ -662,13 +745,13 @@ __global__ void __launch_bounds__(256) k_prefix_tiles(BatchArgs a)
 // ---------------------------------------------------------------------------
 // k_batched: persistent kernel over the tiles of the flattened unit space
 // ---------------------------------------------------------------------------
-template <int U, bool NT>
+template <int U, bool NT, bool PROP>
 __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
 {
     const uint32_t lane = lane_id();
-    const uint64_t ntiles = a.ctl->ntiles;
-    const uint64_t tu = a.ctl->tile_units;
-    const uint64_t total = a.ctl->total_units;
+    const uint64_t ntiles = ufl64(a.ctl->ntiles);
+    const uint64_t tu = ufl64(a.ctl->tile_units);
+    const uint64_t total = ufl64(a.ctl->total_units);
     const uint64_t T = a.count;
     const Region R = a.st->region;
     Acc acc;
@@ -676,18 +759,18 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
     for (;;) {
         uint32_t j = 0;
         if (lane == 0) j = atomicAdd(&a.ctl->counter, 1u);
-        j = __shfl(j, 0);
+        j = ufl32(__shfl(j, 0));
         if (j >= ntiles) break;
         uint64_t u = (uint64_t)j * tu;
         const uint64_t u_end = (u + tu < total) ? u + tu : total;
-        uint64_t t = a.tile_start[j];
+        uint64_t t = ufl32(a.tile_start[j]);
         while (u < u_end) {
-            const uint64_t pt = a.prefix[t], pt1 = a.prefix[t + 1];
+            const uint64_t pt = ufl64(a.prefix[t]), pt1 = ufl64(a.prefix[t + 1]);
             const uint64_t seg_end = pt1 < u_end ? pt1 : u_end;
             const uint64_t nfull = (seg_end - u) & ~63ull;
             if (nfull) {
-                const DV d = load_desc(a.desc, t);
-                run_uniform<U, NT>(d, R, u - pt, u - pt + nfull, acc);
+                const DV d = load_desc_uniform(a.desc, t);
+                run_uniform<U, NT, PROP>(d, R, u - pt, u - pt + nfull, acc);
                 if (a.out) flush_wave(acc, a.out, t);
                 u += nfull;
                 if (u == pt1) ++t;
@@ -706,13 +789,13 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
             if (act) {
                 const DV d = load_desc(a.desc, tl);
                 const uint64_t k = ul - a.prefix[tl];
-                if (k < d.units) run_unit<NT>(d, R, k, acc);
+                if (k < d.units) run_unit<NT, PROP>(d, R, k, acc);
             }
             if (a.out && __ballot(acc.flags != 0u)) flush_segmented(acc, act ? tl : ~0ull, a.out);
             else acc_reset(acc);
             if (g_end < u_end) {
-                const uint64_t t63 = __shfl(tl, 63);
-                t = (a.prefix[t63 + 1] <= g_end) ? t63 + 1 : t63;
+                const uint64_t t63 = ufl64(__shfl(tl, 63));
+                t = (ufl64(a.prefix[t63 + 1]) <= g_end) ? t63 + 1 : t63;
             }
             u = g_end;
         }
@@ -722,7 +805,7 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
 // ---------------------------------------------------------------------------
 // k_plain: one record per launch, waves split its units evenly
 // ---------------------------------------------------------------------------
-template <int U, bool NT>
+template <int U, bool NT, bool PROP>
 __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t units)
 {
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -732,10 +815,10 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t
     const uint64_t k0 = w * span;
     if (k0 >= units) return;
     const uint64_t k1 = (k0 + span < units) ? k0 + span : units;
-    const DV d = load_desc(a.desc, t);
+    const DV d = load_desc_uniform(a.desc, t);
     Acc acc;
     acc_reset(acc);
-    run_uniform<U, NT>(d, a.st->region, k0, k1, acc);
+    run_uniform<U, NT, PROP>(d, a.st->region, k0, k1, acc);
     if (a.out) flush_wave(acc, a.out, t);
 }
 
@@ -814,14 +897,20 @@ hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s)
 template <int U, bool NT>
 static void launch_batched_t(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batched<U, NT>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+    if (a.mode & CG_PROPAGATE)
+        hipLaunchKernelGGL((k_batched<U, NT, true>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_batched<U, NT, false>), dim3(sh.grid), dim3(sh.block), 0, s, a);
 }
 
 template <int U, bool NT>
 static void launch_plain_t(const BatchArgs &a, uint64_t t, uint64_t units, uint32_t grid, uint32_t block,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL((k_plain<U, NT>), dim3(grid), dim3(block), 0, s, a, t, units);
+    if (a.mode & CG_PROPAGATE)
+        hipLaunchKernelGGL((k_plain<U, NT, true>), dim3(grid), dim3(block), 0, s, a, t, units);
+    else
+        hipLaunchKernelGGL((k_plain<U, NT, false>), dim3(grid), dim3(block), 0, s, a, t, units);
 }
 
 #define XC_DISPATCH(FN, ...)                                                   \

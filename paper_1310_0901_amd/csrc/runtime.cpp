@@ -426,7 +426,6 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     }
     const BatchArgs a = make_args(c, w, recs, count, out, mode);
     const LaunchShape sh = shape_of(c, tun);
-    c->tused = 0;
     if (mode & CG_PLAIN) {
         HIPTRY(c, launch_classify(a, s));
         HIPTRY(c, hipMemcpyAsync(w->h_weight, w->weight, count * 8, hipMemcpyDeviceToHost, s));
@@ -796,6 +795,7 @@ int cg_kernel_ms(cg_ctx *c, double *ms, uint64_t *launches)
     }
     *ms = sum;
     if (launches) *launches = c->tused;
+    c->tused = 0;
     return CG_OK;
 }
 
@@ -810,9 +810,11 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     // workload signature: count and log2 of the total units, from a first run
     const bool was_timing = c->timing;
     c->timing = true;
+    c->tused = 0;
     int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, c->tuning);
     if (rc) { c->timing = was_timing; return rc; }
     HIPTRY(c, hipStreamSynchronize(s));
+    c->tused = 0;
     Ctl ctl;
     HIPTRY(c, hipMemcpy(&ctl, c->ws[s]->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     uint32_t lg = 0;
