@@ -1,0 +1,170 @@
+"""The C ABI on the GPU: status codes of the error paths, the paper's worked
+example end to end, graph replays, and concurrent streams."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1310_0901_amd import workloads as W
+from tests import util
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_1310_0901_amd import xfercheck
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    xfercheck.lib()
+    return xfercheck
+
+
+@pytest.fixture(scope="module")
+def H(X):
+    from paper_1310_0901_amd import harness
+    return harness
+
+
+def status(X, fn, *a):
+    try:
+        fn(*a)
+    except X.CgError as e:
+        return e.status
+    return X.CG_OK
+
+
+def test_status_codes(X):
+    ctx = X.cg_create(0, 1 << 16, 4)
+    try:
+        B = W.DEV_BASE
+        assert status(X, X.shadow_alloc, ctx, B, 0) == X.CG_EINVAL
+        assert status(X, X.shadow_alloc, ctx, B, 1000) == X.CG_OK
+        assert status(X, X.shadow_alloc, ctx, B + 999, 10) == X.CG_EOVERLAP
+        assert status(X, X.shadow_alloc, ctx, B - 5, 6) == X.CG_EOVERLAP
+        assert status(X, X.shadow_alloc, ctx, B + 1000, 10) == X.CG_OK          # adjacent
+        assert status(X, X.shadow_free, ctx, B + 1) == X.CG_ENOTFOUND          # not a base
+        assert status(X, X.shadow_set, ctx, B + 990, 20, 0) == X.CG_EINVAL     # leaves the allocation
+        assert status(X, X.shadow_set, ctx, B + 5000, 1, 0) == X.CG_ENOTFOUND
+        assert status(X, X.shadow_ptr, ctx, B + 5000) == X.CG_ENOTFOUND
+        assert status(X, X.shadow_alloc, ctx, B + 8192, 1 << 20) == X.CG_ENOMEM  # pool is 64 KiB
+        assert status(X, X.shadow_alloc, ctx, B + 8192, 100) == X.CG_OK
+        assert status(X, X.shadow_alloc, ctx, B + 9000, 100) == X.CG_OK
+        assert status(X, X.shadow_alloc, ctx, B + 10000, 100) == X.CG_ECAPACITY  # 4 live max
+        assert status(X, X.shadow_free, ctx, B) == X.CG_OK
+        assert status(X, X.shadow_free, ctx, B) == X.CG_ENOTFOUND              # double free
+        assert status(X, X.check_transfers, ctx, 0, 1, 0, X.CG_CHECK, 0) == X.CG_EINVAL
+        assert status(X, X.check_transfers, ctx, 16, 1, 16, 0, 0) == X.CG_EINVAL   # no mode
+        assert status(X, X.check_transfers, ctx, 16, 1, 16, 0x100 | X.CG_CHECK, 0) == X.CG_EINVAL
+        assert status(X, X.check_transfers, ctx, 0, 0, 0, X.CG_CHECK, 0) == X.CG_OK   # empty batch
+        v = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        assert status(X, X.cg_host_register, ctx, 0x1000, 16, v.data_ptr() + 1, v.data_ptr()) == X.CG_EINVAL
+        assert status(X, X.cg_host_register, ctx, 0x1000, 0, v.data_ptr(), v.data_ptr()) == X.CG_EINVAL
+        assert X.cg_stats(ctx)[0] == 3
+        assert "live allocation" in X.cg_last_error(ctx) or X.cg_last_error(ctx)
+    finally:
+        X.cg_destroy(ctx)
+
+
+def test_pin1_worked_example_on_gpu(X, H):
+    """Sec. 4: c holds 1,000,000 floats, the copy back wants 1,000,000
+    doubles; a is allocated right after c."""
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "pin1_worked_example.json")))
+    n = fx["copy_bytes"]
+    c = W.DEV_BASE
+    a = c + fx["c_alloc_bytes"]
+    b = a + fx["a_alloc_bytes"] + 256
+    ctx = X.cg_create(0, 32 << 20, 16)
+    try:
+        hv = torch.full((n + 32,), 0xFF, dtype=torch.uint8, device="cuda")
+        ha = torch.full(((n + 63) // 64,), -1, dtype=torch.int64, device="cuda")
+        X.cg_host_register(ctx, W.HOST_BASE, n, hv.data_ptr(), ha.data_ptr())
+        X.shadow_alloc(ctx, c, fx["c_alloc_bytes"])
+        X.shadow_alloc(ctx, a, fx["a_alloc_bytes"])
+        X.shadow_alloc(ctx, b, fx["b_alloc_bytes"])
+        X.shadow_set(ctx, c, fx["c_alloc_bytes"], 0)      # the kernel wrote c
+        recs = np.array([(c, W.HOST_BASE, n, X.CG_D2H, 0)], W.RECORD_DTYPE)
+        rt = H.records_tensor(recs)
+        out = H.verdicts_tensor(1)
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_PLAIN, X.CG_CHECK | X.CG_PROPAGATE):
+            X.check_transfers(ctx, rt.data_ptr(), 1, out.data_ptr(), mode, torch.cuda.current_stream().cuda_stream)
+            v = H.verdicts_np(out, 1)[0]
+            assert (int(v["flags"]), int(v["first_bad"]), int(v["undef_bytes"]), int(v["avail"])) == \
+                (X.CG_SRC_OVERRUN, fx["found_bytes"], 0, fx["found_bytes"])
+        txt = X.cg_format_verdict((c, W.HOST_BASE, n, X.CG_D2H),
+                                  (int(v["flags"]), int(v["first_bad"]), int(v["undef_bytes"]), int(v["avail"])))
+        assert txt.split("\n") == fx["report_lines"]
+        # propagation wrote c's defined bytes into the host shadow and 0xFF beyond
+        h = hv[:n].cpu().numpy()
+        assert not h[: fx["c_alloc_bytes"]].any() and (h[fx["c_alloc_bytes"]:] == 0xFF).all()
+    finally:
+        X.cg_destroy(ctx)
+
+
+def test_graph_replays_match_eager(X, H):
+    """A captured check replayed several times, with other eager work and
+    synchronisations between the replays: every replay equals the eager run."""
+    w = W.small_config(3)
+    dw = H.DeviceWorld(w)
+    try:
+        s = torch.cuda.current_stream().cuda_stream
+        rt = H.records_tensor(w.records)
+        eager = dw.check(w.records, X.CG_CHECK | X.CG_EAGER)
+        other = w.records[::7].copy()
+        out = H.verdicts_tensor(w.count)
+        for rep in range(4):
+            out.fill_(0xAB)
+            X.check_transfers(dw.ctx, rt.data_ptr(), w.count, out.data_ptr(), X.CG_CHECK, s)
+            torch.cuda.synchronize()
+            util.assert_verdicts_equal(H.verdicts_np(out, w.count), eager, f"replay {rep}")
+            dw.check(other, X.CG_CHECK | X.CG_EAGER)
+            torch.cuda.synchronize()
+    finally:
+        dw.close()
+
+
+def test_two_streams_concurrently(X, H):
+    """Checks issued on two streams at once use separate workspaces and give
+    the same verdicts as alone."""
+    w = W.small_config(3)
+    dw = H.DeviceWorld(w)
+    try:
+        half = w.count // 2
+        r1, r2 = w.records[:half], w.records[half:]
+        alone1, alone2 = dw.check(r1), dw.check(r2)
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        t1, t2 = H.records_tensor(r1), H.records_tensor(r2)
+        o1, o2 = H.verdicts_tensor(len(r1)), H.verdicts_tensor(len(r2))
+        torch.cuda.synchronize()
+        for _ in range(3):
+            X.check_transfers(dw.ctx, t1.data_ptr(), len(r1), o1.data_ptr(), X.CG_CHECK, s1.cuda_stream)
+            X.check_transfers(dw.ctx, t2.data_ptr(), len(r2), o2.data_ptr(), X.CG_CHECK, s2.cuda_stream)
+        torch.cuda.synchronize()
+        util.assert_verdicts_equal(H.verdicts_np(o1, len(r1)), alone1, "stream 1")
+        util.assert_verdicts_equal(H.verdicts_np(o2, len(r2)), alone2, "stream 2")
+    finally:
+        dw.close()
+
+
+def test_shadow_ops_are_ordered_after_checks(X, H):
+    """A free + re-allocation + set issued right after a check (no host sync)
+    does not change what that check saw."""
+    w = W.small_config(1)
+    dw = H.DeviceWorld(w)
+    try:
+        want = dw.check(w.records)
+        s = torch.cuda.current_stream().cuda_stream
+        rt = H.records_tensor(w.records)
+        out = H.verdicts_tensor(w.count)
+        X.check_transfers(dw.ctx, rt.data_ptr(), w.count, out.data_ptr(), X.CG_CHECK, s)
+        live = w.dev.live_idx
+        X.shadow_free(dw.ctx, int(w.dev.base[live[0]]))
+        X.shadow_alloc(dw.ctx, int(w.dev.base[live[0]]), int(w.dev.size[live[0]]))
+        X.shadow_set(dw.ctx, int(w.dev.base[live[0]]), int(w.dev.size[live[0]]), 0)
+        torch.cuda.synchronize()
+        util.assert_verdicts_equal(H.verdicts_np(out, w.count), want, "check before the table change")
+    finally:
+        dw.close()

@@ -130,3 +130,19 @@ def conflict_free(recs, hb, hl, bases, sizes):
         if w is not None:
             writes.append(w)
     return recs[keep]
+
+
+def oracle_subset(w, records, hv, ha):
+    """Oracle state holding only the live allocations that the device pointers
+    of `records` lie in (a verdict depends only on the allocation holding the
+    pointer), for full-size workloads whose whole device shadow is too large."""
+    live = w.dev.live_idx
+    lb = w.dev.base[live].astype(np.int64)
+    ls = w.dev.size[live].astype(np.int64)
+    ptrs = np.concatenate([records["src"][records["kind"] != 0],
+                           records["dst"][records["kind"] != 1]]).astype(np.int64)
+    j = np.searchsorted(lb, ptrs, side="right") - 1
+    inside = (j >= 0) & (ptrs < lb[np.maximum(j, 0)] + ls[np.maximum(j, 0)])
+    idx = np.unique(live[j[inside]])
+    return OracleState(w.host.base, w.host.length, hv, ha, w.dev.base[idx], w.dev.size[idx],
+                       [W.alloc_v(w.dev, int(x)) for x in idx])
