@@ -76,6 +76,61 @@ def cpu_baseline(w, hv, ha, got, target_bytes, threads):
     return gbs, text, same, dt
 
 
+def profiled_traffic(tuning, config):
+    """Bytes per launch of the scan kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by the copy-probe factor), if the kernel source and
+    launch shape are the ones profiled; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_batched_batched-1M_traffic.json")
+    if config != 3 or not os.path.exists(path):
+        return None, "no profile for this workload"
+    prof = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1310_0901_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != prof["kernels_hip_sha256"]:
+        return None, "kernel changed since the counters were taken"
+    if {k: tuning[k] for k in prof["tuning"]} != prof["tuning"]:
+        return None, "launch shape differs from the profiled one"
+    return int(prof["traffic_bytes"]), "bytes per launch, profiles/k_batched_batched-1M_traffic.md"
+
+
+def serving_leg(plain_seconds):
+    """Configuration 5: continuous batching vs the plain path on one event log."""
+    import numpy as np
+    from paper_1310_0901_amd import workloads as W, serving as S
+    t0 = time.perf_counter()
+    sw = W.config5()
+    hv, ha = W.host_v(sw.host), W.host_a(sw.host)
+    log(f"[bench] serving log: {sw.requests.size} requests, {(sw.events['type'] != 0).sum()} alloc/free events "
+        f"({time.perf_counter() - t0:.1f} s)")
+    out = {"workload": f"{sw.name} (configuration 5): {sw.note}; 4 GiB host region",
+           "admission_cap_bytes": 16 << 30}
+    dw = S.serve_world(sw, host_arrays=(hv, ha))
+    try:
+        cfg = S.config(streams=4, max_batch=512)
+        res, summ = S.run(dw, sw, cfg)
+    finally:
+        dw.close()
+    out["batched"] = dict(summ, streams=4, max_batch=512)
+    log(f"[bench] serving batched: {summ}")
+    # plain path on the first `plain_seconds` of the same log (it cannot keep up
+    # with the full offered load), and the batched loop on the same prefix
+    cut = int(np.searchsorted(sw.events["t"], plain_seconds))
+    sub = W.ServeWorkload(sw.name, sw.host, sw.dev, sw.events[:cut].copy(), sw.label, sw.rate)
+    k = int((sub.events["type"] == 0).sum())
+    dw = S.serve_world(sub, host_arrays=(hv, ha))
+    try:
+        pres, psumm = S.run(dw, sub, S.config(plain=True))
+    finally:
+        dw.close()
+    same = all(np.array_equal(pres[f], res[f][:k]) for f in ("flags", "first_bad", "undef_bytes", "avail"))
+    lat_b = (res["t_done"][:k] - res["t_arrive"][:k]) * 1e3
+    out["plain_prefix"] = dict(psumm, seconds_of_log=plain_seconds, verdicts_identical_to_batched=bool(same))
+    out["batched_same_prefix"] = {"p50_ms": round(float(np.percentile(lat_b, 50)), 4),
+                                  "p99_ms": round(float(np.percentile(lat_b, 99)), 4)}
+    log(f"[bench] serving plain (first {plain_seconds} s): {psumm}, identical: {same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +143,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the launch-shape autotuner (by default its cached choice is used, or it tunes)")
     ap.add_argument("--cpu-bytes", type=float, default=12e9)
+    ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg (configuration 5)")
+    ap.add_argument("--plain-serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
@@ -197,8 +254,9 @@ def main():
         result["pct_of_probe_read"] = round(100 * value / rd, 2)
         log(f"[bench] probe read {rd:.0f} GB/s")
 
+    traffic, traffic_note = profiled_traffic(tun, args.config)
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_note": traffic_note,
                           "kernel": "k_batched", "kernel_avg_ms": round(k_avg_ms, 3),
                           "algorithmic_bytes_per_launch": int(bytes_step)}
     if not args.no_cpu:
@@ -208,6 +266,8 @@ def main():
                                   "sample": text, "verdicts_identical_to_gpu": bool(same)}
         log(f"[bench] oracle sample {gbs:.2f} GB/s on {threads} threads, identical: {same}")
     dw.close()
+    if args.serve:
+        result["serving"] = serving_leg(args.plain_serve_seconds)
     print(json.dumps(result), flush=True)
 
 

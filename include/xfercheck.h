@@ -257,6 +257,66 @@ int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip
 /* Copy `bytes` (multiple of 16) from src to dst. */
 int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
 
+
+/* ---- serving: continuous batching of check requests ----------------------- */
+#define CG_EV_CHECK 0u   /* a check request */
+#define CG_EV_ALLOC 1u   /* an allocation: rec.dst = address, rec.n = size */
+#define CG_EV_FREE  2u   /* a free: rec.dst = address */
+
+/* One entry of an event log, 48 bytes, host memory, ordered by t. */
+typedef struct cg_serve_event {
+    double t;          /* arrival time in seconds after the start of the run */
+    uint32_t type;     /* CG_EV_* */
+    uint32_t reserved;
+    cg_transfer rec;
+} cg_serve_event;
+
+typedef struct cg_serve_config {
+    uint32_t streams;        /* micro-batch slots, one HIP stream each (1..16) */
+    uint32_t max_batch;      /* records per micro-batch (1..65536) */
+    uint64_t mem_cap;        /* admission cap: algorithmic shadow bytes in flight */
+    uint32_t plain;          /* 1: baseline, one request per check, one launch per record */
+    uint32_t open_loop;      /* 1: requests arrive at their times t; 0: all at once */
+    uint32_t blocks_per_cu;  /* persistent blocks per CU for a micro-batch (0: 1) */
+    uint32_t reserved;
+} cg_serve_config;
+
+/* Per check request, in event-log order; host memory, 72 bytes. */
+typedef struct cg_serve_result {
+    cg_verdict v;
+    double t_arrive;   /* scheduled arrival (open loop) or 0 */
+    double t_admit;    /* when its micro-batch was issued */
+    double t_done;     /* when its micro-batch finished on the GPU */
+    uint64_t epoch;    /* allocation events applied before the request */
+    uint32_t batch, slot;
+} cg_serve_result;
+
+typedef struct cg_serve_stats {
+    double wall_s;
+    uint64_t requests, batches, events;
+    uint64_t max_inflight_bytes;
+    uint64_t table_versions;   /* device table versions made (merges + full uploads) */
+    double mean_batch;
+} cg_serve_stats;
+
+/*
+ * Serve an event log: a request loop that admits check requests as they
+ * arrive, keeps the shadow and the allocation table resident on the device,
+ * and applies the interleaved allocation / free events in arrival order
+ * (the wrappers of Sec. 2 update the context's list on every allocation and
+ * free and check every copy against it).  Continuous batching: whenever a
+ * slot is free, the requests that have arrived (up to max_batch, and while
+ * the shadow bytes in flight stay within mem_cap) form a micro-batch that is
+ * checked on that slot's stream (a graph replay); micro-batches on different
+ * slots overlap on the device.  Each request is checked against the table as
+ * of its arrival (every event before it in the log is applied, none after).
+ * results (one per CG_EV_CHECK, in log order) and stats are host memory.
+ * Synchronous: returns when every request has finished.  Errors: CG_EINVAL,
+ * status codes of shadow_alloc / shadow_free for a bad event, CG_EHIP.
+ */
+int cg_serve_run(cg_ctx *ctx, const cg_serve_event *events, uint64_t n, const cg_serve_config *cfg,
+                 cg_serve_result *results, cg_serve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

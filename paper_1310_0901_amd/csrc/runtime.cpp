@@ -11,10 +11,13 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <fstream>
 #include <map>
+#include <set>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_logic.h"
@@ -25,13 +28,16 @@ using namespace xc;
 namespace {
 
 constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
-constexpr uint64_t kFillCap = 1ull << 16;     // ranges per fill launch
+constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
+constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
-constexpr size_t kGraphsPerWs = 8;
+constexpr size_t kGraphsPerWs = 16;
+constexpr int kVersions = 4;             // table versions in the device ring
 
 // A captured batched check.  With kernel timing on, the scan kernel is kept in
 // a graph of its own so that events on the caller's stream bracket exactly it.
 struct GraphEntry {
+    const DevState *st;
     const void *recs;
     void *out;
     uint64_t count;
@@ -66,6 +72,25 @@ struct TimingPair {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
+// One version of the device table: sorted base | end | off | top arrays and
+// the DevState that points at them.  `uses` holds, per stream, an event
+// recorded after the last check on that stream that read this version.
+struct TableVersion {
+    uint64_t *tab = nullptr;
+    DevState *st = nullptr;
+    uint64_t n = 0;
+    std::map<hipStream_t, hipEvent_t> uses;
+};
+
+struct Quarantined {
+    uint64_t seq, off, size;   // pool block freed after check number `seq` was issued
+};
+
+struct InFlight {
+    uint64_t seq;
+    hipEvent_t ev;
+};
+
 bool same_tuning(const cg_tuning &x, const cg_tuning &y)
 {
     return x.block == y.block && x.unroll == y.unroll && x.blocks_per_cu == y.blocks_per_cu &&
@@ -85,19 +110,35 @@ struct cg_ctx {
     PoolAllocator *palloc = nullptr;
     AllocTable table;
     uint64_t max_allocs = 0;
-    // device mirror of the table and state
-    uint64_t *d_tab = nullptr;   // base | end | off | top, contiguous
-    DevState *d_state = nullptr;
-    uint64_t *h_stage = nullptr;   // pinned staging for the table upload
+    // device table: a ring of versions; frees and allocations since the
+    // current version wait in pend_del / pend_ins until the next check
+    TableVersion ver[kVersions];
+    int cur = 0;
+    bool full_dirty = true;
+    std::set<uint64_t> pend_del;
+    std::map<uint64_t, AllocEntry> pend_ins;
+    uint64_t *d_delta = nullptr;   // sorted deletes | inserted base | end | off
+    uint8_t *m_keep = nullptr;
+    uint32_t *m_loc = nullptr;
+    uint64_t *m_bsum = nullptr, *m_boff = nullptr;
+    uint64_t *h_stage = nullptr;   // pinned staging for table uploads and deltas
     DevState *h_state = nullptr;
     hipEvent_t ev_stage = nullptr;
     bool stage_busy = false;
-    bool dirty = true;
+    uint64_t versions_made = 0, merges = 0, full_uploads = 0;
+    // shadow-pool blocks of freed allocations wait until every check issued
+    // before the free has finished
+    std::deque<Quarantined> quarantine;
+    std::deque<InFlight> inflight;
+    std::vector<hipEvent_t> ev_pool;
+    uint64_t check_seq = 0, done_seq = 0;
     Region region{0, 0, nullptr, nullptr};
-    // fills
+    // fills: a ring of staging buffers so that a new fill rarely waits for
+    // the copy of an earlier one
     FillRange *d_fill = nullptr, *h_fill = nullptr;
-    hipEvent_t ev_fill = nullptr;
-    bool fill_busy = false;
+    hipEvent_t ev_fill[kFillSlots] = {};
+    bool fill_busy[kFillSlots] = {};
+    int fill_next = 0;
     // ordering
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
@@ -143,64 +184,129 @@ int ctx_end(cg_ctx *c)
     return CG_OK;
 }
 
-// Upload the table and state if they changed (on the context stream).
-int upload(cg_ctx *c)
+// Make a new table version if allocations, frees or the host region changed
+// since the current one.  The new version goes to the next buffer of the ring
+// after the checks that last read that buffer have finished; it is either a
+// full upload from the host mirror or a device merge of the previous version
+// with the sorted frees and allocations made since.
+int materialize(cg_ctx *c)
 {
-    if (!c->dirty) return CG_OK;
+    if (!c->full_dirty && c->pend_del.empty() && c->pend_ins.empty()) return CG_OK;
     if (c->stage_busy) {
         HIPTRY(c, hipEventSynchronize(c->ev_stage));
         c->stage_busy = false;
     }
+    const int t = (c->cur + 1) % kVersions;
+    TableVersion &nv = c->ver[t], &ov = c->ver[c->cur];
+    for (auto &kv : nv.uses) HIPTRY(c, hipStreamWaitEvent(c->s, kv.second, 0));
     const uint64_t n = c->table.size();
     const uint64_t M = c->max_allocs;
-    uint64_t *hb = c->h_stage, *he = hb + M, *ho = he + M, *ht = ho + M;
-    c->table.export_sorted(hb, he, ho);
     uint32_t shift = 0;
     while (((n + (1ull << shift) - 1) >> shift) > (uint64_t)kMaxTop) ++shift;
     const uint32_t ntop = (uint32_t)((n + (1ull << shift) - 1) >> shift);
-    for (uint32_t k = 0; k < ntop; ++k) ht[k] = hb[(uint64_t)k << shift];
+    const uint64_t nd = c->pend_del.size(), ni = c->pend_ins.size();
+    const bool full = c->full_dirty || nd + 3 * ni > 3 * M || (nd + ni) * 4 > n + 64;
+    uint64_t *hs = c->h_stage;
+    if (full) {
+        uint64_t *hb = hs, *he = hb + M, *ho = he + M, *ht = ho + M;
+        c->table.export_sorted(hb, he, ho);
+        for (uint32_t k = 0; k < ntop; ++k) ht[k] = hb[(uint64_t)k << shift];
+        if (n) {
+            HIPTRY(c, hipMemcpyAsync(nv.tab, hb, n * 8, hipMemcpyHostToDevice, c->s));
+            HIPTRY(c, hipMemcpyAsync(nv.tab + M, he, n * 8, hipMemcpyHostToDevice, c->s));
+            HIPTRY(c, hipMemcpyAsync(nv.tab + 2 * M, ho, n * 8, hipMemcpyHostToDevice, c->s));
+            HIPTRY(c, hipMemcpyAsync(nv.tab + 3 * M, ht, ntop * 8ull, hipMemcpyHostToDevice, c->s));
+        }
+        c->full_uploads++;
+    } else {
+        uint64_t *hd = hs, *hib = hd + nd, *hie = hib + ni, *hio = hie + ni;
+        size_t k = 0;
+        for (uint64_t b : c->pend_del) hd[k++] = b;
+        k = 0;
+        for (const auto &kv : c->pend_ins) {
+            hib[k] = kv.first;
+            hie[k] = kv.first + kv.second.size;
+            hio[k] = kv.second.off;
+            ++k;
+        }
+        if (nd + 3 * ni)
+            HIPTRY(c, hipMemcpyAsync(c->d_delta, hs, (nd + 3 * ni) * 8, hipMemcpyHostToDevice, c->s));
+        MergeArgs m{};
+        m.old_base = ov.tab; m.old_end = ov.tab + M; m.old_off = ov.tab + 2 * M; m.n_old = ov.n;
+        m.del = c->d_delta; m.n_del = nd;
+        m.ins_base = c->d_delta + nd; m.ins_end = c->d_delta + nd + ni; m.ins_off = c->d_delta + nd + 2 * ni;
+        m.n_ins = ni;
+        m.new_base = nv.tab; m.new_end = nv.tab + M; m.new_off = nv.tab + 2 * M; m.new_top = nv.tab + 3 * M;
+        m.top_shift = shift; m.ntop = ntop;
+        m.keep = c->m_keep; m.loc = c->m_loc; m.bsum = c->m_bsum; m.boff = c->m_boff;
+        HIPTRY(c, launch_merge(m, c->s));
+        c->merges++;
+    }
     DevState &st = *c->h_state;
-    st.table.base = c->d_tab;
-    st.table.end = c->d_tab + M;
-    st.table.off = c->d_tab + 2 * M;
-    st.table.top = c->d_tab + 3 * M;
+    st.table.base = nv.tab;
+    st.table.end = nv.tab + M;
+    st.table.off = nv.tab + 2 * M;
+    st.table.top = nv.tab + 3 * M;
     st.table.n = n;
     st.table.top_shift = shift;
     st.table.ntop = ntop;
     st.region = c->region;
     st.pool = (uint64_t)c->pool;
-    int rc = ctx_begin(c);
-    if (rc) return rc;
-    if (n) {
-        HIPTRY(c, hipMemcpyAsync(c->d_tab, hb, n * 8, hipMemcpyHostToDevice, c->s));
-        HIPTRY(c, hipMemcpyAsync(c->d_tab + M, he, n * 8, hipMemcpyHostToDevice, c->s));
-        HIPTRY(c, hipMemcpyAsync(c->d_tab + 2 * M, ho, n * 8, hipMemcpyHostToDevice, c->s));
-        HIPTRY(c, hipMemcpyAsync(c->d_tab + 3 * M, ht, ntop * 8ull, hipMemcpyHostToDevice, c->s));
-    }
-    HIPTRY(c, hipMemcpyAsync(c->d_state, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
+    HIPTRY(c, hipMemcpyAsync(nv.st, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
     HIPTRY(c, hipEventRecord(c->ev_stage, c->s));
     c->stage_busy = true;
-    c->dirty = false;
+    nv.n = n;
+    c->cur = t;
+    c->pend_del.clear();
+    c->pend_ins.clear();
+    c->full_dirty = false;
+    c->versions_made++;
     return ctx_end(c);
 }
 
-// Issue fills of [ptr, ptr + len) with v on the context stream.
-int issue_fills(cg_ctx *c, const std::vector<FillRange> &rs)
+// Checks that have finished, in issue order; quarantined pool blocks whose
+// readers are all done go back to the allocator.
+void retire(cg_ctx *c, bool wait_all)
+{
+    while (!c->inflight.empty()) {
+        InFlight &f = c->inflight.front();
+        if (wait_all) (void)hipEventSynchronize(f.ev);
+        else if (hipEventQuery(f.ev) != hipSuccess) break;
+        c->done_seq = f.seq;
+        c->ev_pool.push_back(f.ev);
+        c->inflight.pop_front();
+    }
+    if (c->inflight.empty()) c->done_seq = c->check_seq;
+    while (!c->quarantine.empty() && c->quarantine.front().seq <= c->done_seq) {
+        c->palloc->release(c->quarantine.front().off, c->quarantine.front().size);
+        c->quarantine.pop_front();
+    }
+}
+
+// Issue fills of [ptr, ptr + len) with v on the context stream.  Fills of
+// existing allocations (shadow_set) wait for every check issued before;
+// fills of fresh allocations need not: their pool blocks are read by no check.
+int issue_fills(cg_ctx *c, const std::vector<FillRange> &rs, bool after_checks)
 {
     size_t i = 0;
-    int rc = ctx_begin(c);
-    if (rc) return rc;
+    if (after_checks) {
+        int rc = ctx_begin(c);
+        if (rc) return rc;
+    }
     while (i < rs.size()) {
-        if (c->fill_busy) {
-            HIPTRY(c, hipEventSynchronize(c->ev_fill));
-            c->fill_busy = false;
+        const int f = c->fill_next;
+        c->fill_next = (f + 1) % kFillSlots;
+        if (c->fill_busy[f]) {
+            HIPTRY(c, hipEventSynchronize(c->ev_fill[f]));
+            c->fill_busy[f] = false;
         }
+        FillRange *h = c->h_fill + f * kFillCap, *d = c->d_fill + f * kFillCap;
         size_t k = 0;
-        for (; i < rs.size() && k < kFillCap; ++i) c->h_fill[k++] = rs[i];
-        HIPTRY(c, hipMemcpyAsync(c->d_fill, c->h_fill, k * sizeof(FillRange), hipMemcpyHostToDevice, c->s));
-        HIPTRY(c, launch_fill(c->d_fill, k, c->s));
-        HIPTRY(c, hipEventRecord(c->ev_fill, c->s));
-        c->fill_busy = true;
+        for (; i < rs.size() && k < kFillCap; ++i) h[k++] = rs[i];
+        HIPTRY(c, hipMemcpyAsync(d, h, k * sizeof(FillRange), hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, launch_fill(d, k, c->s));
+        HIPTRY(c, hipEventRecord(c->ev_fill[f], c->s));
+        c->fill_busy[f] = true;
     }
     return ctx_end(c);
 }
@@ -277,7 +383,7 @@ BatchArgs make_args(cg_ctx *c, Workspace *w, const cg_transfer *recs, uint64_t c
     a.count = count;
     a.out = (mode & CG_CHECK) ? out : nullptr;
     a.mode = mode & (CG_CHECK | CG_PROPAGATE);
-    a.st = c->d_state;
+    a.st = c->ver[c->cur].st;
     a.desc = w->desc;
     a.weight = w->weight;
     a.local = w->local;
@@ -417,7 +523,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     Workspace *w;
     int rc = get_ws(c, s, count, &w);
     if (rc) return rc;
-    rc = upload(c);
+    rc = materialize(c);
     if (rc) return rc;
     HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
     if ((mode & CG_DEBUG_CONFLICTS) && (mode & CG_PROPAGATE)) {
@@ -444,7 +550,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         const bool split = c->timing;
         GraphEntry *ge = nullptr;
         for (auto &g : w->graphs)
-            if (g.recs == recs && g.out == out && g.count == count && g.mode == (mode & 3u) &&
+            if (g.st == a.st && g.recs == recs && g.out == out && g.count == count && g.mode == (mode & 3u) &&
                 same_tuning(g.tun, tun) && g.split == split)
                 ge = &g;
         if (!ge) {
@@ -453,7 +559,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
                 destroy_graph(w->graphs.front());
                 w->graphs.erase(w->graphs.begin());
             }
-            GraphEntry g{recs, out, count, mode & 3u, tun, split, nullptr, nullptr, nullptr, nullptr};
+            GraphEntry g{a.st, recs, out, count, mode & 3u, tun, split, nullptr, nullptr, nullptr, nullptr};
             rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0);
             if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2);
             if (rc) { destroy_graph(g); return rc; }
@@ -472,6 +578,16 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     }
     HIPTRY(c, hipEventRecord(w->done, s));
     w->used = true;
+    // bookkeeping for version reuse and the pool quarantine
+    hipEvent_t &vu = c->ver[c->cur].uses[s];
+    if (!vu) HIPTRY(c, hipEventCreateWithFlags(&vu, hipEventDisableTiming));
+    HIPTRY(c, hipEventRecord(vu, s));
+    hipEvent_t ev;
+    if (c->ev_pool.empty()) HIPTRY(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    else { ev = c->ev_pool.back(); c->ev_pool.pop_back(); }
+    HIPTRY(c, hipEventRecord(ev, s));
+    c->inflight.push_back(InFlight{++c->check_seq, ev});
+    if (c->inflight.size() > 256) retire(c, false);
     return CG_OK;
 }
 
@@ -554,16 +670,24 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (hipMalloc(&c->pool, pool) != hipSuccess) return bail(CG_ENOMEM);
     c->pool_bytes = pool;
     c->palloc = new PoolAllocator(pool, 256);
-    if (hipMalloc(&c->d_tab, (3 * max_allocs + kMaxTop) * 8) != hipSuccess) return bail(CG_ENOMEM);
-    if (hipMalloc(&c->d_state, sizeof(DevState)) != hipSuccess) return bail(CG_ENOMEM);
+    for (auto &v : c->ver) {
+        if (hipMalloc(&v.tab, (3 * max_allocs + kMaxTop) * 8) != hipSuccess) return bail(CG_ENOMEM);
+        if (hipMalloc(&v.st, sizeof(DevState)) != hipSuccess) return bail(CG_ENOMEM);
+    }
+    if (hipMalloc(&c->d_delta, (3 * max_allocs + kMaxTop) * 8) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->m_keep, max_allocs) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->m_loc, max_allocs * 4) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->m_bsum, (max_allocs / 256 + 2) * 8) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipMalloc(&c->m_boff, (max_allocs / 256 + 2) * 8) != hipSuccess) return bail(CG_ENOMEM);
     if (hipHostMalloc(&c->h_stage, (3 * max_allocs + kMaxTop) * 8, hipHostMallocDefault) != hipSuccess)
         return bail(CG_ENOMEM);
     if (hipHostMalloc(&c->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) return bail(CG_ENOMEM);
-    if (hipMalloc(&c->d_fill, kFillCap * sizeof(FillRange)) != hipSuccess) return bail(CG_ENOMEM);
-    if (hipHostMalloc(&c->h_fill, kFillCap * sizeof(FillRange), hipHostMallocDefault) != hipSuccess)
+    if (hipMalloc(&c->d_fill, kFillSlots * kFillCap * sizeof(FillRange)) != hipSuccess) return bail(CG_ENOMEM);
+    if (hipHostMalloc(&c->h_fill, kFillSlots * kFillCap * sizeof(FillRange), hipHostMallocDefault) != hipSuccess)
         return bail(CG_ENOMEM);
     if (hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
-    if (hipEventCreateWithFlags(&c->ev_fill, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+    for (auto &e : c->ev_fill)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
     if (hipEventCreateWithFlags(&c->ev_ctx, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
     c->tuning.block = 256;
     c->tuning.unroll = 4;
@@ -576,7 +700,7 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     // an empty table and region, so that checks before any allocation work
-    if (upload(c) != CG_OK) return bail(CG_EHIP);
+    if (materialize(c) != CG_OK) return bail(CG_EHIP);
     if (hipStreamSynchronize(c->s) != hipSuccess) return bail(CG_EHIP);
     *out = c;
     return CG_OK;
@@ -599,14 +723,25 @@ int cg_destroy(cg_ctx *c)
     if (c->s) (void)hipStreamDestroy(c->s);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     (void)hipFree(c->pool);
-    (void)hipFree(c->d_tab);
-    (void)hipFree(c->d_state);
+    for (auto &v : c->ver) {
+        (void)hipFree(v.tab);
+        (void)hipFree(v.st);
+        for (auto &kv : v.uses) (void)hipEventDestroy(kv.second);
+    }
+    for (auto &f : c->inflight) (void)hipEventDestroy(f.ev);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    (void)hipFree(c->d_delta);
+    (void)hipFree(c->m_keep);
+    (void)hipFree(c->m_loc);
+    (void)hipFree(c->m_bsum);
+    (void)hipFree(c->m_boff);
     (void)hipFree(c->d_fill);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_state) (void)hipHostFree(c->h_state);
     if (c->h_fill) (void)hipHostFree(c->h_fill);
     if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
-    if (c->ev_fill) (void)hipEventDestroy(c->ev_fill);
+    for (auto e : c->ev_fill)
+        if (e) (void)hipEventDestroy(e);
     if (c->ev_ctx) (void)hipEventDestroy(c->ev_ctx);
     delete c->palloc;
     delete c;
@@ -624,7 +759,7 @@ int cg_host_register(cg_ctx *c, uint64_t host_base, uint64_t len, uint8_t *v_dev
     c->region.hl = len;
     c->region.v = v_dev;
     c->region.a16 = reinterpret_cast<const uint16_t *>(a_bits_dev);
-    c->dirty = true;
+    c->full_dirty = true;
     return CG_OK;
 }
 
@@ -635,10 +770,15 @@ static int alloc_one(cg_ctx *c, uint64_t addr, uint64_t size, std::vector<FillRa
     if (rc == CG_EOVERLAP) return fail(c, rc, "shadow_alloc: range intersects a live allocation");
     if (c->table.size() >= c->max_allocs) return fail(c, CG_ECAPACITY, "shadow_alloc: table full");
     uint64_t off;
-    if (!c->palloc->alloc(size, &off)) return fail(c, CG_ENOMEM, "shadow_alloc: shadow pool exhausted");
+    retire(c, false);
+    if (!c->palloc->alloc(size, &off)) {
+        if (c->quarantine.empty()) return fail(c, CG_ENOMEM, "shadow_alloc: shadow pool exhausted");
+        retire(c, true);   // wait for the readers of freed blocks
+        if (!c->palloc->alloc(size, &off)) return fail(c, CG_ENOMEM, "shadow_alloc: shadow pool exhausted");
+    }
     c->table.insert(addr, size, off);
+    c->pend_ins[addr] = AllocEntry{size, off};
     add_fill(fills, (uint64_t)c->pool + off, size, 0xFF);
-    c->dirty = true;
     return CG_OK;
 }
 
@@ -648,7 +788,7 @@ int shadow_alloc(cg_ctx *c, uint64_t dev_addr, uint64_t size)
     std::vector<FillRange> fills;
     int rc = alloc_one(c, dev_addr, size, fills);
     if (rc) return rc;
-    return issue_fills(c, fills);
+    return issue_fills(c, fills, false);
 }
 
 int shadow_alloc_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *size, uint64_t k)
@@ -657,7 +797,7 @@ int shadow_alloc_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *size, ui
     std::vector<FillRange> fills;
     int rc = CG_OK;
     for (uint64_t i = 0; i < k && rc == CG_OK; ++i) rc = alloc_one(c, addr[i], size[i], fills);
-    int rc2 = issue_fills(c, fills);
+    int rc2 = issue_fills(c, fills, false);
     return rc ? rc : rc2;
 }
 
@@ -665,8 +805,11 @@ static int free_one(cg_ctx *c, uint64_t addr)
 {
     AllocEntry e;
     if (c->table.erase(addr, &e) != CG_OK) return fail(c, CG_ENOTFOUND, "shadow_free: not the base of a live allocation");
-    c->palloc->release(e.off, e.size);
-    c->dirty = true;
+    // the block may still be read by checks issued before this free
+    c->quarantine.push_back(Quarantined{c->check_seq, e.off, e.size});
+    auto it = c->pend_ins.find(addr);
+    if (it != c->pend_ins.end()) c->pend_ins.erase(it);   // never reached the device table
+    else c->pend_del.insert(addr);
     return CG_OK;
 }
 
@@ -703,7 +846,7 @@ int shadow_set(cg_ctx *c, uint64_t dev_addr, uint64_t n, uint8_t v)
     std::vector<FillRange> fills;
     int rc = set_one(c, dev_addr, n, v, fills);
     if (rc) return rc;
-    return issue_fills(c, fills);
+    return issue_fills(c, fills, true);
 }
 
 int shadow_set_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *n, const uint8_t *v, uint64_t k)
@@ -712,7 +855,7 @@ int shadow_set_batch(cg_ctx *c, const uint64_t *addr, const uint64_t *n, const u
     std::vector<FillRange> fills;
     int rc = CG_OK;
     for (uint64_t i = 0; i < k && rc == CG_OK; ++i) rc = set_one(c, addr[i], n[i], v[i], fills);
-    int rc2 = issue_fills(c, fills);
+    int rc2 = issue_fills(c, fills, true);
     return rc ? rc : rc2;
 }
 
@@ -904,3 +1047,189 @@ int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream)
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// serving loop
+// ===========================================================================
+namespace {
+
+struct Slot {
+    hipStream_t s = nullptr;
+    cg_transfer *d_recs = nullptr, *h_recs = nullptr;
+    cg_verdict *d_out = nullptr, *h_out = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    uint64_t bytes = 0;
+    uint32_t filled = 0;                // records written in h_recs (rest padded)
+    std::vector<uint64_t> reqs;         // result indices of the batch
+};
+
+double footprint(const cg_transfer &r)
+{
+    return (double)r.n * (r.kind == CG_D2D ? 1.0 : 1.125);
+}
+
+void free_slots(std::vector<Slot> &slots)
+{
+    for (auto &sl : slots) {
+        if (sl.s) (void)hipStreamSynchronize(sl.s);
+        (void)hipFree(sl.d_recs);
+        (void)hipFree(sl.d_out);
+        if (sl.h_recs) (void)hipHostFree(sl.h_recs);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.s) (void)hipStreamDestroy(sl.s);
+    }
+}
+
+}  // namespace
+
+extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, const cg_serve_config *cfg,
+                            cg_serve_result *res, cg_serve_stats *stats)
+{
+    if (!c || (n && (!ev || !res)) || !cfg) return CG_EINVAL;
+    const uint32_t S = cfg->plain ? 1u : cfg->streams;
+    const uint32_t B = cfg->plain ? 1u : cfg->max_batch;
+    if (S < 1 || S > 16 || B < 1 || B > 65536 || cfg->mem_cap == 0) return fail(c, CG_EINVAL, "serve: bad config");
+    HIPTRY(c, hipSetDevice(c->dev));
+    cg_tuning tun = c->tuning;
+    tun.blocks_per_cu = cfg->blocks_per_cu ? cfg->blocks_per_cu : 1;
+    if (!valid_tuning(tun)) return fail(c, CG_EINVAL, "serve: bad blocks_per_cu");
+
+    std::vector<Slot> slots(S);
+    auto bail = [&](int rc) { free_slots(slots); return rc; };
+    for (auto &sl : slots) {
+        if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+            hipMalloc(&sl.d_recs, B * sizeof(cg_transfer)) != hipSuccess ||
+            hipMalloc(&sl.d_out, B * sizeof(cg_verdict)) != hipSuccess ||
+            hipHostMalloc(&sl.h_recs, B * sizeof(cg_transfer), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&sl.h_out, B * sizeof(cg_verdict), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&sl.done) != hipSuccess)
+            return bail(fail(c, CG_ENOMEM, "serve: slot buffers"));
+        for (uint32_t k = 0; k < B; ++k) sl.h_recs[k] = cg_transfer{0, 0, 0, 0xFFFFFFFFu, 0};
+        sl.filled = B;
+    }
+    // result index of every check event
+    std::vector<uint64_t> ridx(n);
+    uint64_t nreq = 0;
+    for (uint64_t i = 0; i < n; ++i) ridx[i] = ev[i].type == CG_EV_CHECK ? nreq++ : ~0ull;
+
+    hipEvent_t ev0;
+    if (hipEventCreate(&ev0) != hipSuccess) return bail(fail(c, CG_EHIP, "serve: event"));
+    using clk = std::chrono::steady_clock;
+    const auto T0 = clk::now();
+    if (hipEventRecord(ev0, slots[0].s) != hipSuccess) { (void)hipEventDestroy(ev0); return bail(CG_EHIP); }
+    auto now = [&] { return std::chrono::duration<double>(clk::now() - T0).count(); };
+
+    std::deque<uint64_t> fifo;
+    uint64_t next = 0, epoch = 0, batches = 0, nevents = 0, admitted = 0;
+    double inflight = 0, max_inflight = 0;
+    const uint64_t versions0 = c->versions_made;
+    int rc = CG_OK;
+    while (rc == CG_OK) {
+        bool progress = false;
+        const double t = now();
+        while (next < n && (!cfg->open_loop || ev[next].t <= t)) {
+            if (ev[next].type == CG_EV_CHECK) res[ridx[next]].t_arrive = cfg->open_loop ? ev[next].t : 0.0;
+            fifo.push_back(next++);
+            progress = true;
+        }
+        // finished micro-batches
+        for (uint32_t k = 0; k < S; ++k) {
+            Slot &sl = slots[k];
+            if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev0, sl.done);
+            for (size_t q = 0; q < sl.reqs.size(); ++q) {
+                res[sl.reqs[q]].v = sl.h_out[q];
+                res[sl.reqs[q]].t_done = ms / 1e3;
+            }
+            inflight -= (double)sl.bytes;
+            sl.busy = false;
+            progress = true;
+        }
+        // allocation events at the head apply at once: every request before
+        // them has been issued already
+        while (!fifo.empty() && ev[fifo.front()].type != CG_EV_CHECK) {
+            const cg_serve_event &e = ev[fifo.front()];
+            if (e.type == CG_EV_ALLOC) {
+                std::vector<FillRange> fills;
+                rc = alloc_one(c, e.rec.dst, e.rec.n, fills);
+                if (!rc) rc = issue_fills(c, fills, false);
+            } else if (e.type == CG_EV_FREE) {
+                rc = free_one(c, e.rec.dst);
+            } else {
+                rc = fail(c, CG_EINVAL, "serve: unknown event type");
+            }
+            if (rc) break;
+            ++epoch;
+            ++nevents;
+            fifo.pop_front();
+            progress = true;
+        }
+        if (rc) break;
+        // continuous batching into free slots
+        for (uint32_t k = 0; k < S && !fifo.empty() && rc == CG_OK; ++k) {
+            Slot &sl = slots[k];
+            if (sl.busy || ev[fifo.front()].type != CG_EV_CHECK) continue;
+            sl.reqs.clear();
+            double bytes = 0;
+            while (!fifo.empty() && sl.reqs.size() < B) {
+                const cg_serve_event &e = ev[fifo.front()];
+                if (e.type != CG_EV_CHECK) break;
+                const double fp = footprint(e.rec);
+                if (inflight + bytes + fp > (double)cfg->mem_cap && inflight + bytes > 0) break;
+                const uint64_t r = ridx[fifo.front()];
+                sl.h_recs[sl.reqs.size()] = e.rec;
+                res[r].epoch = epoch;
+                res[r].batch = (uint32_t)batches;
+                res[r].slot = k;
+                sl.reqs.push_back(r);
+                bytes += fp;
+                fifo.pop_front();
+            }
+            if (sl.reqs.empty()) break;   // admission cap reached
+            const uint32_t cnt = (uint32_t)sl.reqs.size();
+            for (uint32_t q = cnt; q < sl.filled; ++q) sl.h_recs[q] = cg_transfer{0, 0, 0, 0xFFFFFFFFu, 0};
+            sl.filled = cnt;
+            const double ta = now();
+            for (uint64_t r : sl.reqs) res[r].t_admit = ta;
+            const uint32_t count = cfg->plain ? cnt : B;   // graph shape: fixed count, padded
+            hipError_t e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
+            if (e1 != hipSuccess) { rc = hip_fail(c, "serve: records upload", e1); break; }
+            rc = run_check(c, sl.d_recs, count, sl.d_out, CG_CHECK | (cfg->plain ? CG_PLAIN : 0u), sl.s, tun);
+            if (rc) break;
+            e1 = hipMemcpyAsync(sl.h_out, sl.d_out, cnt * sizeof(cg_verdict), hipMemcpyDeviceToHost, sl.s);
+            if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);
+            if (e1 != hipSuccess) { rc = hip_fail(c, "serve: verdict download", e1); break; }
+            sl.busy = true;
+            sl.bytes = (uint64_t)bytes;
+            inflight += bytes;
+            max_inflight = std::max(max_inflight, inflight);
+            admitted += cnt;
+            ++batches;
+            progress = true;
+        }
+        if (rc) break;
+        bool any_busy = false;
+        for (auto &sl : slots) any_busy |= sl.busy;
+        if (next == n && fifo.empty() && !any_busy) break;
+        if (!progress) std::this_thread::yield();
+    }
+    const double wall = now();
+    if (rc) {
+        for (auto &sl : slots) (void)hipStreamSynchronize(sl.s);
+    }
+    (void)hipEventDestroy(ev0);
+    free_slots(slots);
+    if (stats) {
+        stats->wall_s = wall;
+        stats->requests = admitted;
+        stats->batches = batches;
+        stats->events = nevents;
+        stats->max_inflight_bytes = (uint64_t)max_inflight;
+        stats->table_versions = c->versions_made - versions0;
+        stats->mean_batch = batches ? (double)admitted / batches : 0;
+    }
+    return rc;
+}

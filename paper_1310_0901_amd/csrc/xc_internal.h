@@ -106,6 +106,24 @@ struct LaunchShape {
     uint32_t tile_units;
 };
 
+// Merge of a table version with the frees and allocations made since
+// (table.hip).  del / ins_* are sorted by base; keep / loc / bsum / boff are
+// scratch sized for n_old (boff has one extra entry: the kept count).
+struct MergeArgs {
+    const uint64_t *old_base, *old_end, *old_off;
+    uint64_t n_old;
+    const uint64_t *del;
+    uint64_t n_del;
+    const uint64_t *ins_base, *ins_end, *ins_off;
+    uint64_t n_ins;
+    uint64_t *new_base, *new_end, *new_off, *new_top;
+    uint32_t top_shift, ntop;
+    uint8_t *keep;
+    uint32_t *loc;
+    uint64_t *bsum, *boff;
+};
+hipError_t launch_merge(const MergeArgs &m, hipStream_t s);
+
 // kernel launchers (kernels.hip); all asynchronous on `s`
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, hipStream_t s);

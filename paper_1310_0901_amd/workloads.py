@@ -44,6 +44,14 @@ RECORD_DTYPE = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"),
 VERDICT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"),
                           ("first_bad", "<u8"), ("undef_bytes", "<u8"),
                           ("avail", "<u8")])
+# serving event log entry (48 bytes) and per-request result (72 bytes)
+EV_CHECK, EV_ALLOC, EV_FREE = 0, 1, 2
+SERVE_EVENT_DTYPE = np.dtype([("t", "<f8"), ("type", "<u4"), ("reserved", "<u4"),
+                              ("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("rsv", "<u4")])
+SERVE_RESULT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
+                               ("undef_bytes", "<u8"), ("avail", "<u8"), ("t_arrive", "<f8"),
+                               ("t_admit", "<f8"), ("t_done", "<f8"), ("epoch", "<u8"),
+                               ("batch", "<u4"), ("slot", "<u4")])
 
 
 @dataclass
@@ -438,6 +446,191 @@ def config4(seed=SEED0 + 4, host_len=2 * GiB, pieces=1, hops=4) -> Workload:
     w.R, w.P = R, P
     w.payload_records, w.payload_byte, w.payload_bit = recs, b, k
     return w
+
+
+# ---------------------------------------------------------------------------
+# configuration 5: serving -- Poisson requests interleaved with allocation events
+# ---------------------------------------------------------------------------
+
+def _mixture(rng, size, weights, comps):
+    """Log-uniform sizes from a mixture of [lo, hi) components."""
+    which = rng.choice(len(comps), size=size, p=weights)
+    out = np.empty(size, np.int64)
+    for k, (lo, hi) in enumerate(comps):
+        m = which == k
+        out[m] = log_uniform_int(rng, lo, hi, int(m.sum()))
+    return out
+
+
+REQ_COMPONENTS = [(64, 4 * KiB), (4 * KiB, 1 * MiB), (1 * MiB, 64 * MiB)]
+
+
+@dataclass
+class ServeWorkload:
+    name: str
+    host: HostSpec
+    dev: DeviceSpec              # the initial state (live allocations at t = 0)
+    events: np.ndarray           # SERVE_EVENT_DTYPE, ordered by t
+    label: np.ndarray            # per check request
+    rate: float
+    note: str = ""
+
+    @property
+    def requests(self) -> np.ndarray:
+        return self.events[self.events["type"] == EV_CHECK]
+
+
+def config5(seed=SEED0 + 5, rate=50_000.0, duration=10.0, n_alloc=975_000, host_len=4 * GiB,
+            event_ratio=10, p_over=0.02, p_uaf=0.01, p_new=0.1, zipf_s=1.1, density=1e-6,
+            req_weights=(0.90, 0.09, 0.01), alloc_weights=(0.99, 0.009, 0.001)) -> ServeWorkload:
+    """Poisson check requests at `rate` for `duration` seconds; one
+    allocation or free event (p = 1/2 each) per `event_ratio` requests.
+
+    Readings where the configuration is silent: request and allocation sizes
+    are log-uniform within each mixture component; the initial allocations
+    are fully written (V = 0) except sparse undefined runs at `density`;
+    allocations made during the run are fresh (V = 0xFF) at new addresses;
+    frees pick a live allocation uniformly; requests pick their device side
+    by Zipf(1.1) over the initial allocations that fit (so a request may hit
+    one freed before it arrives), or with probability p_new an allocation made
+    during the run; kinds 60/30/10 H2D/D2D/D2H; 2 % overruns and 1 %
+    pointers into freed allocations as in configuration 3."""
+    rng = np.random.default_rng(seed)
+    hl = host_len
+    cnt, lens = _sparse_runs(rng, hl, density)
+    starts = rng.integers(0, hl - lens + 1)
+    host = HostSpec(HOST_BASE, hl, runs=np.stack([starts, lens, np.full(cnt, 0xFF)], 1).astype(np.int64))
+    sizes0 = _mixture(rng, n_alloc, list(alloc_weights), REQ_COMPONENTS)
+    bases0 = place_allocations(rng, sizes0).astype(np.int64)
+    tot = int(sizes0.sum())
+    rcnt, rlens = _sparse_runs(rng, tot, density)
+    which = rng.choice(n_alloc, size=rcnt, p=sizes0 / tot)
+    rl = np.minimum(rlens, sizes0[which])
+    roff = (rng.random(rcnt) * (sizes0[which] - rl + 1)).astype(np.int64)
+    dev = DeviceSpec(bases0.astype(np.uint64), sizes0.astype(np.uint64), np.ones(n_alloc, bool),
+                     np.zeros(n_alloc, np.uint8),
+                     np.stack([which, roff, rl, np.full(rcnt, 0xFF)], 1).astype(np.int64))
+
+    # arrivals: one Poisson stream of requests and events
+    total_rate = rate * (1 + 1 / event_ratio)
+    n_arr = int(rng.poisson(total_rate * duration))
+    t = np.sort(rng.uniform(0, duration, size=n_arr))
+    is_ev = rng.random(n_arr) < (1 / (event_ratio + 1))
+    ev_t = t[is_ev]
+    rq_t = t[~is_ev]
+    n_ev, n_rq = ev_t.size, rq_t.size
+
+    # allocation events, simulated in order (frees pick a live allocation)
+    ev_type = np.where(rng.random(n_ev) < 0.5, EV_ALLOC, EV_FREE)
+    new_sizes = _mixture(rng, n_ev, list(alloc_weights), REQ_COMPONENTS)
+    next_base = int(bases0[-1] + sizes0[-1]) + (1 << 20)
+    live = list(range(n_alloc))           # ids into all_base / all_size
+    pos = np.arange(n_alloc)              # id -> index in `live` (or -1)
+    all_base = list(bases0)
+    all_size = list(sizes0)
+    ev_addr = np.zeros(n_ev, np.int64)
+    ev_size = np.zeros(n_ev, np.int64)
+    born = [0.0] * n_alloc                # creation time of every id
+    died = [np.inf] * n_alloc
+    pos = list(pos)
+    pick = rng.random(n_ev)
+    for k in range(n_ev):
+        if ev_type[k] == EV_ALLOC or len(live) < 2:
+            ev_type[k] = EV_ALLOC
+            sz = int(new_sizes[k])
+            i = len(all_base)
+            all_base.append(next_base)
+            all_size.append(sz)
+            born.append(ev_t[k])
+            died.append(np.inf)
+            pos.append(len(live))
+            live.append(i)
+            ev_addr[k], ev_size[k] = next_base, sz
+            next_base += (sz + 255) // 256 * 256 + 256
+        else:
+            j = int(pick[k] * len(live))
+            i = live[j]
+            last = live[-1]
+            live[j] = last
+            pos[last] = j
+            live.pop()
+            pos[i] = -1
+            died[i] = ev_t[k]
+            ev_addr[k] = all_base[i]
+    all_base = np.array(all_base, np.int64)
+    all_size = np.array(all_size, np.int64)
+    born = np.array(born)
+    died = np.array(died)
+
+    # requests
+    kind = rng.choice(3, size=n_rq, p=[0.6, 0.1, 0.3]).astype(np.int64)
+    n = _mixture(rng, n_rq, list(req_weights), REQ_COMPONENTS)
+    srt = np.sort(sizes0)
+    mx = np.where(kind == KIND_D2D, int(srt[-2]), int(srt[-1]))
+    bad = n > mx
+    while bad.any():
+        n[bad] = _mixture(rng, int(bad.sum()), list(req_weights), REQ_COMPONENTS)
+        bad = n > mx
+    u = rng.random(n_rq)
+    label = np.where(u < p_over, LABEL_OVERRUN, np.where(u < p_over + p_uaf, LABEL_UAF, LABEL_CLEAN))
+    delta = rng.integers(1, 65, size=n_rq)
+    label[(label == LABEL_OVERRUN) & (n <= delta)] = LABEL_CLEAN
+    cz = ConditionalZipf(rng, sizes0, zipf_s)
+    need = np.where(label == LABEL_OVERRUN, n - delta, n)
+    inj = cz.draw(rng, need)
+    # requests to allocations made during the run (clipped to fit)
+    n_new_before = np.searchsorted(born[n_alloc:], rq_t, side="right")
+    to_new = (rng.random(n_rq) < p_new) & (n_new_before > 0) & (label == LABEL_CLEAN)
+    ni = n_alloc + (rng.random(n_rq) * np.maximum(n_new_before, 1)).astype(np.int64)
+    inj = np.where(to_new, ni, inj)
+    n = np.where(to_new, np.minimum(n, all_size[inj]), n)
+    L = all_size[inj]
+    o_inj = np.where(label == LABEL_OVERRUN, L - (n - delta), (rng.random(n_rq) * (L - n + 1)).astype(np.int64))
+    side_inj = all_base[inj] + o_inj
+    # pointers into allocations freed before the request (else past the end)
+    uaf = np.flatnonzero(label == LABEL_UAF)
+    dead_t = np.where(np.isfinite(died), died, np.inf)
+    order = np.argsort(dead_t)
+    dead_sorted = dead_t[order]
+    for r in uaf:
+        k = int(np.searchsorted(dead_sorted, rq_t[r], side="left"))
+        if k > 0:
+            i = int(order[int(rng.integers(0, k))])
+            side_inj[r] = all_base[i] + int(rng.integers(0, all_size[i]))
+        else:
+            side_inj[r] = next_base + int(rng.integers(0, 1 << 20))
+    d2d = np.flatnonzero(kind == KIND_D2D)
+    other = cz.draw(rng, n[d2d])
+    same = other == inj[d2d]
+    while same.any():
+        other[same] = cz.draw(rng, n[d2d][same])
+        same = other == inj[d2d]
+    o_oth = (rng.random(d2d.size) * (sizes0[other] - n[d2d] + 1)).astype(np.int64)
+    hostp = HOST_BASE + (rng.random(n_rq) * (hl - n + 1)).astype(np.int64)
+    src = np.where(kind == KIND_H2D, hostp, side_inj)
+    dst = np.where(kind == KIND_D2H, hostp, side_inj)
+    src[d2d] = bases0[other] + o_oth
+
+    events = np.zeros(n_arr, SERVE_EVENT_DTYPE)
+    events["t"] = t
+    ie = np.flatnonzero(is_ev)
+    ir = np.flatnonzero(~is_ev)
+    events["type"][ie] = ev_type
+    events["dst"][ie] = ev_addr.astype(np.uint64)
+    events["n"][ie] = ev_size.astype(np.uint64)
+    events["type"][ir] = EV_CHECK
+    events["src"][ir] = src.astype(np.uint64)
+    events["dst"][ir] = dst.astype(np.uint64)
+    events["n"][ir] = n.astype(np.uint64)
+    events["kind"][ir] = kind
+    return ServeWorkload("serving", host, dev, events, label, rate,
+                         note=f"Poisson {rate:.0f} req/s for {duration:g} s, one alloc/free per "
+                              f"{event_ratio} requests, {n_alloc} initial allocations")
+
+
+def small_serve(seed=SEED0 + 5, duration=0.15) -> ServeWorkload:
+    return config5(seed=seed, duration=duration, n_alloc=2000, host_len=64 * MiB, density=2e-4,
+                   req_weights=(0.95, 0.048, 0.002), alloc_weights=(0.95, 0.045, 0.005))
 
 
 # sizes used by the parity tests: several tiles and a ragged tail, oracle in seconds

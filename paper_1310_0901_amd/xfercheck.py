@@ -53,6 +53,23 @@ class cg_tuning(ctypes.Structure):
         return {k: int(getattr(self, k)) for k in ("block", "unroll", "blocks_per_cu", "tile_units", "nontemporal")}
 
 
+class cg_serve_config(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("mem_cap", ctypes.c_uint64),
+                ("plain", ctypes.c_uint32), ("open_loop", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class cg_serve_stats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("requests", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("events", ctypes.c_uint64), ("max_inflight_bytes", ctypes.c_uint64),
+                ("table_versions", ctypes.c_uint64), ("mean_batch", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+CG_EV_CHECK, CG_EV_ALLOC, CG_EV_FREE = 0, 1, 2
+
 _lib = None
 P, U64, U32, I32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
 PU64 = ctypes.POINTER(ctypes.c_uint64)
@@ -83,6 +100,7 @@ _PROTOS = {
     "cg_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double), PU64]),
     "cg_probe_read": (I32, [P, U64, P, P]),
     "cg_probe_copy": (I32, [P, P, U64, P]),
+    "cg_serve_run": (I32, [P, P, U64, ctypes.POINTER(cg_serve_config), P, ctypes.POINTER(cg_serve_stats)]),
 }
 
 EXPORTS = tuple(_PROTOS)
@@ -236,3 +254,17 @@ def cg_probe_read(dev, nbytes, sink_dev, stream=0) -> None:
 
 def cg_probe_copy(dst, src, nbytes, stream=0) -> None:
     _chk(None, lib().cg_probe_copy(dst, src, nbytes, stream), "cg_probe_copy")
+
+
+def cg_serve_run(ctx, events, cfg: cg_serve_config):
+    """events: numpy array of workloads.SERVE_EVENT_DTYPE (host).  Returns
+    (results as workloads.SERVE_RESULT_DTYPE, stats)."""
+    import numpy as np
+    from .workloads import SERVE_EVENT_DTYPE, SERVE_RESULT_DTYPE
+    ev = np.ascontiguousarray(events, SERVE_EVENT_DTYPE)
+    nreq = int((ev["type"] == CG_EV_CHECK).sum())
+    res = np.zeros(max(nreq, 1), SERVE_RESULT_DTYPE)
+    st = cg_serve_stats()
+    _chk(ctx, lib().cg_serve_run(ctx, ev.ctypes.data, ev.size, ctypes.byref(cfg), res.ctypes.data, ctypes.byref(st)),
+         "cg_serve_run")
+    return res[:nreq], st

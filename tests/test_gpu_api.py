@@ -168,3 +168,80 @@ def test_shadow_ops_are_ordered_after_checks(X, H):
         util.assert_verdicts_equal(H.verdicts_np(out, w.count), want, "check before the table change")
     finally:
         dw.close()
+
+
+def test_table_churn_versions_match_oracle(X, H):
+    """Frees and allocations between batches with no host synchronisation:
+    each batch sees exactly the table of its issue time (device merges and
+    full uploads of the version ring), freed shadow blocks are not reused
+    while earlier checks may read them."""
+    rng = np.random.default_rng(5)
+    hl = 1 << 20
+    hv = np.where(rng.random(hl) < 0.001, 0xFF, 0).astype(np.uint8)
+    n0 = 3000
+    sizes = rng.integers(16, 4096, size=n0)
+    bases = (W.DEV_BASE + np.cumsum(np.concatenate([[0], sizes[:-1]])) + np.arange(n0) * 256).astype(np.uint64)
+    vs = {int(b): np.where(rng.random(int(s)) < 0.002, 0x40, 0).astype(np.uint8) for b, s in zip(bases, sizes)}
+    pool = int(((sizes + 255) // 256 * 256).sum()) + (2 << 20)
+    ctx = X.cg_create(0, pool, n0 + 4000)
+    try:
+        hvt = torch.zeros(hl + 32, dtype=torch.uint8, device="cuda")
+        hvt[:hl].copy_(torch.from_numpy(hv))
+        ha = np.full(hl // 64, np.uint64(0xFFFF_FFFF_FFFF_FFFF), np.uint64)
+        hat = torch.from_numpy(ha.view(np.int64)).cuda()
+        X.cg_host_register(ctx, W.HOST_BASE, hl, hvt.data_ptr(), hat.data_ptr())
+        X.shadow_alloc_batch(ctx, bases, sizes)
+        X.shadow_set_batch(ctx, bases, sizes, np.zeros(n0, np.uint8))
+        for b, v in vs.items():
+            for x in np.flatnonzero(v):
+                X.shadow_set(ctx, b + int(x), 1, int(v[x]))
+        live = dict(vs)
+        next_base = int(bases[-1] + sizes[-1]) + 4096
+        s = torch.cuda.current_stream().cuda_stream
+        pending = []
+        freed = []
+        for step in range(40):
+            nev = 1200 if step == 20 else int(rng.integers(0, 25))
+            for _ in range(nev):
+                if rng.random() < 0.5 and len(live) > 100:
+                    b = list(live)[int(rng.integers(0, len(live)))]
+                    X.shadow_free(ctx, b)
+                    freed.append(b)
+                    del live[b]
+                else:
+                    sz = int(rng.integers(16, 4096))
+                    X.shadow_alloc(ctx, next_base, sz)
+                    live[next_base] = np.full(sz, 0xFF, np.uint8)
+                    next_base += sz + 512
+            keys = list(live)
+            rows = []
+            for _ in range(64):
+                kind = int(rng.integers(0, 3))
+                if rng.random() < 0.1 and freed:
+                    b = freed[int(rng.integers(0, len(freed)))]
+                    L = 64
+                else:
+                    b = keys[int(rng.integers(0, len(keys)))]
+                    L = live[b].size
+                n = int(rng.integers(1, L + 1))
+                o = int(rng.integers(0, L - n + 1))
+                hp = W.HOST_BASE + int(rng.integers(0, hl - n))
+                dp = b + o
+                other = keys[int(rng.integers(0, len(keys)))]
+                src = hp if kind == 0 else dp
+                dst = hp if kind == 1 else (dp if kind == 0 else other)
+                rows.append((src, dst, n, kind, 0))
+            recs = np.array(rows, W.RECORD_DTYPE)
+            rt, out = H.records_tensor(recs), H.verdicts_tensor(len(recs))
+            mode = X.CG_CHECK | (X.CG_PLAIN if step % 7 == 3 else 0)
+            X.check_transfers(ctx, rt.data_ptr(), len(recs), out.data_ptr(), mode, s)
+            snap = {b: v.copy() for b, v in live.items()}
+            pending.append((recs, rt, out, snap))
+        torch.cuda.synchronize()
+        for i, (recs, rt, out, snap) in enumerate(pending):
+            bs = np.array(sorted(snap), np.uint64)
+            o = util.OracleState(W.HOST_BASE, hl, hv.copy(), ha, bs, np.array([snap[int(b)].size for b in bs], np.uint64),
+                                 [snap[int(b)] for b in bs])
+            util.assert_verdicts_equal(H.verdicts_np(out, len(recs)), o.run(recs), f"batch {i}")
+    finally:
+        X.cg_destroy(ctx)
