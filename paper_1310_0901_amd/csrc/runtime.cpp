@@ -1064,9 +1064,10 @@ struct Slot {
     std::vector<uint64_t> reqs;         // result indices of the batch
 };
 
-double footprint(const cg_transfer &r)
+// algorithmic shadow bytes of a request: V bytes plus, for a host side, its A bits
+uint64_t footprint(const cg_transfer &r)
 {
-    return (double)r.n * (r.kind == CG_D2D ? 1.0 : 1.125);
+    return r.kind == CG_D2D ? r.n : r.n + (r.n + 7) / 8;
 }
 
 void free_slots(std::vector<Slot> &slots)
@@ -1123,9 +1124,10 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
 
     std::deque<uint64_t> fifo;
     uint64_t next = 0, epoch = 0, batches = 0, nevents = 0, admitted = 0;
-    double inflight = 0, max_inflight = 0;
+    uint64_t inflight = 0, max_inflight = 0;   // exact integers: the loop waits for zero
     const uint64_t versions0 = c->versions_made;
     int rc = CG_OK;
+    double last_progress = 0;
     while (rc == CG_OK) {
         bool progress = false;
         const double t = now();
@@ -1144,7 +1146,7 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
                 res[sl.reqs[q]].v = sl.h_out[q];
                 res[sl.reqs[q]].t_done = ms / 1e3;
             }
-            inflight -= (double)sl.bytes;
+            inflight -= sl.bytes;
             sl.busy = false;
             progress = true;
         }
@@ -1173,12 +1175,13 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             Slot &sl = slots[k];
             if (sl.busy || ev[fifo.front()].type != CG_EV_CHECK) continue;
             sl.reqs.clear();
-            double bytes = 0;
+            uint64_t bytes = 0;
             while (!fifo.empty() && sl.reqs.size() < B) {
                 const cg_serve_event &e = ev[fifo.front()];
                 if (e.type != CG_EV_CHECK) break;
-                const double fp = footprint(e.rec);
-                if (inflight + bytes + fp > (double)cfg->mem_cap && inflight + bytes > 0) break;
+                const uint64_t fp = footprint(e.rec);
+                // admit while under the cap; a request alone in flight is always admitted
+                if (inflight + bytes + fp > cfg->mem_cap && inflight + bytes > 0) break;
                 const uint64_t r = ridx[fifo.front()];
                 sl.h_recs[sl.reqs.size()] = e.rec;
                 res[r].epoch = epoch;
@@ -1203,7 +1206,7 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);
             if (e1 != hipSuccess) { rc = hip_fail(c, "serve: verdict download", e1); break; }
             sl.busy = true;
-            sl.bytes = (uint64_t)bytes;
+            sl.bytes = bytes;
             inflight += bytes;
             max_inflight = std::max(max_inflight, inflight);
             admitted += cnt;
@@ -1214,7 +1217,17 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
         bool any_busy = false;
         for (auto &sl : slots) any_busy |= sl.busy;
         if (next == n && fifo.empty() && !any_busy) break;
-        if (!progress) std::this_thread::yield();
+        if (progress) {
+            last_progress = t;
+        } else {
+            // requests wait only for the next arrival or for a batch on the GPU
+            const bool waiting_arrival = fifo.empty() && next < n;
+            if (!waiting_arrival && t - last_progress > 120.0) {
+                rc = fail(c, CG_EHIP, "serve: no micro-batch finished for 120 s");
+                break;
+            }
+            std::this_thread::yield();
+        }
     }
     const double wall = now();
     if (rc) {
@@ -1227,7 +1240,7 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
         stats->requests = admitted;
         stats->batches = batches;
         stats->events = nevents;
-        stats->max_inflight_bytes = (uint64_t)max_inflight;
+        stats->max_inflight_bytes = max_inflight;
         stats->table_versions = c->versions_made - versions0;
         stats->mean_batch = batches ? (double)admitted / batches : 0;
     }
