@@ -93,6 +93,105 @@ def profiled_traffic(tuning, config):
     return int(prof["traffic_bytes"]), "bytes per launch, profiles/k_batched_batched-1M_traffic.md"
 
 
+TUNE_CACHE = os.environ.get("XC_TUNE_CACHE", os.path.join(ROOT, "paper_1310_0901_amd", "tuning_cache.jsonl"))
+
+
+def scan_ms(X, ctx):
+    ms, n = X.cg_kernel_ms(ctx)
+    return ms / max(n, 1)
+
+
+def plain_at_scale_leg():
+    """Configuration 2: 4,096 full-size host->device records, plain (one launch
+    per record) against batched, check-only and fused check + propagate."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd import workloads as W, xfercheck as X
+    from paper_1310_0901_amd.harness import DeviceWorld, records_tensor, verdicts_tensor, verdicts_np
+    w = W.config2()
+    dw = DeviceWorld(w)
+    try:
+        ctx, T, s = dw.ctx, w.count, torch.cuda.current_stream().cuda_stream
+        rt, ob, op = records_tensor(w.records), verdicts_tensor(T), verdicts_tensor(T)
+        b = algo_bytes(w.records)
+        tun = {m: X.cg_autotune(ctx, rt.data_ptr(), T, ob.data_ptr(), m, s, TUNE_CACHE).as_dict()
+               for m in (X.CG_CHECK, X.CG_CHECK | X.CG_PROPAGATE)}
+        X.cg_timing(ctx, True)
+        out = {"workload": f"{w.name} (configuration 2): {w.note}, 4 GiB host region, "
+                           f"{int(w.records['n'].sum()) / 1e9:.1f} GB of transfers", "algorithmic_bytes": int(b)}
+        for name, mode, buf in (("batched", X.CG_CHECK, ob), ("plain", X.CG_CHECK | X.CG_PLAIN, op)):
+            X.check_transfers(ctx, rt.data_ptr(), T, buf.data_ptr(), mode, s)   # warm-up
+            torch.cuda.synchronize()
+            X.cg_kernel_ms(ctx)
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                X.check_transfers(ctx, rt.data_ptr(), T, buf.data_ptr(), mode, s)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            k = scan_ms(X, ctx)
+            out[name] = {"ms": round(wall * 1e3, 3), "GBps": round(b / wall / 1e9, 1),
+                         "scan_ms": round(k, 3), "scan_GBps": round(b / (k / 1e3) / 1e9, 1),
+                         "launches_per_step": 1 if name == "batched" else int((w.records["n"] > 0).sum())}
+        same = all(np.array_equal(verdicts_np(ob, T)[f], verdicts_np(op, T)[f])
+                   for f in ("flags", "first_bad", "undef_bytes", "avail"))
+        out["verdicts_identical"] = bool(same)
+        # fused check + propagate (every record writes its own allocation)
+        X.cg_kernel_ms(ctx)
+        X.check_transfers(ctx, rt.data_ptr(), T, ob.data_ptr(), X.CG_CHECK | X.CG_PROPAGATE, s)
+        torch.cuda.synchronize()
+        k = scan_ms(X, ctx)
+        bp = algo_bytes(w.records, propagate=True)
+        out["batched_check_propagate"] = {"scan_ms": round(k, 3), "GBps": round(bp / (k / 1e3) / 1e9, 1),
+                                          "algorithmic_bytes": int(bp)}
+        out["tuning"] = {"check": tun[X.CG_CHECK], "check_propagate": tun[X.CG_CHECK | X.CG_PROPAGATE]}
+    finally:
+        dw.close()
+    log(f"[bench] plain at scale: {out}")
+    return out
+
+
+def propagation_leg():
+    """Configuration 4: 2 GiB of 16-byte records with padding, H2D then four
+    D2D hops, fused check + propagate, one batch per hop; verified against the
+    closed form and the final shadow against host V on the device."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd import workloads as W, xfercheck as X
+    from paper_1310_0901_amd.harness import DeviceWorld, records_tensor, verdicts_tensor, verdicts_np, device_view
+    res = {}
+    for pieces in (1, 4096):
+        w = W.config4(pieces=pieces)
+        dw = DeviceWorld(w)
+        try:
+            ctx, s = dw.ctx, torch.cuda.current_stream().cuda_stream
+            st0 = w.stages[0]
+            rt0, out0 = records_tensor(st0), verdicts_tensor(st0.size)
+            tun = X.cg_autotune(ctx, rt0.data_ptr(), st0.size, out0.data_ptr(), X.CG_CHECK | X.CG_PROPAGATE, s,
+                                TUNE_CACHE).as_dict()
+            X.cg_timing(ctx, True)
+            stages, ok = [], True
+            for h, st in enumerate(w.stages):
+                rt, out = records_tensor(st), verdicts_tensor(st.size)
+                X.cg_kernel_ms(ctx)
+                X.check_transfers(ctx, rt.data_ptr(), st.size, out.data_ptr(), X.CG_CHECK | X.CG_PROPAGATE, s)
+                torch.cuda.synchronize()
+                k = scan_ms(X, ctx)
+                v = verdicts_np(out, st.size)
+                ok &= int(v["undef_bytes"].sum()) == 3 * w.R + w.P
+                b = algo_bytes(st, propagate=True)
+                stages.append({"hop": h, "scan_ms": round(k, 3), "GBps": round(b / (k / 1e3) / 1e9, 1)})
+            last = w.dev.live_idx[-1]
+            dv = device_view(X.shadow_ptr(ctx, int(w.dev.base[last])), w.host.length)
+            ok &= bool(torch.equal(dv, dw.hv[: w.host.length]))
+            res[f"pieces_{pieces}"] = {"stages": stages, "closed_form_and_final_shadow_ok": bool(ok), "tuning": tun}
+        finally:
+            dw.close()
+    log(f"[bench] propagation: {res}")
+    return {"workload": "partial-definedness (configuration 4): 2 GiB of 16-byte records, 3 padding bytes each, "
+                        "1 % single payload bits; H2D then 4 D2D hops with propagation", **res}
+
+
 def serving_leg(plain_seconds):
     """Configuration 5: continuous batching vs the plain path on one event log."""
     import numpy as np
@@ -145,6 +244,8 @@ def main():
     ap.add_argument("--cpu-bytes", type=float, default=12e9)
     ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg (configuration 5)")
     ap.add_argument("--plain-serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="skip the plain-at-scale and propagation legs (configurations 2 and 4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
@@ -176,9 +277,8 @@ def main():
 
     tuned = None
     if args.autotune:
-        cache = os.environ.get("XC_TUNE_CACHE", os.path.join(ROOT, "paper_1310_0901_amd", "tuning_cache.jsonl"))
         t0 = time.perf_counter()
-        tuned = X.cg_autotune(ctx, recs_t.data_ptr(), T, out_t.data_ptr(), X.CG_CHECK, stream, cache).as_dict()
+        tuned = X.cg_autotune(ctx, recs_t.data_ptr(), T, out_t.data_ptr(), X.CG_CHECK, stream, TUNE_CACHE).as_dict()
         log(f"[bench] autotune {time.perf_counter() - t0:.1f} s -> {tuned}")
     tun = X.cg_get_tuning(ctx).as_dict()
 
@@ -266,6 +366,9 @@ def main():
                                   "sample": text, "verdicts_identical_to_gpu": bool(same)}
         log(f"[bench] oracle sample {gbs:.2f} GB/s on {threads} threads, identical: {same}")
     dw.close()
+    if args.legs:
+        result["plain_at_scale"] = plain_at_scale_leg()
+        result["propagation"] = propagation_leg()
     if args.serve:
         result["serving"] = serving_leg(args.plain_serve_seconds)
     print(json.dumps(result), flush=True)

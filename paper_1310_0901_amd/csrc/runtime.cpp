@@ -142,7 +142,8 @@ struct cg_ctx {
     // ordering
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
-    cg_tuning tuning{};
+    cg_tuning tuning{};        // check-only launch shape
+    cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
     // timing
     bool timing = false;
     std::vector<TimingPair> tpairs;   // pairs of the last check
@@ -427,6 +428,35 @@ hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_
 
 int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part);
 
+// The cached graph of this batched check (keyed by table version, buffers,
+// count, mode and launch shape), captured on first use.
+int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const LaunchShape &sh, const cg_tuning &tun, bool split,
+               hipStream_t s, GraphEntry **out)
+{
+    const uint32_t mode = a.mode & 3u;
+    for (auto &g : w->graphs)
+        if (g.st == a.st && g.recs == a.recs && g.count == a.count && g.mode == mode && same_tuning(g.tun, tun) &&
+            g.split == split && g.out == a.out) {
+            *out = &g;
+            return CG_OK;
+        }
+    if (w->graphs.size() >= kGraphsPerWs) {
+        HIPTRY(c, hipStreamSynchronize(s));
+        destroy_graph(w->graphs.front());
+        w->graphs.erase(w->graphs.begin());
+    }
+    GraphEntry g{a.st, a.recs, a.out, a.count, mode, tun, split, nullptr, nullptr, nullptr, nullptr};
+    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0);
+    if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2);
+    if (rc) {
+        destroy_graph(g);
+        return rc;
+    }
+    w->graphs.push_back(g);
+    *out = &w->graphs.back();
+    return CG_OK;
+}
+
 TimingPair *next_pair(cg_ctx *c)
 {
     if (c->tused == c->tpairs.size()) {
@@ -549,23 +579,8 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     } else {
         const bool split = c->timing;
         GraphEntry *ge = nullptr;
-        for (auto &g : w->graphs)
-            if (g.st == a.st && g.recs == recs && g.out == out && g.count == count && g.mode == (mode & 3u) &&
-                same_tuning(g.tun, tun) && g.split == split)
-                ge = &g;
-        if (!ge) {
-            if (w->graphs.size() >= kGraphsPerWs) {
-                HIPTRY(c, hipStreamSynchronize(s));
-                destroy_graph(w->graphs.front());
-                w->graphs.erase(w->graphs.begin());
-            }
-            GraphEntry g{a.st, recs, out, count, mode & 3u, tun, split, nullptr, nullptr, nullptr, nullptr};
-            rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0);
-            if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2);
-            if (rc) { destroy_graph(g); return rc; }
-            w->graphs.push_back(g);
-            ge = &w->graphs.back();
-        }
+        rc = find_graph(c, w, a, sh, tun, split, s, &ge);
+        if (rc) return rc;
         if (split) {
             TimingPair *tp = next_pair(c);
             HIPTRY(c, hipGraphLaunch(ge->exec, s));
@@ -699,6 +714,8 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_BLOCKS_PER_CU")) c->tuning.blocks_per_cu = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
+    c->tuning_prop = c->tuning;
+    c->tuning_prop.unroll = 2;
     // an empty table and region, so that checks before any allocation work
     if (materialize(c) != CG_OK) return bail(CG_EHIP);
     if (hipStreamSynchronize(c->s) != hipSuccess) return bail(CG_EHIP);
@@ -881,7 +898,8 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
     if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
     if (count >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 records per call");
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
-    return run_check(c, recs_dev, count, out_dev, mode, (hipStream_t)hip_stream, c->tuning);
+    return run_check(c, recs_dev, count, out_dev, mode, (hipStream_t)hip_stream,
+                     (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
 }
 
 int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)
@@ -916,6 +934,7 @@ int cg_set_tuning(cg_ctx *c, const cg_tuning *t)
     if (!c || !t) return CG_EINVAL;
     if (!valid_tuning(*t)) return fail(c, CG_EINVAL, "tuning out of range");
     c->tuning = *t;
+    c->tuning_prop = *t;
     return CG_OK;
 }
 
@@ -950,11 +969,12 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     hipStream_t s = (hipStream_t)hip_stream;
     mode &= (CG_CHECK | CG_PROPAGATE);
     if (!mode) return CG_EINVAL;
+    cg_tuning &target = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
     // workload signature: count and log2 of the total units, from a first run
     const bool was_timing = c->timing;
     c->timing = true;
     c->tused = 0;
-    int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, c->tuning);
+    int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, target);
     if (rc) { c->timing = was_timing; return rc; }
     HIPTRY(c, hipStreamSynchronize(s));
     c->tused = 0;
@@ -969,11 +989,11 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
         std::string line;
         while (std::getline(in, line)) {
             if (line.find("\"key\": \"" + key.str() + "\"") == std::string::npos) continue;
-            cg_tuning t = c->tuning;
+            cg_tuning t = target;
             if (parse_field(line, "block", &t.block) && parse_field(line, "unroll", &t.unroll) &&
                 parse_field(line, "blocks_per_cu", &t.blocks_per_cu) && parse_field(line, "tile_units", &t.tile_units) &&
                 parse_field(line, "nontemporal", &t.nontemporal) && valid_tuning(t)) {
-                c->tuning = t;
+                target = t;
                 c->timing = was_timing;
                 if (best) *best = t;
                 return CG_OK;
@@ -994,7 +1014,7 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
         *ms = sum / 2;
         return CG_OK;
     };
-    cg_tuning cur = c->tuning;
+    cg_tuning cur = target;
     double cur_ms;
     rc = measure(cur, &cur_ms);
     if (rc) { c->timing = was_timing; return rc; }
@@ -1025,7 +1045,7 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     }
     c->timing = was_timing;
     if (rc) return rc;
-    c->tuning = cur;
+    target = cur;
     if (best) *best = cur;
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
@@ -1085,6 +1105,24 @@ void free_slots(std::vector<Slot> &slots)
 
 }  // namespace
 
+// Before the clock starts: the slot's workspace and one captured graph per
+// table version of the ring, so that no allocation or capture happens while
+// requests wait.
+int prewarm(cg_ctx *c, hipStream_t s, const cg_transfer *recs, uint64_t count, cg_verdict *out, const cg_tuning &tun)
+{
+    Workspace *w;
+    int rc = get_ws(c, s, count, &w);
+    if (rc) return rc;
+    const LaunchShape sh = shape_of(c, tun);
+    for (int v = 0; v < kVersions && !rc; ++v) {
+        BatchArgs a = make_args(c, w, recs, count, out, CG_CHECK);
+        a.st = c->ver[v].st;
+        GraphEntry *ge;
+        rc = find_graph(c, w, a, sh, tun, false, s, &ge);
+    }
+    return rc;
+}
+
 extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, const cg_serve_config *cfg,
                             cg_serve_result *res, cg_serve_stats *stats)
 {
@@ -1109,6 +1147,16 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             return bail(fail(c, CG_ENOMEM, "serve: slot buffers"));
         for (uint32_t k = 0; k < B; ++k) sl.h_recs[k] = cg_transfer{0, 0, 0, 0xFFFFFFFFu, 0};
         sl.filled = B;
+    }
+    {
+        // the table as it stands now, and the code of every kernel the loop
+        // launches, are on the device before the clock starts
+        int rc0 = materialize(c);
+        if (!rc0 && launch_merge_warm(c->s) != hipSuccess) rc0 = fail(c, CG_EHIP, "serve: warm-up launch");
+        for (auto &sl : slots)
+            if (!rc0 && !cfg->plain) rc0 = prewarm(c, sl.s, sl.d_recs, B, sl.d_out, tun);
+        if (!rc0 && hipStreamSynchronize(c->s) != hipSuccess) rc0 = fail(c, CG_EHIP, "serve: warm-up sync");
+        if (rc0) return bail(rc0);
     }
     // result index of every check event
     std::vector<uint64_t> ridx(n);

@@ -133,4 +133,11 @@ hipError_t launch_merge(const MergeArgs &m, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_merge_warm(hipStream_t s)
+{
+    MergeArgs m{};
+    hipLaunchKernelGGL(k_merge_top, dim3(1), dim3(kB), 0, s, m);   // ntop = 0: loads the code only
+    return hipGetLastError();
+}
+
 }  // namespace xc

@@ -123,6 +123,7 @@ struct MergeArgs {
     uint64_t *bsum, *boff;
 };
 hipError_t launch_merge(const MergeArgs &m, hipStream_t s);
+hipError_t launch_merge_warm(hipStream_t s);
 
 // kernel launchers (kernels.hip); all asynchronous on `s`
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
