@@ -405,7 +405,10 @@ __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64
                         acc_min(acc, i0db + 16 * cr + __builtin_ctz(ud));
                     }
                 }
-                if (prop) {
+                if (prop && d.s == 0) {
+                    // source and destination chunks coincide (equal phases)
+                    if (wm) store_masked(d.dst_sh + (uint64_t)(16 * eb) + (uint32_t)(16 * cr), prop_val(v[j], ok[j]), wm);
+                } else if (prop) {
                     const u32x4 own = prop_val(v[j], ok[j]);
                     u32x4 nxt;
                     nxt.x = __shfl_down(own.x, 1);
