@@ -101,6 +101,40 @@ def scan_ms(X, ctx):
     return ms / max(n, 1)
 
 
+def plain_tiny_leg():
+    """Configuration 1: 64 host->device records on a 1 MiB region; launch-bound,
+    so the figure is latency per call (median of 50 synchronous calls)."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd import workloads as W, xfercheck as X
+    from paper_1310_0901_amd.harness import DeviceWorld, records_tensor, verdicts_tensor, verdicts_np
+    w = W.config1()
+    dw = DeviceWorld(w)
+    out = {"workload": f"{w.name} (configuration 1): {w.note}"}
+    try:
+        ctx, T, s = dw.ctx, w.count, torch.cuda.current_stream().cuda_stream
+        rt, ob = records_tensor(w.records), verdicts_tensor(T)
+        res = {}
+        for name, mode in (("batched_graph", X.CG_CHECK), ("batched_eager", X.CG_CHECK | X.CG_EAGER),
+                           ("plain", X.CG_CHECK | X.CG_PLAIN)):
+            ts = []
+            for i in range(55):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                X.check_transfers(ctx, rt.data_ptr(), T, ob.data_ptr(), mode, s)
+                torch.cuda.synchronize()
+                if i >= 5:
+                    ts.append(time.perf_counter() - t0)
+            res[name] = verdicts_np(ob, T)
+            out[name] = {"median_us_per_call": round(float(np.median(ts)) * 1e6, 1)}
+        out["verdicts_identical"] = bool(all(np.array_equal(res["plain"][f], res["batched_graph"][f])
+                                             for f in ("flags", "first_bad", "undef_bytes", "avail")))
+    finally:
+        dw.close()
+    log(f"[bench] plain tiny: {out}")
+    return out
+
+
 def plain_at_scale_leg():
     """Configuration 2: 4,096 full-size host->device records, plain (one launch
     per record) against batched, check-only and fused check + propagate."""
@@ -367,6 +401,7 @@ def main():
         log(f"[bench] oracle sample {gbs:.2f} GB/s on {threads} threads, identical: {same}")
     dw.close()
     if args.legs:
+        result["plain_tiny"] = plain_tiny_leg()
         result["plain_at_scale"] = plain_at_scale_leg()
         result["propagation"] = propagation_leg()
     if args.serve:
