@@ -759,10 +759,12 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
     const Region R = a.st->region;
     Acc acc;
     acc_reset(acc);
+    // first tile: the wave's own index (no atomic, so that the waves of a
+    // small batch leave at once); later tiles from the device counter
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    uint64_t jn = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     for (;;) {
-        uint32_t j = 0;
-        if (lane == 0) j = atomicAdd(&a.ctl->counter, 1u);
-        j = ufl32(__shfl(j, 0));
+        const uint64_t j = ufl64(jn);
         if (j >= ntiles) break;
         uint64_t u = (uint64_t)j * tu;
         const uint64_t u_end = (u + tu < total) ? u + tu : total;
@@ -802,6 +804,9 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
             }
             u = g_end;
         }
+        uint32_t nx = 0;
+        if (lane == 0) nx = atomicAdd(&a.ctl->counter, 1u);
+        jn = (uint64_t)waves + ufl32(__shfl(nx, 0));
     }
 }
 
