@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
 // ---------------------------------------------------------------------------
 // k_scan_sums: one block, exclusive scan of the classify-block sums
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_units)
+__global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_units, uint32_t waves)
 {
     __shared__ uint64_t wsum[16];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
@@ -720,7 +720,10 @@ __global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_u
     }
     if (tid == 1023) {
         const uint64_t total = off + x;
+        // tiles of at most tile_units, small enough that every wave of the
+        // persistent grid gets a few of them, and few enough to fit tile_start
         uint64_t tu = tile_units;
+        while (tu > kMinTile && (total + tu - 1) / tu < 4ull * waves) tu >>= 1;
         while ((total + tu - 1) / tu > a.tiles_cap) tu <<= 1;
         a.ctl->total_units = total;
         a.ctl->tile_units = tu;
@@ -889,9 +892,9 @@ hipError_t launch_classify(const BatchArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, hipStream_t s)
+hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, a, tile_units);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, a, tile_units, waves);
     return hipGetLastError();
 }
 

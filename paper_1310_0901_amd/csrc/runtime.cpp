@@ -412,7 +412,7 @@ hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_
 {
     hipError_t e;
     if ((e = launch_classify(a, s)) != hipSuccess) return e;
-    if ((e = launch_scan_sums(a, sh.tile_units, s)) != hipSuccess) return e;
+    if ((e = launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s)) != hipSuccess) return e;
     return launch_prefix_tiles(a, s);
 }
 

@@ -81,6 +81,7 @@ struct FillRange {
 };
 
 constexpr int kMaxTop = 1024;        // LDS-staged top level of the table
+constexpr uint64_t kMinTile = 1024;  // smallest work tile, in 16-byte units
 constexpr int kClassifyBlock = 256;  // records per classify block
 constexpr uint64_t kScanLimit = 1ull << 62;  // byte indices scanned per record
 
@@ -127,7 +128,7 @@ hipError_t launch_merge_warm(hipStream_t s);
 
 // kernel launchers (kernels.hip); all asynchronous on `s`
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
-hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, hipStream_t s);
+hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s);
 hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);
 hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s);
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
