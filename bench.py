@@ -208,13 +208,19 @@ def propagation_leg():
             for h, st in enumerate(w.stages):
                 rt, out = records_tensor(st), verdicts_tensor(st.size)
                 X.cg_kernel_ms(ctx)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
                 X.check_transfers(ctx, rt.data_ptr(), st.size, out.data_ptr(), X.CG_CHECK | X.CG_PROPAGATE, s)
+                e1.record()
                 torch.cuda.synchronize()
                 k = scan_ms(X, ctx)
+                whole = e0.elapsed_time(e1)
                 v = verdicts_np(out, st.size)
                 ok &= int(v["undef_bytes"].sum()) == 3 * w.R + w.P
                 b = algo_bytes(st, propagate=True)
-                stages.append({"hop": h, "scan_ms": round(k, 3), "GBps": round(b / (k / 1e3) / 1e9, 1)})
+                stages.append({"hop": h, "scan_ms": round(k, 3), "GBps": round(b / (k / 1e3) / 1e9, 1),
+                               "whole_check_ms": round(whole, 3)})
             last = w.dev.live_idx[-1]
             dv = device_view(X.shadow_ptr(ctx, int(w.dev.base[last])), w.host.length)
             ok &= bool(torch.equal(dv, dw.hv[: w.host.length]))

@@ -13,7 +13,7 @@
 //                  range-derived verdict fields, scan descriptor, work weight,
 //                  block-local exclusive scan of the weights;
 //   k_scan_sums    one block: exclusive scan of the per-block sums, tile size;
-//   k_prefix_tiles global prefix and first record of every work tile;
+//   k_prefix_tiles global prefix; k_tile_starts first record of every tile;
 //   k_batched      persistent kernel: tiles of the flattened 16-byte unit space
 //                  taken from a device counter; 16-byte V loads and aligned
 //                  16-bit A loads, SWAR non-zero masks, popcount / ctz for the
@@ -734,18 +734,30 @@ __global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_u
 }
 
 // ---------------------------------------------------------------------------
-// k_prefix_tiles: global prefix and the first record of every tile
+// k_prefix_tiles: global prefix; k_tile_starts: first record of every tile
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_prefix_tiles(BatchArgs a)
 {
     const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= a.count) return;
-    const uint64_t p = a.local[t] + a.boff[t / kClassifyBlock];
-    a.prefix[t] = p;
-    const uint64_t w = a.weight[t] ? a.weight[t] : 1;
-    const uint64_t tu = a.ctl->tile_units;
-    const uint64_t j0 = (p + tu - 1) / tu, j1 = (p + w + tu - 1) / tu;
-    for (uint64_t j = j0; j < j1; ++j) a.tile_start[j] = (uint32_t)t;
+    a.prefix[t] = a.local[t] + a.boff[t / kClassifyBlock];
+}
+
+// One lane per tile (grid-stride): the last record whose prefix is at or
+// below the tile's first unit (prefixes strictly increase: weights >= 1).
+__global__ void __launch_bounds__(256) k_tile_starts(BatchArgs a)
+{
+    const uint64_t ntiles = a.ctl->ntiles, tu = a.ctl->tile_units;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ntiles; j += stride) {
+        const uint64_t u = j * tu;
+        uint64_t lo = 0, hi = a.count - 1;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) >> 1;
+            if (a.prefix[mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        a.tile_start[j] = (uint32_t)lo;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -902,6 +914,7 @@ hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s)
 {
     const uint64_t blocks = (a.count + 255) / 256;
     hipLaunchKernelGGL(k_prefix_tiles, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tile_starts, dim3(1024), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
