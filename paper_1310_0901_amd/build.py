@@ -16,6 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libxfercheck.so")
+PRELOAD = os.path.join(HERE, "libxfercheck_preload.so")
+EXAMPLE_SRC = os.path.join(ROOT, "tests", "native", "worked_example.hip")
+EXAMPLE = os.path.join(ROOT, "tests", "native", "worked_example")
 ARCH = os.environ.get("XC_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -44,6 +47,14 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run(["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    # the HIP API interposer (LD_PRELOAD), linked against the library
+    tmp = PRELOAD + ".tmp"
+    _run(["hipcc", *HIP_FLAGS, "-x", "hip", "-shared", "-o", tmp, os.path.join(CSRC, "interpose.cpp"),
+          f"-L{HERE}", "-lxfercheck", "-Wl,-rpath,$ORIGIN", "-ldl"])
+    os.replace(tmp, PRELOAD)
+    # the paper's example program, run under the interposer by the tests
+    _run(["hipcc", "-O2", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-o", EXAMPLE, EXAMPLE_SRC])
     if verbose:
         print("built", LIB)
     return LIB

@@ -1,0 +1,281 @@
+// HIP API interposer: the wrapper deployment of the method, for HIP programs.
+//
+// The paper places its wrappers around the driver API's allocation, free and
+// copy functions (Sec. 1.2, Sec. 2, Fig. 1) and loads them before the driver
+// library (Sec. 3), so that every copy is checked against the context's list
+// of allocations before it runs and a report names the bytes the copy needs
+// and the bytes the allocation holds (Sec. 4.5, Listing 6).  Here the same
+// wrappers sit around hipMalloc / hipFree / hipMemset / hipMemcpy*, loaded
+// with LD_PRELOAD, and feed the transfer checker (xfercheck.h):
+//   hipMalloc  -> shadow_alloc (new memory is not defined yet)
+//   hipFree    -> shadow_free
+//   hipMemset  -> shadow_set(0) (the bytes become defined)
+//   hipMemcpy  -> check_transfers on one record, report, then the real copy;
+//                 host->device and device->device copies also carry the V
+//                 bits into the destination shadow.
+// The host program itself is not instrumented, so host bytes of a copy count
+// as addressable and defined.  Kernels are not instrumented either (the
+// paper's outlook, Sec. 5.1), so undefined-source notes for device sources
+// are off unless XC_REPORT_DEVICE_UNDEF=1.
+//
+// A copy whose device side is unallocated or too small is not performed (the
+// call returns hipErrorInvalidValue, as the driver in the paper's example
+// fails the call with an invalid-argument error), unless XC_ALLOW_BAD=1.
+//
+// Environment: XC_POOL_BYTES (shadow pool, default 1 GiB), XC_MAX_ALLOCS
+// (default 1,048,576), XC_REPORT_DEVICE_UNDEF, XC_ALLOW_BAD, XC_QUIET=1 (no
+// summary line).
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/xfercheck.h"
+
+namespace {
+
+thread_local int inside = 0;   // > 0 while the checker itself calls HIP
+
+struct Guard {
+    Guard() { ++inside; }
+    ~Guard() { --inside; }
+};
+
+template <typename F>
+F real(const char *name)
+{
+    return reinterpret_cast<F>(dlsym(RTLD_NEXT, name));
+}
+
+using malloc_t = hipError_t (*)(void **, size_t);
+using free_t = hipError_t (*)(void *);
+using memset_t = hipError_t (*)(void *, int, size_t);
+using memcpy_t = hipError_t (*)(void *, const void *, size_t, hipMemcpyKind);
+using htod_t = hipError_t (*)(hipDeviceptr_t, const void *, size_t);
+using dtoh_t = hipError_t (*)(void *, hipDeviceptr_t, size_t);
+using dtod_t = hipError_t (*)(hipDeviceptr_t, hipDeviceptr_t, size_t);
+
+struct State {
+    std::mutex mu;
+    cg_ctx *ctx = nullptr;
+    bool failed = false;
+    hipStream_t s = nullptr;
+    cg_transfer *d_rec = nullptr;
+    cg_verdict *d_ver = nullptr;
+    uint8_t *zeros = nullptr;     // V of "defined" host bytes
+    uint64_t *ones = nullptr;     // A of "addressable" host bytes
+    uint64_t cap = 0;             // bytes covered by zeros / ones
+    bool device_undef = false;
+    bool allow_bad = false;
+    bool quiet = false;
+    uint64_t copies = 0, errors = 0;
+} G;
+
+uint64_t env_u64(const char *k, uint64_t d)
+{
+    const char *v = getenv(k);
+    return v ? strtoull(v, nullptr, 0) : d;
+}
+
+void summary()
+{
+    if (G.ctx && !G.quiet)
+        fprintf(stderr, "==xfercheck== %" PRIu64 " copies checked, %" PRIu64 " with errors\n", G.copies, G.errors);
+}
+
+bool ensure_ctx()
+{
+    if (G.ctx) return true;
+    if (G.failed) return false;
+    Guard g;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const uint64_t pool = env_u64("XC_POOL_BYTES", 1ull << 30);
+    const uint64_t maxa = env_u64("XC_MAX_ALLOCS", 1ull << 20);
+    int rc = cg_create(&G.ctx, dev, pool, maxa);
+    if (rc == CG_OK && hipStreamCreateWithFlags(&G.s, hipStreamNonBlocking) != hipSuccess) rc = CG_EHIP;
+    if (rc == CG_OK && hipMalloc(reinterpret_cast<void **>(&G.d_rec), sizeof(cg_transfer)) != hipSuccess) rc = CG_ENOMEM;
+    if (rc == CG_OK && hipMalloc(reinterpret_cast<void **>(&G.d_ver), sizeof(cg_verdict)) != hipSuccess) rc = CG_ENOMEM;
+    if (rc != CG_OK) {
+        fprintf(stderr, "==xfercheck== cannot start the checker: %s\n", cg_strerror(rc));
+        G.failed = true;
+        G.ctx = nullptr;
+        return false;
+    }
+    G.device_undef = env_u64("XC_REPORT_DEVICE_UNDEF", 0) != 0;
+    G.allow_bad = env_u64("XC_ALLOW_BAD", 0) != 0;
+    G.quiet = env_u64("XC_QUIET", 0) != 0;
+    atexit(summary);
+    return true;
+}
+
+// zeros / ones buffers covering at least n host bytes
+bool ensure_host_cover(uint64_t n)
+{
+    if (n <= G.cap) return true;
+    Guard g;
+    uint64_t cap = G.cap ? G.cap : (1ull << 20);
+    while (cap < n) cap <<= 1;
+    (void)hipStreamSynchronize(G.s);
+    (void)hipFree(G.zeros);
+    (void)hipFree(G.ones);
+    G.zeros = nullptr;
+    G.ones = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&G.zeros), cap + 16) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&G.ones), cap / 8 + 8) != hipSuccess ||
+        hipMemsetAsync(G.zeros, 0, cap + 16, G.s) != hipSuccess ||
+        hipMemsetAsync(G.ones, 0xFF, cap / 8 + 8, G.s) != hipSuccess ||
+        hipStreamSynchronize(G.s) != hipSuccess) {
+        G.cap = 0;
+        return false;
+    }
+    G.cap = cap;
+    return true;
+}
+
+const char *kind_name(uint32_t k)
+{
+    return k == CG_H2D ? "hipMemcpyHostToDevice" : k == CG_D2H ? "hipMemcpyDeviceToHost" : "hipMemcpyDeviceToDevice";
+}
+
+constexpr uint32_t kRangeFaults = CG_SRC_UNALLOC | CG_SRC_OVERRUN | CG_DST_UNALLOC | CG_DST_OVERRUN;
+
+// Check one copy before it runs and print the report; false if the copy must
+// not be performed (its device side is unallocated or too small).
+bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t kind)
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return true;
+    Guard g;
+    cg_transfer r{(uint64_t)src, (uint64_t)dst, (uint64_t)n, kind, 0};
+    uint32_t mode = CG_CHECK;
+    if (kind != CG_D2D) {
+        const uint64_t hp = kind == CG_H2D ? r.src : r.dst;
+        if (!ensure_host_cover(n) || cg_host_register(G.ctx, hp, n ? n : 1, G.zeros, G.ones) != CG_OK) return true;
+    }
+    if (kind != CG_D2H) mode |= CG_PROPAGATE;   // the zeros buffer must stay zero
+    cg_verdict v{};
+    if (hipMemcpyAsync(G.d_rec, &r, sizeof r, hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_transfers(G.ctx, G.d_rec, 1, G.d_ver, mode, G.s) != CG_OK ||
+        hipMemcpyAsync(&v, G.d_ver, sizeof v, hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+        hipStreamSynchronize(G.s) != hipSuccess) {
+        fprintf(stderr, "==xfercheck== check failed: %s\n", cg_last_error(G.ctx));
+        return true;
+    }
+    ++G.copies;
+    if (!G.device_undef && kind != CG_H2D) v.flags &= ~CG_SRC_UNDEF;
+    if (!v.flags) return true;
+    char buf[1024];
+    cg_format_verdict(&r, &v, buf, sizeof buf);
+    ++G.errors;
+    fprintf(stderr, "%s\n at %s(dst=%p, src=%p, %zu bytes, %s)\n", buf, api, dst, src, n, kind_name(kind));
+    return G.allow_bad || !(v.flags & kRangeFaults);
+}
+
+uint32_t direction(void *dst, const void *src, hipMemcpyKind k)
+{
+    switch (k) {
+    case hipMemcpyHostToDevice: return CG_H2D;
+    case hipMemcpyDeviceToHost: return CG_D2H;
+    case hipMemcpyDeviceToDevice: return CG_D2D;
+    case hipMemcpyDefault: {
+        Guard g;
+        hipPointerAttribute_t a, b;
+        const bool dd = hipPointerGetAttributes(&a, dst) == hipSuccess && a.type == hipMemoryTypeDevice;
+        const bool sd = hipPointerGetAttributes(&b, src) == hipSuccess && b.type == hipMemoryTypeDevice;
+        (void)hipGetLastError();
+        if (sd && dd) return CG_D2D;
+        if (dd) return CG_H2D;
+        if (sd) return CG_D2H;
+        return 99;
+    }
+    default: return 99;   // host->host: not a device transfer
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+hipError_t hipMalloc(void **ptr, size_t size)
+{
+    static malloc_t f = real<malloc_t>("hipMalloc");
+    const hipError_t e = f(ptr, size);
+    if (inside || e != hipSuccess || !ptr || !*ptr || size == 0) return e;
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return e;
+    Guard g;
+    const int rc = shadow_alloc(G.ctx, (uint64_t)*ptr, size);
+    if (rc != CG_OK) fprintf(stderr, "==xfercheck== hipMalloc(%zu) at %p not tracked: %s\n", size, *ptr, cg_strerror(rc));
+    return e;
+}
+
+hipError_t hipFree(void *ptr)
+{
+    static free_t f = real<free_t>("hipFree");
+    if (!inside && ptr) {
+        std::lock_guard<std::mutex> lk(G.mu);
+        if (ensure_ctx()) {
+            Guard g;
+            if (shadow_free(G.ctx, (uint64_t)ptr) != CG_OK) {
+                ++G.errors;
+                fprintf(stderr, "Error: hipFree of %p, which is not the start of an allocated device region.\n", ptr);
+            }
+        }
+    }
+    return f(ptr);
+}
+
+hipError_t hipMemset(void *dst, int value, size_t n)
+{
+    static memset_t f = real<memset_t>("hipMemset");
+    if (!inside && n) {
+        std::lock_guard<std::mutex> lk(G.mu);
+        if (ensure_ctx()) {
+            Guard g;
+            if (shadow_set(G.ctx, (uint64_t)dst, n, 0) != CG_OK) {
+                ++G.errors;
+                fprintf(stderr, "Error: hipMemset of %zu bytes at %p leaves allocated device memory.\n", n, dst);
+                if (!G.allow_bad) return hipErrorInvalidValue;
+            }
+        }
+    }
+    return f(dst, value, n);
+}
+
+hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind kind)
+{
+    static memcpy_t f = real<memcpy_t>("hipMemcpy");
+    if (!inside && n) {
+        const uint32_t d = direction(dst, src, kind);
+        if (d <= CG_D2D && !check_copy("hipMemcpy", dst, src, n, d)) return hipErrorInvalidValue;
+    }
+    return f(dst, src, n, kind);
+}
+
+hipError_t hipMemcpyHtoD(hipDeviceptr_t dst, const void *src, size_t n)
+{
+    static htod_t f = real<htod_t>("hipMemcpyHtoD");
+    if (!inside && n && !check_copy("hipMemcpyHtoD", dst, src, n, CG_H2D)) return hipErrorInvalidValue;
+    return f(dst, src, n);
+}
+
+hipError_t hipMemcpyDtoH(void *dst, hipDeviceptr_t src, size_t n)
+{
+    static dtoh_t f = real<dtoh_t>("hipMemcpyDtoH");
+    if (!inside && n && !check_copy("hipMemcpyDtoH", dst, src, n, CG_D2H)) return hipErrorInvalidValue;
+    return f(dst, src, n);
+}
+
+hipError_t hipMemcpyDtoD(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n)
+{
+    static dtod_t f = real<dtod_t>("hipMemcpyDtoD");
+    if (!inside && n && !check_copy("hipMemcpyDtoD", dst, src, n, CG_D2D)) return hipErrorInvalidValue;
+    return f(dst, src, n);
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// The program of the paper's usage example (Sec. 4, Listing 2), in HIP: the
+// result vector c is allocated for 1,000,000 floats but copied back as
+// 1,000,000 doubles.  The kernel here writes only the elements that fit, so
+// the program itself never touches memory outside its allocations; the copy
+// back is what the checker must catch.  "correct" allocates c properly.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+__global__ void vecsum(double *c, const double *a, const double *b, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.x) c[i] = a[i] + b[i];
+}
+
+int main(int argc, char **argv)
+{
+    const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;
+    const int size = 1000000;
+    double *c, *a, *b;
+    double *c_host = (double *)malloc(size * sizeof(double));
+    const size_t c_bytes = correct ? size * sizeof(double) : size * sizeof(float);
+    if (hipMalloc((void **)&c, c_bytes) != hipSuccess || hipMalloc((void **)&a, size * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&b, size * sizeof(double)) != hipSuccess)
+        return 2;
+    hipMemset(a, 0, size * sizeof(double));
+    hipMemset(b, 0, size * sizeof(double));
+    const int fits = (int)(c_bytes / sizeof(double));
+    hipLaunchKernelGGL(vecsum, dim3(256), dim3(256), 0, 0, c, a, b, fits);
+    if (hipDeviceSynchronize() != hipSuccess) return 3;
+    hipMemset(c, 0, c_bytes);   // stands for the kernel's writes, which the checker does not see
+    const hipError_t e = hipMemcpy(c_host, c, size * sizeof(double), hipMemcpyDeviceToHost);
+    printf("hipMemcpy returned %d (%s)\n", (int)e, hipGetErrorString(e));
+    hipFree(c);
+    hipFree(a);
+    hipFree(b);
+    free(c_host);
+    return 0;
+}

@@ -57,3 +57,14 @@ def test_host_logic_under_sanitizers(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all host logic checks passed" in r.stdout
+
+
+def test_preload_wraps_the_hip_calls():
+    """The interposer exports the allocation, free, memset and copy entry
+    points it wraps (the wrapper deployment of Sec. 3)."""
+    import subprocess
+    so = os.path.join(ROOT, "paper_1310_0901_amd", "libxfercheck_preload.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True, check=True).stdout
+    names = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for f in ("hipMalloc", "hipFree", "hipMemset", "hipMemcpy", "hipMemcpyHtoD", "hipMemcpyDtoH", "hipMemcpyDtoD"):
+        assert f in names, f
