@@ -22,6 +22,10 @@
 // call returns hipErrorInvalidValue, as the driver in the paper's example
 // fails the call with an invalid-argument error), unless XC_ALLOW_BAD=1.
 //
+// hipMemcpyAsync is checked when it is issued; hipMemcpy2D is checked as one
+// batch of its rows (strided copies, the case of the paper's footnote to
+// the error list of Sec. 2) and reported once, with its first faulty row.
+//
 // Environment: XC_POOL_BYTES (shadow pool, default 1 GiB), XC_MAX_ALLOCS
 // (default 1,048,576), XC_REPORT_DEVICE_UNDEF, XC_ALLOW_BAD, XC_QUIET=1 (no
 // summary line).
@@ -33,6 +37,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "../../include/xfercheck.h"
 
@@ -58,6 +63,8 @@ using memcpy_t = hipError_t (*)(void *, const void *, size_t, hipMemcpyKind);
 using htod_t = hipError_t (*)(hipDeviceptr_t, const void *, size_t);
 using dtoh_t = hipError_t (*)(void *, hipDeviceptr_t, size_t);
 using dtod_t = hipError_t (*)(hipDeviceptr_t, hipDeviceptr_t, size_t);
+using memcpy_async_t = hipError_t (*)(void *, const void *, size_t, hipMemcpyKind, hipStream_t);
+using memcpy2d_t = hipError_t (*)(void *, size_t, const void *, size_t, size_t, size_t, hipMemcpyKind);
 
 struct State {
     std::mutex mu;
@@ -66,6 +73,7 @@ struct State {
     hipStream_t s = nullptr;
     cg_transfer *d_rec = nullptr;
     cg_verdict *d_ver = nullptr;
+    uint64_t rec_cap = 1;         // records d_rec / d_ver hold
     uint8_t *zeros = nullptr;     // V of "defined" host bytes
     uint64_t *ones = nullptr;     // A of "addressable" host bytes
     uint64_t cap = 0;             // bytes covered by zeros / ones
@@ -144,36 +152,84 @@ const char *kind_name(uint32_t k)
 
 constexpr uint32_t kRangeFaults = CG_SRC_UNALLOC | CG_SRC_OVERRUN | CG_DST_UNALLOC | CG_DST_OVERRUN;
 
-// Check one copy before it runs and print the report; false if the copy must
-// not be performed (its device side is unallocated or too small).
-bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t kind)
+// records / verdicts buffers for at least k rows
+bool ensure_rows(uint64_t k)
+{
+    if (k <= G.rec_cap) return true;
+    Guard g;
+    (void)hipStreamSynchronize(G.s);
+    (void)hipFree(G.d_rec);
+    (void)hipFree(G.d_ver);
+    G.d_rec = nullptr;
+    G.d_ver = nullptr;
+    G.rec_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&G.d_rec), k * sizeof(cg_transfer)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&G.d_ver), k * sizeof(cg_verdict)) != hipSuccess)
+        return false;
+    G.rec_cap = k;
+    return true;
+}
+
+// Check a copy of `rows` rows of `width` bytes (a plain copy is one row)
+// before it runs and print the report; false if the copy must not be
+// performed (a device side is unallocated or too small).
+bool check_rows(const char *api, uint8_t *dst, size_t dpitch, const uint8_t *src, size_t spitch, size_t width,
+                size_t rows, uint32_t kind)
 {
     std::lock_guard<std::mutex> lk(G.mu);
-    if (!ensure_ctx()) return true;
+    if (!ensure_ctx() || !ensure_rows(rows)) return true;
     Guard g;
-    cg_transfer r{(uint64_t)src, (uint64_t)dst, (uint64_t)n, kind, 0};
+    std::vector<cg_transfer> r(rows);
+    for (size_t i = 0; i < rows; ++i)
+        r[i] = cg_transfer{(uint64_t)(src + i * spitch), (uint64_t)(dst + i * dpitch), (uint64_t)width, kind, 0};
     uint32_t mode = CG_CHECK;
     if (kind != CG_D2D) {
-        const uint64_t hp = kind == CG_H2D ? r.src : r.dst;
-        if (!ensure_host_cover(n) || cg_host_register(G.ctx, hp, n ? n : 1, G.zeros, G.ones) != CG_OK) return true;
+        // the host rows as one region: first row start to last row end
+        const uint64_t hp = kind == CG_H2D ? r[0].src : r[0].dst;
+        const uint64_t hpitch = kind == CG_H2D ? spitch : dpitch;
+        const uint64_t span = (rows - 1) * hpitch + width;
+        if (!ensure_host_cover(span) || cg_host_register(G.ctx, hp, span ? span : 1, G.zeros, G.ones) != CG_OK)
+            return true;
     }
-    if (kind != CG_D2H) mode |= CG_PROPAGATE;   // the zeros buffer must stay zero
-    cg_verdict v{};
-    if (hipMemcpyAsync(G.d_rec, &r, sizeof r, hipMemcpyHostToDevice, G.s) != hipSuccess ||
-        check_transfers(G.ctx, G.d_rec, 1, G.d_ver, mode, G.s) != CG_OK ||
-        hipMemcpyAsync(&v, G.d_ver, sizeof v, hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+    // no propagation into host shadow (the zeros buffer must stay zero), nor
+    // when destination rows overlap (their order would be unspecified)
+    if (kind != CG_D2H && (rows == 1 || dpitch >= width)) mode |= CG_PROPAGATE;
+    std::vector<cg_verdict> v(rows);
+    if (hipMemcpyAsync(G.d_rec, r.data(), rows * sizeof(cg_transfer), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_transfers(G.ctx, G.d_rec, rows, G.d_ver, mode, G.s) != CG_OK ||
+        hipMemcpyAsync(v.data(), G.d_ver, rows * sizeof(cg_verdict), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
         hipStreamSynchronize(G.s) != hipSuccess) {
         fprintf(stderr, "==xfercheck== check failed: %s\n", cg_last_error(G.ctx));
         return true;
     }
     ++G.copies;
-    if (!G.device_undef && kind != CG_H2D) v.flags &= ~CG_SRC_UNDEF;
-    if (!v.flags) return true;
+    size_t bad_rows = 0, first = rows;
+    uint32_t all = 0;
+    for (size_t i = 0; i < rows; ++i) {
+        if (!G.device_undef && kind != CG_H2D) v[i].flags &= ~CG_SRC_UNDEF;
+        if (v[i].flags) {
+            ++bad_rows;
+            if (first == rows) first = i;
+            all |= v[i].flags;
+        }
+    }
+    if (!bad_rows) return true;
     char buf[1024];
-    cg_format_verdict(&r, &v, buf, sizeof buf);
+    cg_format_verdict(&r[first], &v[first], buf, sizeof buf);
     ++G.errors;
-    fprintf(stderr, "%s\n at %s(dst=%p, src=%p, %zu bytes, %s)\n", buf, api, dst, src, n, kind_name(kind));
-    return G.allow_bad || !(v.flags & kRangeFaults);
+    if (rows == 1)
+        fprintf(stderr, "%s\n at %s(dst=%p, src=%p, %zu bytes, %s)\n", buf, api, (void *)dst, (const void *)src, width,
+                kind_name(kind));
+    else
+        fprintf(stderr, "%s\n in row %zu of %zu (%zu rows with errors) at %s(dst=%p, dpitch=%zu, src=%p, spitch=%zu, "
+                        "width=%zu, %s)\n",
+                buf, first, rows, bad_rows, api, (void *)dst, dpitch, (const void *)src, spitch, width, kind_name(kind));
+    return G.allow_bad || !(all & kRangeFaults);
+}
+
+bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t kind)
+{
+    return check_rows(api, (uint8_t *)dst, 0, (const uint8_t *)src, 0, n, 1, kind);
 }
 
 uint32_t direction(void *dst, const void *src, hipMemcpyKind k)
@@ -276,6 +332,29 @@ hipError_t hipMemcpyDtoD(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n)
     static dtod_t f = real<dtod_t>("hipMemcpyDtoD");
     if (!inside && n && !check_copy("hipMemcpyDtoD", dst, src, n, CG_D2D)) return hipErrorInvalidValue;
     return f(dst, src, n);
+}
+
+hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind kind, hipStream_t stream)
+{
+    static memcpy_async_t f = real<memcpy_async_t>("hipMemcpyAsync");
+    if (!inside && n) {
+        const uint32_t d = direction(dst, src, kind);
+        if (d <= CG_D2D && !check_copy("hipMemcpyAsync", dst, src, n, d)) return hipErrorInvalidValue;
+    }
+    return f(dst, src, n, kind, stream);
+}
+
+hipError_t hipMemcpy2D(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t height,
+                       hipMemcpyKind kind)
+{
+    static memcpy2d_t f = real<memcpy2d_t>("hipMemcpy2D");
+    if (!inside && width && height) {
+        const uint32_t d = direction(dst, src, kind);
+        if (d <= CG_D2D && !check_rows("hipMemcpy2D", (uint8_t *)dst, dpitch, (const uint8_t *)src, spitch, width,
+                                       height, d))
+            return hipErrorInvalidValue;
+    }
+    return f(dst, dpitch, src, spitch, width, height, kind);
 }
 
 }  // extern "C"

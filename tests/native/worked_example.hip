@@ -14,8 +14,36 @@ __global__ void vecsum(double *c, const double *a, const double *b, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.x) c[i] = a[i] + b[i];
 }
 
+// A pitched copy whose rows are wider than the destination pitch: the last
+// row runs past the allocation.  And an asynchronous copy of the example's
+// size into the float-sized buffer.
+static int pitched_and_async()
+{
+    const size_t rows = 100, pitch = 256, width = 300;
+    uint8_t *d = nullptr, *big = nullptr;
+    uint8_t *h = (uint8_t *)calloc(rows * width, 1);
+    if (hipMalloc((void **)&d, rows * pitch) != hipSuccess || hipMalloc((void **)&big, 4000000) != hipSuccess) return 2;
+    hipError_t e = hipMemcpy2D(d, pitch, h, width, pitch, rows, hipMemcpyHostToDevice);   // fits
+    printf("hipMemcpy2D fitting returned %d\n", (int)e);
+    e = hipMemcpy2D(d, pitch, h, width, width, rows, hipMemcpyHostToDevice);              // last row overruns
+    printf("hipMemcpy2D overrun returned %d\n", (int)e);
+    double *hd = (double *)calloc(1000000, sizeof(double));
+    hipStream_t s;
+    if (hipStreamCreate(&s) != hipSuccess) return 2;
+    e = hipMemcpyAsync(big, hd, 1000000 * sizeof(double), hipMemcpyHostToDevice, s);
+    printf("hipMemcpyAsync returned %d\n", (int)e);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    hipFree(d);
+    hipFree(big);
+    free(h);
+    free(hd);
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
+    if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
     const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;
     const int size = 1000000;
     double *c, *a, *b;

@@ -44,3 +44,20 @@ def test_corrected_program_is_clean():
     assert "Error" not in r.stderr
     assert "hipMemcpy returned 0 " in r.stdout
     assert "1 copies checked, 0 with errors" in r.stderr
+
+
+def test_pitched_and_async_copies():
+    """hipMemcpy2D is checked as a batch of its rows (the strided case of the
+    footnote to Sec. 2's error list); hipMemcpyAsync is checked when issued."""
+    r = run_example("pitched")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0
+    assert "hipMemcpy2D fitting returned 0" in r.stdout
+    assert "hipMemcpy2D overrun returned 1" in r.stdout
+    assert "hipMemcpyAsync returned 1" in r.stdout
+    err = r.stderr
+    assert "Error: Allocated device memory too small for host->device copy." in err
+    assert "Expected 300 allocated bytes but only found 256." in err
+    assert "in row 99 of 100 (1 rows with errors)" in err
+    assert "Expected 8000000 allocated bytes but only found 4000000." in err
+    assert "3 copies checked, 2 with errors" in err
