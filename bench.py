@@ -389,10 +389,18 @@ def main():
         src = dw.hv[:cp_bytes]
         dst = torch.empty(cp_bytes, dtype=torch.uint8, device=dev)
         X.cg_probe_copy(dst.data_ptr(), src.data_ptr(), cp_bytes, stream)
+        e0.record()
+        for _ in range(5):
+            X.cg_probe_copy(dst.data_ptr(), src.data_ptr(), cp_bytes, stream)
+        e1.record()
         torch.cuda.synchronize(dev)
+        # read + write bytes: the practical ceiling of the propagating variant
+        cp = 2 * cp_bytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        del dst
         result["probe_read_GBps"] = round(rd, 1)
         result["pct_of_probe_read"] = round(100 * value / rd, 2)
-        log(f"[bench] probe read {rd:.0f} GB/s")
+        result["probe_copy_GBps"] = round(cp, 1)
+        log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write)")
 
     traffic, traffic_note = profiled_traffic(tun, args.config)
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
