@@ -128,3 +128,34 @@ def run_sequential(world: World, records, propagate=False):
         if propagate:
             apply_writes(cur, w, kind == 1)
     return out, cur
+
+
+def race_flags(rows, streams, epochs=None):
+    """Concurrent-access flags by byte sets: every byte a record reads or
+    writes is entered in a map byte -> accesses; a record is flagged where
+    one of its bytes is also written (for its reads) or read or written (for
+    its writes) by a record of another stream in the same epoch.  rows are
+    (kind, src, dst, n) tuples as in run_snapshot; flags use 1 = source,
+    2 = destination, 4 = not checked (see oracle.c for the reading)."""
+    epochs = epochs or [0] * len(rows)
+    unchecked = set()
+    touched = {}
+    for t, (kind, src, dst, n) in enumerate(rows):
+        if kind > 2 or (n > 0 and (src + n > 1 << 48 or dst + n > 1 << 48 or epochs[t] >= 1 << 15)):
+            unchecked.add(t)
+            continue
+        for x in range(src, src + n):
+            touched.setdefault(x, []).append((t, "r"))
+        for x in range(dst, dst + n):
+            touched.setdefault(x, []).append((t, "w"))
+    flags = [4 if t in unchecked else 0 for t in range(len(rows))]
+    for x, acc in touched.items():
+        for t, how in acc:
+            for u, how_u in acc:
+                if u == t or streams[u] == streams[t] or epochs[u] != epochs[t]:
+                    continue
+                if how == "w":
+                    flags[t] |= 2
+                elif how_u == "w":
+                    flags[t] |= 1
+    return flags

@@ -204,3 +204,70 @@ int oracle_run(uint64_t hb, uint64_t hl, uint8_t *hv, const uint64_t *ha,
     }
     return 0;
 }
+
+/*
+ * Concurrent accesses.  Next to the copy errors, Sec. 2 names the detection
+ * of some concurrent accesses in programs that use several threads, without
+ * describing a mechanism.  The reading evaluated here:
+ *   - a record (src, dst, n, kind) reads the bytes R = [src, src + n) and
+ *     writes the bytes W = [dst, dst + n), all in the process's one address
+ *     space (host and device pointers never coincide);
+ *   - each record also carries the stream it was issued on and an epoch,
+ *     the number of synchronising calls made before it was issued; two
+ *     records are ordered when they share a stream or differ in epoch;
+ *   - distinct records a and b conflict when they are unordered and
+ *     W_a meets W_b, W_a meets R_b, or R_a meets W_b (two reads never
+ *     conflict);
+ *   - flags of a: RACE_SRC when R_a meets W_b of a conflicting b, RACE_DST
+ *     when W_a meets W_b or R_b of a conflicting b;
+ *   - a record is not checked (RACE_UNCHECKED, and it meets nothing) when
+ *     its kind is not 0, 1 or 2, or when n > 0 and src + n or dst + n
+ *     exceeds 2^48 or its epoch is 2^15 or more.  n == 0 touches no byte.
+ * Each requested record is compared with every other record, one pair at a
+ * time.
+ */
+enum { OR_RACE_SRC = 1u, OR_RACE_DST = 2u, OR_RACE_UNCHECKED = 4u };
+#define OR_ADDR_LIMIT (1ull << 48)
+#define OR_EPOCH_LIMIT (1u << 15)
+
+static int race_unchecked(const or_record *r, uint32_t epoch)
+{
+    if (r->kind > OR_D2D) return 1;
+    if (r->n == 0) return 0;
+    if ((wide)r->src + r->n > OR_ADDR_LIMIT || (wide)r->dst + r->n > OR_ADDR_LIMIT) return 1;
+    return epoch >= OR_EPOCH_LIMIT;
+}
+
+/* do [a, a + na) and [b, b + nb) share a byte? */
+static int meets(uint64_t a, uint64_t na, uint64_t b, uint64_t nb)
+{
+    return na > 0 && nb > 0 && (wide)a < (wide)b + nb && (wide)b < (wide)a + na;
+}
+
+void oracle_race(uint64_t count, const or_record *recs, const uint32_t *streams,
+                 const uint32_t *epochs, uint64_t nwhich, const uint64_t *which,
+                 uint32_t *flags)
+{
+    for (uint64_t k = 0; k < nwhich; k++) {
+        uint64_t a = which[k];
+        const or_record *ra = &recs[a];
+        uint32_t ea = epochs ? epochs[a] : 0;
+        uint32_t f = 0;
+        if (race_unchecked(ra, ea)) {
+            flags[k] = OR_RACE_UNCHECKED;
+            continue;
+        }
+        for (uint64_t b = 0; b < count; b++) {
+            if (b == a) continue;
+            const or_record *rb = &recs[b];
+            uint32_t eb = epochs ? epochs[b] : 0;
+            if (race_unchecked(rb, eb)) continue;
+            if (eb != ea || streams[b] == streams[a]) continue;
+            if (meets(ra->dst, ra->n, rb->dst, rb->n) || meets(ra->dst, ra->n, rb->src, rb->n))
+                f |= OR_RACE_DST;
+            if (meets(ra->src, ra->n, rb->dst, rb->n))
+                f |= OR_RACE_SRC;
+        }
+        flags[k] = f;
+    }
+}

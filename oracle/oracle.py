@@ -22,6 +22,8 @@ SRC_UNADDR, SRC_UNDEF, SRC_UNALLOC, SRC_OVERRUN = 1, 2, 4, 8
 DST_UNADDR, DST_UNALLOC, DST_OVERRUN, OVERLAP, BAD_KIND = 16, 32, 64, 128, 256
 NONE = 0xFFFF_FFFF_FFFF_FFFF
 MODE_CHECK, MODE_PROPAGATE = 1, 2
+RACE_SRC, RACE_DST, RACE_UNCHECKED = 1, 2, 4
+ADDR_LIMIT, EPOCH_LIMIT = 1 << 48, 1 << 15
 REC = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("reserved", "<u4")])
 VER = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
                 ("undef_bytes", "<u8"), ("avail", "<u8")])
@@ -50,6 +52,10 @@ def load(path: str = LIB):
                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+            lib.oracle_race.restype = None
+            lib.oracle_race.argtypes = [
+                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
             if path != LIB:
                 return lib
             _lib = lib
@@ -111,3 +117,54 @@ class OracleState:
         for t in ts:
             t.join()
         return out
+
+
+def race(records, streams, epochs=None, which=None, threads: int = 1, lib=None) -> np.ndarray:
+    """Concurrent-access flags (RACE_*) of the records listed in `which`
+    (default: all), each compared with every other record of the batch;
+    the reading of Sec. 2's concurrent accesses is stated in oracle.c."""
+    lib = lib or load()
+    recs = np.ascontiguousarray(records, REC)
+    st = np.ascontiguousarray(streams, np.uint32)
+    ep = None if epochs is None else np.ascontiguousarray(epochs, np.uint32)
+    assert st.size == recs.size and (ep is None or ep.size == recs.size)
+    idx = np.arange(recs.size, dtype=np.uint64) if which is None else np.ascontiguousarray(which, np.uint64)
+    out = np.zeros(idx.size, np.uint32)
+    bounds = np.linspace(0, idx.size, max(1, threads) + 1).astype(np.int64)
+
+    def work(a, b):
+        if b > a:
+            lib.oracle_race(recs.size, recs.ctypes.data, st.ctypes.data,
+                            None if ep is None else ep.ctypes.data, b - a,
+                            idx[a:b].ctypes.data, out[a:b].ctypes.data)
+
+    ts = [threading.Thread(target=work, args=(int(bounds[i]), int(bounds[i + 1])))
+          for i in range(len(bounds) - 1)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    return out
+
+
+def conflict(ra, rb, sa, sb, ea=0, eb=0):
+    """(dst_hit, src_hit) of record a against one other record b: whether
+    a's written bytes meet b's read or written bytes, and whether a's read
+    bytes meet b's written bytes, when the two are unordered (different
+    streams, same epoch) and both are checked.  One pair, by definition."""
+    def checked(r, e):
+        if int(r["kind"]) > 2:
+            return False
+        n = int(r["n"])
+        return n == 0 or (int(r["src"]) + n <= ADDR_LIMIT and int(r["dst"]) + n <= ADDR_LIMIT
+                          and int(e) < EPOCH_LIMIT)
+
+    def meets(a, na, b, nb):
+        return na > 0 and nb > 0 and a < b + nb and b < a + na
+
+    if not (checked(ra, ea) and checked(rb, eb)) or int(ea) != int(eb) or int(sa) == int(sb):
+        return False, False
+    n_a, n_b = int(ra["n"]), int(rb["n"])
+    dst = meets(int(ra["dst"]), n_a, int(rb["dst"]), n_b) or meets(int(ra["dst"]), n_a, int(rb["src"]), n_b)
+    src = meets(int(ra["src"]), n_a, int(rb["dst"]), n_b)
+    return dst, src

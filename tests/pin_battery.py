@@ -52,6 +52,9 @@ def main(path):
     v = st.run(recs([(1, c, c_host, n)]))[0]
     assert (int(v["flags"]), int(v["first_bad"]), int(v["avail"])) == \
         (oracle.SRC_OVERRUN, fx["found_bytes"], fx["found_bytes"]), "worked example"
+    # the concurrent-access join
+    from tests.test_oracle_race import check_pins
+    check_pins(lib)
     return 0
 
 

@@ -25,6 +25,17 @@ MUTANTS = {
     "dst unaddr never raised": ("if (dst_host && !ok_d) flags |= OR_DST_UNADDR;", ""),
     "device V index shifted": ("rd->av[as][r->src - rd->abase[as] + i]", "rd->av[as][r->src - rd->abase[as] + (i ? i - 1 : 0)]"),
     "propagation into overlapping copies": ("if (propagate && !overlap && ok_d)", "if (propagate && ok_d)"),
+    "race ignores streams": ("if (eb != ea || streams[b] == streams[a]) continue;", "if (eb != ea) continue;"),
+    "race ignores epochs": ("if (eb != ea || streams[b] == streams[a]) continue;",
+                            "if (streams[b] == streams[a]) continue;"),
+    "reads conflict with reads": ("if (meets(ra->src, ra->n, rb->dst, rb->n))",
+                                  "if (meets(ra->src, ra->n, rb->dst, rb->n) || meets(ra->src, ra->n, rb->src, rb->n))"),
+    "race ranges end inclusive": ("(wide)a < (wide)b + nb && (wide)b < (wide)a + na",
+                                  "(wide)a <= (wide)b + nb && (wide)b <= (wide)a + na"),
+    "race address limit inclusive": ("(wide)r->src + r->n > OR_ADDR_LIMIT || (wide)r->dst + r->n > OR_ADDR_LIMIT",
+                                     "(wide)r->src + r->n >= OR_ADDR_LIMIT || (wide)r->dst + r->n >= OR_ADDR_LIMIT"),
+    "unchecked records still meet": ("            if (race_unchecked(rb, eb)) continue;\n", ""),
+    "write-write conflicts missed": ("meets(ra->dst, ra->n, rb->dst, rb->n) || ", ""),
     "zero length reports avail": ("if (n == 0) {\n        out->flags = 0; out->reserved = 0;\n        out->first_bad = OR_NONE; out->undef_bytes = 0; out->avail = 0;\n        return;\n    }", ""),
 }
 
