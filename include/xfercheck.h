@@ -217,6 +217,44 @@ int cg_sync(cg_ctx *ctx);
 /* Number of live allocations and bytes of shadow pool in use. */
 int cg_stats(cg_ctx *ctx, uint64_t *live_allocs, uint64_t *pool_used);
 
+/* ---- concurrent accesses ------------------------------------------------- */
+/*
+ * Sec. 2 counts some concurrent accesses, when a program uses several
+ * threads, among the errors the checker reports; the paper describes no
+ * mechanism.  Reading used here: a record reads [src, src + n) and writes
+ * [dst, dst + n) of the process's one address space (host and device
+ * pointers never coincide); streams[i] is the stream (or thread) record i
+ * was issued on, epochs[i] the number of synchronising calls made before it.
+ * Records on one stream, or in different epochs, are ordered.  Two distinct
+ * unordered records conflict when a written range of one meets a read or
+ * written range of the other; two reads never conflict.
+ */
+#define CG_RACE_SRC       0x1u  /* the source bytes are written by a conflicting record */
+#define CG_RACE_DST       0x2u  /* the destination bytes are read or written by a conflicting record */
+#define CG_RACE_UNCHECKED 0x4u  /* kind not 0/1/2, or n > 0 with src + n or dst + n > 2^48 or epoch >= 2^15 */
+
+/* One result, 16 bytes, in device memory: the flags above, and the index of
+ * one record this one conflicts with (CG_NONE when there is none).  When
+ * several records conflict with it, which one is named is unspecified. */
+typedef struct cg_race {
+    uint32_t flags, reserved;
+    uint64_t partner;
+} cg_race;
+
+/*
+ * Join `count` records (count <= 2^30) at recs_dev against each other and
+ * write one cg_race per record to out_dev, on `hip_stream`.  streams_dev
+ * holds count uint32 stream ids; epochs_dev holds count uint32 epochs, or is
+ * NULL for all epochs 0.  All arrays are device memory that the caller keeps
+ * alive until the stream has synced.  Records with n == 0 touch nothing.
+ * The shadow state and the allocation table are not used: this is a pure
+ * function of the records.  Device work space is kept per stream and grows
+ * to the largest batch seen.
+ * Errors: CG_EINVAL (null pointers, count too large), CG_EHIP / CG_ENOMEM.
+ */
+int check_concurrent(cg_ctx *ctx, const cg_transfer *recs_dev, const uint32_t *streams_dev,
+                     const uint32_t *epochs_dev, uint64_t count, cg_race *out_dev, void *hip_stream);
+
 /* ---- tuning (the batched kernel's launch shape) -------------------------- */
 typedef struct cg_tuning {
     uint32_t block;          /* threads per block: 256 or 512 */

@@ -1,0 +1,622 @@
+// Concurrent-access detection over a batch of transfer records (gfx950).
+//
+// Sec. 2 counts some concurrent accesses, in programs that use several
+// threads, among the errors a checker reports; the paper gives no mechanism.
+// Here each record reads [src, src + n) and writes [dst, dst + n) of the
+// process's one address space, and carries the stream it was issued on and an
+// epoch (the synchronising calls made before it).  Two records conflict when
+// they share the epoch, run on different streams, and a written range of one
+// meets a read or written range of the other.
+//
+// The join is an interval sweep.  Every record gives two intervals whose key
+// is (epoch << 48 | address), so intervals of different epochs never meet.
+// The keys are sorted by an 8-bit LSD radix sort; a pass whose digit is the
+// same in every key is skipped on the device.  An interval then meets an
+// interval of another stream that starts no later exactly when the furthest
+// end among earlier intervals of other streams lies past its start, and one
+// that starts later exactly when the smallest start among later intervals of
+// other streams lies before its end.  "Best among other streams" is kept as
+// the best two entries of distinct streams; that combine is associative and
+// commutative, so both directions are one reduce-then-scan over tiles.
+#include <hip/hip_runtime.h>
+
+#include "race.h"
+
+namespace xc {
+namespace {
+
+constexpr uint32_t kNoRec = 0xFFFFFFFFu;
+constexpr uint32_t kNoStream = 0xFFFFFFFFu;
+constexpr uint64_t kInvalidKey = 1ull << 63;
+constexpr uint64_t kAddrLimit = 1ull << 48;
+constexpr uint32_t kEpochLimit = 1u << 15;
+
+constexpr int kT = 256;                          // threads per block
+constexpr int kWaves = kT / 64;
+constexpr int kSortTile = 4096;                  // keys per sort tile
+constexpr int kWaveItems = kSortTile / kWaves;   // contiguous keys per wave
+constexpr int kRounds = kWaveItems / 64;
+constexpr int kSweepItems = 8;                   // consecutive elements per thread
+constexpr int kSweepTile = kT * kSweepItems;
+
+// ---- records -------------------------------------------------------------
+
+__device__ __forceinline__ bool rec_checked(const cg_transfer &t, uint32_t e)
+{
+    if (t.kind > CG_D2D) return false;
+    if (t.n == 0) return true;
+    return t.src <= kAddrLimit && t.n <= kAddrLimit - t.src && t.dst <= kAddrLimit &&
+           t.n <= kAddrLimit - t.dst && e < kEpochLimit;
+}
+
+// interval i of record i / 2: the source range for even i, the destination
+// range for odd i; empty and unchecked ranges sort last
+__device__ __forceinline__ uint64_t interval_key(const cg_transfer *recs, const uint32_t *epochs, uint64_t i)
+{
+    const cg_transfer t = recs[i >> 1];
+    const uint32_t e = epochs ? epochs[i >> 1] : 0u;
+    if (t.n == 0 || !rec_checked(t, e)) return kInvalidKey;
+    return ((uint64_t)e << 48) | ((i & 1) ? t.dst : t.src);
+}
+
+// ---- sort plan: passes over digits that differ somewhere -------------------
+
+__device__ __forceinline__ bool pass_live(uint64_t mask, int pass) { return ((mask >> (8 * pass)) & 0xFFu) != 0; }
+
+// which of the two buffers holds the keys before `pass`
+__device__ __forceinline__ int pass_parity(uint64_t mask, int pass)
+{
+    int p = 0;
+    for (int q = 0; q < pass; ++q) p ^= pass_live(mask, q) ? 1 : 0;
+    return p;
+}
+
+__global__ void k_race_init(uint64_t *mask) { *mask = 0; }
+
+__global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const uint32_t *epochs, uint64_t m,
+                                                  uint64_t *keys, uint32_t *vals, uint64_t *mask)
+{
+    __shared__ uint64_t part[kWaves];
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t k0 = interval_key(recs, epochs, 0);
+    uint64_t x = 0;
+    if (i < m) {
+        const uint64_t k = interval_key(recs, epochs, i);
+        keys[i] = k;
+        vals[i] = (uint32_t)i;
+        x = k ^ k0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t y = 0;
+        for (int w = 0; w < kWaves; ++w) y |= part[w];
+        if (y) atomicOr((unsigned long long *)mask, (unsigned long long)y);
+    }
+}
+
+// ---- radix sort ----------------------------------------------------------
+
+// lanes of the wave whose valid digit equals this lane's
+__device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t y = __ballot(bit);
+        m &= bit ? y : ~y;
+    }
+    return valid ? m : 0ull;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
+
+// exclusive sum over the block's threads; *total receives the block sum
+__device__ uint32_t block_excl_sum(uint32_t x, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kWaves];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (l >= d) inc += y;
+    }
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int j = 0; j < kWaves; ++j) {
+        if (j < w) off += wsum[j];
+        tot += wsum[j];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+// per-tile digit counts, digit-major: counts[d * tiles + tile]
+__global__ __launch_bounds__(kT) void k_race_count(const uint64_t *ka, const uint64_t *kb, uint64_t m,
+                                                   uint32_t tiles, const uint64_t *maskp, int pass,
+                                                   uint32_t *counts)
+{
+    const uint64_t mask = *maskp;
+    if (!pass_live(mask, pass)) return;
+    const uint64_t *kin = pass_parity(mask, pass) ? kb : ka;
+    const int shift = 8 * pass;
+    __shared__ uint32_t h[kWaves][256];
+    for (int j = threadIdx.x; j < kWaves * 256; j += kT) (&h[0][0])[j] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveItems + l;
+    uint32_t d[kRounds];
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const uint64_t idx = base + (uint64_t)i * 64;
+        d[i] = idx < m ? (uint32_t)(kin[idx] >> shift) & 0xFFu : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const bool valid = base + (uint64_t)i * 64 < m;
+        const uint64_t peers = match8(d[i], valid);
+        if (valid && (peers & lanes_below()) == 0) h[w][d[i]] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    uint32_t c = 0;
+    for (int j = 0; j < kWaves; ++j) c += h[j][t];
+    counts[(uint64_t)t * tiles + blockIdx.x] = c;
+}
+
+// per digit (one block each): exclusive prefix of the tile counts in place,
+// and the digit's total
+__global__ __launch_bounds__(kT) void k_race_scan_digits(uint32_t *counts, uint32_t tiles, uint32_t *dtot,
+                                                         const uint64_t *maskp, int pass)
+{
+    if (!pass_live(*maskp, pass)) return;
+    uint32_t *row = counts + (uint64_t)blockIdx.x * tiles;
+    const uint32_t per = (tiles + kT - 1) / kT;
+    const uint32_t lo = min(tiles, threadIdx.x * per), hi = min(tiles, lo + per);
+    uint32_t s = 0;
+    for (uint32_t j = lo; j < hi; ++j) s += row[j];
+    uint32_t tot;
+    uint32_t run = block_excl_sum(s, &tot);
+    for (uint32_t j = lo; j < hi; ++j) {
+        const uint32_t c = row[j];
+        row[j] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = tot;
+}
+
+// stable scatter of one tile: ranks within the tile, a local sort through
+// LDS, then runs of equal digits written contiguously
+__global__ __launch_bounds__(kT) void k_race_scatter(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
+                                                     uint64_t m, uint32_t tiles, const uint64_t *maskp, int pass,
+                                                     const uint32_t *counts, const uint32_t *dtot)
+{
+    const uint64_t mask = *maskp;
+    if (!pass_live(mask, pass)) return;
+    const int par = pass_parity(mask, pass);
+    const uint64_t *kin = par ? kb : ka;
+    const uint32_t *vin = par ? vb : va;
+    uint64_t *kout = par ? ka : kb;
+    uint32_t *vout = par ? va : vb;
+    const int shift = 8 * pass;
+
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t wrun[kWaves][256];   // per wave: running count, then exclusive prefix across waves
+    __shared__ uint32_t dstart[256];         // first tile-local position of each digit
+    __shared__ uint32_t gbase[256];          // global position of this tile's first key of each digit
+
+    for (int j = threadIdx.x; j < kWaves * 256; j += kT) (&wrun[0][0])[j] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveItems + l;
+    uint64_t k[kRounds];
+    uint32_t v[kRounds], pk[kRounds];
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const uint64_t idx = base + (uint64_t)i * 64;
+        k[i] = idx < m ? kin[idx] : 0ull;
+        v[i] = idx < m ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const bool valid = base + (uint64_t)i * 64 < m;
+        const uint32_t d = (uint32_t)(k[i] >> shift) & 0xFFu;
+        const uint64_t peers = match8(d, valid);
+        const uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
+        uint32_t run = 0;
+        if (valid) run = wrun[w][d];
+        if (valid && rank == 0) wrun[w][d] = run + (uint32_t)__popcll(peers);
+        pk[i] = valid ? (d << 16) | (run + rank) : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    uint32_t acc = 0;
+    for (int j = 0; j < kWaves; ++j) {
+        const uint32_t c = wrun[j][t];
+        wrun[j][t] = acc;
+        acc += c;
+    }
+    uint32_t unused;
+    dstart[t] = block_excl_sum(acc, &unused);
+    gbase[t] = block_excl_sum(dtot[t], &unused) + counts[(uint64_t)t * tiles + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        if (pk[i] != 0xFFFFFFFFu) {
+            const uint32_t d = pk[i] >> 16;
+            const uint32_t pos = dstart[d] + wrun[w][d] + (pk[i] & 0xFFFFu);
+            skey[pos] = k[i];
+            sval[pos] = v[i];
+        }
+    }
+    __syncthreads();
+    const uint64_t left = m - (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t nvalid = left < (uint64_t)kSortTile ? (uint32_t)left : (uint32_t)kSortTile;
+    for (uint32_t j = t; j < nvalid; j += kT) {
+        const uint64_t key = skey[j];
+        const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+        const uint64_t g = (uint64_t)gbase[d] + (j - dstart[d]);
+        if (g < m) {
+            kout[g] = key;
+            vout[g] = sval[j];
+        }
+    }
+}
+
+// ---- sweep ---------------------------------------------------------------
+
+// The best two entries (value, record) of distinct streams: (v1, s1, r1) is
+// the best overall, (v2, r2) the best of any stream other than s1.  "Best" is
+// the larger value, ties to the smaller record index.  Ends are kept as they
+// are (furthest end wins); starts as their complement (smallest start wins).
+struct Top2 {
+    uint64_t v1, v2;
+    uint32_t s1, r1, r2;
+};
+
+__device__ __forceinline__ bool beats(uint64_t va, uint32_t ra, uint64_t vb, uint32_t rb)
+{
+    return va > vb || (va == vb && ra < rb);
+}
+
+__device__ __forceinline__ Top2 t2_none() { return Top2{0, 0, kNoStream, kNoRec, kNoRec}; }
+
+__device__ __forceinline__ Top2 t2_combine(const Top2 &x, const Top2 &y)
+{
+    const bool xw = beats(x.v1, x.r1, y.v1, y.r1);
+    const Top2 a = xw ? x : y, b = xw ? y : x;
+    Top2 o;
+    o.v1 = a.v1;
+    o.s1 = a.s1;
+    o.r1 = a.r1;
+    const bool other = b.s1 != a.s1;
+    const uint64_t cv = other ? b.v1 : b.v2;
+    const uint32_t cr = other ? b.r1 : b.r2;
+    const bool keep = beats(a.v2, a.r2, cv, cr);
+    o.v2 = keep ? a.v2 : cv;
+    o.r2 = keep ? a.r2 : cr;
+    return o;
+}
+
+__device__ __forceinline__ Top2 t2_add(const Top2 &x, uint64_t v, uint32_t s, uint32_t r)
+{
+    return t2_combine(x, Top2{v, 0, s, r, kNoRec});
+}
+
+// the best entry of a stream other than s
+__device__ __forceinline__ void t2_other(const Top2 &x, uint32_t s, uint64_t *v, uint32_t *r)
+{
+    const bool first = x.s1 != s;
+    *v = first ? x.v1 : x.v2;
+    *r = first ? x.r1 : x.r2;
+}
+
+template <bool UP>
+__device__ __forceinline__ Top2 t2_shfl(const Top2 &x, int d)
+{
+    Top2 y;
+    y.v1 = UP ? __shfl_up(x.v1, d) : __shfl_down(x.v1, d);
+    y.v2 = UP ? __shfl_up(x.v2, d) : __shfl_down(x.v2, d);
+    y.s1 = UP ? __shfl_up(x.s1, d) : __shfl_down(x.s1, d);
+    y.r1 = UP ? __shfl_up(x.r1, d) : __shfl_down(x.r1, d);
+    y.r2 = UP ? __shfl_up(x.r2, d) : __shfl_down(x.r2, d);
+    return y;
+}
+
+// combine of x over the block's threads before this one (FWD) or after it
+template <bool FWD>
+__device__ Top2 block_excl(const Top2 &x)
+{
+    __shared__ Top2 wtot[kWaves];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    Top2 inc = x;
+    for (int d = 1; d < 64; d <<= 1) {
+        const Top2 y = t2_shfl<FWD>(inc, d);
+        if (FWD ? l >= d : l + d < 64) inc = t2_combine(inc, y);
+    }
+    Top2 ex = t2_shfl<FWD>(inc, 1);
+    if (FWD ? l == 0 : l == 63) ex = t2_none();
+    if (FWD ? l == 63 : l == 0) wtot[w] = inc;
+    __syncthreads();
+    for (int j = 0; j < kWaves; ++j)
+        if (FWD ? j < w : j > w) ex = t2_combine(ex, wtot[j]);
+    __syncthreads();
+    return ex;
+}
+
+__device__ Top2 block_all(const Top2 &x)
+{
+    __shared__ Top2 wtot[kWaves];
+    Top2 a = x;
+    for (int d = 32; d >= 1; d >>= 1) {
+        Top2 y;
+        y.v1 = __shfl_xor(a.v1, d);
+        y.v2 = __shfl_xor(a.v2, d);
+        y.s1 = __shfl_xor(a.s1, d);
+        y.r1 = __shfl_xor(a.r1, d);
+        y.r2 = __shfl_xor(a.r2, d);
+        a = t2_combine(a, y);
+    }
+    if ((threadIdx.x & 63) == 0) wtot[threadIdx.x >> 6] = a;
+    __syncthreads();
+    Top2 o = wtot[0];
+    for (int j = 1; j < kWaves; ++j) o = t2_combine(o, wtot[j]);
+    __syncthreads();
+    return o;
+}
+
+// one interval of the sorted order
+struct Elem {
+    uint64_t start, end;
+    uint32_t s, r, iv;
+    bool valid, w, present;
+};
+
+__device__ __forceinline__ Elem load_elem(const uint64_t *K, const uint32_t *V, const cg_transfer *recs,
+                                          const uint32_t *streams, uint64_t p, uint64_t m)
+{
+    Elem e{kInvalidKey, 0, kNoStream, kNoRec, 0, false, false, false};
+    if (p < m) {
+        const uint64_t k = K[p];
+        e.iv = V[p];
+        e.present = e.iv < m;
+        if (e.present && !(k >> 63)) {
+            e.valid = true;
+            e.r = e.iv >> 1;
+            e.w = (e.iv & 1u) != 0;
+            e.start = k;
+            e.end = k + recs[e.r].n;
+            e.s = streams[e.r];
+        }
+    }
+    return e;
+}
+
+// the four running combines: ends and starts, of all intervals and of writes
+struct Sweep {
+    Top2 fa, fw, ba, bw;
+};
+
+__device__ __forceinline__ void sweep_add_fwd(Sweep &x, const Elem &e)
+{
+    if (!e.valid) return;
+    x.fa = t2_add(x.fa, e.end, e.s, e.r);
+    if (e.w) x.fw = t2_add(x.fw, e.end, e.s, e.r);
+}
+
+__device__ __forceinline__ void sweep_add_bwd(Sweep &x, const Elem &e)
+{
+    if (!e.valid) return;
+    x.ba = t2_add(x.ba, ~e.start, e.s, e.r);
+    if (e.w) x.bw = t2_add(x.bw, ~e.start, e.s, e.r);
+}
+
+__device__ __forceinline__ const uint64_t *sorted_keys(const uint64_t *ka, const uint64_t *kb, uint64_t mask)
+{
+    return pass_parity(mask, 8) ? kb : ka;
+}
+
+__device__ __forceinline__ const uint32_t *sorted_vals(const uint32_t *va, const uint32_t *vb, uint64_t mask)
+{
+    return pass_parity(mask, 8) ? vb : va;
+}
+
+__global__ __launch_bounds__(kT) void k_race_sweep_reduce(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
+                                                          const uint32_t *vb, const uint64_t *maskp,
+                                                          const cg_transfer *recs, const uint32_t *streams,
+                                                          uint64_t m, Top2 *agg)
+{
+    const uint64_t mask = *maskp;
+    const uint64_t *K = sorted_keys(ka, kb, mask);
+    const uint32_t *V = sorted_vals(va, vb, mask);
+    const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + (uint64_t)threadIdx.x * kSweepItems;
+    Sweep x{t2_none(), t2_none(), t2_none(), t2_none()};
+    for (int j = 0; j < kSweepItems; ++j) {
+        const Elem e = load_elem(K, V, recs, streams, base + j, m);
+        sweep_add_fwd(x, e);
+        sweep_add_bwd(x, e);
+    }
+    const Top2 fa = block_all(x.fa), fw = block_all(x.fw), ba = block_all(x.ba), bw = block_all(x.bw);
+    if (threadIdx.x == 0) {
+        Top2 *o = agg + (uint64_t)blockIdx.x * 4;
+        o[0] = fa;
+        o[1] = fw;
+        o[2] = ba;
+        o[3] = bw;
+    }
+}
+
+// per sweep tile: combine of the tiles before it (ends) and after it (starts)
+__global__ __launch_bounds__(kT) void k_race_sweep_scan(const Top2 *agg, uint32_t tiles, Top2 *pre)
+{
+    const uint32_t per = (tiles + kT - 1) / kT;
+    const uint32_t lo = min(tiles, threadIdx.x * per), hi = min(tiles, lo + per);
+    Sweep c{t2_none(), t2_none(), t2_none(), t2_none()};
+    for (uint32_t b = lo; b < hi; ++b) {
+        c.fa = t2_combine(c.fa, agg[(uint64_t)b * 4 + 0]);
+        c.fw = t2_combine(c.fw, agg[(uint64_t)b * 4 + 1]);
+        c.ba = t2_combine(c.ba, agg[(uint64_t)b * 4 + 2]);
+        c.bw = t2_combine(c.bw, agg[(uint64_t)b * 4 + 3]);
+    }
+    Top2 fa = block_excl<true>(c.fa), fw = block_excl<true>(c.fw);
+    Top2 ba = block_excl<false>(c.ba), bw = block_excl<false>(c.bw);
+    for (uint32_t b = lo; b < hi; ++b) {
+        pre[(uint64_t)b * 4 + 0] = fa;
+        pre[(uint64_t)b * 4 + 1] = fw;
+        fa = t2_combine(fa, agg[(uint64_t)b * 4 + 0]);
+        fw = t2_combine(fw, agg[(uint64_t)b * 4 + 1]);
+    }
+    for (uint32_t b = hi; b > lo; --b) {
+        pre[(uint64_t)(b - 1) * 4 + 2] = ba;
+        pre[(uint64_t)(b - 1) * 4 + 3] = bw;
+        ba = t2_combine(ba, agg[(uint64_t)(b - 1) * 4 + 2]);
+        bw = t2_combine(bw, agg[(uint64_t)(b - 1) * 4 + 3]);
+    }
+}
+
+// per interval: a record of another stream it meets (writes: any access;
+// reads: writes), or kNoRec
+__global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
+                                                         const uint32_t *vb, const uint64_t *maskp,
+                                                         const cg_transfer *recs, const uint32_t *streams,
+                                                         uint64_t m, const Top2 *pre, uint32_t *res)
+{
+    const uint64_t mask = *maskp;
+    const uint64_t *K = sorted_keys(ka, kb, mask);
+    const uint32_t *V = sorted_vals(va, vb, mask);
+    const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + (uint64_t)threadIdx.x * kSweepItems;
+    Elem e[kSweepItems];
+    Sweep own{t2_none(), t2_none(), t2_none(), t2_none()};
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {
+        e[j] = load_elem(K, V, recs, streams, base + j, m);
+        sweep_add_fwd(own, e[j]);
+        sweep_add_bwd(own, e[j]);
+    }
+    const Top2 *P = pre + (uint64_t)blockIdx.x * 4;
+    Sweep x;
+    x.fa = t2_combine(P[0], block_excl<true>(own.fa));
+    x.fw = t2_combine(P[1], block_excl<true>(own.fw));
+    x.ba = t2_combine(P[2], block_excl<false>(own.ba));
+    x.bw = t2_combine(P[3], block_excl<false>(own.bw));
+    uint32_t hit[kSweepItems];
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {
+        hit[j] = kNoRec;
+        if (e[j].valid) {
+            uint64_t v;
+            uint32_t r;
+            t2_other(e[j].w ? x.fa : x.fw, e[j].s, &v, &r);
+            if (v > e[j].start) hit[j] = r;
+        }
+        sweep_add_fwd(x, e[j]);
+    }
+#pragma unroll
+    for (int j = kSweepItems - 1; j >= 0; --j) {
+        if (e[j].valid && hit[j] == kNoRec) {
+            uint64_t v;
+            uint32_t r;
+            t2_other(e[j].w ? x.ba : x.bw, e[j].s, &v, &r);
+            if (~v < e[j].end) hit[j] = r;
+        }
+        sweep_add_bwd(x, e[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j)
+        if (e[j].present) res[e[j].iv] = hit[j];
+}
+
+__global__ __launch_bounds__(kT) void k_race_finalize(const cg_transfer *recs, const uint32_t *epochs,
+                                                      uint64_t count, const uint32_t *res, cg_race *out)
+{
+    const uint64_t r = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= count) return;
+    const cg_transfer t = recs[r];
+    const uint32_t e = epochs ? epochs[r] : 0u;
+    cg_race o;
+    o.reserved = 0;
+    if (!rec_checked(t, e)) {
+        o.flags = CG_RACE_UNCHECKED;
+        o.partner = CG_NONE;
+    } else {
+        const uint32_t ps = res[2 * r], pd = res[2 * r + 1];
+        o.flags = (ps != kNoRec ? CG_RACE_SRC : 0u) | (pd != kNoRec ? CG_RACE_DST : 0u);
+        const uint32_t p = pd != kNoRec ? pd : ps;
+        o.partner = p == kNoRec ? CG_NONE : (uint64_t)p;
+    }
+    out[r] = o;
+}
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+hipError_t race_reserve(RaceWs &w, uint64_t intervals)
+{
+    if (intervals <= w.cap) return hipSuccess;
+    race_release(w);
+    const uint64_t tiles = ceil_div(intervals, kSortTile), sweeps = ceil_div(intervals, kSweepTile);
+    hipError_t e = hipSuccess;
+    auto get = [&](void **p, uint64_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 8);
+    };
+    for (int i = 0; i < 2; ++i) {
+        get((void **)&w.keys[i], intervals * sizeof(uint64_t));
+        get((void **)&w.vals[i], intervals * sizeof(uint32_t));
+    }
+    get((void **)&w.counts, 256 * tiles * sizeof(uint32_t));
+    get((void **)&w.dtot, 256 * sizeof(uint32_t));
+    get((void **)&w.mask, sizeof(uint64_t));
+    get((void **)&w.res, intervals * sizeof(uint32_t));
+    get(&w.agg, sweeps * 4 * sizeof(Top2));
+    get(&w.pre, sweeps * 4 * sizeof(Top2));
+    if (e != hipSuccess) {
+        race_release(w);
+        return e;
+    }
+    w.cap = intervals;
+    return hipSuccess;
+}
+
+void race_release(RaceWs &w)
+{
+    void *ps[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.counts, w.dtot, w.mask, w.res, w.agg, w.pre};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    w = RaceWs{};
+}
+
+hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *streams, const uint32_t *epochs,
+                       uint64_t count, cg_race *out, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const uint64_t m = 2 * count;
+    const uint32_t tiles = (uint32_t)ceil_div(m, kSortTile);
+    const uint32_t sweeps = (uint32_t)ceil_div(m, kSweepTile);
+    hipLaunchKernelGGL(k_race_init, dim3(1), dim3(1), 0, s, w.mask);
+    hipLaunchKernelGGL(k_race_keys, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, recs, epochs, m, w.keys[0],
+                       w.vals[0], w.mask);
+    for (int pass = 0; pass < 8; ++pass) {
+        hipLaunchKernelGGL(k_race_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], m, tiles, w.mask, pass,
+                           w.counts);
+        hipLaunchKernelGGL(k_race_scan_digits, dim3(256), dim3(kT), 0, s, w.counts, tiles, w.dtot, w.mask, pass);
+        hipLaunchKernelGGL(k_race_scatter, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
+                           m, tiles, w.mask, pass, w.counts, w.dtot);
+    }
+    Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
+    hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
+                       w.mask, recs, streams, m, agg);
+    hipLaunchKernelGGL(k_race_sweep_scan, dim3(1), dim3(kT), 0, s, agg, sweeps, pre);
+    hipLaunchKernelGGL(k_race_sweep_apply, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
+                       w.mask, recs, streams, m, pre, w.res);
+    hipLaunchKernelGGL(k_race_finalize, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, recs, epochs, count,
+                       w.res, out);
+    return hipGetLastError();
+}
+
+}  // namespace xc

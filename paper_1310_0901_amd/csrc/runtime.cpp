@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "host_logic.h"
+#include "race.h"
 #include "xc_internal.h"
 
 using namespace xc;
@@ -142,6 +143,7 @@ struct cg_ctx {
     // ordering
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
+    std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
     // timing
@@ -733,6 +735,7 @@ int cg_destroy(cg_ctx *c)
         if (kv.second->done) (void)hipEventDestroy(kv.second->done);
         delete kv.second;
     }
+    for (auto &kv : c->race_ws) race_release(kv.second);
     for (auto &p : c->tpairs) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -905,6 +908,30 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
 int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)
 {
     return check_transfers(c, recs_dev, count, nullptr, CG_PROPAGATE, hip_stream);
+}
+
+int check_concurrent(cg_ctx *c, const cg_transfer *recs_dev, const uint32_t *streams_dev, const uint32_t *epochs_dev,
+                     uint64_t count, cg_race *out_dev, void *hip_stream)
+{
+    if (!c) return CG_EINVAL;
+    if (count == 0) return CG_OK;
+    if (!recs_dev || !streams_dev || !out_dev) return fail(c, CG_EINVAL, "null records, streams or results");
+    if (count > (1ull << 30)) return fail(c, CG_EINVAL, "at most 2^30 records per join");
+    if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    RaceWs &w = c->race_ws[s];
+    if (w.cap < 2 * count) {
+        // the buffers may still be read by an earlier join on this stream
+        HIPTRY(c, hipStreamSynchronize(s));
+        uint64_t cap = 1u << 12;
+        while (cap < 2 * count) cap <<= 1;
+        const hipError_t e = race_reserve(w, cap);
+        if (e == hipErrorOutOfMemory) return fail(c, CG_ENOMEM, "join work space");
+        if (e != hipSuccess) return fail(c, CG_EHIP, std::string("join work space: ") + hipGetErrorString(e));
+    }
+    const hipError_t e = race_launch(w, recs_dev, streams_dev, epochs_dev, count, out_dev, s);
+    if (e != hipSuccess) return fail(c, CG_EHIP, std::string("join launch: ") + hipGetErrorString(e));
+    return CG_OK;
 }
 
 int cg_sync(cg_ctx *c)

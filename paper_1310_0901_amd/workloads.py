@@ -46,6 +46,8 @@ VERDICT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"),
                           ("avail", "<u8")])
 # serving event log entry (48 bytes) and per-request result (72 bytes)
 EV_CHECK, EV_ALLOC, EV_FREE = 0, 1, 2
+# one result of the concurrent-access join (cg_race)
+RACE_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("partner", "<u8")])
 SERVE_EVENT_DTYPE = np.dtype([("t", "<f8"), ("type", "<u4"), ("reserved", "<u4"),
                               ("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("rsv", "<u4")])
 SERVE_RESULT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
@@ -650,3 +652,54 @@ def small_config(k: int) -> Workload:
 
 def full_config(k: int) -> Workload:
     return {1: config1, 2: config2, 3: config3, 4: config4}[k]()
+
+
+# ---- concurrent-access batches ------------------------------------------------
+
+@dataclass
+class RaceBatch:
+    """Records with the stream each was issued on and its epoch (synchronising
+    calls before it)."""
+    records: np.ndarray      # RECORD_DTYPE
+    streams: np.ndarray      # uint32
+    epochs: np.ndarray       # uint32
+    desc: str = ""
+
+
+def race_from_records(records, seed=SEED0 + 6, streams=8, epoch_len=4096, desc="") -> RaceBatch:
+    """A multi-stream program's copies: each record on one of `streams`
+    streams (uniform), with a synchronisation after every `epoch_len` copies."""
+    rng = np.random.default_rng(seed)
+    T = records.size
+    st = rng.integers(0, streams, size=T).astype(np.uint32)
+    ep = (np.arange(T, dtype=np.int64) // epoch_len).astype(np.uint32)
+    return RaceBatch(np.ascontiguousarray(records, RECORD_DTYPE), st, ep, desc)
+
+
+def race_config(seed=SEED0 + 6, streams=8, epoch_len=4096) -> RaceBatch:
+    """The 1,000,000 transfers of configuration 3 issued from `streams`
+    streams, synchronised every `epoch_len` copies."""
+    w = config3()
+    return race_from_records(w.records, seed, streams, epoch_len,
+                             f"race-1M: configuration 3's {w.records.size} transfers on {streams} streams, "
+                             f"a synchronisation every {epoch_len} copies")
+
+
+def small_race(seed=SEED0 + 7, count=20_000, window=1 << 16, streams=8, epochs=4,
+               p_bad_kind=0.01, p_empty=0.02) -> RaceBatch:
+    """Dense overlaps: records over a 64 KiB device window and a 64 KiB host
+    window, log-uniform sizes 1..4096, a few bad kinds and empty records."""
+    rng = np.random.default_rng(seed)
+    kind = rng.choice(3, size=count, p=[0.4, 0.3, 0.3]).astype(np.int64)
+    n = log_uniform_int(rng, 1, 4096, count)
+    n[rng.random(count) < p_empty] = 0
+    dev = lambda: DEV_BASE + rng.integers(0, window, size=count)
+    host = HOST_BASE + rng.integers(0, window, size=count)
+    d1, d2 = dev(), dev()
+    src = np.where(kind == KIND_H2D, host, d1)
+    dst = np.where(kind == KIND_D2H, host, np.where(kind == KIND_D2D, d2, d1))
+    kind[rng.random(count) < p_bad_kind] = 3
+    recs = make_records(kind, src, dst, n)
+    st = rng.integers(0, streams, size=count).astype(np.uint32)
+    ep = rng.integers(0, epochs, size=count).astype(np.uint32)
+    return RaceBatch(recs, st, ep, f"small-race: {count} records, {streams} streams, {epochs} epochs")

@@ -24,6 +24,7 @@ CG_SRC_UNADDR, CG_SRC_UNDEF, CG_SRC_UNALLOC, CG_SRC_OVERRUN = 0x1, 0x2, 0x4, 0x8
 CG_DST_UNADDR, CG_DST_UNALLOC, CG_DST_OVERRUN = 0x10, 0x20, 0x40
 CG_OVERLAP, CG_BAD_KIND = 0x80, 0x100
 CG_NONE = 0xFFFF_FFFF_FFFF_FFFF
+CG_RACE_SRC, CG_RACE_DST, CG_RACE_UNCHECKED = 0x1, 0x2, 0x4
 # modes
 CG_CHECK, CG_PROPAGATE, CG_PLAIN, CG_DEBUG_CONFLICTS, CG_EAGER = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -88,6 +89,7 @@ _PROTOS = {
     "shadow_ptr": (I32, [P, U64, ctypes.POINTER(P)]),
     "check_transfers": (I32, [P, P, U64, P, U32, P]),
     "propagate_shadow": (I32, [P, P, U64, P]),
+    "check_concurrent": (I32, [P, P, P, P, U64, P, P]),
     "cg_format_verdict": (I32, [ctypes.POINTER(cg_transfer), ctypes.POINTER(cg_verdict), ctypes.c_char_p, U64]),
     "cg_strerror": (ctypes.c_char_p, [I32]),
     "cg_last_error": (ctypes.c_char_p, [P]),
@@ -193,6 +195,12 @@ def check_transfers(ctx, recs_dev, count, out_dev, mode, stream=0) -> None:
 
 def propagate_shadow(ctx, recs_dev, count, stream=0) -> None:
     _chk(ctx, lib().propagate_shadow(ctx, recs_dev, count, stream), "propagate_shadow")
+
+
+def check_concurrent(ctx, recs_dev, streams_dev, epochs_dev, count, out_dev, stream=0) -> None:
+    """epochs_dev may be 0/None (all records in epoch 0)."""
+    _chk(ctx, lib().check_concurrent(ctx, recs_dev, streams_dev, epochs_dev or None, count, out_dev, stream),
+         "check_concurrent")
 
 
 def cg_format_verdict(rec, verdict) -> str:
