@@ -270,6 +270,46 @@ def serving_leg(plain_seconds):
     return out
 
 
+def concurrency_leg(records, reps=10):
+    """Concurrent-access join: the 1,000,000 transfers of configuration 3 on
+    8 streams with a synchronisation every 4,096 copies; whole-join time from
+    events on the stream the join runs on."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd import workloads as W, xfercheck as X
+    b = W.race_from_records(records)
+    T = b.records.size
+    dev = torch.device("cuda", 0)
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).copy()).to(dev)
+    rt, st, et = up(b.records), up(b.streams), up(b.epochs)
+    out = torch.empty(T * 16, dtype=torch.uint8, device=dev)
+    ctx = X.cg_create(0, 1 << 16, 16)
+    try:
+        s = torch.cuda.current_stream(dev)
+        run = lambda: X.check_concurrent(ctx, rt.data_ptr(), st.data_ptr(), et.data_ptr(), T, out.data_ptr(),
+                                         s.cuda_stream)
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            run()
+        e1.record(s)
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1) / reps
+        res = out.cpu().numpy().view(W.RACE_DTYPE)
+    finally:
+        X.cg_destroy(ctx)
+    f = res["flags"]
+    o = {"workload": "race-1M: configuration 3's transfers on 8 streams, a synchronisation every 4096 copies",
+         "records": int(T), "ms_per_join": round(ms, 3), "records_per_s": round(T / (ms / 1e3), 1),
+         "flagged_src": int(((f & X.CG_RACE_SRC) != 0).sum()), "flagged_dst": int(((f & X.CG_RACE_DST) != 0).sum()),
+         "unchecked": int(((f & X.CG_RACE_UNCHECKED) != 0).sum())}
+    log(f"[bench] concurrency: {o}")
+    return o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,7 +326,16 @@ def main():
     ap.add_argument("--plain-serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="skip the plain-at-scale and propagation legs (configurations 2 and 4)")
+    ap.add_argument("--leg", choices=["plain_tiny", "plain_at_scale", "propagation", "concurrency", "serving"],
+                    help="run only this extra leg and print its JSON (for profiling)")
     args = ap.parse_args()
+    if args.leg:
+        from paper_1310_0901_amd import workloads as W
+        legs = {"plain_tiny": plain_tiny_leg, "plain_at_scale": plain_at_scale_leg, "propagation": propagation_leg,
+                "concurrency": lambda: concurrency_leg(W.config3().records),
+                "serving": lambda: serving_leg(args.plain_serve_seconds)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
                                    "(see the design notes), --gpus must be 1"}))
@@ -415,6 +464,7 @@ def main():
         log(f"[bench] oracle sample {gbs:.2f} GB/s on {threads} threads, identical: {same}")
     dw.close()
     if args.legs:
+        result["concurrency"] = concurrency_leg(w.records)
         result["plain_tiny"] = plain_tiny_leg()
         result["plain_at_scale"] = plain_at_scale_leg()
         result["propagation"] = propagation_leg()

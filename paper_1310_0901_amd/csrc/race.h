@@ -16,6 +16,7 @@ struct RaceWs {
     uint32_t *counts = nullptr;               // per-digit, per-tile counts [256][tiles]
     uint32_t *dtot = nullptr;                 // per-digit totals [256]
     uint64_t *mask = nullptr;                 // key bits that differ between intervals
+    uint64_t *parts = nullptr;                // per key-building block: its part of mask
     uint32_t *res = nullptr;                  // per-interval partner (or none)
     void *agg = nullptr;                      // per sweep tile: 4 monoid aggregates
     void *pre = nullptr;                      // per sweep tile: prefix / suffix of those

@@ -71,10 +71,8 @@ __device__ __forceinline__ int pass_parity(uint64_t mask, int pass)
     return p;
 }
 
-__global__ void k_race_init(uint64_t *mask) { *mask = 0; }
-
 __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const uint32_t *epochs, uint64_t m,
-                                                  uint64_t *keys, uint32_t *vals, uint64_t *mask)
+                                                  uint64_t *keys, uint32_t *vals, uint64_t *parts)
 {
     __shared__ uint64_t part[kWaves];
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
@@ -92,7 +90,23 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
     if (threadIdx.x == 0) {
         uint64_t y = 0;
         for (int w = 0; w < kWaves; ++w) y |= part[w];
-        if (y) atomicOr((unsigned long long *)mask, (unsigned long long)y);
+        parts[blockIdx.x] = y;
+    }
+}
+
+// the key bits that differ anywhere: OR of the per-block partials
+__global__ __launch_bounds__(kT) void k_race_mask(const uint64_t *parts, uint32_t nparts, uint64_t *mask)
+{
+    __shared__ uint64_t part[kWaves];
+    uint64_t x = 0;
+    for (uint32_t j = threadIdx.x; j < nparts; j += kT) x |= parts[j];
+    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t y = 0;
+        for (int w = 0; w < kWaves; ++w) y |= part[w];
+        *mask = y;
     }
 }
 
@@ -270,25 +284,22 @@ __global__ __launch_bounds__(kT) void k_race_scatter(uint64_t *ka, uint64_t *kb,
 
 // ---- sweep ---------------------------------------------------------------
 
-// The best two entries (value, record) of distinct streams: (v1, s1, r1) is
-// the best overall, (v2, r2) the best of any stream other than s1.  "Best" is
-// the larger value, ties to the smaller record index.  Ends are kept as they
-// are (furthest end wins); starts as their complement (smallest start wins).
+// The best two entries (value, record) of distinct streams: (v1, s1, r1) has
+// the largest value, (v2, r2) the largest value of any stream other than s1.
+// Ends are kept as they are (furthest end wins), starts as their complement
+// (smallest start wins).  Between equal values either entry may be kept: the
+// values, which decide every conflict, come out the same, and any entry kept
+// names a valid partner; the combining order is fixed, so results repeat.
 struct Top2 {
     uint64_t v1, v2;
     uint32_t s1, r1, r2;
 };
 
-__device__ __forceinline__ bool beats(uint64_t va, uint32_t ra, uint64_t vb, uint32_t rb)
-{
-    return va > vb || (va == vb && ra < rb);
-}
-
 __device__ __forceinline__ Top2 t2_none() { return Top2{0, 0, kNoStream, kNoRec, kNoRec}; }
 
 __device__ __forceinline__ Top2 t2_combine(const Top2 &x, const Top2 &y)
 {
-    const bool xw = beats(x.v1, x.r1, y.v1, y.r1);
+    const bool xw = x.v1 >= y.v1;
     const Top2 a = xw ? x : y, b = xw ? y : x;
     Top2 o;
     o.v1 = a.v1;
@@ -297,15 +308,29 @@ __device__ __forceinline__ Top2 t2_combine(const Top2 &x, const Top2 &y)
     const bool other = b.s1 != a.s1;
     const uint64_t cv = other ? b.v1 : b.v2;
     const uint32_t cr = other ? b.r1 : b.r2;
-    const bool keep = beats(a.v2, a.r2, cv, cr);
+    const bool keep = a.v2 >= cv;
     o.v2 = keep ? a.v2 : cv;
     o.r2 = keep ? a.r2 : cr;
     return o;
 }
 
+// insert one entry
 __device__ __forceinline__ Top2 t2_add(const Top2 &x, uint64_t v, uint32_t s, uint32_t r)
 {
-    return t2_combine(x, Top2{v, 0, s, r, kNoRec});
+    Top2 o = x;
+    if (v > x.v1) {
+        // the old best stays as the second unless it has this stream
+        const bool other = x.s1 != s;
+        o.v2 = other ? x.v1 : x.v2;
+        o.r2 = other ? x.r1 : x.r2;
+        o.v1 = v;
+        o.s1 = s;
+        o.r1 = r;
+    } else if (s != x.s1 && v > x.v2) {
+        o.v2 = v;
+        o.r2 = r;
+    }
+    return o;
 }
 
 // the best entry of a stream other than s
@@ -377,24 +402,58 @@ struct Elem {
     bool valid, w, present;
 };
 
-__device__ __forceinline__ Elem load_elem(const uint64_t *K, const uint32_t *V, const cg_transfer *recs,
-                                          const uint32_t *streams, uint64_t p, uint64_t m)
+// The sorted order's keys K and interval ids V, with the end keys E and
+// streams S that k_race_gather laid out beside them.
+struct Sorted {
+    const uint64_t *K, *E;
+    const uint32_t *V, *S;
+};
+
+__device__ __forceinline__ Sorted sorted_view(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
+                                              const uint32_t *vb, uint64_t mask)
+{
+    const bool b = pass_parity(mask, 8) != 0;
+    return Sorted{b ? kb : ka, b ? ka : kb, b ? vb : va, b ? va : vb};
+}
+
+__device__ __forceinline__ Elem load_elem(const Sorted &o, uint64_t p, uint64_t m)
 {
     Elem e{kInvalidKey, 0, kNoStream, kNoRec, 0, false, false, false};
     if (p < m) {
-        const uint64_t k = K[p];
-        e.iv = V[p];
+        const uint64_t k = o.K[p];
+        e.iv = o.V[p];
         e.present = e.iv < m;
         if (e.present && !(k >> 63)) {
             e.valid = true;
             e.r = e.iv >> 1;
             e.w = (e.iv & 1u) != 0;
             e.start = k;
-            e.end = k + recs[e.r].n;
-            e.s = streams[e.r];
+            e.end = o.E[p];
+            e.s = o.S[p];
         }
     }
     return e;
+}
+
+// end key and stream of every sorted interval, written into the ping-pong
+// buffers that do not hold the sorted order
+__global__ __launch_bounds__(kT) void k_race_gather(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
+                                                    const uint64_t *maskp, const cg_transfer *recs,
+                                                    const uint32_t *streams, uint64_t m)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= m) return;
+    const bool b = pass_parity(*maskp, 8) != 0;
+    const uint64_t k = (b ? kb : ka)[p];
+    const uint32_t iv = (b ? vb : va)[p];
+    uint64_t end = 0;
+    uint32_t s = kNoStream;
+    if (!(k >> 63) && iv < m) {
+        end = k + recs[iv >> 1].n;
+        s = streams[iv >> 1];
+    }
+    (b ? ka : kb)[p] = end;
+    (b ? va : vb)[p] = s;
 }
 
 // the four running combines: ends and starts, of all intervals and of writes
@@ -416,28 +475,16 @@ __device__ __forceinline__ void sweep_add_bwd(Sweep &x, const Elem &e)
     if (e.w) x.bw = t2_add(x.bw, ~e.start, e.s, e.r);
 }
 
-__device__ __forceinline__ const uint64_t *sorted_keys(const uint64_t *ka, const uint64_t *kb, uint64_t mask)
-{
-    return pass_parity(mask, 8) ? kb : ka;
-}
-
-__device__ __forceinline__ const uint32_t *sorted_vals(const uint32_t *va, const uint32_t *vb, uint64_t mask)
-{
-    return pass_parity(mask, 8) ? vb : va;
-}
-
 __global__ __launch_bounds__(kT) void k_race_sweep_reduce(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
-                                                          const uint32_t *vb, const uint64_t *maskp,
-                                                          const cg_transfer *recs, const uint32_t *streams,
-                                                          uint64_t m, Top2 *agg)
+                                                          const uint32_t *vb, const uint64_t *maskp, uint64_t m,
+                                                          Top2 *agg)
 {
-    const uint64_t mask = *maskp;
-    const uint64_t *K = sorted_keys(ka, kb, mask);
-    const uint32_t *V = sorted_vals(va, vb, mask);
-    const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + (uint64_t)threadIdx.x * kSweepItems;
+    const Sorted o = sorted_view(ka, kb, va, vb, *maskp);
+    // the combines do not depend on order: read the tile lane-contiguously
+    const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + threadIdx.x;
     Sweep x{t2_none(), t2_none(), t2_none(), t2_none()};
     for (int j = 0; j < kSweepItems; ++j) {
-        const Elem e = load_elem(K, V, recs, streams, base + j, m);
+        const Elem e = load_elem(o, base + (uint64_t)j * kT, m);
         sweep_add_fwd(x, e);
         sweep_add_bwd(x, e);
     }
@@ -481,22 +528,56 @@ __global__ __launch_bounds__(kT) void k_race_sweep_scan(const Top2 *agg, uint32_
 
 // per interval: a record of another stream it meets (writes: any access;
 // reads: writes), or kNoRec
+// LDS slot of tile element i: one pad slot per kSweepItems elements, so that
+// threads reading their own consecutive runs spread over the banks
+__device__ __forceinline__ int pad_slot(int i) { return i + i / kSweepItems; }
+constexpr int kSweepSlots = kSweepTile + kSweepTile / kSweepItems;
+
 __global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
-                                                         const uint32_t *vb, const uint64_t *maskp,
-                                                         const cg_transfer *recs, const uint32_t *streams,
-                                                         uint64_t m, const Top2 *pre, uint32_t *res)
+                                                         const uint32_t *vb, const uint64_t *maskp, uint64_t m,
+                                                         const Top2 *pre, uint32_t *res)
 {
-    const uint64_t mask = *maskp;
-    const uint64_t *K = sorted_keys(ka, kb, mask);
-    const uint32_t *V = sorted_vals(va, vb, mask);
-    const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + (uint64_t)threadIdx.x * kSweepItems;
-    Elem e[kSweepItems];
-    Sweep own{t2_none(), t2_none(), t2_none(), t2_none()};
-#pragma unroll
+    __shared__ uint64_t sk[kSweepSlots], se[kSweepSlots];
+    __shared__ uint32_t sv[kSweepSlots], ss[kSweepSlots];
+    const Sorted o = sorted_view(ka, kb, va, vb, *maskp);
+    const uint64_t tile = (uint64_t)blockIdx.x * kSweepTile;
+    // stage the tile through LDS: read lane-contiguously, walk per thread
     for (int j = 0; j < kSweepItems; ++j) {
-        e[j] = load_elem(K, V, recs, streams, base + j, m);
-        sweep_add_fwd(own, e[j]);
-        sweep_add_bwd(own, e[j]);
+        const int i = j * kT + threadIdx.x;
+        const uint64_t p = tile + i;
+        const int q = pad_slot(i);
+        if (p < m) {
+            sk[q] = o.K[p];
+            se[q] = o.E[p];
+            sv[q] = o.V[p];
+            ss[q] = o.S[p];
+        } else {
+            sk[q] = kInvalidKey;
+            sv[q] = kNoRec;
+        }
+    }
+    __syncthreads();
+    const int first = threadIdx.x * kSweepItems;
+    auto elem = [&](int j) {
+        const int q = pad_slot(first + j);
+        Elem e{kInvalidKey, 0, kNoStream, kNoRec, sv[q], false, false, false};
+        e.present = e.iv < m;
+        const uint64_t k = sk[q];
+        if (e.present && !(k >> 63)) {
+            e.valid = true;
+            e.r = e.iv >> 1;
+            e.w = (e.iv & 1u) != 0;
+            e.start = k;
+            e.end = se[q];
+            e.s = ss[q];
+        }
+        return e;
+    };
+    Sweep own{t2_none(), t2_none(), t2_none(), t2_none()};
+    for (int j = 0; j < kSweepItems; ++j) {
+        const Elem e = elem(j);
+        sweep_add_fwd(own, e);
+        sweep_add_bwd(own, e);
     }
     const Top2 *P = pre + (uint64_t)blockIdx.x * 4;
     Sweep x;
@@ -507,28 +588,28 @@ __global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, con
     uint32_t hit[kSweepItems];
 #pragma unroll
     for (int j = 0; j < kSweepItems; ++j) {
+        const Elem e = elem(j);
         hit[j] = kNoRec;
-        if (e[j].valid) {
+        if (e.valid) {
             uint64_t v;
             uint32_t r;
-            t2_other(e[j].w ? x.fa : x.fw, e[j].s, &v, &r);
-            if (v > e[j].start) hit[j] = r;
+            t2_other(e.w ? x.fa : x.fw, e.s, &v, &r);
+            if (v > e.start) hit[j] = r;
         }
-        sweep_add_fwd(x, e[j]);
+        sweep_add_fwd(x, e);
     }
 #pragma unroll
     for (int j = kSweepItems - 1; j >= 0; --j) {
-        if (e[j].valid && hit[j] == kNoRec) {
+        const Elem e = elem(j);
+        if (e.valid && hit[j] == kNoRec) {
             uint64_t v;
             uint32_t r;
-            t2_other(e[j].w ? x.ba : x.bw, e[j].s, &v, &r);
-            if (~v < e[j].end) hit[j] = r;
+            t2_other(e.w ? x.ba : x.bw, e.s, &v, &r);
+            if (~v < e.end) hit[j] = r;
         }
-        sweep_add_bwd(x, e[j]);
+        sweep_add_bwd(x, e);
+        if (e.present) res[e.iv] = hit[j];
     }
-#pragma unroll
-    for (int j = 0; j < kSweepItems; ++j)
-        if (e[j].present) res[e[j].iv] = hit[j];
 }
 
 __global__ __launch_bounds__(kT) void k_race_finalize(const cg_transfer *recs, const uint32_t *epochs,
@@ -572,6 +653,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
     get((void **)&w.counts, 256 * tiles * sizeof(uint32_t));
     get((void **)&w.dtot, 256 * sizeof(uint32_t));
     get((void **)&w.mask, sizeof(uint64_t));
+    get((void **)&w.parts, ceil_div(intervals, kT) * sizeof(uint64_t));
     get((void **)&w.res, intervals * sizeof(uint32_t));
     get(&w.agg, sweeps * 4 * sizeof(Top2));
     get(&w.pre, sweeps * 4 * sizeof(Top2));
@@ -585,7 +667,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
 
 void race_release(RaceWs &w)
 {
-    void *ps[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.counts, w.dtot, w.mask, w.res, w.agg, w.pre};
+    void *ps[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.counts, w.dtot, w.mask, w.parts, w.res, w.agg, w.pre};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     w = RaceWs{};
@@ -598,9 +680,9 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
     const uint64_t m = 2 * count;
     const uint32_t tiles = (uint32_t)ceil_div(m, kSortTile);
     const uint32_t sweeps = (uint32_t)ceil_div(m, kSweepTile);
-    hipLaunchKernelGGL(k_race_init, dim3(1), dim3(1), 0, s, w.mask);
-    hipLaunchKernelGGL(k_race_keys, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, recs, epochs, m, w.keys[0],
-                       w.vals[0], w.mask);
+    const uint32_t kblocks = (uint32_t)ceil_div(m, kT);
+    hipLaunchKernelGGL(k_race_keys, dim3(kblocks), dim3(kT), 0, s, recs, epochs, m, w.keys[0], w.vals[0], w.parts);
+    hipLaunchKernelGGL(k_race_mask, dim3(1), dim3(kT), 0, s, w.parts, kblocks, w.mask);
     for (int pass = 0; pass < 8; ++pass) {
         hipLaunchKernelGGL(k_race_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], m, tiles, w.mask, pass,
                            w.counts);
@@ -609,11 +691,13 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
                            m, tiles, w.mask, pass, w.counts, w.dtot);
     }
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
+    hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0],
+                       w.vals[1], w.mask, recs, streams, m);
     hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
-                       w.mask, recs, streams, m, agg);
+                       w.mask, m, agg);
     hipLaunchKernelGGL(k_race_sweep_scan, dim3(1), dim3(kT), 0, s, agg, sweeps, pre);
     hipLaunchKernelGGL(k_race_sweep_apply, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
-                       w.mask, recs, streams, m, pre, w.res);
+                       w.mask, m, pre, w.res);
     hipLaunchKernelGGL(k_race_finalize, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, recs, epochs, count,
                        w.res, out);
     return hipGetLastError();
