@@ -26,6 +26,16 @@
 // batch of its rows (strided copies, the case of the paper's footnote to
 // the error list of Sec. 2) and reported once, with its first faulty row.
 //
+// Concurrent accesses (the error class of Sec. 2 for programs with several
+// threads): every asynchronous copy that was performed joins a window, with
+// the stream it was issued on.  The next synchronising call (device, stream
+// or event synchronisation, a stream waiting for an event, a synchronous copy
+// or hipFree) closes the window: check_concurrent joins its copies, and every
+// pair on different streams where one writes bytes the other reads or writes
+// is reported.  Copies of one window are taken as unordered unless they share
+// a stream; copies in different windows as ordered, so a race across a
+// synchronising call is not reported (no false reports, possibly missed ones).
+//
 // Environment: XC_POOL_BYTES (shadow pool, default 1 GiB), XC_MAX_ALLOCS
 // (default 1,048,576), XC_REPORT_DEVICE_UNDEF, XC_ALLOW_BAD, XC_QUIET=1 (no
 // summary line).
@@ -36,7 +46,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <mutex>
+#include <set>
 #include <vector>
 
 #include "../../include/xfercheck.h"
@@ -65,6 +78,16 @@ using dtoh_t = hipError_t (*)(void *, hipDeviceptr_t, size_t);
 using dtod_t = hipError_t (*)(hipDeviceptr_t, hipDeviceptr_t, size_t);
 using memcpy_async_t = hipError_t (*)(void *, const void *, size_t, hipMemcpyKind, hipStream_t);
 using memcpy2d_t = hipError_t (*)(void *, size_t, const void *, size_t, size_t, size_t, hipMemcpyKind);
+using devsync_t = hipError_t (*)();
+using streamsync_t = hipError_t (*)(hipStream_t);
+using eventsync_t = hipError_t (*)(hipEvent_t);
+using waitevent_t = hipError_t (*)(hipStream_t, hipEvent_t, unsigned int);
+
+// an asynchronous copy waiting in the window
+struct WinCopy {
+    cg_transfer r;
+    hipStream_t stream;
+};
 
 struct State {
     std::mutex mu;
@@ -81,6 +104,13 @@ struct State {
     bool allow_bad = false;
     bool quiet = false;
     uint64_t copies = 0, errors = 0;
+    // the window of asynchronous copies since the last synchronising call
+    std::vector<WinCopy> win;
+    cg_transfer *d_wrec = nullptr;
+    uint32_t *d_wsid = nullptr;
+    cg_race *d_wres = nullptr;
+    uint64_t win_cap = 0;
+    uint64_t races = 0;
 } G;
 
 uint64_t env_u64(const char *k, uint64_t d)
@@ -91,8 +121,11 @@ uint64_t env_u64(const char *k, uint64_t d)
 
 void summary()
 {
-    if (G.ctx && !G.quiet)
-        fprintf(stderr, "==xfercheck== %" PRIu64 " copies checked, %" PRIu64 " with errors\n", G.copies, G.errors);
+    if (G.ctx && !G.quiet) {
+        fprintf(stderr, "==xfercheck== %" PRIu64 " copies checked, %" PRIu64 " with errors", G.copies, G.errors);
+        if (G.races) fprintf(stderr, ", %" PRIu64 " concurrent-access pairs", G.races);
+        fprintf(stderr, "\n");
+    }
 }
 
 bool ensure_ctx()
@@ -232,6 +265,87 @@ bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t 
     return check_rows(api, (uint8_t *)dst, 0, (const uint8_t *)src, 0, n, 1, kind);
 }
 
+bool meets(uint64_t a, uint64_t na, uint64_t b, uint64_t nb) { return na && nb && a < b + nb && b < a + na; }
+
+void describe(char *buf, size_t len, const cg_transfer &r, hipStream_t s)
+{
+    snprintf(buf, len, "hipMemcpyAsync(dst=%p, src=%p, %" PRIu64 " bytes, %s) on stream %p", (void *)r.dst,
+             (void *)r.src, r.n, kind_name(r.kind), (void *)s);
+}
+
+// Join the window's copies and report each conflicting pair once; the caller
+// holds G.mu.  The window is emptied.
+void close_window()
+{
+    std::vector<WinCopy> w;
+    w.swap(G.win);
+    if (w.size() < 2 || !G.ctx) return;
+    std::map<hipStream_t, uint32_t> ids;
+    std::vector<uint32_t> sid(w.size());
+    std::vector<cg_transfer> r(w.size());
+    for (size_t i = 0; i < w.size(); ++i) {
+        sid[i] = ids.emplace(w[i].stream, (uint32_t)ids.size()).first->second;
+        r[i] = w[i].r;
+    }
+    if (ids.size() < 2) return;   // one stream: all ordered
+    Guard g;
+    const uint64_t n = w.size();
+    if (n > G.win_cap) {
+        (void)hipStreamSynchronize(G.s);
+        (void)hipFree(G.d_wrec);
+        (void)hipFree(G.d_wsid);
+        (void)hipFree(G.d_wres);
+        G.d_wrec = nullptr;
+        G.d_wsid = nullptr;
+        G.d_wres = nullptr;
+        G.win_cap = 0;
+        uint64_t cap = 64;
+        while (cap < n) cap <<= 1;
+        if (hipMalloc(reinterpret_cast<void **>(&G.d_wrec), cap * sizeof(cg_transfer)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&G.d_wsid), cap * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&G.d_wres), cap * sizeof(cg_race)) != hipSuccess) {
+            fprintf(stderr, "==xfercheck== concurrent-access check skipped: out of device memory\n");
+            return;
+        }
+        G.win_cap = cap;
+    }
+    std::vector<cg_race> res(n);
+    if (hipMemcpyAsync(G.d_wrec, r.data(), n * sizeof(cg_transfer), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        hipMemcpyAsync(G.d_wsid, sid.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_concurrent(G.ctx, G.d_wrec, G.d_wsid, nullptr, n, G.d_wres, G.s) != CG_OK ||
+        hipMemcpyAsync(res.data(), G.d_wres, n * sizeof(cg_race), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+        hipStreamSynchronize(G.s) != hipSuccess) {
+        fprintf(stderr, "==xfercheck== concurrent-access check failed: %s\n", cg_last_error(G.ctx));
+        return;
+    }
+    std::set<std::pair<uint64_t, uint64_t>> seen;
+    for (uint64_t a = 0; a < n; ++a) {
+        if (!(res[a].flags & (CG_RACE_SRC | CG_RACE_DST)) || res[a].partner >= n) continue;
+        const uint64_t b = res[a].partner;
+        if (!seen.insert({std::min(a, b), std::max(a, b)}).second) continue;
+        const cg_transfer &x = r[a], &y = r[b];
+        // what the first copy does to the shared bytes, and what the second does
+        const bool ww = meets(x.dst, x.n, y.dst, y.n), wr = meets(x.dst, x.n, y.src, y.n);
+        const char *va = (ww || wr) ? "writes" : "reads", *vb = (ww || !wr) ? "writes" : "reads";
+        char da[256], db[256];
+        describe(da, sizeof da, x, w[a].stream);
+        describe(db, sizeof db, y, w[b].stream);
+        fprintf(stderr,
+                "Error: Concurrent copies access the same bytes without synchronisation.\n %s\n %s bytes that\n %s\n "
+                "%s.\n",
+                da, va, db, vb);
+        ++G.races;
+        ++G.errors;
+    }
+}
+
+// a synchronising call: the copies issued so far are ordered before what follows
+void sync_point()
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!G.win.empty()) close_window();
+}
+
 uint32_t direction(void *dst, const void *src, hipMemcpyKind k)
 {
     switch (k) {
@@ -273,6 +387,7 @@ hipError_t hipMalloc(void **ptr, size_t size)
 hipError_t hipFree(void *ptr)
 {
     static free_t f = real<free_t>("hipFree");
+    if (!inside) sync_point();
     if (!inside && ptr) {
         std::lock_guard<std::mutex> lk(G.mu);
         if (ensure_ctx()) {
@@ -306,6 +421,7 @@ hipError_t hipMemset(void *dst, int value, size_t n)
 hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind kind)
 {
     static memcpy_t f = real<memcpy_t>("hipMemcpy");
+    if (!inside) sync_point();
     if (!inside && n) {
         const uint32_t d = direction(dst, src, kind);
         if (d <= CG_D2D && !check_copy("hipMemcpy", dst, src, n, d)) return hipErrorInvalidValue;
@@ -316,6 +432,7 @@ hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind kind)
 hipError_t hipMemcpyHtoD(hipDeviceptr_t dst, const void *src, size_t n)
 {
     static htod_t f = real<htod_t>("hipMemcpyHtoD");
+    if (!inside) sync_point();
     if (!inside && n && !check_copy("hipMemcpyHtoD", dst, src, n, CG_H2D)) return hipErrorInvalidValue;
     return f(dst, src, n);
 }
@@ -323,6 +440,7 @@ hipError_t hipMemcpyHtoD(hipDeviceptr_t dst, const void *src, size_t n)
 hipError_t hipMemcpyDtoH(void *dst, hipDeviceptr_t src, size_t n)
 {
     static dtoh_t f = real<dtoh_t>("hipMemcpyDtoH");
+    if (!inside) sync_point();
     if (!inside && n && !check_copy("hipMemcpyDtoH", dst, src, n, CG_D2H)) return hipErrorInvalidValue;
     return f(dst, src, n);
 }
@@ -330,6 +448,7 @@ hipError_t hipMemcpyDtoH(void *dst, hipDeviceptr_t src, size_t n)
 hipError_t hipMemcpyDtoD(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n)
 {
     static dtod_t f = real<dtod_t>("hipMemcpyDtoD");
+    if (!inside) sync_point();
     if (!inside && n && !check_copy("hipMemcpyDtoD", dst, src, n, CG_D2D)) return hipErrorInvalidValue;
     return f(dst, src, n);
 }
@@ -339,15 +458,48 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind ki
     static memcpy_async_t f = real<memcpy_async_t>("hipMemcpyAsync");
     if (!inside && n) {
         const uint32_t d = direction(dst, src, kind);
-        if (d <= CG_D2D && !check_copy("hipMemcpyAsync", dst, src, n, d)) return hipErrorInvalidValue;
+        if (d <= CG_D2D) {
+            if (!check_copy("hipMemcpyAsync", dst, src, n, d)) return hipErrorInvalidValue;
+            std::lock_guard<std::mutex> lk(G.mu);
+            G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream});
+        }
     }
     return f(dst, src, n, kind, stream);
+}
+
+hipError_t hipDeviceSynchronize(void)
+{
+    static devsync_t f = real<devsync_t>("hipDeviceSynchronize");
+    if (!inside) sync_point();
+    return f();
+}
+
+hipError_t hipStreamSynchronize(hipStream_t stream)
+{
+    static streamsync_t f = real<streamsync_t>("hipStreamSynchronize");
+    if (!inside) sync_point();
+    return f(stream);
+}
+
+hipError_t hipEventSynchronize(hipEvent_t event)
+{
+    static eventsync_t f = real<eventsync_t>("hipEventSynchronize");
+    if (!inside) sync_point();
+    return f(event);
+}
+
+hipError_t hipStreamWaitEvent(hipStream_t stream, hipEvent_t event, unsigned int flags)
+{
+    static waitevent_t f = real<waitevent_t>("hipStreamWaitEvent");
+    if (!inside) sync_point();
+    return f(stream, event, flags);
 }
 
 hipError_t hipMemcpy2D(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t height,
                        hipMemcpyKind kind)
 {
     static memcpy2d_t f = real<memcpy2d_t>("hipMemcpy2D");
+    if (!inside) sync_point();
     if (!inside && width && height) {
         const uint32_t d = direction(dst, src, kind);
         if (d <= CG_D2D && !check_rows("hipMemcpy2D", (uint8_t *)dst, dpitch, (const uint8_t *)src, spitch, width,

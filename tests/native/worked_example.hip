@@ -41,9 +41,60 @@ static int pitched_and_async()
     return 0;
 }
 
+// Copies on two streams with no synchronisation between them: two uploads
+// into overlapping device bytes, then an upload and a download sharing 2 KiB;
+// then orderings that must stay quiet (one stream, a synchronisation between,
+// disjoint bytes, two reads of the same bytes).
+static int streams()
+{
+    const size_t MB = 1 << 20;
+    uint8_t *d = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;
+    if (hipMalloc((void **)&d, 2 * MB) != hipSuccess) return 2;
+    if (hipHostMalloc((void **)&h1, MB) != hipSuccess || hipHostMalloc((void **)&h2, MB) != hipSuccess ||
+        hipHostMalloc((void **)&h3, MB) != hipSuccess)
+        return 2;
+    hipMemset(d, 0, 2 * MB);
+    hipStream_t s1, s2;
+    if (hipStreamCreate(&s1) != hipSuccess || hipStreamCreate(&s2) != hipSuccess) return 2;
+    // racing: overlapping uploads
+    hipMemcpyAsync(d, h1, MB, hipMemcpyHostToDevice, s1);
+    hipMemcpyAsync(d + MB / 2, h2, MB, hipMemcpyHostToDevice, s2);
+    (void)hipDeviceSynchronize();
+    // racing: an upload and a download sharing 2 KiB
+    hipMemcpyAsync(d, h1, 4096, hipMemcpyHostToDevice, s1);
+    hipMemcpyAsync(h3, d + 2048, 4096, hipMemcpyDeviceToHost, s2);
+    (void)hipStreamSynchronize(s1);
+    // ordered: one stream
+    hipMemcpyAsync(d, h1, MB, hipMemcpyHostToDevice, s1);
+    hipMemcpyAsync(h3, d, MB, hipMemcpyDeviceToHost, s1);
+    (void)hipDeviceSynchronize();
+    // ordered: a synchronisation between
+    hipMemcpyAsync(d, h1, MB, hipMemcpyHostToDevice, s1);
+    (void)hipStreamSynchronize(s1);
+    hipMemcpyAsync(h3, d, MB, hipMemcpyDeviceToHost, s2);
+    (void)hipDeviceSynchronize();
+    // disjoint bytes
+    hipMemcpyAsync(d, h1, MB, hipMemcpyHostToDevice, s1);
+    hipMemcpyAsync(d + MB, h2, MB, hipMemcpyHostToDevice, s2);
+    (void)hipDeviceSynchronize();
+    // two reads of the same device bytes
+    hipMemcpyAsync(h1, d, 1024, hipMemcpyDeviceToHost, s1);
+    hipMemcpyAsync(h2, d, 1024, hipMemcpyDeviceToHost, s2);
+    (void)hipDeviceSynchronize();
+    (void)hipStreamDestroy(s1);
+    (void)hipStreamDestroy(s2);
+    hipFree(d);
+    (void)hipHostFree(h1);
+    (void)hipHostFree(h2);
+    (void)hipHostFree(h3);
+    printf("streams done\n");
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
     if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
+    if (argc > 1 && strcmp(argv[1], "streams") == 0) return streams();
     const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;
     const int size = 1000000;
     double *c, *a, *b;

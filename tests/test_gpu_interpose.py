@@ -61,3 +61,25 @@ def test_pitched_and_async_copies():
     assert "in row 99 of 100 (1 rows with errors)" in err
     assert "Expected 8000000 allocated bytes but only found 4000000." in err
     assert "3 copies checked, 2 with errors" in err
+
+
+def test_concurrent_copies_on_streams():
+    """Asynchronous copies on different streams with no synchronisation
+    between them, where one writes bytes the other reads or writes, are
+    reported once per pair at the next synchronising call; copies on one
+    stream, separated by a synchronisation, on disjoint bytes, or both only
+    reading, are not (the concurrent accesses of Sec. 2)."""
+    r = run_example("streams")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0 and "streams done" in r.stdout
+    err = r.stderr
+    head = "Error: Concurrent copies access the same bytes without synchronisation."
+    assert err.count(head) == 2
+    first, second = err.split(head)[1:3]
+    # the two uploads write the same half megabyte
+    assert "1048576 bytes, hipMemcpyHostToDevice" in first and "writes bytes that" in first
+    assert first.rstrip().split("\n")[-1].strip().startswith("writes.")
+    # the upload writes bytes the download reads
+    assert "4096 bytes, hipMemcpyHostToDevice" in second and "4096 bytes, hipMemcpyDeviceToHost" in second
+    assert "writes bytes that" in second and "\n reads." in second
+    assert "12 copies checked, 2 with errors, 2 concurrent-access pairs" in err
