@@ -159,3 +159,24 @@ def race_flags(rows, streams, epochs=None):
                 elif how_u == "w":
                     flags[t] |= 1
     return flags
+
+
+def pointer_checks(allocs, ptrs):
+    """(flags, base, avail) of each pointer by address sets: the allocation
+    whose byte set holds p, else the one whose byte set holds p - 1 and ends at
+    p; allocs maps base -> size (see oracle.c for the reading)."""
+    owner = {}
+    for b, z in allocs.items():
+        for x in range(b, b + z):
+            owner[x] = b
+    out = []
+    for p in ptrs:
+        if p in owner:
+            b = owner[p]
+        elif p - 1 in owner and owner[p - 1] + allocs[owner[p - 1]] == p:
+            b = owner[p - 1]
+        else:
+            out.append((1, 0, 0))
+            continue
+        out.append((0, b, b + allocs[b] - p))
+    return out

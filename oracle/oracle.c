@@ -271,3 +271,41 @@ void oracle_race(uint64_t count, const or_record *recs, const uint32_t *streams,
         flags[k] = f;
     }
 }
+
+/*
+ * Kernel-argument pointers.  The outlook (Sec. 5.1) proposes checking the
+ * pointer arguments of kernel launches against the same list of allocations.
+ * Reading evaluated here: a pointer p is valid when a live allocation
+ * [base, base + size) holds it, or when it is one past the end of one
+ * (p == base + size, as C allows for array ends); an allocation that holds p
+ * wins over one that p is one past.  Then base is that allocation's base and
+ * avail = base + size - p (0 one past the end).  Otherwise PTR_UNALLOC with
+ * base = avail = 0.
+ */
+enum { OR_PTR_UNALLOC = 1u };
+typedef struct { uint32_t flags, reserved; uint64_t base, avail; } or_ptr;
+
+void oracle_pointers(uint64_t nalloc, const uint64_t *abase, const uint64_t *asize, uint64_t count,
+                     const uint64_t *ptrs, or_ptr *out)
+{
+    for (uint64_t t = 0; t < count; t++) {
+        uint64_t p = ptrs[t];
+        int64_t hold = -1, past = -1;
+        for (uint64_t j = 0; j < nalloc; j++) {
+            wide end = (wide)abase[j] + asize[j];
+            if ((wide)abase[j] <= p && (wide)p < end) hold = (int64_t)j;
+            else if ((wide)p == end) past = (int64_t)j;
+        }
+        int64_t j = hold >= 0 ? hold : past;
+        out[t].reserved = 0;
+        if (j < 0) {
+            out[t].flags = OR_PTR_UNALLOC;
+            out[t].base = 0;
+            out[t].avail = 0;
+        } else {
+            out[t].flags = 0;
+            out[t].base = abase[j];
+            out[t].avail = abase[j] + asize[j] - p;
+        }
+    }
+}

@@ -23,6 +23,8 @@ DST_UNADDR, DST_UNALLOC, DST_OVERRUN, OVERLAP, BAD_KIND = 16, 32, 64, 128, 256
 NONE = 0xFFFF_FFFF_FFFF_FFFF
 MODE_CHECK, MODE_PROPAGATE = 1, 2
 RACE_SRC, RACE_DST, RACE_UNCHECKED = 1, 2, 4
+PTR_UNALLOC = 1
+PTR = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("base", "<u8"), ("avail", "<u8")])
 ADDR_LIMIT, EPOCH_LIMIT = 1 << 48, 1 << 15
 REC = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("reserved", "<u4")])
 VER = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
@@ -52,6 +54,9 @@ def load(path: str = LIB):
                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+            lib.oracle_pointers.restype = None
+            lib.oracle_pointers.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                            ctypes.c_void_p, ctypes.c_void_p]
             lib.oracle_race.restype = None
             lib.oracle_race.argtypes = [
                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -168,3 +173,15 @@ def conflict(ra, rb, sa, sb, ea=0, eb=0):
     dst = meets(int(ra["dst"]), n_a, int(rb["dst"]), n_b) or meets(int(ra["dst"]), n_a, int(rb["src"]), n_b)
     src = meets(int(ra["src"]), n_a, int(rb["dst"]), n_b)
     return dst, src
+
+
+def pointers(bases, sizes, ptrs, lib=None) -> np.ndarray:
+    """Check pointers (kernel arguments, Sec. 5.1) against live allocations
+    given as base and size arrays; the reading is stated in oracle.c."""
+    lib = lib or load()
+    b = np.ascontiguousarray(bases, np.uint64)
+    z = np.ascontiguousarray(sizes, np.uint64)
+    p = np.ascontiguousarray(ptrs, np.uint64)
+    out = np.zeros(p.size, PTR)
+    lib.oracle_pointers(b.size, b.ctypes.data, z.ctypes.data, p.size, p.ctypes.data, out.ctypes.data)
+    return out

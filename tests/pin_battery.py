@@ -55,6 +55,9 @@ def main(path):
     # the concurrent-access join
     from tests.test_oracle_race import check_pins
     check_pins(lib)
+    # the pointer check
+    from tests.test_oracle_pointers import check_pins as check_pointer_pins
+    check_pointer_pins(lib)
     return 0
 
 

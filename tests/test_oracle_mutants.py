@@ -36,6 +36,11 @@ MUTANTS = {
                                      "(wide)r->src + r->n >= OR_ADDR_LIMIT || (wide)r->dst + r->n >= OR_ADDR_LIMIT"),
     "unchecked records still meet": ("            if (race_unchecked(rb, eb)) continue;\n", ""),
     "write-write conflicts missed": ("meets(ra->dst, ra->n, rb->dst, rb->n) || ", ""),
+    "pointer one past the end rejected": ("            else if ((wide)p == end) past = (int64_t)j;\n", ""),
+    "pointer one past wins over holding": ("int64_t j = hold >= 0 ? hold : past;", "int64_t j = past >= 0 ? past : hold;"),
+    "pointer end inclusive": ("if ((wide)abase[j] <= p && (wide)p < end) hold = (int64_t)j;",
+                              "if ((wide)abase[j] <= p && (wide)p <= end) hold = (int64_t)j;"),
+    "pointer avail from base": ("out[t].avail = abase[j] + asize[j] - p;", "out[t].avail = asize[j];"),
     "zero length reports avail": ("if (n == 0) {\n        out->flags = 0; out->reserved = 0;\n        out->first_bad = OR_NONE; out->undef_bytes = 0; out->avail = 0;\n        return;\n    }", ""),
 }
 
