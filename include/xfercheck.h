@@ -255,6 +255,33 @@ typedef struct cg_race {
 int check_concurrent(cg_ctx *ctx, const cg_transfer *recs_dev, const uint32_t *streams_dev,
                      const uint32_t *epochs_dev, uint64_t count, cg_race *out_dev, void *hip_stream);
 
+/* ---- kernel-argument pointers ---------------------------------------------- */
+/*
+ * The outlook (Sec. 5.1) proposes checking the pointer arguments of kernel
+ * launches against the same list of allocations.  A pointer p is valid when a
+ * live allocation [base, base + size) holds it, or when it is one past the end
+ * of one (p == base + size, as C allows for array ends); an allocation that
+ * holds p wins over one that p is one past.
+ */
+#define CG_PTR_UNALLOC 0x1u   /* no live allocation holds p or ends at p */
+
+/* One result, 24 bytes, in device memory: the flag above, the allocation's
+ * base, and avail = base + size - p (0 one past the end); base = avail = 0
+ * with CG_PTR_UNALLOC. */
+typedef struct cg_ptr_check {
+    uint32_t flags, reserved;
+    uint64_t base, avail;
+} cg_ptr_check;
+
+/*
+ * Look up `count` pointers at ptrs_dev (device memory, u64 each) among the
+ * live allocations and write one cg_ptr_check per pointer to out_dev (device
+ * memory), on `hip_stream`.  Like check_transfers it sees every shadow_alloc /
+ * shadow_free made before it; the caller keeps both arrays alive until the
+ * stream has synced.  Errors: CG_EINVAL (null pointers), CG_EHIP.
+ */
+int check_pointers(cg_ctx *ctx, const uint64_t *ptrs_dev, uint64_t count, cg_ptr_check *out_dev, void *hip_stream);
+
 /* ---- tuning (the batched kernel's launch shape) -------------------------- */
 typedef struct cg_tuning {
     uint32_t block;          /* threads per block: 256 or 512 */

@@ -693,6 +693,40 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// k_pointers: pointer queries (kernel arguments) against the live allocations,
+// through the same table lookup as the transfers
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kClassifyBlock) k_pointers(const DevState *stp, const uint64_t *ptrs, uint64_t count,
+                                                             cg_ptr_check *out)
+{
+    __shared__ uint64_t top[kMaxTop];
+    const DevState st = *stp;
+    for (uint32_t k = threadIdx.x; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + threadIdx.x;
+    if (t >= count) return;
+    const uint64_t p = ptrs[t];
+    int64_t j = table_lookup(st.table, top, p);
+    if (j < 0 && p > 0) {
+        // one past the end of an allocation
+        const int64_t k = table_lookup(st.table, top, p - 1);
+        if (k >= 0 && st.table.end[k] == p) j = k;
+    }
+    cg_ptr_check o;
+    o.reserved = 0;
+    if (j < 0) {
+        o.flags = CG_PTR_UNALLOC;
+        o.base = 0;
+        o.avail = 0;
+    } else {
+        o.flags = 0;
+        o.base = st.table.base[j];
+        o.avail = st.table.end[j] - p;
+    }
+    out[t] = o;
+}
+
+// ---------------------------------------------------------------------------
 // k_scan_sums: one block, exclusive scan of the classify-block sums
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_units, uint32_t waves)
@@ -961,6 +995,13 @@ hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const 
     if (grid > sh.grid) grid = sh.grid;
     if (grid == 0) grid = 1;
     XC_DISPATCH(launch_plain_t, a, rec, units, (uint32_t)grid, sh.block, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pointers(const DevState *st, const uint64_t *ptrs, uint64_t count, cg_ptr_check *out, hipStream_t s)
+{
+    const uint64_t blocks = (count + kClassifyBlock - 1) / kClassifyBlock;
+    hipLaunchKernelGGL(k_pointers, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, st, ptrs, count, out);
     return hipGetLastError();
 }
 

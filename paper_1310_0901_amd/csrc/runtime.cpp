@@ -549,6 +549,8 @@ int debug_conflicts(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, hipS
     return CG_OK;
 }
 
+int note_use(cg_ctx *c, hipStream_t s);
+
 int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *out, uint32_t mode,
               hipStream_t s, const cg_tuning &tun)
 {
@@ -595,7 +597,14 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     }
     HIPTRY(c, hipEventRecord(w->done, s));
     w->used = true;
-    // bookkeeping for version reuse and the pool quarantine
+    return note_use(c, s);
+}
+
+// Bookkeeping after work on stream s that reads the current table version:
+// the version's ring slot is not overwritten, and pool blocks freed later are
+// not reused, before that work has finished.
+int note_use(cg_ctx *c, hipStream_t s)
+{
     hipEvent_t &vu = c->ver[c->cur].uses[s];
     if (!vu) HIPTRY(c, hipEventCreateWithFlags(&vu, hipEventDisableTiming));
     HIPTRY(c, hipEventRecord(vu, s));
@@ -908,6 +917,21 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
 int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)
 {
     return check_transfers(c, recs_dev, count, nullptr, CG_PROPAGATE, hip_stream);
+}
+
+int check_pointers(cg_ctx *c, const uint64_t *ptrs_dev, uint64_t count, cg_ptr_check *out_dev, void *hip_stream)
+{
+    if (!c) return CG_EINVAL;
+    if (count == 0) return CG_OK;
+    if (!ptrs_dev || !out_dev) return fail(c, CG_EINVAL, "null pointers or results");
+    if (count >= (1ull << 40)) return fail(c, CG_EINVAL, "too many pointers");
+    if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int rc = materialize(c);
+    if (rc) return rc;
+    HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+    HIPTRY(c, launch_pointers(c->ver[c->cur].st, ptrs_dev, count, out_dev, s));
+    return note_use(c, s);
 }
 
 int check_concurrent(cg_ctx *c, const cg_transfer *recs_dev, const uint32_t *streams_dev, const uint32_t *epochs_dev,

@@ -46,6 +46,8 @@ VERDICT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"),
                           ("avail", "<u8")])
 # serving event log entry (48 bytes) and per-request result (72 bytes)
 EV_CHECK, EV_ALLOC, EV_FREE = 0, 1, 2
+# one result of the pointer check (cg_ptr_check)
+PTR_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("base", "<u8"), ("avail", "<u8")])
 # one result of the concurrent-access join (cg_race)
 RACE_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("partner", "<u8")])
 SERVE_EVENT_DTYPE = np.dtype([("t", "<f8"), ("type", "<u4"), ("reserved", "<u4"),
@@ -703,3 +705,39 @@ def small_race(seed=SEED0 + 7, count=20_000, window=1 << 16, streams=8, epochs=4
     st = rng.integers(0, streams, size=count).astype(np.uint32)
     ep = rng.integers(0, epochs, size=count).astype(np.uint32)
     return RaceBatch(recs, st, ep, f"small-race: {count} records, {streams} streams, {epochs} epochs")
+
+
+
+# ---- kernel-argument pointers -------------------------------------------------
+
+@dataclass
+class PointerBatch:
+    """Live allocations (sorted bases and sizes), allocations freed since, and
+    pointers to look up among the live ones."""
+    bases: np.ndarray
+    sizes: np.ndarray
+    freed: np.ndarray        # indices into bases/sizes of allocations to free before the lookup
+    ptrs: np.ndarray
+    desc: str = ""
+
+
+def pointer_batch(seed=SEED0 + 8, n_alloc=975_000, n_ptrs=1_000_000, min_size=64, max_size=4096,
+                  freed_frac=0.01) -> PointerBatch:
+    """Kernel-argument pointers against a table the size of configuration 5's:
+    a third each inside allocations (uniform offset), one past an allocation's
+    end, and uniform over the whole address span (mostly in gaps); 1 % of the
+    allocations are freed before the lookup."""
+    rng = np.random.default_rng(seed)
+    sizes = log_uniform_int(rng, min_size, max_size, n_alloc)
+    bases = place_allocations(rng, sizes).astype(np.int64)
+    freed = np.sort(rng.choice(n_alloc, size=int(freed_frac * n_alloc), replace=False))
+    k = n_ptrs // 3
+    j = rng.integers(0, n_alloc, size=k)
+    inside = bases[j] + (rng.random(k) * sizes[j]).astype(np.int64)
+    j2 = rng.integers(0, n_alloc, size=k)
+    past = bases[j2] + sizes[j2]
+    lo, hi = int(bases[0]) - 4096, int(bases[-1] + sizes[-1]) + 4096
+    anywhere = rng.integers(lo, hi, size=n_ptrs - 2 * k)
+    ptrs = rng.permutation(np.concatenate([inside, past, anywhere])).astype(np.uint64)
+    return PointerBatch(bases.astype(np.uint64), sizes.astype(np.uint64), freed, ptrs,
+                        f"pointers: {n_ptrs} lookups among {n_alloc - freed.size} live allocations")

@@ -25,6 +25,7 @@ CG_DST_UNADDR, CG_DST_UNALLOC, CG_DST_OVERRUN = 0x10, 0x20, 0x40
 CG_OVERLAP, CG_BAD_KIND = 0x80, 0x100
 CG_NONE = 0xFFFF_FFFF_FFFF_FFFF
 CG_RACE_SRC, CG_RACE_DST, CG_RACE_UNCHECKED = 0x1, 0x2, 0x4
+CG_PTR_UNALLOC = 0x1
 # modes
 CG_CHECK, CG_PROPAGATE, CG_PLAIN, CG_DEBUG_CONFLICTS, CG_EAGER = 0x1, 0x2, 0x4, 0x8, 0x10
 
@@ -90,6 +91,7 @@ _PROTOS = {
     "check_transfers": (I32, [P, P, U64, P, U32, P]),
     "propagate_shadow": (I32, [P, P, U64, P]),
     "check_concurrent": (I32, [P, P, P, P, U64, P, P]),
+    "check_pointers": (I32, [P, P, U64, P, P]),
     "cg_format_verdict": (I32, [ctypes.POINTER(cg_transfer), ctypes.POINTER(cg_verdict), ctypes.c_char_p, U64]),
     "cg_strerror": (ctypes.c_char_p, [I32]),
     "cg_last_error": (ctypes.c_char_p, [P]),
@@ -201,6 +203,10 @@ def check_concurrent(ctx, recs_dev, streams_dev, epochs_dev, count, out_dev, str
     """epochs_dev may be 0/None (all records in epoch 0)."""
     _chk(ctx, lib().check_concurrent(ctx, recs_dev, streams_dev, epochs_dev or None, count, out_dev, stream),
          "check_concurrent")
+
+
+def check_pointers(ctx, ptrs_dev, count, out_dev, stream=0) -> None:
+    _chk(ctx, lib().check_pointers(ctx, ptrs_dev, count, out_dev, stream), "check_pointers")
 
 
 def cg_format_verdict(rec, verdict) -> str:
