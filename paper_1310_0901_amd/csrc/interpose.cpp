@@ -36,9 +36,19 @@
 // a stream; copies in different windows as ordered, so a race across a
 // synchronising call is not reported (no false reports, possibly missed ones).
 //
+// Kernel arguments (the outlook of Sec. 5.1): hipLaunchKernel is wrapped, the
+// kernel's parameter list is recovered by demangling its name, and every
+// raw-pointer argument that is neither null nor pinned host memory is looked
+// up among the live allocations with check_pointers.  A pointer that is
+// neither inside nor one past the end of a live allocation (freed or never
+// allocated) is reported and the launch is refused.  Pointers inside structs
+// passed by value, and kernels declared extern "C" (no parameter types in
+// their names), are not checked.  XC_NO_KERNEL_ARGS=1 turns this off.
+//
 // Environment: XC_POOL_BYTES (shadow pool, default 1 GiB), XC_MAX_ALLOCS
 // (default 1,048,576), XC_REPORT_DEVICE_UNDEF, XC_ALLOW_BAD, XC_QUIET=1 (no
-// summary line).
+// summary line), XC_NO_KERNEL_ARGS.
+#include <cxxabi.h>
 #include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
@@ -50,6 +60,8 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/xfercheck.h"
@@ -57,6 +69,15 @@
 namespace {
 
 thread_local int inside = 0;   // > 0 while the checker itself calls HIP
+// the error of the last call this thread refused, reported by hipGetLastError /
+// hipPeekAtLastError like the runtime's own errors
+thread_local hipError_t refused = hipSuccess;
+
+hipError_t refuse()
+{
+    refused = hipErrorInvalidValue;
+    return hipErrorInvalidValue;
+}
 
 struct Guard {
     Guard() { ++inside; }
@@ -82,6 +103,19 @@ using devsync_t = hipError_t (*)();
 using streamsync_t = hipError_t (*)(hipStream_t);
 using eventsync_t = hipError_t (*)(hipEvent_t);
 using waitevent_t = hipError_t (*)(hipStream_t, hipEvent_t, unsigned int);
+using launch_t = hipError_t (*)(const void *, dim3, dim3, void **, size_t, hipStream_t);
+using malloc_flags_t = hipError_t (*)(void **, size_t, unsigned int);
+using malloc_async_t = hipError_t (*)(void **, size_t, hipStream_t);
+using free_async_t = hipError_t (*)(void *, hipStream_t);
+using lasterr_t = hipError_t (*)();
+
+// a kernel's parameter list as far as its name tells it
+struct KernelSig {
+    std::string name;              // demangled signature (or the name as given)
+    std::vector<std::string> params;
+    std::vector<bool> is_ptr;
+    bool known = false;            // parameter types recovered
+};
 
 // an asynchronous copy waiting in the window
 struct WinCopy {
@@ -111,6 +145,13 @@ struct State {
     cg_race *d_wres = nullptr;
     uint64_t win_cap = 0;
     uint64_t races = 0;
+    // kernel arguments
+    bool kernel_args = true;
+    std::unordered_map<const void *, KernelSig> sigs;
+    uint64_t *d_ptrs = nullptr;
+    cg_ptr_check *d_pres = nullptr;
+    uint64_t ptr_cap = 0;
+    uint64_t launches = 0;
 } G;
 
 uint64_t env_u64(const char *k, uint64_t d)
@@ -123,6 +164,7 @@ void summary()
 {
     if (G.ctx && !G.quiet) {
         fprintf(stderr, "==xfercheck== %" PRIu64 " copies checked, %" PRIu64 " with errors", G.copies, G.errors);
+        if (G.launches) fprintf(stderr, ", %" PRIu64 " kernel launches checked", G.launches);
         if (G.races) fprintf(stderr, ", %" PRIu64 " concurrent-access pairs", G.races);
         fprintf(stderr, "\n");
     }
@@ -150,6 +192,7 @@ bool ensure_ctx()
     G.device_undef = env_u64("XC_REPORT_DEVICE_UNDEF", 0) != 0;
     G.allow_bad = env_u64("XC_ALLOW_BAD", 0) != 0;
     G.quiet = env_u64("XC_QUIET", 0) != 0;
+    G.kernel_args = env_u64("XC_NO_KERNEL_ARGS", 0) == 0;
     atexit(summary);
     return true;
 }
@@ -346,6 +389,134 @@ void sync_point()
     if (!G.win.empty()) close_window();
 }
 
+std::string trim(const std::string &x)
+{
+    const size_t a = x.find_first_not_of(' '), b = x.find_last_not_of(' ');
+    return a == std::string::npos ? std::string() : x.substr(a, b - a + 1);
+}
+
+// Parameter list of a kernel from its mangled name: demangle, take the
+// parenthesised list that ends the name, split it at top-level commas.  A
+// parameter is a raw pointer when its type ends in '*' once qualifiers of the
+// pointer itself are dropped.
+KernelSig parse_signature(const char *mangled)
+{
+    KernelSig k;
+    k.name = mangled ? mangled : "?";
+    if (!mangled) return k;
+    int st = 0;
+    char *d = abi::__cxa_demangle(mangled, nullptr, nullptr, &st);
+    if (st != 0 || !d) {
+        free(d);
+        return k;   // not a C++ name: no parameter types
+    }
+    const std::string s(d);
+    free(d);
+    k.name = s;
+    if (s.empty() || s.back() != ')') return k;
+    int depth = 0;
+    size_t open = std::string::npos;
+    for (size_t i = s.size(); i-- > 0;) {
+        if (s[i] == ')') ++depth;
+        else if (s[i] == '(' && --depth == 0) {
+            open = i;
+            break;
+        }
+    }
+    if (open == std::string::npos) return k;
+    const std::string list = s.substr(open + 1, s.size() - open - 2);
+    std::string cur;
+    int dp = 0;
+    for (char ch : list) {
+        if (ch == '(' || ch == '<' || ch == '[') ++dp;
+        if (ch == ')' || ch == '>' || ch == ']') --dp;
+        if (ch == ',' && dp == 0) {
+            k.params.push_back(trim(cur));
+            cur.clear();
+        } else {
+            cur += ch;
+        }
+    }
+    if (!trim(cur).empty()) k.params.push_back(trim(cur));
+    if (k.params.size() == 1 && k.params[0] == "void") k.params.clear();
+    for (const std::string &p : k.params) {
+        std::string t = p;
+        for (const char *q : {" const", " volatile", " restrict", " __restrict"}) {
+            const size_t n = strlen(q);
+            while (t.size() > n && t.compare(t.size() - n, n, q) == 0) t = trim(t.substr(0, t.size() - n));
+        }
+        k.is_ptr.push_back(!t.empty() && t.back() == '*');
+    }
+    k.known = true;
+    return k;
+}
+
+bool pinned_host(uint64_t p)
+{
+    hipPointerAttribute_t a;
+    const bool host = hipPointerGetAttributes(&a, (const void *)p) == hipSuccess && a.type == hipMemoryTypeHost;
+    (void)hipGetLastError();
+    return host;
+}
+
+// Check the pointer arguments of a launch; false if it must not run.
+bool check_launch(const char *api, const void *fn, void **args, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return true;
+    Guard g;
+    auto it = G.sigs.find(fn);
+    if (it == G.sigs.end()) it = G.sigs.emplace(fn, parse_signature(hipKernelNameRefByPtr(fn, stream))).first;
+    const KernelSig &k = it->second;
+    if (!k.known) return true;
+    std::vector<uint64_t> ptrs;
+    std::vector<size_t> which;
+    for (size_t i = 0; i < k.is_ptr.size(); ++i) {
+        if (!k.is_ptr[i]) continue;
+        uint64_t p = 0;
+        memcpy(&p, args[i], sizeof p);
+        if (p == 0 || pinned_host(p)) continue;
+        ptrs.push_back(p);
+        which.push_back(i);
+    }
+    ++G.launches;
+    if (ptrs.empty()) return true;
+    const uint64_t n = ptrs.size();
+    if (n > G.ptr_cap) {
+        (void)hipStreamSynchronize(G.s);
+        (void)hipFree(G.d_ptrs);
+        (void)hipFree(G.d_pres);
+        G.d_ptrs = nullptr;
+        G.d_pres = nullptr;
+        G.ptr_cap = 0;
+        const uint64_t cap = n < 64 ? 64 : n;
+        if (hipMalloc(reinterpret_cast<void **>(&G.d_ptrs), cap * sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&G.d_pres), cap * sizeof(cg_ptr_check)) != hipSuccess)
+            return true;
+        G.ptr_cap = cap;
+    }
+    std::vector<cg_ptr_check> res(n);
+    if (hipMemcpyAsync(G.d_ptrs, ptrs.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_pointers(G.ctx, G.d_ptrs, n, G.d_pres, G.s) != CG_OK ||
+        hipMemcpyAsync(res.data(), G.d_pres, n * sizeof(cg_ptr_check), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+        hipStreamSynchronize(G.s) != hipSuccess) {
+        fprintf(stderr, "==xfercheck== kernel argument check failed: %s\n", cg_last_error(G.ctx));
+        return true;
+    }
+    bool ok = true;
+    for (uint64_t j = 0; j < n; ++j) {
+        if (!(res[j].flags & CG_PTR_UNALLOC)) continue;
+        ok = false;
+        ++G.errors;
+        fprintf(stderr,
+                "Error: Kernel argument %zu (%s) points into no allocated device region.\n"
+                " %p is neither inside nor one past the end of a live allocation (freed or never allocated).\n"
+                " at %s(%s)\n",
+                which[j], k.params[which[j]].c_str(), (void *)ptrs[j], api, k.name.c_str());
+    }
+    return ok || G.allow_bad;
+}
+
 uint32_t direction(void *dst, const void *src, hipMemcpyKind k)
 {
     switch (k) {
@@ -367,6 +538,26 @@ uint32_t direction(void *dst, const void *src, hipMemcpyKind k)
     }
 }
 
+void track_alloc(const char *api, void *p, size_t size)
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return;
+    Guard g;
+    const int rc = shadow_alloc(G.ctx, (uint64_t)p, size);
+    if (rc != CG_OK) fprintf(stderr, "==xfercheck== %s(%zu) at %p not tracked: %s\n", api, size, p, cg_strerror(rc));
+}
+
+void track_free(const char *api, void *p)
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return;
+    Guard g;
+    if (shadow_free(G.ctx, (uint64_t)p) != CG_OK) {
+        ++G.errors;
+        fprintf(stderr, "Error: %s of %p, which is not the start of an allocated device region.\n", api, p);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -375,12 +566,7 @@ hipError_t hipMalloc(void **ptr, size_t size)
 {
     static malloc_t f = real<malloc_t>("hipMalloc");
     const hipError_t e = f(ptr, size);
-    if (inside || e != hipSuccess || !ptr || !*ptr || size == 0) return e;
-    std::lock_guard<std::mutex> lk(G.mu);
-    if (!ensure_ctx()) return e;
-    Guard g;
-    const int rc = shadow_alloc(G.ctx, (uint64_t)*ptr, size);
-    if (rc != CG_OK) fprintf(stderr, "==xfercheck== hipMalloc(%zu) at %p not tracked: %s\n", size, *ptr, cg_strerror(rc));
+    if (!inside && e == hipSuccess && ptr && *ptr && size) track_alloc("hipMalloc", *ptr, size);
     return e;
 }
 
@@ -388,16 +574,7 @@ hipError_t hipFree(void *ptr)
 {
     static free_t f = real<free_t>("hipFree");
     if (!inside) sync_point();
-    if (!inside && ptr) {
-        std::lock_guard<std::mutex> lk(G.mu);
-        if (ensure_ctx()) {
-            Guard g;
-            if (shadow_free(G.ctx, (uint64_t)ptr) != CG_OK) {
-                ++G.errors;
-                fprintf(stderr, "Error: hipFree of %p, which is not the start of an allocated device region.\n", ptr);
-            }
-        }
-    }
+    if (!inside && ptr) track_free("hipFree", ptr);
     return f(ptr);
 }
 
@@ -411,7 +588,7 @@ hipError_t hipMemset(void *dst, int value, size_t n)
             if (shadow_set(G.ctx, (uint64_t)dst, n, 0) != CG_OK) {
                 ++G.errors;
                 fprintf(stderr, "Error: hipMemset of %zu bytes at %p leaves allocated device memory.\n", n, dst);
-                if (!G.allow_bad) return hipErrorInvalidValue;
+                if (!G.allow_bad) return refuse();
             }
         }
     }
@@ -424,7 +601,7 @@ hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind kind)
     if (!inside) sync_point();
     if (!inside && n) {
         const uint32_t d = direction(dst, src, kind);
-        if (d <= CG_D2D && !check_copy("hipMemcpy", dst, src, n, d)) return hipErrorInvalidValue;
+        if (d <= CG_D2D && !check_copy("hipMemcpy", dst, src, n, d)) return refuse();
     }
     return f(dst, src, n, kind);
 }
@@ -433,7 +610,7 @@ hipError_t hipMemcpyHtoD(hipDeviceptr_t dst, const void *src, size_t n)
 {
     static htod_t f = real<htod_t>("hipMemcpyHtoD");
     if (!inside) sync_point();
-    if (!inside && n && !check_copy("hipMemcpyHtoD", dst, src, n, CG_H2D)) return hipErrorInvalidValue;
+    if (!inside && n && !check_copy("hipMemcpyHtoD", dst, src, n, CG_H2D)) return refuse();
     return f(dst, src, n);
 }
 
@@ -441,7 +618,7 @@ hipError_t hipMemcpyDtoH(void *dst, hipDeviceptr_t src, size_t n)
 {
     static dtoh_t f = real<dtoh_t>("hipMemcpyDtoH");
     if (!inside) sync_point();
-    if (!inside && n && !check_copy("hipMemcpyDtoH", dst, src, n, CG_D2H)) return hipErrorInvalidValue;
+    if (!inside && n && !check_copy("hipMemcpyDtoH", dst, src, n, CG_D2H)) return refuse();
     return f(dst, src, n);
 }
 
@@ -449,7 +626,7 @@ hipError_t hipMemcpyDtoD(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n)
 {
     static dtod_t f = real<dtod_t>("hipMemcpyDtoD");
     if (!inside) sync_point();
-    if (!inside && n && !check_copy("hipMemcpyDtoD", dst, src, n, CG_D2D)) return hipErrorInvalidValue;
+    if (!inside && n && !check_copy("hipMemcpyDtoD", dst, src, n, CG_D2D)) return refuse();
     return f(dst, src, n);
 }
 
@@ -459,12 +636,68 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind ki
     if (!inside && n) {
         const uint32_t d = direction(dst, src, kind);
         if (d <= CG_D2D) {
-            if (!check_copy("hipMemcpyAsync", dst, src, n, d)) return hipErrorInvalidValue;
+            if (!check_copy("hipMemcpyAsync", dst, src, n, d)) return refuse();
             std::lock_guard<std::mutex> lk(G.mu);
             G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream});
         }
     }
     return f(dst, src, n, kind, stream);
+}
+
+hipError_t hipLaunchKernel(const void *fn, dim3 grid, dim3 block, void **args, size_t shmem, hipStream_t stream)
+{
+    static launch_t f = real<launch_t>("hipLaunchKernel");
+    if (!inside && args && G.kernel_args && !check_launch("hipLaunchKernel", fn, args, stream))
+        return refuse();
+    return f(fn, grid, block, args, shmem, stream);
+}
+
+hipError_t hipMallocManaged(void **ptr, size_t size, unsigned int flags)
+{
+    static malloc_flags_t f = real<malloc_flags_t>("hipMallocManaged");
+    const hipError_t e = f(ptr, size, flags);
+    if (!inside && e == hipSuccess && ptr && *ptr && size) track_alloc("hipMallocManaged", *ptr, size);
+    return e;
+}
+
+hipError_t hipExtMallocWithFlags(void **ptr, size_t size, unsigned int flags)
+{
+    static malloc_flags_t f = real<malloc_flags_t>("hipExtMallocWithFlags");
+    const hipError_t e = f(ptr, size, flags);
+    if (!inside && e == hipSuccess && ptr && *ptr && size) track_alloc("hipExtMallocWithFlags", *ptr, size);
+    return e;
+}
+
+hipError_t hipMallocAsync(void **ptr, size_t size, hipStream_t stream)
+{
+    static malloc_async_t f = real<malloc_async_t>("hipMallocAsync");
+    const hipError_t e = f(ptr, size, stream);
+    if (!inside && e == hipSuccess && ptr && *ptr && size) track_alloc("hipMallocAsync", *ptr, size);
+    return e;
+}
+
+hipError_t hipFreeAsync(void *ptr, hipStream_t stream)
+{
+    static free_async_t f = real<free_async_t>("hipFreeAsync");
+    if (!inside && ptr) track_free("hipFreeAsync", ptr);
+    return f(ptr, stream);
+}
+
+hipError_t hipGetLastError(void)
+{
+    static lasterr_t f = real<lasterr_t>("hipGetLastError");
+    const hipError_t e = f();
+    if (inside || refused == hipSuccess) return e;
+    const hipError_t r = refused;
+    refused = hipSuccess;
+    return r;
+}
+
+hipError_t hipPeekAtLastError(void)
+{
+    static lasterr_t f = real<lasterr_t>("hipPeekAtLastError");
+    const hipError_t e = f();
+    return (inside || refused == hipSuccess) ? e : refused;
 }
 
 hipError_t hipDeviceSynchronize(void)
@@ -504,7 +737,7 @@ hipError_t hipMemcpy2D(void *dst, size_t dpitch, const void *src, size_t spitch,
         const uint32_t d = direction(dst, src, kind);
         if (d <= CG_D2D && !check_rows("hipMemcpy2D", (uint8_t *)dst, dpitch, (const uint8_t *)src, spitch, width,
                                        height, d))
-            return hipErrorInvalidValue;
+            return refuse();
     }
     return f(dst, dpitch, src, spitch, width, height, kind);
 }

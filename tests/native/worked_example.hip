@@ -91,8 +91,46 @@ static int streams()
     return 0;
 }
 
+// Kernel arguments: launches with valid pointers (inside an allocation, one
+// past its end, null, pinned host memory), then with a freed pointer and with
+// a pointer to ordinary host memory.  The refused launches pass n = 0, so the
+// kernel would touch nothing even if it ran.
+static int kernel_args()
+{
+    const int n = 1 << 16;
+    double *a = nullptr, *b = nullptr, *c = nullptr, *gone = nullptr, *pinned = nullptr;
+    if (hipMalloc((void **)&a, n * sizeof(double)) != hipSuccess || hipMalloc((void **)&b, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&gone, n * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&pinned, n * sizeof(double)) != hipSuccess)
+        return 2;
+    hipMemset(a, 0, n * sizeof(double));
+    hipMemset(b, 0, n * sizeof(double));
+    hipFree(gone);
+    double *plain = (double *)malloc(n * sizeof(double));
+    hipLaunchKernelGGL(vecsum, dim3(64), dim3(256), 0, 0, c, a, b, n);
+    printf("valid launch returned %d\n", (int)hipGetLastError());
+    hipLaunchKernelGGL(vecsum, dim3(64), dim3(256), 0, 0, c, a, b + n, 0);
+    printf("one-past-the-end launch returned %d\n", (int)hipGetLastError());
+    hipLaunchKernelGGL(vecsum, dim3(64), dim3(256), 0, 0, pinned, (const double *)nullptr, (const double *)nullptr, 0);
+    printf("null and pinned launch returned %d\n", (int)hipGetLastError());
+    // 16 elements into the freed block: its first byte may equal c's one-past-the-end pointer
+    hipLaunchKernelGGL(vecsum, dim3(64), dim3(256), 0, 0, c, gone + 16, b, 0);
+    printf("freed argument launch returned %d\n", (int)hipGetLastError());
+    hipLaunchKernelGGL(vecsum, dim3(64), dim3(256), 0, 0, c, a, plain, 0);
+    printf("host pointer launch returned %d\n", (int)hipGetLastError());
+    (void)hipDeviceSynchronize();
+    hipFree(a);
+    hipFree(b);
+    hipFree(c);
+    (void)hipHostFree(pinned);
+    free(plain);
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
+    if (argc > 1 && strcmp(argv[1], "kernelargs") == 0) return kernel_args();
     if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
     if (argc > 1 && strcmp(argv[1], "streams") == 0) return streams();
     const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;

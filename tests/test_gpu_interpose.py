@@ -83,3 +83,23 @@ def test_concurrent_copies_on_streams():
     assert "4096 bytes, hipMemcpyHostToDevice" in second and "4096 bytes, hipMemcpyDeviceToHost" in second
     assert "writes bytes that" in second and "\n reads." in second
     assert "12 copies checked, 2 with errors, 2 concurrent-access pairs" in err
+
+
+def test_kernel_arguments():
+    """hipLaunchKernel's raw-pointer arguments are looked up among the live
+    allocations (the outlook of Sec. 5.1): pointers inside an allocation, one
+    past its end, null or pinned host memory pass; a freed pointer and a
+    pointer to ordinary host memory are reported and the launch refused."""
+    r = run_example("kernelargs")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0
+    out = r.stdout
+    for line in ("valid launch returned 0", "one-past-the-end launch returned 0", "null and pinned launch returned 0",
+                 "freed argument launch returned 1", "host pointer launch returned 1"):
+        assert line in out
+    err = r.stderr
+    assert err.count("Error: Kernel argument") == 2
+    assert "Error: Kernel argument 1 (double const*) points into no allocated device region." in err
+    assert "Error: Kernel argument 2 (double const*) points into no allocated device region." in err
+    assert "at hipLaunchKernel(vecsum(double*, double const*, double const*, int))" in err
+    assert "0 copies checked, 2 with errors, 5 kernel launches checked" in err
