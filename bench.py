@@ -310,6 +310,43 @@ def concurrency_leg(records, reps=10):
     return o
 
 
+def kernel_args_leg(reps=20):
+    """Kernel-argument pointer lookups: 1,000,000 pointers against a table of
+    965,250 live allocations (configuration 5's size, 1 % freed), whole-call
+    time from events on the stream the lookup runs on."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd import workloads as W, xfercheck as X
+    b = W.pointer_batch()
+    dev = torch.device("cuda", 0)
+    pool = int(((b.sizes.astype(np.int64) + 255) // 256 * 256).sum()) + (1 << 20)
+    ctx = X.cg_create(0, pool, b.bases.size + 64)
+    try:
+        X.shadow_alloc_batch(ctx, b.bases, b.sizes)
+        X.shadow_free_batch(ctx, b.bases[b.freed])
+        p = torch.from_numpy(b.ptrs.view(np.uint8).copy()).to(dev)
+        out = torch.empty(b.ptrs.size * 24, dtype=torch.uint8, device=dev)
+        s = torch.cuda.current_stream(dev)
+        run = lambda: X.check_pointers(ctx, p.data_ptr(), b.ptrs.size, out.data_ptr(), s.cuda_stream)
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            run()
+        e1.record(s)
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1) / reps
+        res = out.cpu().numpy().view(W.PTR_DTYPE)
+    finally:
+        X.cg_destroy(ctx)
+    o = {"workload": b.desc, "ms_per_call": round(ms, 4), "lookups_per_s": round(b.ptrs.size / (ms / 1e3), 1),
+         "unallocated": int((res["flags"] != 0).sum())}
+    log(f"[bench] kernel args: {o}")
+    return o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,13 +363,14 @@ def main():
     ap.add_argument("--plain-serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="skip the plain-at-scale and propagation legs (configurations 2 and 4)")
-    ap.add_argument("--leg", choices=["plain_tiny", "plain_at_scale", "propagation", "concurrency", "serving"],
+    ap.add_argument("--leg", choices=["plain_tiny", "plain_at_scale", "propagation", "concurrency", "kernel_args",
+                                      "serving"],
                     help="run only this extra leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.leg:
         from paper_1310_0901_amd import workloads as W
         legs = {"plain_tiny": plain_tiny_leg, "plain_at_scale": plain_at_scale_leg, "propagation": propagation_leg,
-                "concurrency": lambda: concurrency_leg(W.config3().records),
+                "concurrency": lambda: concurrency_leg(W.config3().records), "kernel_args": kernel_args_leg,
                 "serving": lambda: serving_leg(args.plain_serve_seconds)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
@@ -465,6 +503,7 @@ def main():
     dw.close()
     if args.legs:
         result["concurrency"] = concurrency_leg(w.records)
+        result["kernel_args"] = kernel_args_leg()
         result["plain_tiny"] = plain_tiny_leg()
         result["plain_at_scale"] = plain_at_scale_leg()
         result["propagation"] = propagation_leg()

@@ -84,9 +84,11 @@ __global__ void __launch_bounds__(1024) k_merge_sums(MergeArgs m)
     if (tid == 1023) m.boff[nb] = off + x;   // number of kept entries
 }
 
-// kept entries among the first j old entries
+// kept entries among the first j old entries (none when the old version is
+// empty: then k_merge_keep and k_merge_sums do not run and boff is not written)
 __device__ __forceinline__ uint64_t kept_before(const MergeArgs &m, uint64_t j)
 {
+    if (m.n_old == 0) return 0;
     const uint64_t nb = (m.n_old + kB - 1) / kB;
     if (j >= m.n_old) return m.boff[nb];
     return m.boff[j / kB] + m.loc[j];

@@ -245,3 +245,39 @@ def test_table_churn_versions_match_oracle(X, H):
             util.assert_verdicts_equal(H.verdicts_np(out, len(recs)), o.run(recs), f"batch {i}")
     finally:
         X.cg_destroy(ctx)
+
+
+def test_first_version_merged_into_empty_table(X):
+    """A few allocations after the empty start: the next table version is a
+    device merge of an empty old version with the inserts (no kept entries).
+    Verdicts match the oracle, and pointer lookups see the new entries."""
+    from oracle import oracle
+    B = W.DEV_BASE
+    ctx = X.cg_create(0, 1 << 20, 64)
+    try:
+        X.shadow_alloc(ctx, B, 1000)
+        X.shadow_alloc(ctx, B + 4096, 100)
+        recs = np.array([(B, B + 4096, 100, 2, 0), (B, B + 4096, 101, 2, 0), (B + 999, B + 4096, 2, 2, 0)],
+                        W.RECORD_DTYPE)
+        rt = torch.from_numpy(recs.view(np.uint8).copy()).to("cuda:0")
+        out = torch.zeros(recs.size * 32, dtype=torch.uint8, device="cuda:0")
+        s = torch.cuda.current_stream()
+        X.check_transfers(ctx, rt.data_ptr(), recs.size, out.data_ptr(), X.CG_CHECK | X.CG_EAGER, s.cuda_stream)
+        s.synchronize()
+        got = out.cpu().numpy().view(W.VERDICT_DTYPE)
+        st = oracle.OracleState(0x1000, 64, np.zeros(64, np.uint8), np.full(1, ~np.uint64(0), np.uint64),
+                                np.array([B, B + 4096], np.uint64), np.array([1000, 100], np.uint64),
+                                [np.full(1000, 0xFF, np.uint8), np.full(100, 0xFF, np.uint8)])
+        want = st.run(recs)
+        for f in ("flags", "first_bad", "undef_bytes", "avail"):
+            assert np.array_equal(got[f], want[f]), f
+        ptrs = np.array([B, B + 1000, B + 4096 + 50, B + 2000], np.uint64)
+        pt = torch.from_numpy(ptrs.view(np.uint8).copy()).to("cuda:0")
+        po = torch.zeros(ptrs.size * 24, dtype=torch.uint8, device="cuda:0")
+        X.check_pointers(ctx, pt.data_ptr(), ptrs.size, po.data_ptr(), s.cuda_stream)
+        s.synchronize()
+        pr = po.cpu().numpy().view(W.PTR_DTYPE)
+        assert pr["flags"].tolist() == [0, 0, 0, X.CG_PTR_UNALLOC]
+        assert pr["base"].tolist() == [B, B, B + 4096, 0] and pr["avail"].tolist() == [1000, 0, 50, 0]
+    finally:
+        X.cg_destroy(ctx)
