@@ -101,6 +101,13 @@ class OracleState:
             raise MemoryError("oracle snapshot allocation failed")
         return out
 
+    def run2d(self, records2d, check=True, propagate=False) -> np.ndarray:
+        """Pitched 2D copies: all rows of all records as one batch (snapshot
+        semantics), then one verdict per record (see combine_rows)."""
+        rows, first, counts = expand_rows(records2d)
+        rv = self.run(rows, check=check, propagate=propagate)
+        return combine_rows(records2d, rv, first, counts)
+
     def run_threads(self, records, threads: int) -> np.ndarray:
         """Check-only evaluation split over contiguous record ranges on
         `threads` host threads (ctypes releases the GIL during the call)."""
@@ -122,6 +129,51 @@ class OracleState:
         for t in ts:
             t.join()
         return out
+
+
+REC2D = np.dtype([("src", "<u8"), ("dst", "<u8"), ("width", "<u8"), ("rows", "<u8"), ("spitch", "<u8"),
+                  ("dpitch", "<u8"), ("kind", "<u4"), ("reserved", "<u4", (3,))])
+
+
+def expand_rows(records2d):
+    """The row records of pitched 2D copies (the strided copies of the
+    footnote to Sec. 2's error list): row r of a record reads
+    [src + r*spitch, + width) and writes [dst + r*dpitch, + width).  Returns
+    the rows and, per 2D record, the index of its first row."""
+    r2 = np.ascontiguousarray(records2d, REC2D)
+    counts = np.where(r2["width"] > 0, r2["rows"], 0).astype(np.int64)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    rows = np.zeros(int(counts.sum()), REC)
+    k = 0
+    for t in range(r2.size):
+        for r in range(int(counts[t])):
+            rows[k] = (int(r2["src"][t]) + r * int(r2["spitch"][t]), int(r2["dst"][t]) + r * int(r2["dpitch"][t]),
+                       int(r2["width"][t]), int(r2["kind"][t]), 0)
+            k += 1
+    return rows, first, counts
+
+
+def combine_rows(records2d, row_verdicts, first, counts):
+    """One verdict per 2D record from its rows' verdicts: the bytes of the copy
+    are numbered row by row (byte c of row r is r*width + c), so flags are the
+    OR over rows, first_bad the smallest r*width + first_bad_r, undef_bytes the
+    sum, and avail the first row's (bytes from the copy's start pointer to the
+    end of its allocation).  No rows: {0, NONE, 0, 0}; a bad kind with rows
+    gives the rows' BAD_KIND."""
+    r2 = np.ascontiguousarray(records2d, REC2D)
+    out = np.zeros(r2.size, VER)
+    out["first_bad"] = NONE
+    for t in range(r2.size):
+        w = int(r2["width"][t])
+        for r in range(int(counts[t])):
+            v = row_verdicts[int(first[t]) + r]
+            out["flags"][t] |= v["flags"]
+            if int(v["first_bad"]) != NONE:
+                out["first_bad"][t] = min(int(out["first_bad"][t]), r * w + int(v["first_bad"]))
+            out["undef_bytes"][t] += v["undef_bytes"]
+        if counts[t]:
+            out["avail"][t] = row_verdicts[int(first[t])]["avail"]
+    return out
 
 
 def race(records, streams, epochs=None, which=None, threads: int = 1, lib=None) -> np.ndarray:

@@ -58,6 +58,9 @@ def main(path):
     # the pointer check
     from tests.test_oracle_pointers import check_pins as check_pointer_pins
     check_pointer_pins(lib)
+    # pitched 2D copies
+    from tests.test_oracle_2d import check_pins as check_2d_pins
+    check_2d_pins(lib)
     return 0
 
 
