@@ -194,6 +194,33 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
 int check_transfers(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count,
                     cg_verdict *out_dev, uint32_t mode, void *hip_stream);
 
+/*
+ * A pitched 2D copy, 64 bytes, in device memory: `rows` rows of `width`
+ * bytes; row r reads [src + r*spitch, + width) and writes
+ * [dst + r*dpitch, + width) (the strided copies of the footnote to Sec. 2's
+ * error list).  `reserved` is ignored.
+ */
+typedef struct cg_transfer2d {
+    uint64_t src, dst, width, rows, spitch, dpitch;
+    uint32_t kind, reserved[3];
+} cg_transfer2d;
+
+/*
+ * check_transfers for pitched 2D copies: every row of every record is one
+ * transfer of the same batch (snapshot semantics, and the no-conflict
+ * precondition of CG_PROPAGATE covers the rows), and one verdict per record
+ * is written to out_dev.  The bytes of a 2D copy are numbered row by row
+ * (byte c of row r is r*width + c): flags = OR over its rows, first_bad =
+ * smallest r*width + first_bad_r, undef_bytes = sum, avail = the first row's
+ * (bytes from src / dst to the end of its allocation).  A record with no
+ * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers.  The
+ * call waits for the caller's stream once, to learn the number of rows
+ * (at most 2^32 - 1 in total).  Errors: as check_transfers, and CG_EINVAL for
+ * too many rows.
+ */
+int check_transfers_2d(cg_ctx *ctx, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev,
+                       uint32_t mode, void *hip_stream);
+
 /* Propagation only: check_transfers(ctx, recs, count, NULL, CG_PROPAGATE, stream). */
 int propagate_shadow(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, void *hip_stream);
 

@@ -83,6 +83,15 @@ struct TableVersion {
     std::map<hipStream_t, hipEvent_t> uses;
 };
 
+// Row expansion of pitched 2D copies on one stream.
+struct StridedWs {
+    uint64_t rec_cap = 0, row_cap = 0;
+    uint64_t *first = nullptr, *bsum = nullptr, *total = nullptr, *h_total = nullptr;
+    cg_transfer *rows = nullptr;
+    uint32_t *rec_of = nullptr;
+    cg_verdict *rowv = nullptr;
+};
+
 struct Quarantined {
     uint64_t seq, off, size;   // pool block freed after check number `seq` was issued
 };
@@ -144,6 +153,7 @@ struct cg_ctx {
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
     std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
+    std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
     // timing
@@ -745,6 +755,16 @@ int cg_destroy(cg_ctx *c)
         delete kv.second;
     }
     for (auto &kv : c->race_ws) race_release(kv.second);
+    for (auto &kv : c->strided_ws) {
+        StridedWs &w = kv.second;
+        (void)hipFree(w.first);
+        (void)hipFree(w.bsum);
+        (void)hipFree(w.total);
+        (void)hipFree(w.rows);
+        (void)hipFree(w.rec_of);
+        (void)hipFree(w.rowv);
+        if (w.h_total) (void)hipHostFree(w.h_total);
+    }
     for (auto &p : c->tpairs) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -917,6 +937,65 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
 int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)
 {
     return check_transfers(c, recs_dev, count, nullptr, CG_PROPAGATE, hip_stream);
+}
+
+int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev, uint32_t mode,
+                       void *hip_stream)
+{
+    if (!c) return CG_EINVAL;
+    if (!(mode & (CG_CHECK | CG_PROPAGATE))) return fail(c, CG_EINVAL, "mode needs CG_CHECK or CG_PROPAGATE");
+    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER))
+        return fail(c, CG_EINVAL, "unknown mode bits");
+    if (count == 0) return CG_OK;
+    if (!recs_dev) return fail(c, CG_EINVAL, "null records");
+    if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
+    if (count >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 records per call");
+    if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    StridedWs &w = c->strided_ws[s];
+    if (w.rec_cap < count) {
+        // the buffers may still be in use by an earlier call on this stream
+        HIPTRY(c, hipStreamSynchronize(s));
+        (void)hipFree(w.first);
+        (void)hipFree(w.bsum);
+        w.first = w.bsum = nullptr;
+        w.rec_cap = 0;
+        uint64_t cap = 1024;
+        while (cap < count) cap <<= 1;
+        HIPTRY(c, hipMalloc(&w.first, cap * 8));
+        HIPTRY(c, hipMalloc(&w.bsum, (cap / 256 + 1) * 8));
+        if (!w.total) HIPTRY(c, hipMalloc(&w.total, 8));
+        if (!w.h_total) HIPTRY(c, hipHostMalloc(&w.h_total, 8, hipHostMallocDefault));
+        w.rec_cap = cap;
+    }
+    HIPTRY(c, launch_2d_prefix(recs_dev, count, w.first, w.bsum, w.total, s));
+    HIPTRY(c, hipMemcpyAsync(w.h_total, w.total, 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    const uint64_t nrows = *w.h_total;
+    if (nrows >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 rows per call");
+    if (nrows) {
+        if (w.row_cap < nrows) {
+            (void)hipFree(w.rows);
+            (void)hipFree(w.rec_of);
+            (void)hipFree(w.rowv);
+            w.rows = nullptr;
+            w.rec_of = nullptr;
+            w.rowv = nullptr;
+            w.row_cap = 0;
+            uint64_t cap = 1024;
+            while (cap < nrows) cap <<= 1;
+            HIPTRY(c, hipMalloc(&w.rows, cap * sizeof(cg_transfer)));
+            HIPTRY(c, hipMalloc(&w.rec_of, cap * 4));
+            HIPTRY(c, hipMalloc(&w.rowv, cap * sizeof(cg_verdict)));
+            w.row_cap = cap;
+        }
+        HIPTRY(c, launch_2d_expand(recs_dev, w.first, count, nrows, w.rows, w.rec_of, s));
+        const int rc = run_check(c, w.rows, nrows, (mode & CG_CHECK) ? w.rowv : nullptr, mode, s,
+                                 (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
+        if (rc) return rc;
+    }
+    if (mode & CG_CHECK) HIPTRY(c, launch_2d_fold(recs_dev, w.first, count, w.rec_of, w.rowv, nrows, out_dev, s));
+    return CG_OK;
 }
 
 int check_pointers(cg_ctx *c, const uint64_t *ptrs_dev, uint64_t count, cg_ptr_check *out_dev, void *hip_stream)

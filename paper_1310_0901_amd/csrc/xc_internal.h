@@ -134,6 +134,12 @@ hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
                         hipStream_t s);
 hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
+hipError_t launch_2d_prefix(const cg_transfer2d *recs, uint64_t count, uint64_t *first, uint64_t *bsum,
+                            uint64_t *total, hipStream_t s);
+hipError_t launch_2d_expand(const cg_transfer2d *recs, const uint64_t *first, uint64_t count, uint64_t nrows,
+                            cg_transfer *rows, uint32_t *rec_of, hipStream_t s);
+hipError_t launch_2d_fold(const cg_transfer2d *recs, const uint64_t *first, uint64_t count, const uint32_t *rec_of,
+                          const cg_verdict *rowv, uint64_t nrows, cg_verdict *out, hipStream_t s);
 hipError_t launch_pointers(const DevState *st, const uint64_t *ptrs, uint64_t count, cg_ptr_check *out, hipStream_t s);
 hipError_t launch_probe_read(const void *p, uint64_t bytes, uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_copy(void *d, const void *p, uint64_t bytes, hipStream_t s);

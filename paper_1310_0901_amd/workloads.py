@@ -46,6 +46,9 @@ VERDICT_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"),
                           ("avail", "<u8")])
 # serving event log entry (48 bytes) and per-request result (72 bytes)
 EV_CHECK, EV_ALLOC, EV_FREE = 0, 1, 2
+# one pitched 2D copy (cg_transfer2d)
+RECORD2D_DTYPE = np.dtype([("src", "<u8"), ("dst", "<u8"), ("width", "<u8"), ("rows", "<u8"), ("spitch", "<u8"),
+                           ("dpitch", "<u8"), ("kind", "<u4"), ("reserved", "<u4", (3,))])
 # one result of the pointer check (cg_ptr_check)
 PTR_DTYPE = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("base", "<u8"), ("avail", "<u8")])
 # one result of the concurrent-access join (cg_race)

@@ -92,6 +92,7 @@ _PROTOS = {
     "propagate_shadow": (I32, [P, P, U64, P]),
     "check_concurrent": (I32, [P, P, P, P, U64, P, P]),
     "check_pointers": (I32, [P, P, U64, P, P]),
+    "check_transfers_2d": (I32, [P, P, U64, P, U32, P]),
     "cg_format_verdict": (I32, [ctypes.POINTER(cg_transfer), ctypes.POINTER(cg_verdict), ctypes.c_char_p, U64]),
     "cg_strerror": (ctypes.c_char_p, [I32]),
     "cg_last_error": (ctypes.c_char_p, [P]),
@@ -203,6 +204,10 @@ def check_concurrent(ctx, recs_dev, streams_dev, epochs_dev, count, out_dev, str
     """epochs_dev may be 0/None (all records in epoch 0)."""
     _chk(ctx, lib().check_concurrent(ctx, recs_dev, streams_dev, epochs_dev or None, count, out_dev, stream),
          "check_concurrent")
+
+
+def check_transfers_2d(ctx, recs_dev, count, out_dev, mode, stream=0) -> None:
+    _chk(ctx, lib().check_transfers_2d(ctx, recs_dev, count, out_dev, mode, stream), "check_transfers_2d")
 
 
 def check_pointers(ctx, ptrs_dev, count, out_dev, stream=0) -> None:
