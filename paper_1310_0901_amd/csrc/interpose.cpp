@@ -108,6 +108,12 @@ using malloc_flags_t = hipError_t (*)(void **, size_t, unsigned int);
 using malloc_async_t = hipError_t (*)(void **, size_t, hipStream_t);
 using free_async_t = hipError_t (*)(void *, hipStream_t);
 using lasterr_t = hipError_t (*)();
+using memcpy2d_async_t = hipError_t (*)(void *, size_t, const void *, size_t, size_t, size_t, hipMemcpyKind,
+                                        hipStream_t);
+using memcpy3d_t = hipError_t (*)(const hipMemcpy3DParms *);
+using memcpy3d_async_t = hipError_t (*)(const hipMemcpy3DParms *, hipStream_t);
+using malloc_pitch_t = hipError_t (*)(void **, size_t *, size_t, size_t);
+using malloc3d_t = hipError_t (*)(hipPitchedPtr *, hipExtent);
 
 // a kernel's parameter list as far as its name tells it
 struct KernelSig {
@@ -131,6 +137,9 @@ struct State {
     cg_transfer *d_rec = nullptr;
     cg_verdict *d_ver = nullptr;
     uint64_t rec_cap = 1;         // records d_rec / d_ver hold
+    cg_transfer2d *d_rec2d = nullptr;
+    cg_verdict *d_ver2d = nullptr;
+    uint64_t slice_cap = 0;       // pitched records d_rec2d / d_ver2d hold
     uint8_t *zeros = nullptr;     // V of "defined" host bytes
     uint64_t *ones = nullptr;     // A of "addressable" host bytes
     uint64_t cap = 0;             // bytes covered by zeros / ones
@@ -246,66 +255,170 @@ bool ensure_rows(uint64_t k)
     return true;
 }
 
-// Check a copy of `rows` rows of `width` bytes (a plain copy is one row)
-// before it runs and print the report; false if the copy must not be
-// performed (a device side is unallocated or too small).
-bool check_rows(const char *api, uint8_t *dst, size_t dpitch, const uint8_t *src, size_t spitch, size_t width,
-                size_t rows, uint32_t kind)
+// A copy of depth slices of height rows of width bytes: row y of slice z
+// reads src + z*sslice + y*spitch and writes dst + z*dslice + y*dpitch.  A
+// plain copy is one row, a 2D copy one slice.
+struct Pitched {
+    uint8_t *dst;
+    const uint8_t *src;
+    size_t width, height, depth, dpitch, spitch, dslice, sslice;
+};
+
+// device buffers for k pitched records and their verdicts
+bool ensure_slices(uint64_t k)
+{
+    if (k <= G.slice_cap) return true;
+    Guard g;
+    (void)hipStreamSynchronize(G.s);
+    (void)hipFree(G.d_rec2d);
+    (void)hipFree(G.d_ver2d);
+    G.d_rec2d = nullptr;
+    G.d_ver2d = nullptr;
+    G.slice_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&G.d_rec2d), k * sizeof(cg_transfer2d)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&G.d_ver2d), k * sizeof(cg_verdict)) != hipSuccess)
+        return false;
+    G.slice_cap = k;
+    return true;
+}
+
+// Check a copy before it runs and print the report; false if the copy must
+// not be performed (a device side is unallocated or too small).  The whole
+// copy is one check (one 2D record per slice); only when it has findings are
+// its rows checked one by one, to name the first faulty row.
+bool check_pitched(const char *api, const Pitched &p, uint32_t kind)
 {
     std::lock_guard<std::mutex> lk(G.mu);
-    if (!ensure_ctx() || !ensure_rows(rows)) return true;
+    if (!ensure_ctx()) return true;
     Guard g;
-    std::vector<cg_transfer> r(rows);
-    for (size_t i = 0; i < rows; ++i)
-        r[i] = cg_transfer{(uint64_t)(src + i * spitch), (uint64_t)(dst + i * dpitch), (uint64_t)width, kind, 0};
-    uint32_t mode = CG_CHECK;
+    const uint64_t nrows = (uint64_t)p.height * p.depth;
     if (kind != CG_D2D) {
-        // the host rows as one region: first row start to last row end
-        const uint64_t hp = kind == CG_H2D ? r[0].src : r[0].dst;
-        const uint64_t hpitch = kind == CG_H2D ? spitch : dpitch;
-        const uint64_t span = (rows - 1) * hpitch + width;
+        // the host side as one region: first row start to last row end
+        const bool hsrc = kind == CG_H2D;
+        const uint64_t hp = hsrc ? (uint64_t)p.src : (uint64_t)p.dst;
+        const uint64_t pitch = hsrc ? p.spitch : p.dpitch, slice = hsrc ? p.sslice : p.dslice;
+        const uint64_t span = (p.depth - 1) * slice + (p.height - 1) * pitch + p.width;
         if (!ensure_host_cover(span) || cg_host_register(G.ctx, hp, span ? span : 1, G.zeros, G.ones) != CG_OK)
             return true;
     }
     // no propagation into host shadow (the zeros buffer must stay zero), nor
     // when destination rows overlap (their order would be unspecified)
-    if (kind != CG_D2H && (rows == 1 || dpitch >= width)) mode |= CG_PROPAGATE;
-    std::vector<cg_verdict> v(rows);
-    if (hipMemcpyAsync(G.d_rec, r.data(), rows * sizeof(cg_transfer), hipMemcpyHostToDevice, G.s) != hipSuccess ||
-        check_transfers(G.ctx, G.d_rec, rows, G.d_ver, mode, G.s) != CG_OK ||
-        hipMemcpyAsync(v.data(), G.d_ver, rows * sizeof(cg_verdict), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+    const bool rows_apart = (p.height == 1 || p.dpitch >= p.width) &&
+                            (p.depth == 1 || p.dslice >= (p.height - 1) * p.dpitch + p.width);
+    const uint32_t mode = CG_CHECK | (kind != CG_D2H && rows_apart ? CG_PROPAGATE : 0u);
+    auto masked = [&](uint32_t f) { return (!G.device_undef && kind != CG_H2D) ? f & ~CG_SRC_UNDEF : f; };
+    bool bad = false;
+    if (nrows == 1) {
+        if (!ensure_rows(1)) return true;
+        cg_transfer r{(uint64_t)p.src, (uint64_t)p.dst, (uint64_t)p.width, kind, 0};
+        cg_verdict v;
+        if (hipMemcpyAsync(G.d_rec, &r, sizeof r, hipMemcpyHostToDevice, G.s) != hipSuccess ||
+            check_transfers(G.ctx, G.d_rec, 1, G.d_ver, mode, G.s) != CG_OK ||
+            hipMemcpyAsync(&v, G.d_ver, sizeof v, hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+            hipStreamSynchronize(G.s) != hipSuccess) {
+            fprintf(stderr, "==xfercheck== check failed: %s\n", cg_last_error(G.ctx));
+            return true;
+        }
+        ++G.copies;
+        if (!masked(v.flags)) return true;
+        char buf[1024];
+        v.flags = masked(v.flags);
+        cg_format_verdict(&r, &v, buf, sizeof buf);
+        ++G.errors;
+        fprintf(stderr, "%s\n at %s(dst=%p, src=%p, %zu bytes, %s)\n", buf, api, (void *)p.dst, (const void *)p.src,
+                p.width, kind_name(kind));
+        return G.allow_bad || !(v.flags & kRangeFaults);
+    }
+    if (!ensure_slices(p.depth)) return true;
+    std::vector<cg_transfer2d> r2(p.depth);
+    for (size_t z = 0; z < p.depth; ++z)
+        r2[z] = cg_transfer2d{(uint64_t)(p.src + z * p.sslice), (uint64_t)(p.dst + z * p.dslice), (uint64_t)p.width,
+                              (uint64_t)p.height, (uint64_t)p.spitch, (uint64_t)p.dpitch, kind, {0, 0, 0}};
+    std::vector<cg_verdict> v2(p.depth);
+    if (hipMemcpyAsync(G.d_rec2d, r2.data(), p.depth * sizeof(cg_transfer2d), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_transfers_2d(G.ctx, G.d_rec2d, p.depth, G.d_ver2d, mode, G.s) != CG_OK ||
+        hipMemcpyAsync(v2.data(), G.d_ver2d, p.depth * sizeof(cg_verdict), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
         hipStreamSynchronize(G.s) != hipSuccess) {
         fprintf(stderr, "==xfercheck== check failed: %s\n", cg_last_error(G.ctx));
         return true;
     }
     ++G.copies;
-    size_t bad_rows = 0, first = rows;
+    for (const cg_verdict &v : v2) bad = bad || masked(v.flags) != 0;
+    if (!bad) return true;
+    // locate: every row, checked without propagation
+    if (!ensure_rows(nrows)) return true;
+    std::vector<cg_transfer> r(nrows);
+    for (size_t z = 0, k = 0; z < p.depth; ++z)
+        for (size_t y = 0; y < p.height; ++y, ++k)
+            r[k] = cg_transfer{(uint64_t)(p.src + z * p.sslice + y * p.spitch),
+                               (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width, kind, 0};
+    std::vector<cg_verdict> v(nrows);
+    if (hipMemcpyAsync(G.d_rec, r.data(), nrows * sizeof(cg_transfer), hipMemcpyHostToDevice, G.s) != hipSuccess ||
+        check_transfers(G.ctx, G.d_rec, nrows, G.d_ver, CG_CHECK, G.s) != CG_OK ||
+        hipMemcpyAsync(v.data(), G.d_ver, nrows * sizeof(cg_verdict), hipMemcpyDeviceToHost, G.s) != hipSuccess ||
+        hipStreamSynchronize(G.s) != hipSuccess) {
+        fprintf(stderr, "==xfercheck== check failed: %s\n", cg_last_error(G.ctx));
+        return true;
+    }
+    size_t bad_rows = 0, first = nrows;
     uint32_t all = 0;
-    for (size_t i = 0; i < rows; ++i) {
-        if (!G.device_undef && kind != CG_H2D) v[i].flags &= ~CG_SRC_UNDEF;
-        if (v[i].flags) {
+    for (size_t k = 0; k < nrows; ++k) {
+        v[k].flags = masked(v[k].flags);
+        if (v[k].flags) {
             ++bad_rows;
-            if (first == rows) first = i;
-            all |= v[i].flags;
+            if (first == nrows) first = k;
+            all |= v[k].flags;
         }
     }
     if (!bad_rows) return true;
     char buf[1024];
     cg_format_verdict(&r[first], &v[first], buf, sizeof buf);
     ++G.errors;
-    if (rows == 1)
-        fprintf(stderr, "%s\n at %s(dst=%p, src=%p, %zu bytes, %s)\n", buf, api, (void *)dst, (const void *)src, width,
-                kind_name(kind));
-    else
+    if (p.depth == 1)
         fprintf(stderr, "%s\n in row %zu of %zu (%zu rows with errors) at %s(dst=%p, dpitch=%zu, src=%p, spitch=%zu, "
                         "width=%zu, %s)\n",
-                buf, first, rows, bad_rows, api, (void *)dst, dpitch, (const void *)src, spitch, width, kind_name(kind));
+                buf, first, nrows, bad_rows, api, (void *)p.dst, p.dpitch, (const void *)p.src, p.spitch, p.width,
+                kind_name(kind));
+    else
+        fprintf(stderr, "%s\n in row %zu of slice %zu (%zu x %zu rows, %zu with errors) at %s(dst=%p, src=%p, "
+                        "width=%zu, height=%zu, depth=%zu, %s)\n",
+                buf, first % p.height, first / p.height, p.height, p.depth, bad_rows, api, (void *)p.dst,
+                (const void *)p.src, p.width, p.height, p.depth, kind_name(kind));
     return G.allow_bad || !(all & kRangeFaults);
 }
 
 bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t kind)
 {
-    return check_rows(api, (uint8_t *)dst, 0, (const uint8_t *)src, 0, n, 1, kind);
+    return check_pitched(api, Pitched{(uint8_t *)dst, (const uint8_t *)src, n, 1, 1, 0, 0, 0, 0}, kind);
+}
+
+// the rows of a pitched asynchronous copy join the concurrent-access window
+void window_rows(const Pitched &p, uint32_t kind, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lk(G.mu);
+    for (size_t z = 0; z < p.depth; ++z)
+        for (size_t y = 0; y < p.height; ++y)
+            G.win.push_back(WinCopy{cg_transfer{(uint64_t)(p.src + z * p.sslice + y * p.spitch),
+                                                (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width,
+                                                kind, 0},
+                                    stream});
+}
+
+// a 3D copy of linear memory as a Pitched copy
+Pitched pitched_3d(const hipMemcpy3DParms *q)
+{
+    const hipPitchedPtr &s = q->srcPtr, &d = q->dstPtr;
+    Pitched p;
+    p.src = (const uint8_t *)s.ptr + q->srcPos.z * s.pitch * s.ysize + q->srcPos.y * s.pitch + q->srcPos.x;
+    p.dst = (uint8_t *)d.ptr + q->dstPos.z * d.pitch * d.ysize + q->dstPos.y * d.pitch + q->dstPos.x;
+    p.width = q->extent.width;
+    p.height = q->extent.height;
+    p.depth = q->extent.depth;
+    p.spitch = s.pitch;
+    p.dpitch = d.pitch;
+    p.sslice = s.pitch * s.ysize;
+    p.dslice = d.pitch * d.ysize;
+    return p;
 }
 
 bool meets(uint64_t a, uint64_t na, uint64_t b, uint64_t nb) { return na && nb && a < b + nb && b < a + na; }
@@ -735,11 +848,81 @@ hipError_t hipMemcpy2D(void *dst, size_t dpitch, const void *src, size_t spitch,
     if (!inside) sync_point();
     if (!inside && width && height) {
         const uint32_t d = direction(dst, src, kind);
-        if (d <= CG_D2D && !check_rows("hipMemcpy2D", (uint8_t *)dst, dpitch, (const uint8_t *)src, spitch, width,
-                                       height, d))
+        if (d <= CG_D2D &&
+            !check_pitched("hipMemcpy2D", Pitched{(uint8_t *)dst, (const uint8_t *)src, width, height, 1, dpitch, spitch,
+                                                  0, 0},
+                           d))
             return refuse();
     }
     return f(dst, dpitch, src, spitch, width, height, kind);
+}
+
+hipError_t hipMemcpy2DAsync(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t height,
+                            hipMemcpyKind kind, hipStream_t stream)
+{
+    static memcpy2d_async_t f = real<memcpy2d_async_t>("hipMemcpy2DAsync");
+    if (!inside && width && height) {
+        const uint32_t d = direction(dst, src, kind);
+        const Pitched p{(uint8_t *)dst, (const uint8_t *)src, width, height, 1, dpitch, spitch, 0, 0};
+        if (d <= CG_D2D) {
+            if (!check_pitched("hipMemcpy2DAsync", p, d)) return refuse();
+            window_rows(p, d, stream);
+        }
+    }
+    return f(dst, dpitch, src, spitch, width, height, kind, stream);
+}
+
+hipError_t hipMemcpy3D(const hipMemcpy3DParms *q)
+{
+    static memcpy3d_t f = real<memcpy3d_t>("hipMemcpy3D");
+    if (!inside) sync_point();
+    if (!inside && q && !q->srcArray && !q->dstArray && q->extent.width && q->extent.height && q->extent.depth) {
+        const Pitched p = pitched_3d(q);
+        const uint32_t d = direction(p.dst, p.src, q->kind);
+        if (d <= CG_D2D && !check_pitched("hipMemcpy3D", p, d)) return refuse();
+    }
+    return f(q);
+}
+
+hipError_t hipMemcpy3DAsync(const hipMemcpy3DParms *q, hipStream_t stream)
+{
+    static memcpy3d_async_t f = real<memcpy3d_async_t>("hipMemcpy3DAsync");
+    if (!inside && q && !q->srcArray && !q->dstArray && q->extent.width && q->extent.height && q->extent.depth) {
+        const Pitched p = pitched_3d(q);
+        const uint32_t d = direction(p.dst, p.src, q->kind);
+        if (d <= CG_D2D) {
+            if (!check_pitched("hipMemcpy3DAsync", p, d)) return refuse();
+            window_rows(p, d, stream);
+        }
+    }
+    return f(q, stream);
+}
+
+hipError_t hipMallocPitch(void **ptr, size_t *pitch, size_t width, size_t height)
+{
+    static malloc_pitch_t f = real<malloc_pitch_t>("hipMallocPitch");
+    hipError_t e;
+    {
+        Guard g;   // an allocation made inside is tracked here, once
+        e = f(ptr, pitch, width, height);
+    }
+    if (!inside && e == hipSuccess && ptr && *ptr && pitch && *pitch && height)
+        track_alloc("hipMallocPitch", *ptr, *pitch * height);
+    return e;
+}
+
+hipError_t hipMalloc3D(hipPitchedPtr *pp, hipExtent extent)
+{
+    static malloc3d_t f = real<malloc3d_t>("hipMalloc3D");
+    const bool outer = !inside;
+    hipError_t e;
+    {
+        Guard g;
+        e = f(pp, extent);
+    }
+    if (outer && e == hipSuccess && pp && pp->ptr && pp->pitch && extent.height && extent.depth)
+        track_alloc("hipMalloc3D", pp->ptr, pp->pitch * extent.height * extent.depth);
+    return e;
 }
 
 }  // extern "C"

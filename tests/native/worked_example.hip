@@ -128,8 +128,49 @@ static int kernel_args()
     return 0;
 }
 
+// Pitched allocations: hipMallocPitch with a 2D copy that fits and one whose
+// last row finds 100 of its 300 bytes; hipMalloc3D with a 3D copy that fits
+// and one whose last row of the last slice finds 32 of its 64 bytes; an
+// asynchronous 2D copy that overruns.
+static int pitched_3d()
+{
+    const size_t w = 300, h = 50;
+    uint8_t *pp = nullptr;
+    size_t pitch = 0;
+    if (hipMallocPitch((void **)&pp, &pitch, w, h) != hipSuccess) return 2;
+    uint8_t *host = (uint8_t *)calloc(64 * 1024, 1);
+    hipError_t e = hipMemcpy2D(pp, pitch, host, w, w, h, hipMemcpyHostToDevice);
+    printf("pitched 2D fitting returned %d\n", (int)e);
+    e = hipMemcpy2D(pp + (pitch - 100), pitch, host, w, w, h, hipMemcpyHostToDevice);
+    printf("pitched 2D overrun returned %d\n", (int)e);
+    hipPitchedPtr p3;
+    const hipExtent ext = make_hipExtent(64, 8, 4);
+    if (hipMalloc3D(&p3, ext) != hipSuccess) return 2;
+    hipMemcpy3DParms q = {};
+    q.srcPtr = make_hipPitchedPtr(host, 64, 64, 8);
+    q.dstPtr = p3;
+    q.extent = ext;
+    q.kind = hipMemcpyHostToDevice;
+    e = hipMemcpy3D(&q);
+    printf("3D fitting returned %d\n", (int)e);
+    q.dstPos = make_hipPos(p3.pitch - 32, 0, 0);
+    e = hipMemcpy3D(&q);
+    printf("3D overrun returned %d\n", (int)e);
+    hipStream_t s;
+    if (hipStreamCreate(&s) != hipSuccess) return 2;
+    e = hipMemcpy2DAsync(pp + (pitch - 100), pitch, host, w, w, h, hipMemcpyHostToDevice, s);
+    printf("2D async overrun returned %d\n", (int)e);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    hipFree(pp);
+    hipFree(p3.ptr);
+    free(host);
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
+    if (argc > 1 && strcmp(argv[1], "pitched3d") == 0) return pitched_3d();
     if (argc > 1 && strcmp(argv[1], "kernelargs") == 0) return kernel_args();
     if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
     if (argc > 1 && strcmp(argv[1], "streams") == 0) return streams();

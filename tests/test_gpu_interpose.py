@@ -103,3 +103,22 @@ def test_kernel_arguments():
     assert "Error: Kernel argument 2 (double const*) points into no allocated device region." in err
     assert "at hipLaunchKernel(vecsum(double*, double const*, double const*, int))" in err
     assert "0 copies checked, 2 with errors, 5 kernel launches checked" in err
+
+
+def test_pitched_allocations_and_3d_copies():
+    """hipMallocPitch and hipMalloc3D allocations are tracked with their
+    pitched sizes; hipMemcpy2D, hipMemcpy2DAsync and hipMemcpy3D are checked
+    as pitched records on the GPU, and a faulty copy names its first faulty
+    row (and slice)."""
+    r = run_example("pitched3d")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0
+    for line in ("pitched 2D fitting returned 0", "pitched 2D overrun returned 1", "3D fitting returned 0",
+                 "3D overrun returned 1", "2D async overrun returned 1"):
+        assert line in r.stdout
+    err = r.stderr
+    assert err.count("Expected 300 allocated bytes but only found 100.") == 2
+    assert err.count("in row 49 of 50 (1 rows with errors)") == 2
+    assert "Expected 64 allocated bytes but only found 32." in err
+    assert "in row 7 of slice 3 (8 x 4 rows, 1 with errors) at hipMemcpy3D(" in err
+    assert "5 copies checked, 3 with errors" in err
