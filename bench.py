@@ -179,6 +179,23 @@ def plain_at_scale_leg():
         out["batched_check_propagate"] = {"scan_ms": round(k, 3), "GBps": round(bp / (k / 1e3) / 1e9, 1),
                                           "algorithmic_bytes": int(bp)}
         out["tuning"] = {"check": tun[X.CG_CHECK], "check_propagate": tun[X.CG_CHECK | X.CG_PROPAGATE]}
+        # the same copies as pitched 2D copies of 4 KiB rows (contiguous pitches), one check_transfers_2d call
+        r2 = np.zeros(T, W.RECORD2D_DTYPE)
+        rows = w.records["n"] // 4096
+        r2["src"], r2["dst"], r2["kind"] = w.records["src"], w.records["dst"], w.records["kind"]
+        r2["width"], r2["rows"], r2["spitch"], r2["dpitch"] = 4096, rows, 4096, 4096
+        b2 = int((rows * 4096).sum()) * 9 // 8
+        rt2 = torch.from_numpy(r2.view(np.uint8).copy()).to(rt.device)
+        X.cg_timing(ctx, False)
+        X.check_transfers_2d(ctx, rt2.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            X.check_transfers_2d(ctx, rt2.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 3
+        out["pitched_2d"] = {"records": T, "rows": int(rows.sum()), "ms": round(wall * 1e3, 3),
+                             "GBps": round(b2 / wall / 1e9, 1), "algorithmic_bytes": b2}
     finally:
         dw.close()
     log(f"[bench] plain at scale: {out}")

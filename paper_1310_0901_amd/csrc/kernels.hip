@@ -818,16 +818,45 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
         uint64_t u = (uint64_t)j * tu;
         const uint64_t u_end = (u + tu < total) ? u + tu : total;
         uint64_t t = ufl32(a.tile_start[j]);
+        // record t's units [pt, pt1) and, once loaded, its descriptor d; when a
+        // record is finished by the wave-uniform loop, the next record's
+        // metadata is loaded together with this record's data, so that
+        // mid-size records do not pay two round trips each
+        uint64_t pt = ufl64(a.prefix[t]), pt1 = ufl64(a.prefix[t + 1]);
+        bool have_d = false;
+        DV d = make_dv(Desc{});
         while (u < u_end) {
-            const uint64_t pt = ufl64(a.prefix[t]), pt1 = ufl64(a.prefix[t + 1]);
+            // a run of 64 units or more goes through the wave-uniform loop whole
+            // (its last iteration may be partial); shorter runs, which may hold
+            // several records, go one unit per lane
             const uint64_t seg_end = pt1 < u_end ? pt1 : u_end;
-            const uint64_t nfull = (seg_end - u) & ~63ull;
+            const uint64_t nfull = seg_end - u >= 64 ? seg_end - u : 0;
             if (nfull) {
-                const DV d = load_desc_uniform(a.desc, t);
+                if (!have_d) d = load_desc_uniform(a.desc, t);
+                const bool ahead = u + nfull == pt1 && u + nfull < u_end && t + 1 < T;
+                uint64_t npt1 = pt1;
+                DV nd = d;
+                if (ahead) {
+                    npt1 = ufl64(a.prefix[t + 2]);
+                    nd = load_desc_uniform(a.desc, t + 1);
+                }
                 run_uniform<U, NT, PROP>(d, R, u - pt, u - pt + nfull, acc);
                 if (a.out) flush_wave(acc, a.out, t);
                 u += nfull;
-                if (u == pt1) ++t;
+                if (u == pt1) {
+                    ++t;
+                    pt = pt1;
+                    if (ahead) {
+                        pt1 = npt1;
+                        d = nd;
+                        have_d = true;
+                    } else {
+                        if (u < u_end) pt1 = ufl64(a.prefix[t + 1]);
+                        have_d = false;
+                    }
+                } else {
+                    have_d = true;
+                }
                 continue;
             }
             // up to 64 units, one per lane, possibly of several records
@@ -850,6 +879,9 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
             if (g_end < u_end) {
                 const uint64_t t63 = ufl64(__shfl(tl, 63));
                 t = (ufl64(a.prefix[t63 + 1]) <= g_end) ? t63 + 1 : t63;
+                pt = ufl64(a.prefix[t]);
+                pt1 = ufl64(a.prefix[t + 1]);
+                have_d = false;
             }
             u = g_end;
         }
