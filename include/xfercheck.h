@@ -75,6 +75,7 @@ extern "C" {
 #define CG_PLAIN           0x04u  /* one kernel launch per transfer (baseline path) */
 #define CG_DEBUG_CONFLICTS 0x08u  /* host-side verification of the no-conflict rule (synchronous) */
 #define CG_EAGER           0x10u  /* batched path without graph capture */
+#define CG_KEEP_ORDER      0x20u  /* work a large batch in the given order (no reordering by source address) */
 
 /*
  * One transfer record, 32 bytes, in device memory (the parameters of a
@@ -179,7 +180,11 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  * per record to out_dev (device memory, 32 bytes each), on `hip_stream`
  * (a hipStream_t; NULL = the null stream).
  *   mode: CG_CHECK and/or CG_PROPAGATE, optionally with CG_PLAIN (one launch
- *   per record), CG_EAGER (no graph capture) or CG_DEBUG_CONFLICTS.
+ *   per record), CG_EAGER (no graph capture), CG_DEBUG_CONFLICTS or
+ *   CG_KEEP_ORDER.  A batched check of 16,384 records or more is worked in
+ *   ascending order of source address (records reading the same bytes run
+ *   close together); verdicts are written at the records' own positions
+ *   either way, and CG_KEEP_ORDER works the batch in the given order.
  * With CG_PROPAGATE every valid destination byte receives the source's V
  * byte, or 0xFF where the source byte is not valid; overlapping D2D records
  * are not propagated.  All records read the shadow as it was before the

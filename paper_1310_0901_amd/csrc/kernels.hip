@@ -550,7 +550,8 @@ __device__ __forceinline__ uint64_t clamp_scan(uint64_t x) { return x < kScanLim
 // descriptor; return its number of units.
 __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
 {
-    const cg_transfer r = a.recs[t];
+    const uint64_t rt = a.perm ? a.perm[t] : t;   // the record at position t
+    const cg_transfer r = a.recs[rt];
     const uint64_t n = r.n;
     Desc ds = {};
     uint32_t flags = 0;
@@ -658,7 +659,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
         v.first_bad = first;
         v.undef_bytes = 0;
         v.avail = avail;
-        a.out[t] = v;
+        a.out[rt] = v;
     }
     return units;
 }
@@ -841,7 +842,7 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
                     nd = load_desc_uniform(a.desc, t + 1);
                 }
                 run_uniform<U, NT, PROP>(d, R, u - pt, u - pt + nfull, acc);
-                if (a.out) flush_wave(acc, a.out, t);
+                if (a.out) flush_wave(acc, a.out, a.perm ? ufl32(a.perm[t]) : t);
                 u += nfull;
                 if (u == pt1) {
                     ++t;
@@ -874,7 +875,8 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
                 const uint64_t k = ul - a.prefix[tl];
                 if (k < d.units) run_unit<NT, PROP>(d, R, k, acc);
             }
-            if (a.out && __ballot(acc.flags != 0u)) flush_segmented(acc, act ? tl : ~0ull, a.out);
+            if (a.out && __ballot(acc.flags != 0u))
+                flush_segmented(acc, act ? (a.perm ? (uint64_t)a.perm[tl] : tl) : ~0ull, a.out);
             else acc_reset(acc);
             if (g_end < u_end) {
                 const uint64_t t63 = ufl64(__shfl(tl, 63));

@@ -5,18 +5,16 @@
 #include <hip/hip_runtime_api.h>
 
 #include "../../include/xfercheck.h"
+#include "sort.h"
 
 namespace xc {
 
 // Device buffers of one join, sized for `cap` intervals (two per record).
+// After the sort, the sort's spare pair of buffers holds each sorted
+// interval's end key and stream.
 struct RaceWs {
     uint64_t cap = 0;
-    uint64_t *keys[2] = {nullptr, nullptr};   // sort keys, ping-pong
-    uint32_t *vals[2] = {nullptr, nullptr};   // interval ids, ping-pong
-    uint32_t *counts = nullptr;               // per-digit, per-tile counts [256][tiles]
-    uint32_t *dtot = nullptr;                 // per-digit totals [256]
-    uint64_t *mask = nullptr;                 // key bits that differ between intervals
-    uint64_t *parts = nullptr;                // per key-building block: its part of mask
+    SortWs sort;
     uint32_t *res = nullptr;                  // per-interval partner (or none)
     void *agg = nullptr;                      // per sweep tile: 4 monoid aggregates
     void *pre = nullptr;                      // per sweep tile: prefix / suffix of those

@@ -10,8 +10,8 @@
 //
 // The join is an interval sweep.  Every record gives two intervals whose key
 // is (epoch << 48 | address), so intervals of different epochs never meet.
-// The keys are sorted by an 8-bit LSD radix sort; a pass whose digit is the
-// same in every key is skipped on the device.  An interval then meets an
+// The keys are sorted by the 8-bit LSD radix sort of sort.hip, which skips a
+// pass whose digit is the same in every key.  An interval then meets an
 // interval of another stream that starts no later exactly when the furthest
 // end among earlier intervals of other streams lies past its start, and one
 // that starts later exactly when the smallest start among later intervals of
@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "race.h"
+#include "sort.h"
 
 namespace xc {
 namespace {
@@ -33,11 +34,9 @@ constexpr uint32_t kEpochLimit = 1u << 15;
 
 constexpr int kT = 256;                          // threads per block
 constexpr int kWaves = kT / 64;
-constexpr int kSortTile = 4096;                  // keys per sort tile
-constexpr int kWaveItems = kSortTile / kWaves;   // contiguous keys per wave
-constexpr int kRounds = kWaveItems / 64;
 constexpr int kSweepItems = 8;                   // consecutive elements per thread
 constexpr int kSweepTile = kT * kSweepItems;
+static_assert(kT == kSortKeyBlock, "one part of the key mask per block of k_race_keys");
 
 // ---- records -------------------------------------------------------------
 
@@ -57,18 +56,6 @@ __device__ __forceinline__ uint64_t interval_key(const cg_transfer *recs, const 
     const uint32_t e = epochs ? epochs[i >> 1] : 0u;
     if (t.n == 0 || !rec_checked(t, e)) return kInvalidKey;
     return ((uint64_t)e << 48) | ((i & 1) ? t.dst : t.src);
-}
-
-// ---- sort plan: passes over digits that differ somewhere -------------------
-
-__device__ __forceinline__ bool pass_live(uint64_t mask, int pass) { return ((mask >> (8 * pass)) & 0xFFu) != 0; }
-
-// which of the two buffers holds the keys before `pass`
-__device__ __forceinline__ int pass_parity(uint64_t mask, int pass)
-{
-    int p = 0;
-    for (int q = 0; q < pass; ++q) p ^= pass_live(mask, q) ? 1 : 0;
-    return p;
 }
 
 __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const uint32_t *epochs, uint64_t m,
@@ -91,194 +78,6 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
         uint64_t y = 0;
         for (int w = 0; w < kWaves; ++w) y |= part[w];
         parts[blockIdx.x] = y;
-    }
-}
-
-// the key bits that differ anywhere: OR of the per-block partials
-__global__ __launch_bounds__(kT) void k_race_mask(const uint64_t *parts, uint32_t nparts, uint64_t *mask)
-{
-    __shared__ uint64_t part[kWaves];
-    uint64_t x = 0;
-    for (uint32_t j = threadIdx.x; j < nparts; j += kT) x |= parts[j];
-    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t y = 0;
-        for (int w = 0; w < kWaves; ++w) y |= part[w];
-        *mask = y;
-    }
-}
-
-// ---- radix sort ----------------------------------------------------------
-
-// lanes of the wave whose valid digit equals this lane's
-__device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
-{
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t y = __ballot(bit);
-        m &= bit ? y : ~y;
-    }
-    return valid ? m : 0ull;
-}
-
-__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
-
-// exclusive sum over the block's threads; *total receives the block sum
-__device__ uint32_t block_excl_sum(uint32_t x, uint32_t *total)
-{
-    __shared__ uint32_t wsum[kWaves];
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t inc = x;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(inc, d);
-        if (l >= d) inc += y;
-    }
-    if (l == 63) wsum[w] = inc;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (int j = 0; j < kWaves; ++j) {
-        if (j < w) off += wsum[j];
-        tot += wsum[j];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + inc - x;
-}
-
-// per-tile digit counts, digit-major: counts[d * tiles + tile]
-__global__ __launch_bounds__(kT) void k_race_count(const uint64_t *ka, const uint64_t *kb, uint64_t m,
-                                                   uint32_t tiles, const uint64_t *maskp, int pass,
-                                                   uint32_t *counts)
-{
-    const uint64_t mask = *maskp;
-    if (!pass_live(mask, pass)) return;
-    const uint64_t *kin = pass_parity(mask, pass) ? kb : ka;
-    const int shift = 8 * pass;
-    __shared__ uint32_t h[kWaves][256];
-    for (int j = threadIdx.x; j < kWaves * 256; j += kT) (&h[0][0])[j] = 0;
-    __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveItems + l;
-    uint32_t d[kRounds];
-#pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
-        const uint64_t idx = base + (uint64_t)i * 64;
-        d[i] = idx < m ? (uint32_t)(kin[idx] >> shift) & 0xFFu : 0u;
-    }
-#pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
-        const bool valid = base + (uint64_t)i * 64 < m;
-        const uint64_t peers = match8(d[i], valid);
-        if (valid && (peers & lanes_below()) == 0) h[w][d[i]] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    uint32_t c = 0;
-    for (int j = 0; j < kWaves; ++j) c += h[j][t];
-    counts[(uint64_t)t * tiles + blockIdx.x] = c;
-}
-
-// per digit (one block each): exclusive prefix of the tile counts in place,
-// and the digit's total
-__global__ __launch_bounds__(kT) void k_race_scan_digits(uint32_t *counts, uint32_t tiles, uint32_t *dtot,
-                                                         const uint64_t *maskp, int pass)
-{
-    if (!pass_live(*maskp, pass)) return;
-    uint32_t *row = counts + (uint64_t)blockIdx.x * tiles;
-    const uint32_t per = (tiles + kT - 1) / kT;
-    const uint32_t lo = min(tiles, threadIdx.x * per), hi = min(tiles, lo + per);
-    uint32_t s = 0;
-    for (uint32_t j = lo; j < hi; ++j) s += row[j];
-    uint32_t tot;
-    uint32_t run = block_excl_sum(s, &tot);
-    for (uint32_t j = lo; j < hi; ++j) {
-        const uint32_t c = row[j];
-        row[j] = run;
-        run += c;
-    }
-    if (threadIdx.x == 0) dtot[blockIdx.x] = tot;
-}
-
-// stable scatter of one tile: ranks within the tile, a local sort through
-// LDS, then runs of equal digits written contiguously
-__global__ __launch_bounds__(kT) void k_race_scatter(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
-                                                     uint64_t m, uint32_t tiles, const uint64_t *maskp, int pass,
-                                                     const uint32_t *counts, const uint32_t *dtot)
-{
-    const uint64_t mask = *maskp;
-    if (!pass_live(mask, pass)) return;
-    const int par = pass_parity(mask, pass);
-    const uint64_t *kin = par ? kb : ka;
-    const uint32_t *vin = par ? vb : va;
-    uint64_t *kout = par ? ka : kb;
-    uint32_t *vout = par ? va : vb;
-    const int shift = 8 * pass;
-
-    __shared__ uint64_t skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
-    __shared__ uint32_t wrun[kWaves][256];   // per wave: running count, then exclusive prefix across waves
-    __shared__ uint32_t dstart[256];         // first tile-local position of each digit
-    __shared__ uint32_t gbase[256];          // global position of this tile's first key of each digit
-
-    for (int j = threadIdx.x; j < kWaves * 256; j += kT) (&wrun[0][0])[j] = 0;
-    __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveItems + l;
-    uint64_t k[kRounds];
-    uint32_t v[kRounds], pk[kRounds];
-#pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
-        const uint64_t idx = base + (uint64_t)i * 64;
-        k[i] = idx < m ? kin[idx] : 0ull;
-        v[i] = idx < m ? vin[idx] : 0u;
-    }
-#pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
-        const bool valid = base + (uint64_t)i * 64 < m;
-        const uint32_t d = (uint32_t)(k[i] >> shift) & 0xFFu;
-        const uint64_t peers = match8(d, valid);
-        const uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
-        uint32_t run = 0;
-        if (valid) run = wrun[w][d];
-        if (valid && rank == 0) wrun[w][d] = run + (uint32_t)__popcll(peers);
-        pk[i] = valid ? (d << 16) | (run + rank) : 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    uint32_t acc = 0;
-    for (int j = 0; j < kWaves; ++j) {
-        const uint32_t c = wrun[j][t];
-        wrun[j][t] = acc;
-        acc += c;
-    }
-    uint32_t unused;
-    dstart[t] = block_excl_sum(acc, &unused);
-    gbase[t] = block_excl_sum(dtot[t], &unused) + counts[(uint64_t)t * tiles + blockIdx.x];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kRounds; ++i) {
-        if (pk[i] != 0xFFFFFFFFu) {
-            const uint32_t d = pk[i] >> 16;
-            const uint32_t pos = dstart[d] + wrun[w][d] + (pk[i] & 0xFFFFu);
-            skey[pos] = k[i];
-            sval[pos] = v[i];
-        }
-    }
-    __syncthreads();
-    const uint64_t left = m - (uint64_t)blockIdx.x * kSortTile;
-    const uint32_t nvalid = left < (uint64_t)kSortTile ? (uint32_t)left : (uint32_t)kSortTile;
-    for (uint32_t j = t; j < nvalid; j += kT) {
-        const uint64_t key = skey[j];
-        const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
-        const uint64_t g = (uint64_t)gbase[d] + (j - dstart[d]);
-        if (g < m) {
-            kout[g] = key;
-            vout[g] = sval[j];
-        }
     }
 }
 
@@ -412,7 +211,7 @@ struct Sorted {
 __device__ __forceinline__ Sorted sorted_view(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
                                               const uint32_t *vb, uint64_t mask)
 {
-    const bool b = pass_parity(mask, 8) != 0;
+    const bool b = sort_parity(mask) != 0;
     return Sorted{b ? kb : ka, b ? ka : kb, b ? vb : va, b ? va : vb};
 }
 
@@ -443,7 +242,7 @@ __global__ __launch_bounds__(kT) void k_race_gather(uint64_t *ka, uint64_t *kb, 
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (p >= m) return;
-    const bool b = pass_parity(*maskp, 8) != 0;
+    const bool b = sort_parity(*maskp) != 0;
     const uint64_t k = (b ? kb : ka)[p];
     const uint32_t iv = (b ? vb : va)[p];
     uint64_t end = 0;
@@ -641,19 +440,11 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
 {
     if (intervals <= w.cap) return hipSuccess;
     race_release(w);
-    const uint64_t tiles = ceil_div(intervals, kSortTile), sweeps = ceil_div(intervals, kSweepTile);
-    hipError_t e = hipSuccess;
+    hipError_t e = sort_reserve(w.sort, intervals);
+    const uint64_t sweeps = ceil_div(intervals, kSweepTile);
     auto get = [&](void **p, uint64_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 8);
     };
-    for (int i = 0; i < 2; ++i) {
-        get((void **)&w.keys[i], intervals * sizeof(uint64_t));
-        get((void **)&w.vals[i], intervals * sizeof(uint32_t));
-    }
-    get((void **)&w.counts, 256 * tiles * sizeof(uint32_t));
-    get((void **)&w.dtot, 256 * sizeof(uint32_t));
-    get((void **)&w.mask, sizeof(uint64_t));
-    get((void **)&w.parts, ceil_div(intervals, kT) * sizeof(uint64_t));
     get((void **)&w.res, intervals * sizeof(uint32_t));
     get(&w.agg, sweeps * 4 * sizeof(Top2));
     get(&w.pre, sweeps * 4 * sizeof(Top2));
@@ -667,7 +458,8 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
 
 void race_release(RaceWs &w)
 {
-    void *ps[] = {w.keys[0], w.keys[1], w.vals[0], w.vals[1], w.counts, w.dtot, w.mask, w.parts, w.res, w.agg, w.pre};
+    sort_release(w.sort);
+    void *ps[] = {w.res, w.agg, w.pre};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     w = RaceWs{};
@@ -678,26 +470,20 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
 {
     if (count == 0) return hipSuccess;
     const uint64_t m = 2 * count;
-    const uint32_t tiles = (uint32_t)ceil_div(m, kSortTile);
     const uint32_t sweeps = (uint32_t)ceil_div(m, kSweepTile);
-    const uint32_t kblocks = (uint32_t)ceil_div(m, kT);
-    hipLaunchKernelGGL(k_race_keys, dim3(kblocks), dim3(kT), 0, s, recs, epochs, m, w.keys[0], w.vals[0], w.parts);
-    hipLaunchKernelGGL(k_race_mask, dim3(1), dim3(kT), 0, s, w.parts, kblocks, w.mask);
-    for (int pass = 0; pass < 8; ++pass) {
-        hipLaunchKernelGGL(k_race_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], m, tiles, w.mask, pass,
-                           w.counts);
-        hipLaunchKernelGGL(k_race_scan_digits, dim3(256), dim3(kT), 0, s, w.counts, tiles, w.dtot, w.mask, pass);
-        hipLaunchKernelGGL(k_race_scatter, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
-                           m, tiles, w.mask, pass, w.counts, w.dtot);
-    }
+    SortWs &q = w.sort;
+    hipLaunchKernelGGL(k_race_keys, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, recs, epochs, m, q.keys[0],
+                       q.vals[0], q.parts);
+    hipError_t e = sort_pairs(q, m, s);
+    if (e != hipSuccess) return e;
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
-    hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0],
-                       w.vals[1], w.mask, recs, streams, m);
-    hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
-                       w.mask, m, agg);
+    hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0],
+                       q.vals[1], q.mask, recs, streams, m);
+    hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1],
+                       q.mask, m, agg);
     hipLaunchKernelGGL(k_race_sweep_scan, dim3(1), dim3(kT), 0, s, agg, sweeps, pre);
-    hipLaunchKernelGGL(k_race_sweep_apply, dim3(sweeps), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1],
-                       w.mask, m, pre, w.res);
+    hipLaunchKernelGGL(k_race_sweep_apply, dim3(sweeps), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1],
+                       q.mask, m, pre, w.res);
     hipLaunchKernelGGL(k_race_finalize, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, recs, epochs, count,
                        w.res, out);
     return hipGetLastError();

@@ -22,6 +22,7 @@
 
 #include "host_logic.h"
 #include "race.h"
+#include "sort.h"
 #include "xc_internal.h"
 
 using namespace xc;
@@ -67,6 +68,9 @@ struct Workspace {
     hipEvent_t done = nullptr;      // recorded after every check issued on this stream
     bool used = false;
     std::vector<GraphEntry> graphs;
+    // ordering of large batches by source address (allocated on first use)
+    SortWs sort;
+    uint32_t *perm = nullptr;
 };
 
 struct TimingPair {
@@ -153,6 +157,7 @@ struct cg_ctx {
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
     std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
+    uint64_t reorder_min = 16384;            // batches this large are worked in source-address order
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
@@ -347,6 +352,9 @@ void free_ws(Workspace *w)
     (void)hipFree(w->tile_start);
     (void)hipFree(w->ctl);
     if (w->h_weight) (void)hipHostFree(w->h_weight);
+    sort_release(w->sort);
+    (void)hipFree(w->perm);
+    w->perm = nullptr;
     w->desc = nullptr;
     w->weight = w->local = w->bsum = w->boff = w->prefix = nullptr;
     w->tile_start = nullptr;
@@ -420,32 +428,35 @@ LaunchShape shape_of(cg_ctx *c, const cg_tuning &t)
     return sh;
 }
 
-hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
+hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, SortWs *sort)
 {
     hipError_t e;
+    if (a.perm && (e = sort_by_source(*sort, a.recs, a.count, const_cast<uint32_t *>(a.perm), s)) != hipSuccess)
+        return e;
     if ((e = launch_classify(a, s)) != hipSuccess) return e;
     if ((e = launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s)) != hipSuccess) return e;
     return launch_prefix_tiles(a, s);
 }
 
-hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp)
+hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp, SortWs *sort)
 {
     hipError_t e;
-    if ((e = enqueue_prepare(a, sh, s)) != hipSuccess) return e;
+    if ((e = enqueue_prepare(a, sh, s, sort)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->a, s)) != hipSuccess) return e;
     if ((e = launch_batched(a, sh, s)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->b, s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
-int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part);
+int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part,
+            SortWs *sort);
 
 // The cached graph of this batched check (keyed by table version, buffers,
 // count, mode and launch shape), captured on first use.
 int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const LaunchShape &sh, const cg_tuning &tun, bool split,
                hipStream_t s, GraphEntry **out)
 {
-    const uint32_t mode = a.mode & 3u;
+    const uint32_t mode = (a.mode & 3u) | (a.perm ? 4u : 0u);
     for (auto &g : w->graphs)
         if (g.st == a.st && g.recs == a.recs && g.count == a.count && g.mode == mode && same_tuning(g.tun, tun) &&
             g.split == split && g.out == a.out) {
@@ -458,8 +469,8 @@ int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const LaunchShape &s
         w->graphs.erase(w->graphs.begin());
     }
     GraphEntry g{a.st, a.recs, a.out, a.count, mode, tun, split, nullptr, nullptr, nullptr, nullptr};
-    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0);
-    if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2);
+    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0, &w->sort);
+    if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2, &w->sort);
     if (rc) {
         destroy_graph(g);
         return rc;
@@ -574,7 +585,22 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         rc = debug_conflicts(c, recs, count, s);
         if (rc) return rc;
     }
-    const BatchArgs a = make_args(c, w, recs, count, out, mode);
+    BatchArgs a = make_args(c, w, recs, count, out, mode);
+    if (!(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min) {
+        // large batches are worked in order of source address, so that records
+        // reading the same bytes run close together and re-reads hit in cache
+        if (w->sort.cap < count) {
+            HIPTRY(c, hipStreamSynchronize(s));   // the old buffers may still be in use
+            for (auto &g : w->graphs) destroy_graph(g);
+            w->graphs.clear();
+            (void)hipFree(w->perm);
+            w->perm = nullptr;
+            const hipError_t e = sort_reserve(w->sort, w->cap);
+            if (e != hipSuccess) return hip_fail(c, "sort work space", e);
+            HIPTRY(c, hipMalloc(&w->perm, w->cap * 4));
+        }
+        a.perm = w->perm;
+    }
     const LaunchShape sh = shape_of(c, tun);
     if (mode & CG_PLAIN) {
         HIPTRY(c, launch_classify(a, s));
@@ -589,7 +615,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
     } else if (mode & CG_EAGER) {
         TimingPair *tp = c->timing ? next_pair(c) : nullptr;
-        HIPTRY(c, enqueue_batched(a, sh, s, tp));
+        HIPTRY(c, enqueue_batched(a, sh, s, tp, &w->sort));
     } else {
         const bool split = c->timing;
         GraphEntry *ge = nullptr;
@@ -629,11 +655,12 @@ int note_use(cg_ctx *c, hipStream_t s)
 
 // Capture part 0 (the whole batched check), 1 (the preparation kernels) or
 // 2 (the scan kernel) into an executable graph.
-int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part)
+int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part,
+            SortWs *sort)
 {
     HIPTRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr)
-                 : part == 1 ? enqueue_prepare(a, sh, c->cap)
+    hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr, sort)
+                 : part == 1 ? enqueue_prepare(a, sh, c->cap, sort)
                              : launch_batched(a, sh, c->cap);
     hipError_t e2 = hipStreamEndCapture(c->cap, g);
     if (e != hipSuccess) return hip_fail(c, "graph capture", e);
@@ -734,6 +761,7 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_BLOCK")) c->tuning.block = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_BLOCKS_PER_CU")) c->tuning.blocks_per_cu = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_REORDER_MIN")) c->reorder_min = strtoull(e, nullptr, 0);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
     c->tuning_prop.unroll = 2;
@@ -923,7 +951,7 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
 {
     if (!c) return CG_EINVAL;
     if (!(mode & (CG_CHECK | CG_PROPAGATE))) return fail(c, CG_EINVAL, "mode needs CG_CHECK or CG_PROPAGATE");
-    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER))
+    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER | CG_KEEP_ORDER))
         return fail(c, CG_EINVAL, "unknown mode bits");
     if (count == 0) return CG_OK;
     if (!recs_dev) return fail(c, CG_EINVAL, "null records");
@@ -944,7 +972,7 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
 {
     if (!c) return CG_EINVAL;
     if (!(mode & (CG_CHECK | CG_PROPAGATE))) return fail(c, CG_EINVAL, "mode needs CG_CHECK or CG_PROPAGATE");
-    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER))
+    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_DEBUG_CONFLICTS | CG_EAGER | CG_KEEP_ORDER))
         return fail(c, CG_EINVAL, "unknown mode bits");
     if (count == 0) return CG_OK;
     if (!recs_dev) return fail(c, CG_EINVAL, "null records");

@@ -1,0 +1,50 @@
+// Stable radix sort of (u64 key, u32 value) pairs on the device (sort.hip),
+// used by the concurrent-access join and to order large check batches by
+// source address.  Internal interface.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "../../include/xfercheck.h"
+
+namespace xc {
+
+// Work space of one sort of up to `cap` pairs.  keys[0] / vals[0] take the
+// input; the sorted pairs end in keys[b] / vals[b] with b = sort_parity(mask)
+// (known only on the device); the other pair of buffers is free afterwards.
+struct SortWs {
+    uint64_t cap = 0;
+    uint64_t *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    uint32_t *counts = nullptr;   // per-digit, per-tile counts [256][tiles]
+    uint32_t *dtot = nullptr;     // per-digit totals [256]
+    uint64_t *parts = nullptr;    // per key-building block: OR of (key ^ first key)
+    uint64_t *mask = nullptr;     // key bits that differ anywhere
+};
+
+constexpr int kSortKeyBlock = 256;   // keys per key-building block (one part each)
+
+hipError_t sort_reserve(SortWs &w, uint64_t n);
+void sort_release(SortWs &w);
+
+// Sort the n pairs in keys[0] / vals[0]; parts[0 .. ceil(n / kSortKeyBlock))
+// must hold the key-building blocks' parts.
+hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s);
+
+// perm[i] = index of the i-th of `count` records in ascending order of source
+// address (ties in input order).
+hipError_t sort_by_source(SortWs &w, const cg_transfer *recs, uint64_t count, uint32_t *perm, hipStream_t s);
+
+// a pass over key byte `pass` is skipped when that byte is the same in every key
+__device__ __forceinline__ bool sort_pass_live(uint64_t mask, int pass) { return ((mask >> (8 * pass)) & 0xFFu) != 0; }
+
+// which of the two buffers holds the keys before `pass` (pass 8: after the sort)
+__device__ __forceinline__ int sort_parity(uint64_t mask, int pass = 8)
+{
+    int p = 0;
+    for (int q = 0; q < pass; ++q) p ^= sort_pass_live(mask, q) ? 1 : 0;
+    return p;
+}
+
+}  // namespace xc

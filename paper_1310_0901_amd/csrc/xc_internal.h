@@ -100,6 +100,10 @@ struct BatchArgs {
     uint32_t *tile_start;   // first record of each tile
     uint64_t tiles_cap;
     Ctl *ctl;
+    // when not null, the batch is worked in this order: position t holds
+    // record perm[t] (records, verdicts and findings are indexed through it;
+    // descriptors, weights and prefixes are by position)
+    const uint32_t *perm;
 };
 
 struct LaunchShape {

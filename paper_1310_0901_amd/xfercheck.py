@@ -27,7 +27,7 @@ CG_NONE = 0xFFFF_FFFF_FFFF_FFFF
 CG_RACE_SRC, CG_RACE_DST, CG_RACE_UNCHECKED = 0x1, 0x2, 0x4
 CG_PTR_UNALLOC = 0x1
 # modes
-CG_CHECK, CG_PROPAGATE, CG_PLAIN, CG_DEBUG_CONFLICTS, CG_EAGER = 0x1, 0x2, 0x4, 0x8, 0x10
+CG_CHECK, CG_PROPAGATE, CG_PLAIN, CG_DEBUG_CONFLICTS, CG_EAGER, CG_KEEP_ORDER = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 
 
 class CgError(RuntimeError):
