@@ -1125,14 +1125,17 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     if (!c || !recs_dev || !count) return CG_EINVAL;
     if ((mode & CG_CHECK) && !out_dev) return CG_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
+    const uint32_t keep = mode & CG_KEEP_ORDER;
     mode &= (CG_CHECK | CG_PROPAGATE);
     if (!mode) return CG_EINVAL;
+    // the batch is worked in source-address order unless kept (as run_check decides)
+    const bool reordered = !keep && count >= c->reorder_min;
     cg_tuning &target = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
     // workload signature: count and log2 of the total units, from a first run
     const bool was_timing = c->timing;
     c->timing = true;
     c->tused = 0;
-    int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, target);
+    int rc = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER | keep, s, target);
     if (rc) { c->timing = was_timing; return rc; }
     HIPTRY(c, hipStreamSynchronize(s));
     c->tused = 0;
@@ -1141,7 +1144,7 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     uint32_t lg = 0;
     while ((1ull << lg) < ctl.total_units) ++lg;
     std::ostringstream key;
-    key << c->arch << "/cu" << c->cu_count << "/n" << count << "/u2^" << lg << "/m" << mode;
+    key << c->arch << "/cu" << c->cu_count << "/n" << count << "/u2^" << lg << "/m" << mode << (reordered ? "/o" : "");
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
@@ -1161,7 +1164,7 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     auto measure = [&](const cg_tuning &t, double *ms) -> int {
         double sum = 0;
         for (int rep = 0; rep < 3; ++rep) {
-            int r = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER, s, t);
+            int r = run_check(c, recs_dev, count, out_dev, mode | CG_EAGER | keep, s, t);
             if (r) return r;
             double x;
             uint64_t l;
