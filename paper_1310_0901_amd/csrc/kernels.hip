@@ -727,6 +727,11 @@ __global__ void __launch_bounds__(kClassifyBlock) k_pointers(const DevState *stp
     out[t] = o;
 }
 
+// MI355X has 8 XCDs, each with its own L2; the blocks of a launch are placed
+// on them round robin (block b on XCD b mod 8).
+constexpr uint32_t kXcds = 8;
+constexpr uint64_t kNoTile = ~0ull;
+
 // ---------------------------------------------------------------------------
 // k_scan_sums: one block, exclusive scan of the classify-block sums
 // ---------------------------------------------------------------------------
@@ -763,7 +768,7 @@ __global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_u
         a.ctl->total_units = total;
         a.ctl->tile_units = tu;
         a.ctl->ntiles = (total + tu - 1) / tu;
-        a.ctl->counter = 0;
+        for (int x = 0; x < kXcds; ++x) a.ctl->counter[x] = 0;
         a.prefix[a.count] = total;
     }
 }
@@ -809,13 +814,34 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
     const Region R = a.st->region;
     Acc acc;
     acc_reset(acc);
-    // first tile: the wave's own index (no atomic, so that the waves of a
-    // small batch leave at once); later tiles from the device counter
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    uint64_t jn = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // Tiles are split into kXcds contiguous chunks, chunk x worked by the
+    // waves of the blocks that run on XCD x, in ascending order, so that the
+    // neighbouring records of a batch sorted by address share that XCD's L2.
+    // First tile: the wave's own index in its chunk (no atomic, so that the
+    // waves of a small batch leave at once); later tiles from the chunk's
+    // counter; a wave whose chunk is used up takes tiles from the others'.
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    auto chunk_lo = [&](uint32_t x) { return ntiles * x / kXcds; };
+    auto waves_on = [&](uint32_t x) { return (uint64_t)((gridDim.x + kXcds - 1 - x) / kXcds) * wpb; };
+    uint64_t jn = chunk_lo(xcd) + (uint64_t)(blockIdx.x / kXcds) * wpb + (threadIdx.x >> 6);
+    if (jn >= chunk_lo(xcd + 1)) jn = kNoTile;
+    uint32_t y = xcd, left = kXcds;
     for (;;) {
+        while (jn == kNoTile && left > 0) {
+            uint32_t nx = 0;
+            if (lane == 0) nx = atomicAdd(&a.ctl->counter[y], 1u);
+            const uint64_t c = chunk_lo(y) + waves_on(y) + ufl32(__shfl(nx, 0));
+            if (c < chunk_lo(y + 1)) {
+                jn = c;
+            } else {
+                y = (y + 1) % kXcds;
+                --left;
+            }
+        }
+        if (jn == kNoTile) break;
         const uint64_t j = ufl64(jn);
-        if (j >= ntiles) break;
+        jn = kNoTile;
         uint64_t u = (uint64_t)j * tu;
         const uint64_t u_end = (u + tu < total) ? u + tu : total;
         uint64_t t = ufl32(a.tile_start[j]);
@@ -887,9 +913,6 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
             }
             u = g_end;
         }
-        uint32_t nx = 0;
-        if (lane == 0) nx = atomicAdd(&a.ctl->counter, 1u);
-        jn = (uint64_t)waves + ufl32(__shfl(nx, 0));
     }
 }
 

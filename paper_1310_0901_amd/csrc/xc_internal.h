@@ -48,10 +48,10 @@ struct alignas(64) Ctl {
     uint64_t total_units;   // sum of max(units, 1)
     uint64_t ntiles;
     uint64_t tile_units;    // units per tile actually used
-    uint32_t counter;       // dynamic tile counter
-    uint32_t pad0;
-    uint64_t pad[4];
+    uint32_t counter[8];    // per XCD: tiles taken from its chunk beyond the first tiles
+    uint64_t pad[1];
 };
+static_assert(sizeof(Ctl) == 64, "control block layout");
 
 struct Region {
     uint64_t hb, hl;
