@@ -820,22 +820,31 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
     // First tile: the wave's own index in its chunk (no atomic, so that the
     // waves of a small batch leave at once); later tiles from the chunk's
     // counter; a wave whose chunk is used up takes tiles from the others'.
+    // Only a batch worked in address order has that locality to keep; any
+    // other batch is one chunk for all waves (tiles interleaved over XCDs).
+    const uint32_t nch = a.perm ? kXcds : 1u;
     const uint32_t wpb = blockDim.x >> 6;
-    const uint32_t xcd = blockIdx.x % kXcds;
-    auto chunk_lo = [&](uint32_t x) { return ntiles * x / kXcds; };
-    auto waves_on = [&](uint32_t x) { return (uint64_t)((gridDim.x + kXcds - 1 - x) / kXcds) * wpb; };
-    uint64_t jn = chunk_lo(xcd) + (uint64_t)(blockIdx.x / kXcds) * wpb + (threadIdx.x >> 6);
+    const uint32_t xcd = blockIdx.x % nch;
+    auto chunk_lo = [&](uint32_t x) { return ntiles * x / nch; };
+    auto waves_on = [&](uint32_t x) { return (uint64_t)((gridDim.x + nch - 1 - x) / nch) * wpb; };
+    uint64_t jn = chunk_lo(xcd) + (uint64_t)(blockIdx.x / nch) * wpb + (threadIdx.x >> 6);
     if (jn >= chunk_lo(xcd + 1)) jn = kNoTile;
-    uint32_t y = xcd, left = kXcds;
+    uint32_t y = xcd, left = nch;
     for (;;) {
         while (jn == kNoTile && left > 0) {
-            uint32_t nx = 0;
-            if (lane == 0) nx = atomicAdd(&a.ctl->counter[y], 1u);
-            const uint64_t c = chunk_lo(y) + waves_on(y) + ufl32(__shfl(nx, 0));
-            if (c < chunk_lo(y + 1)) {
+            // a chunk no larger than its number of waves is all first tiles:
+            // nothing to take there, and no atomic (small batches leave at once)
+            const uint64_t lo = chunk_lo(y), hi = chunk_lo(y + 1);
+            uint64_t c = hi;
+            if (hi - lo > waves_on(y)) {
+                uint32_t nx = 0;
+                if (lane == 0) nx = atomicAdd(&a.ctl->counter[y], 1u);
+                c = lo + waves_on(y) + ufl32(__shfl(nx, 0));
+            }
+            if (c < hi) {
                 jn = c;
             } else {
-                y = (y + 1) % kXcds;
+                y = (y + 1) % nch;
                 --left;
             }
         }
