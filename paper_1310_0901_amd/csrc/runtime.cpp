@@ -1201,7 +1201,18 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     }
     if (!rc) {
         cands.clear();
-        for (uint32_t tu : {1u << 14, 1u << 16, 1u << 18}) { cg_tuning t = cur; t.tile_units = tu; cands.push_back(t); }
+        for (uint32_t tu : {1u << 12, 1u << 13, 1u << 14, 1u << 15, 1u << 16, 1u << 18}) {
+            cg_tuning t = cur;
+            t.tile_units = tu;
+            cands.push_back(t);
+        }
+        rc = try_set(cands);
+    }
+    if (!rc) {
+        // the occupancy that suits a tile size may differ from the first pick
+        cands.clear();
+        for (uint32_t b : {256u, 512u})
+            for (uint32_t bpc : {1u, 2u, 4u, 8u}) { cg_tuning t = cur; t.block = b; t.blocks_per_cu = bpc; cands.push_back(t); }
         rc = try_set(cands);
     }
     c->timing = was_timing;
