@@ -129,6 +129,10 @@ struct WinCopy {
     hipStream_t stream;
 };
 
+// A window this long is joined at once, as if a synchronising call had come:
+// a race between copies on both sides of that point is not reported.
+constexpr size_t kWindowMax = size_t(1) << 20;
+
 struct State {
     std::mutex mu;
     cg_ctx *ctx = nullptr;
@@ -393,6 +397,8 @@ bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t 
 }
 
 // the rows of a pitched asynchronous copy join the concurrent-access window
+void close_window();
+
 void window_rows(const Pitched &p, uint32_t kind, hipStream_t stream)
 {
     std::lock_guard<std::mutex> lk(G.mu);
@@ -402,6 +408,7 @@ void window_rows(const Pitched &p, uint32_t kind, hipStream_t stream)
                                                 (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width,
                                                 kind, 0},
                                     stream});
+    if (G.win.size() >= kWindowMax) close_window();
 }
 
 // a 3D copy of linear memory as a Pitched copy
@@ -752,6 +759,7 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind ki
             if (!check_copy("hipMemcpyAsync", dst, src, n, d)) return refuse();
             std::lock_guard<std::mutex> lk(G.mu);
             G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream});
+            if (G.win.size() >= kWindowMax) close_window();
         }
     }
     return f(dst, src, n, kind, stream);
