@@ -181,7 +181,7 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  * (a hipStream_t; NULL = the null stream).
  *   mode: CG_CHECK and/or CG_PROPAGATE, optionally with CG_PLAIN (one launch
  *   per record), CG_EAGER (no graph capture), CG_DEBUG_CONFLICTS or
- *   CG_KEEP_ORDER.  A batched check of 16,384 records or more is worked in
+ *   CG_KEEP_ORDER.  A batched check of 16,384 to 2^31 - 1 records is worked in
  *   ascending order of source address (records reading the same bytes run
  *   close together); verdicts are written at the records' own positions
  *   either way, and CG_KEEP_ORDER works the batch in the given order.
@@ -221,7 +221,7 @@ typedef struct cg_transfer2d {
  * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers.  The
  * call waits for the caller's stream once, to learn the number of rows
  * (at most 2^32 - 1 in total).  Errors: as check_transfers, and CG_EINVAL for
- * too many rows.
+ * 2^31 records or more, or too many rows.
  */
 int check_transfers_2d(cg_ctx *ctx, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev,
                        uint32_t mode, void *hip_stream);
@@ -310,7 +310,8 @@ typedef struct cg_ptr_check {
  * live allocations and write one cg_ptr_check per pointer to out_dev (device
  * memory), on `hip_stream`.  Like check_transfers it sees every shadow_alloc /
  * shadow_free made before it; the caller keeps both arrays alive until the
- * stream has synced.  Errors: CG_EINVAL (null pointers), CG_EHIP.
+ * stream has synced.  Errors: CG_EINVAL (null pointers, count of 2^31 or
+ * more), CG_EHIP.
  */
 int check_pointers(cg_ctx *ctx, const uint64_t *ptrs_dev, uint64_t count, cg_ptr_check *out_dev, void *hip_stream);
 

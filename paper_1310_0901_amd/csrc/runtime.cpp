@@ -586,7 +586,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (rc) return rc;
     }
     BatchArgs a = make_args(c, w, recs, count, out, mode);
-    if (!(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min) {
+    if (!(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min && count < (1ull << 31)) {
         // large batches are worked in order of source address, so that records
         // reading the same bytes run close together and re-reads hit in cache
         if (w->sort.cap < count) {
@@ -977,7 +977,7 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
     if (count == 0) return CG_OK;
     if (!recs_dev) return fail(c, CG_EINVAL, "null records");
     if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
-    if (count >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 records per call");
+    if (count >= (1ull << 31)) return fail(c, CG_EINVAL, "at most 2^31 - 1 records per call");
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
     const hipStream_t s = (hipStream_t)hip_stream;
     StridedWs &w = c->strided_ws[s];
@@ -1031,7 +1031,7 @@ int check_pointers(cg_ctx *c, const uint64_t *ptrs_dev, uint64_t count, cg_ptr_c
     if (!c) return CG_EINVAL;
     if (count == 0) return CG_OK;
     if (!ptrs_dev || !out_dev) return fail(c, CG_EINVAL, "null pointers or results");
-    if (count >= (1ull << 40)) return fail(c, CG_EINVAL, "too many pointers");
+    if (count >= (1ull << 31)) return fail(c, CG_EINVAL, "at most 2^31 - 1 pointers per call");
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
     const hipStream_t s = (hipStream_t)hip_stream;
     int rc = materialize(c);
@@ -1129,7 +1129,7 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     mode &= (CG_CHECK | CG_PROPAGATE);
     if (!mode) return CG_EINVAL;
     // the batch is worked in source-address order unless kept (as run_check decides)
-    const bool reordered = !keep && count >= c->reorder_min;
+    const bool reordered = !keep && count >= c->reorder_min && count < (1ull << 31);
     cg_tuning &target = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
     // workload signature: count and log2 of the total units, from a first run
     const bool was_timing = c->timing;
