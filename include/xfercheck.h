@@ -193,7 +193,8 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  * CG_ECONFLICT, under CG_DEBUG_CONFLICTS).
  * The caller keeps recs_dev and out_dev alive until the stream has synced.
  * out_dev may be NULL when CG_CHECK is not set.
- * Errors: CG_EINVAL (null pointers, mode without CHECK/PROPAGATE),
+ * Errors: CG_EINVAL (null pointers, mode without CHECK/PROPAGATE, more than
+ * 2^32 - 1024 records),
  * CG_ESTATE (a host-side record but no host region registered), CG_EHIP.
  */
 int check_transfers(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count,
@@ -220,7 +221,7 @@ typedef struct cg_transfer2d {
  * (bytes from src / dst to the end of its allocation).  A record with no
  * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers.  The
  * call waits for the caller's stream once, to learn the number of rows
- * (at most 2^32 - 1 in total).  Errors: as check_transfers, and CG_EINVAL for
+ * (at most 2^32 - 1024 in total).  Errors: as check_transfers, and CG_EINVAL for
  * 2^31 records or more, or too many rows.
  */
 int check_transfers_2d(cg_ctx *ctx, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev,

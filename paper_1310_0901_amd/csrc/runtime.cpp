@@ -956,7 +956,8 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
     if (count == 0) return CG_OK;
     if (!recs_dev) return fail(c, CG_EINVAL, "null records");
     if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
-    if (count >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 records per call");
+    // one lane per record in the classify grid, whose size must fit in 32 bits
+    if (count > (1ull << 32) - 1024) return fail(c, CG_EINVAL, "at most 2^32 - 1024 records per call");
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
     return run_check(c, recs_dev, count, out_dev, mode, (hipStream_t)hip_stream,
                      (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
@@ -1000,7 +1001,7 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
     HIPTRY(c, hipMemcpyAsync(w.h_total, w.total, 8, hipMemcpyDeviceToHost, s));
     HIPTRY(c, hipStreamSynchronize(s));
     const uint64_t nrows = *w.h_total;
-    if (nrows >= (1ull << 32)) return fail(c, CG_EINVAL, "at most 2^32 - 1 rows per call");
+    if (nrows > (1ull << 32) - 1024) return fail(c, CG_EINVAL, "at most 2^32 - 1024 rows per call");
     if (nrows) {
         if (w.row_cap < nrows) {
             (void)hipFree(w.rows);
