@@ -8,14 +8,19 @@
 // carried through host/device, device/host and device/device copies (Sec. 5).
 //
 // Pipeline of one batched check (all integer, bit-exact):
+//   (sort.hip)     large batches only: the order of the records by source
+//                  address, so that records reading the same bytes run close
+//                  together; every kernel below then works by position and
+//                  reaches records and verdicts through that permutation;
 //   k_classify     one lane per record: decode, interval lookup in the
 //                  sorted allocation table (top level staged in LDS),
 //                  range-derived verdict fields, scan descriptor, work weight,
 //                  block-local exclusive scan of the weights;
 //   k_scan_sums    one block: exclusive scan of the per-block sums, tile size;
 //   k_prefix_tiles global prefix; k_tile_starts first record of every tile;
-//   k_batched      persistent kernel: tiles of the flattened 16-byte unit space
-//                  taken from a device counter; 16-byte V loads and aligned
+//   k_batched      persistent kernel: tiles of the flattened 16-byte unit space,
+//                  one contiguous chunk per XCD for a reordered batch, taken
+//                  from per-chunk device counters; 16-byte V loads and aligned
 //                  16-bit A loads, SWAR non-zero masks, popcount / ctz for the
 //                  undefined count and first fault, DPP wave reductions, rare
 //                  global atomics; optional realigned V store to the
