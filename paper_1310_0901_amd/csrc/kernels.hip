@@ -8,18 +8,20 @@
 // carried through host/device, device/host and device/device copies (Sec. 5).
 //
 // Pipeline of one batched check (all integer, bit-exact):
-//   (sort.hip)     large batches only: the order of the records by source
-//                  address, so that records reading the same bytes run close
-//                  together; every kernel below then works by position and
-//                  reaches records and verdicts through that permutation;
 //   k_classify     one lane per record: decode, interval lookup in the
 //                  sorted allocation table (top level staged in LDS),
 //                  range-derived verdict fields, scan descriptor, work weight,
 //                  block-local exclusive scan of the weights;
+//   (segment.hip)  large batches only: every record's units cut at blocks of
+//                  source memory, the pieces sorted by block and laid out as
+//                  the batch's positions (descriptors, weights, block-local
+//                  scan), so that work reading the same bytes runs together;
+//                  the kernels below work by position and send findings to
+//                  each position's record;
 //   k_scan_sums    one block: exclusive scan of the per-block sums, tile size;
 //   k_prefix_tiles global prefix; k_tile_starts first record of every tile;
 //   k_batched      persistent kernel: tiles of the flattened 16-byte unit space,
-//                  one contiguous chunk per XCD for a reordered batch, taken
+//                  one contiguous chunk per XCD for a segmented batch, taken
 //                  from per-chunk device counters; 16-byte V loads and aligned
 //                  16-bit A loads, SWAR non-zero masks, popcount / ctz for the
 //                  undefined count and first fault, DPP wave reductions, rare
@@ -555,8 +557,7 @@ __device__ __forceinline__ uint64_t clamp_scan(uint64_t x) { return x < kScanLim
 // descriptor; return its number of units.
 __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
 {
-    const uint64_t rt = a.perm ? a.perm[t] : t;   // the record at position t
-    const cg_transfer r = a.recs[rt];
+    const cg_transfer r = a.recs[t];
     const uint64_t n = r.n;
     Desc ds = {};
     uint32_t flags = 0;
@@ -664,7 +665,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
         v.first_bad = first;
         v.undef_bytes = 0;
         v.avail = avail;
-        a.out[rt] = v;
+        a.out[t] = v;
     }
     return units;
 }
@@ -821,11 +822,12 @@ __global__ void __launch_bounds__(512) k_batched(BatchArgs a)
     acc_reset(acc);
     // Tiles are split into kXcds contiguous chunks, chunk x worked by the
     // waves of the blocks that run on XCD x, in ascending order, so that the
-    // neighbouring records of a batch sorted by address share that XCD's L2.
+    // neighbouring segments of a batch sorted by source block share that
+    // XCD's L2.
     // First tile: the wave's own index in its chunk (no atomic, so that the
     // waves of a small batch leave at once); later tiles from the chunk's
     // counter; a wave whose chunk is used up takes tiles from the others'.
-    // Only a batch worked in address order has that locality to keep; any
+    // Only a batch worked as segments has that locality to keep; any
     // other batch is one chunk for all waves (tiles interleaved over XCDs).
     const uint32_t nch = a.perm ? kXcds : 1u;
     const uint32_t wpb = blockDim.x >> 6;

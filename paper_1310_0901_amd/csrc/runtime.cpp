@@ -33,6 +33,7 @@ constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
 constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
 constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
+constexpr uint64_t kSegMaxRecords = 1ull << 30;   // largest batch worked as segments
 constexpr size_t kGraphsPerWs = 16;
 constexpr int kVersions = 4;             // table versions in the device ring
 
@@ -68,7 +69,14 @@ struct Workspace {
     hipEvent_t done = nullptr;      // recorded after every check issued on this stream
     bool used = false;
     std::vector<GraphEntry> graphs;
-    // ordering of large batches by source address (allocated on first use)
+    // large batches worked as source-block segments (allocated on first use):
+    // per record the classify output and first segment, per segment its
+    // record, the sort of the segments, and per position its record
+    uint64_t seg_cap = 0;    // records
+    Desc *rdesc = nullptr;
+    uint64_t *rweight = nullptr, *rlocal = nullptr, *rbsum = nullptr, *sfirst = nullptr, *sbsum = nullptr;
+    uint64_t *meta = nullptr;
+    uint32_t *srec = nullptr;
     SortWs sort;
     uint32_t *perm = nullptr;
 };
@@ -157,7 +165,8 @@ struct cg_ctx {
     hipEvent_t ev_ctx = nullptr;
     std::map<hipStream_t, Workspace *> ws;
     std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
-    uint64_t reorder_min = 16384;            // batches this large are worked in source-address order
+    uint64_t reorder_min = 16384;            // batches this large are worked as source-block segments
+    uint32_t seg_min_log2 = 20;              // smallest source block of the segments, log2
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
@@ -339,6 +348,18 @@ void add_fill(std::vector<FillRange> &rs, uint64_t ptr, uint64_t len, uint8_t v)
     }
 }
 
+void free_seg(Workspace *w)
+{
+    void *ps[] = {w->rdesc, w->rweight, w->rlocal, w->rbsum, w->sfirst, w->sbsum, w->meta, w->srec, w->perm};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    sort_release(w->sort);
+    w->rdesc = nullptr;
+    w->rweight = w->rlocal = w->rbsum = w->sfirst = w->sbsum = w->meta = nullptr;
+    w->srec = w->perm = nullptr;
+    w->seg_cap = 0;
+}
+
 void free_ws(Workspace *w)
 {
     for (auto &g : w->graphs) destroy_graph(g);
@@ -352,9 +373,7 @@ void free_ws(Workspace *w)
     (void)hipFree(w->tile_start);
     (void)hipFree(w->ctl);
     if (w->h_weight) (void)hipHostFree(w->h_weight);
-    sort_release(w->sort);
-    (void)hipFree(w->perm);
-    w->perm = nullptr;
+    free_seg(w);
     w->desc = nullptr;
     w->weight = w->local = w->bsum = w->boff = w->prefix = nullptr;
     w->tile_start = nullptr;
@@ -428,20 +447,32 @@ LaunchShape shape_of(cg_ctx *c, const cg_tuning &t)
     return sh;
 }
 
-hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, SortWs *sort)
+// A batch worked as source-block segments: k_classify over the records in
+// their given order (ar), then the segments (g) as the positions of the batch.
+struct SegPlan {
+    BatchArgs ar;
+    SegArgs g;
+    SortWs *sort;
+};
+
+hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp)
 {
     hipError_t e;
-    if (a.perm && (e = sort_by_source(*sort, a.recs, a.count, const_cast<uint32_t *>(a.perm), s)) != hipSuccess)
+    if (sp) {
+        if ((e = launch_classify(sp->ar, s)) != hipSuccess) return e;
+        if ((e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess) return e;
+    } else if ((e = launch_classify(a, s)) != hipSuccess) {
         return e;
-    if ((e = launch_classify(a, s)) != hipSuccess) return e;
+    }
     if ((e = launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s)) != hipSuccess) return e;
     return launch_prefix_tiles(a, s);
 }
 
-hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp, SortWs *sort)
+hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp,
+                           const SegPlan *sp)
 {
     hipError_t e;
-    if ((e = enqueue_prepare(a, sh, s, sort)) != hipSuccess) return e;
+    if ((e = enqueue_prepare(a, sh, s, sp)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->a, s)) != hipSuccess) return e;
     if ((e = launch_batched(a, sh, s)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->b, s)) != hipSuccess) return e;
@@ -449,12 +480,12 @@ hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_
 }
 
 int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part,
-            SortWs *sort);
+            const SegPlan *sp);
 
 // The cached graph of this batched check (keyed by table version, buffers,
 // count, mode and launch shape), captured on first use.
-int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const LaunchShape &sh, const cg_tuning &tun, bool split,
-               hipStream_t s, GraphEntry **out)
+int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const SegPlan *sp, const LaunchShape &sh,
+               const cg_tuning &tun, bool split, hipStream_t s, GraphEntry **out)
 {
     const uint32_t mode = (a.mode & 3u) | (a.perm ? 4u : 0u);
     for (auto &g : w->graphs)
@@ -469,8 +500,8 @@ int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const LaunchShape &s
         w->graphs.erase(w->graphs.begin());
     }
     GraphEntry g{a.st, a.recs, a.out, a.count, mode, tun, split, nullptr, nullptr, nullptr, nullptr};
-    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0, &w->sort);
-    if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2, &w->sort);
+    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0, sp);
+    if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2, sp);
     if (rc) {
         destroy_graph(g);
         return rc;
@@ -572,11 +603,48 @@ int debug_conflicts(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, hipS
 
 int note_use(cg_ctx *c, hipStream_t s);
 
+// Batches of at least reorder_min records (and at most kSegMaxRecords, so
+// that the 3 * count positions have 32-bit indices) are worked as
+// source-block segments unless the caller keeps the given order.
+bool segmented(const cg_ctx *c, uint64_t count, uint32_t mode)
+{
+    return !(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min && count <= kSegMaxRecords;
+}
+
+// Segment buffers for `count` records; the positions (w->cap) are already
+// at least 3 * count.
+int reserve_segments(cg_ctx *c, Workspace *w, uint64_t count, hipStream_t s)
+{
+    if (w->seg_cap >= count && w->sort.cap >= w->cap) return CG_OK;
+    HIPTRY(c, hipStreamSynchronize(s));   // the old buffers may still be in use
+    for (auto &g : w->graphs) destroy_graph(g);
+    w->graphs.clear();
+    free_seg(w);
+    uint64_t cap = 1024;
+    while (cap < count) cap <<= 1;
+    const uint64_t nb = (cap + kClassifyBlock - 1) / kClassifyBlock;
+    HIPTRY(c, hipMalloc(&w->rdesc, cap * sizeof(Desc)));
+    HIPTRY(c, hipMalloc(&w->rweight, cap * 8));
+    HIPTRY(c, hipMalloc(&w->rlocal, cap * 8));
+    HIPTRY(c, hipMalloc(&w->sfirst, cap * 8));
+    HIPTRY(c, hipMalloc(&w->rbsum, nb * 8));
+    HIPTRY(c, hipMalloc(&w->sbsum, nb * 8));
+    HIPTRY(c, hipMalloc(&w->meta, 64));
+    HIPTRY(c, hipMalloc(&w->srec, w->cap * 4));
+    HIPTRY(c, hipMalloc(&w->perm, w->cap * 4));
+    const hipError_t e = sort_reserve(w->sort, w->cap);
+    if (e != hipSuccess) return hip_fail(c, "segment sort work space", e);
+    w->seg_cap = cap;
+    return CG_OK;
+}
+
 int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *out, uint32_t mode,
               hipStream_t s, const cg_tuning &tun)
 {
     Workspace *w;
-    int rc = get_ws(c, s, count, &w);
+    const bool seg = segmented(c, count, mode);
+    const uint64_t npos = seg ? 3 * count : count;   // positions of the batch
+    int rc = get_ws(c, s, npos, &w);
     if (rc) return rc;
     rc = materialize(c);
     if (rc) return rc;
@@ -585,21 +653,27 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         rc = debug_conflicts(c, recs, count, s);
         if (rc) return rc;
     }
-    BatchArgs a = make_args(c, w, recs, count, out, mode);
-    if (!(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min && count < (1ull << 31)) {
-        // large batches are worked in order of source address, so that records
-        // reading the same bytes run close together and re-reads hit in cache
-        if (w->sort.cap < count) {
-            HIPTRY(c, hipStreamSynchronize(s));   // the old buffers may still be in use
-            for (auto &g : w->graphs) destroy_graph(g);
-            w->graphs.clear();
-            (void)hipFree(w->perm);
-            w->perm = nullptr;
-            const hipError_t e = sort_reserve(w->sort, w->cap);
-            if (e != hipSuccess) return hip_fail(c, "sort work space", e);
-            HIPTRY(c, hipMalloc(&w->perm, w->cap * 4));
-        }
+    BatchArgs a = make_args(c, w, recs, npos, out, mode);
+    SegPlan plan{};
+    const SegPlan *sp = nullptr;
+    if (seg) {
+        // the work on each block of source memory runs together, so that
+        // re-reads of the same bytes hit in cache
+        rc = reserve_segments(c, w, count, s);
+        if (rc) return rc;
+        plan.ar = make_args(c, w, recs, count, out, mode);
+        plan.ar.desc = w->rdesc;
+        plan.ar.weight = w->rweight;
+        plan.ar.local = w->rlocal;
+        plan.ar.bsum = w->rbsum;
+        plan.ar.boff = nullptr;
+        plan.ar.prefix = nullptr;
+        plan.ar.tile_start = nullptr;
+        plan.ar.ctl = nullptr;
+        plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2};
+        plan.sort = &w->sort;
         a.perm = w->perm;
+        sp = &plan;
     }
     const LaunchShape sh = shape_of(c, tun);
     if (mode & CG_PLAIN) {
@@ -615,11 +689,11 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
     } else if (mode & CG_EAGER) {
         TimingPair *tp = c->timing ? next_pair(c) : nullptr;
-        HIPTRY(c, enqueue_batched(a, sh, s, tp, &w->sort));
+        HIPTRY(c, enqueue_batched(a, sh, s, tp, sp));
     } else {
         const bool split = c->timing;
         GraphEntry *ge = nullptr;
-        rc = find_graph(c, w, a, sh, tun, split, s, &ge);
+        rc = find_graph(c, w, a, sp, sh, tun, split, s, &ge);
         if (rc) return rc;
         if (split) {
             TimingPair *tp = next_pair(c);
@@ -656,11 +730,11 @@ int note_use(cg_ctx *c, hipStream_t s)
 // Capture part 0 (the whole batched check), 1 (the preparation kernels) or
 // 2 (the scan kernel) into an executable graph.
 int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, const LaunchShape &sh, int part,
-            SortWs *sort)
+            const SegPlan *sp)
 {
     HIPTRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr, sort)
-                 : part == 1 ? enqueue_prepare(a, sh, c->cap, sort)
+    hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr, sp)
+                 : part == 1 ? enqueue_prepare(a, sh, c->cap, sp)
                              : launch_batched(a, sh, c->cap);
     hipError_t e2 = hipStreamEndCapture(c->cap, g);
     if (e != hipSuccess) return hip_fail(c, "graph capture", e);
@@ -762,6 +836,8 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_BLOCKS_PER_CU")) c->tuning.blocks_per_cu = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_REORDER_MIN")) c->reorder_min = strtoull(e, nullptr, 0);
+    if (const char *e = getenv("XC_SEG_MIN_LOG2")) c->seg_min_log2 = (uint32_t)atoi(e);
+    if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
     c->tuning_prop.unroll = 2;
@@ -1129,8 +1205,8 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     const uint32_t keep = mode & CG_KEEP_ORDER;
     mode &= (CG_CHECK | CG_PROPAGATE);
     if (!mode) return CG_EINVAL;
-    // the batch is worked in source-address order unless kept (as run_check decides)
-    const bool reordered = !keep && count >= c->reorder_min && count < (1ull << 31);
+    // the batch is worked as source-block segments unless kept (as run_check decides)
+    const bool reordered = segmented(c, count, mode | keep);
     cg_tuning &target = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
     // workload signature: count and log2 of the total units, from a first run
     const bool was_timing = c->timing;
@@ -1291,7 +1367,7 @@ int prewarm(cg_ctx *c, hipStream_t s, const cg_transfer *recs, uint64_t count, c
         BatchArgs a = make_args(c, w, recs, count, out, CG_CHECK);
         a.st = c->ver[v].st;
         GraphEntry *ge;
-        rc = find_graph(c, w, a, sh, tun, false, s, &ge);
+        rc = find_graph(c, w, a, nullptr, sh, tun, false, s, &ge);
     }
     return rc;
 }
@@ -1421,7 +1497,9 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             const uint32_t count = cfg->plain ? cnt : B;   // graph shape: fixed count, padded
             hipError_t e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
             if (e1 != hipSuccess) { rc = hip_fail(c, "serve: records upload", e1); break; }
-            rc = run_check(c, sl.d_recs, count, sl.d_out, CG_CHECK | (cfg->plain ? CG_PLAIN : 0u), sl.s, tun);
+            // micro-batches keep their order (their graphs are captured before the clock starts)
+            rc = run_check(c, sl.d_recs, count, sl.d_out, CG_CHECK | CG_KEEP_ORDER | (cfg->plain ? CG_PLAIN : 0u),
+                           sl.s, tun);
             if (rc) break;
             e1 = hipMemcpyAsync(sl.h_out, sl.d_out, cnt * sizeof(cg_verdict), hipMemcpyDeviceToHost, sl.s);
             if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);

@@ -1,6 +1,6 @@
 // Stable radix sort of (u64 key, u32 value) pairs on the device (sort.hip),
-// used by the concurrent-access join and to order large check batches by
-// source address.  Internal interface.
+// used by the concurrent-access join and to order the work of large check
+// batches by source block (segment.hip).  Internal interface.
 #pragma once
 
 #include <stdint.h>
@@ -28,13 +28,12 @@ constexpr int kSortKeyBlock = 256;   // keys per key-building block (one part ea
 hipError_t sort_reserve(SortWs &w, uint64_t n);
 void sort_release(SortWs &w);
 
-// Sort the n pairs in keys[0] / vals[0]; parts[0 .. ceil(n / kSortKeyBlock))
-// must hold the key-building blocks' parts.
-hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s);
-
-// perm[i] = index of the i-th of `count` records in ascending order of source
-// address (ties in input order).
-hipError_t sort_by_source(SortWs &w, const cg_transfer *recs, uint64_t count, uint32_t *perm, hipStream_t s);
+// Sort the first pairs in keys[0] / vals[0]: n of them, or, when n_dev is
+// given, the count in device memory at n_dev (at most n; read when the
+// kernels run, so that a count computed on the device needs no copy back).
+// parts[0 .. ceil(n / kSortKeyBlock)) must hold the key-building blocks'
+// parts (0 for blocks past the keys).
+hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev = nullptr);
 
 // a pass over key byte `pass` is skipped when that byte is the same in every key
 __device__ __forceinline__ bool sort_pass_live(uint64_t mask, int pass) { return ((mask >> (8 * pass)) & 0xFFu) != 0; }

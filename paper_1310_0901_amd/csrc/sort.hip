@@ -52,6 +52,15 @@ __device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
 
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
+// keys to sort: mcap, or the count held in device memory when there is one
+// (never above mcap)
+__device__ __forceinline__ uint64_t sort_count_of(uint64_t mcap, const uint64_t *mdev)
+{
+    if (!mdev) return mcap;
+    const uint64_t m = *mdev;
+    return m < mcap ? m : mcap;
+}
+
 // exclusive sum over the block's threads; *total receives the block sum
 __device__ uint32_t block_excl_sum(uint32_t x, uint32_t *total)
 {
@@ -75,12 +84,13 @@ __device__ uint32_t block_excl_sum(uint32_t x, uint32_t *total)
 }
 
 // per-tile digit counts, digit-major: counts[d * tiles + tile]
-__global__ __launch_bounds__(kT) void k_sort_count(const uint64_t *ka, const uint64_t *kb, uint64_t m,
-                                                   uint32_t tiles, const uint64_t *maskp, int pass,
-                                                   uint32_t *counts)
+__global__ __launch_bounds__(kT) void k_sort_count(const uint64_t *ka, const uint64_t *kb, uint64_t mcap,
+                                                   const uint64_t *mdev, uint32_t tiles, const uint64_t *maskp,
+                                                   int pass, uint32_t *counts)
 {
     const uint64_t mask = *maskp;
     if (!sort_pass_live(mask, pass)) return;
+    const uint64_t m = sort_count_of(mcap, mdev);
     const uint64_t *kin = sort_parity(mask, pass) ? kb : ka;
     const int shift = 8 * pass;
     __shared__ uint32_t h[kWaves][256];
@@ -131,11 +141,14 @@ __global__ __launch_bounds__(kT) void k_sort_scan_digits(uint32_t *counts, uint3
 // stable scatter of one tile: ranks within the tile, a local sort through
 // LDS, then runs of equal digits written contiguously
 __global__ __launch_bounds__(kT) void k_sort_scatter(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
-                                                     uint64_t m, uint32_t tiles, const uint64_t *maskp, int pass,
-                                                     const uint32_t *counts, const uint32_t *dtot)
+                                                     uint64_t mcap, const uint64_t *mdev, uint32_t tiles,
+                                                     const uint64_t *maskp, int pass, const uint32_t *counts,
+                                                     const uint32_t *dtot)
 {
     const uint64_t mask = *maskp;
     if (!sort_pass_live(mask, pass)) return;
+    const uint64_t m = sort_count_of(mcap, mdev);
+    if ((uint64_t)blockIdx.x * kSortTile >= m) return;   // a tile past the keys (the whole block leaves)
     const int par = sort_parity(mask, pass);
     const uint64_t *kin = par ? kb : ka;
     const uint32_t *vin = par ? vb : va;
@@ -208,39 +221,6 @@ __global__ __launch_bounds__(kT) void k_sort_scatter(uint64_t *ka, uint64_t *kb,
 }
 
 
-// key = source address of record i, value = i, and the block's part of the mask
-__global__ __launch_bounds__(kT) void k_sort_src_keys(const cg_transfer *recs, uint64_t n, uint64_t *keys,
-                                                      uint32_t *vals, uint64_t *parts)
-{
-    __shared__ uint64_t part[kWaves];
-    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    const uint64_t k0 = recs[0].src;
-    uint64_t x = 0;
-    if (i < n) {
-        const uint64_t k = recs[i].src;
-        keys[i] = k;
-        vals[i] = (uint32_t)i;
-        x = k ^ k0;
-    }
-    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t y = 0;
-        for (int w = 0; w < kWaves; ++w) y |= part[w];
-        parts[blockIdx.x] = y;
-    }
-}
-
-// the sorted values, from whichever buffer holds them
-__global__ __launch_bounds__(kT) void k_sort_values_out(const uint32_t *va, const uint32_t *vb, const uint64_t *maskp,
-                                                        uint64_t n, uint32_t *out)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= n) return;
-    out[i] = (sort_parity(*maskp) ? vb : va)[i];
-}
-
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -278,29 +258,18 @@ void sort_release(SortWs &w)
     w = SortWs{};
 }
 
-hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s)
+hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev)
 {
     if (n == 0) return hipSuccess;
     const uint32_t tiles = (uint32_t)ceil_div(n, kSortTile);
     hipLaunchKernelGGL(k_sort_mask, dim3(1), dim3(kT), 0, s, w.parts, (uint32_t)ceil_div(n, kT), w.mask);
     for (int pass = 0; pass < 8; ++pass) {
-        hipLaunchKernelGGL(k_sort_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], n, tiles, w.mask, pass,
-                           w.counts);
+        hipLaunchKernelGGL(k_sort_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], n, n_dev, tiles, w.mask,
+                           pass, w.counts);
         hipLaunchKernelGGL(k_sort_scan_digits, dim3(256), dim3(kT), 0, s, w.counts, tiles, w.dtot, w.mask, pass);
         hipLaunchKernelGGL(k_sort_scatter, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], w.vals[0], w.vals[1], n,
-                           tiles, w.mask, pass, w.counts, w.dtot);
+                           n_dev, tiles, w.mask, pass, w.counts, w.dtot);
     }
-    return hipGetLastError();
-}
-
-hipError_t sort_by_source(SortWs &w, const cg_transfer *recs, uint64_t count, uint32_t *perm, hipStream_t s)
-{
-    if (count == 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)ceil_div(count, kT);
-    hipLaunchKernelGGL(k_sort_src_keys, dim3(blocks), dim3(kT), 0, s, recs, count, w.keys[0], w.vals[0], w.parts);
-    hipError_t e = sort_pairs(w, count, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_values_out, dim3(blocks), dim3(kT), 0, s, w.vals[0], w.vals[1], w.mask, count, perm);
     return hipGetLastError();
 }
 

@@ -100,10 +100,25 @@ struct BatchArgs {
     uint32_t *tile_start;   // first record of each tile
     uint64_t tiles_cap;
     Ctl *ctl;
-    // when not null, the batch is worked in this order: position t holds
-    // record perm[t] (records, verdicts and findings are indexed through it;
-    // descriptors, weights and prefixes are by position)
+    // when not null, position t works for record perm[t]: findings go to
+    // that record's verdict (descriptors, weights and prefixes are by
+    // position; the positions are source-block segments, segment.hip)
     const uint32_t *perm;
+};
+
+// Cutting a batch's records into source-block segments (segment.hip).
+// rdesc / wbsum come from k_classify run over the records in their given
+// order; the segments become `npos` = 3 * count positions of the batch.
+struct SegArgs {
+    const Desc *rdesc;      // per record
+    uint64_t count;         // records (at least 1)
+    uint64_t npos;          // positions provided: 3 * count
+    const uint64_t *wbsum;  // k_classify's block sums of the work weights
+    uint64_t *first;        // per record: first segment
+    uint64_t *sbsum;        // per record block: segment sums, then their prefix
+    uint32_t *srec;         // per segment: its record
+    uint64_t *meta;         // [0] segments, [1] log2 of the block size
+    uint32_t min_log2;      // smallest block size, log2
 };
 
 struct LaunchShape {
@@ -138,6 +153,12 @@ hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
                         hipStream_t s);
 hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
+
+// segment.hip: segments of the records described by g, sorted by source
+// block, written as the positions of ap (desc, weight, local, bsum) with
+// perm[p] the record of position p; `sort` holds at least g.npos pairs
+struct SortWs;
+hipError_t launch_segments(const SegArgs &g, SortWs &sort, const BatchArgs &ap, uint32_t *perm, hipStream_t s);
 hipError_t launch_2d_prefix(const cg_transfer2d *recs, uint64_t count, uint64_t *first, uint64_t *bsum,
                             uint64_t *total, hipStream_t s);
 hipError_t launch_2d_expand(const cg_transfer2d *recs, const uint64_t *first, uint64_t count, uint64_t nrows,

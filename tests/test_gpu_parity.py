@@ -153,12 +153,15 @@ def test_conflicting_batch_is_refused(X, H):
         dw.close()
 
 
+@pytest.mark.parametrize("seg_log2", ["20", "4"])
 @pytest.mark.parametrize("seed", [31, 32, 33])
-def test_reordered_batches(X, H, seed, monkeypatch):
-    """Batches worked in source-address order (forced here for small
-    batches): verdicts and every shadow byte equal the oracle's, and equal
-    the verdicts of the same batch worked in its given order."""
+def test_reordered_batches(X, H, seed, seg_log2, monkeypatch):
+    """Batches worked as source-block segments (forced here for small
+    batches; with a 16-byte floor on the block size, records are cut into
+    several segments each): verdicts and every shadow byte equal the
+    oracle's, and equal the verdicts of the same batch in its given order."""
     monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SEG_MIN_LOG2", seg_log2)
     rng = np.random.default_rng(seed)
     hl, hv, a, bases, sizes, vs = util.random_world(rng, dens=0.02)
     recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 600, max_n=30_000)
@@ -171,6 +174,42 @@ def test_reordered_batches(X, H, seed, monkeypatch):
     finally:
         dw.close()
     # check + propagate on a conflict-free subset
+    cf = util.conflict_free(recs, W.HOST_BASE, hl, bases, sizes)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, cf)
+    o = util.oracle_for(w)
+    want = o.run(cf, propagate=True)
+    dw = H.DeviceWorld(w)
+    try:
+        util.assert_verdicts_equal(dw.check(cf, X.CG_CHECK | X.CG_PROPAGATE), want, f"seed {seed} propagate")
+        for j in range(bases.size):
+            assert np.array_equal(dw.alloc_shadow(bases[j], sizes[j]), o.vs[j]), f"allocation {j}"
+        assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
+    finally:
+        dw.close()
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_segments_of_large_records(X, H, seed, monkeypatch):
+    """Records of up to 3 MB beside small ones, worked as segments: the block
+    size follows the mean record size, so large records are cut into many
+    segments (some of them in blocks other records also read), and single
+    records or a few units straddle block ends.  Check, and check +
+    propagate on a conflict-free subset with every shadow byte compared."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SEG_MIN_LOG2", "4")
+    rng = np.random.default_rng(seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=6 << 20, nalloc=8, max_size=4 << 20, dens=1e-4)
+    big = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 12, max_n=3 << 20)
+    small = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 400, max_n=2000)
+    recs = np.concatenate([small[:200], big, small[200:]])
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_EAGER, X.CG_CHECK | X.CG_KEEP_ORDER):
+            util.assert_verdicts_equal(dw.check(recs, mode), want, f"seed {seed} mode {mode}")
+    finally:
+        dw.close()
     cf = util.conflict_free(recs, W.HOST_BASE, hl, bases, sizes)
     w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, cf)
     o = util.oracle_for(w)
