@@ -454,7 +454,8 @@ def main():
         "config": {"workload": f"{w.name} (configuration {args.config}): {w.note}",
                    "records": T, "live_allocations": int(w.dev.live_idx.size),
                    "host_region_bytes": int(w.host.length), "transfer_bytes": int(w.records["n"].sum()),
-                   "mode": "check", "path": "batched: classify + scan + persistent scan kernel, hipGraph replay",
+                   "mode": "check", "path": "batched: classify + source-block segments + scan + persistent scan kernel, "
+                           "hipGraph replay",
                    "tuning": tun},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "transfers_per_s": round(T / (wall / args.steps), 1),
@@ -510,9 +511,9 @@ def main():
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_note": traffic_note,
                           "kernel": "k_batched", "kernel_avg_ms": round(k_avg_ms, 3),
-                          "note": "achieved counts the bytes the check examines; large batches are worked in "
-                                  "source-address order, so re-reads of the same bytes hit in L2 / Infinity Cache "
-                                  "and traffic (L2 misses to the fabric) is below them",
+                          "note": "achieved counts the bytes the check examines; a large batch is worked as "
+                                  "segments of its records sorted by block of source memory, so re-reads of the "
+                                  "same bytes hit in L2 and traffic (L2 misses to the fabric) is below them",
                           "algorithmic_bytes_per_launch": int(bytes_step)}
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)

@@ -322,6 +322,36 @@ __device__ __forceinline__ void flush_wave(Acc &a, cg_verdict *out, uint64_t t)
 // ---------------------------------------------------------------------------
 // uniform mode: the whole wave works on units [k_begin, k_end) of one record
 // ---------------------------------------------------------------------------
+
+// Chunks 64 j + lane (j < U) of an interior iteration: V from vbase, source A
+// words from abase (SA), destination A words from dbase (DA); true when every
+// V byte of the wave's chunks is 0 and every A bit 1.
+template <int U, bool NT, bool SA, bool DA>
+__device__ __forceinline__ bool clean_interior(uint64_t vbase, uint64_t abase, uint64_t dbase)
+{
+    const gcptr<u32x4> vp = reinterpret_cast<gcptr<u32x4>>(vbase);
+    const gcptr<uint16_t> ap = reinterpret_cast<gcptr<uint16_t>>(abase);
+    const gcptr<uint16_t> dp = reinterpret_cast<gcptr<uint16_t>>(dbase);
+    const uint32_t lane = lane_id();
+    u32x4 w[U];
+    uint32_t sa[U], da[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const uint32_t cr = 64u * j + lane;
+        if constexpr (NT) w[j] = __builtin_nontemporal_load(vp + cr);
+        else w[j] = vp[cr];
+        if constexpr (SA) sa[j] = ap[cr];
+        if constexpr (DA) da[j] = dp[cr];
+    }
+    uint32_t bad = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        bad |= w[j].x | w[j].y | w[j].z | w[j].w;
+        if constexpr (SA) bad |= sa[j] ^ 0xFFFFu;
+        if constexpr (DA) bad |= da[j] ^ 0xFFFFu;
+    }
+    return __ballot(bad != 0u) == 0;
+}
 template <int U, bool NT, bool PROP>
 __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64_t k_begin, uint64_t k_end,
                                             Acc &acc)
@@ -349,6 +379,33 @@ __device__ __forceinline__ void run_uniform(const DV &d, const Region &R, uint64
         const int32_t chi = ((vhi + 15) >> 4) < 64 * U ? ((vhi + 15) >> 4) : 64 * U;
         const uint64_t vbase = d.src_sh + (uint64_t)(16 * cb);
         const uint64_t abase = a16b + (uint64_t)((d.a_src + 16 * cb) >> 3);
+
+        // Interior iteration of a check (kernels built without propagation,
+        // whose register budget allows three waves per SIMD): every lane's U
+        // source chunks lie wholly inside the valid source range (and, for a
+        // host destination, its chunks inside the valid destination range), so
+        // no byte mask or index clamp is needed.  When every V byte is 0 and
+        // every A bit 1, the code below would find nothing and the iteration
+        // ends here; otherwise (rare) that code runs the iteration again and
+        // reports exactly.
+        if (!PROP && check && vlo <= 0 && vhi >= 16 * 64 * U && kend >= 64 * U) {
+            bool dfull = true;
+            uint64_t dbase = 0;
+            if (dsta) {
+                const int64_t eb = (int64_t)(d.e0 + kb);
+                const int64_t i0db = 16 * eb - (int64_t)d.psi;
+                dfull = clamp32(d.d_lo - i0db) <= 0 && clamp32(d.d_hi - i0db) >= 16 * 64 * U;
+                dbase = a16b + (uint64_t)((d.a_dst + 16 * eb) >> 3);
+            }
+            if (dfull) {
+                // a host destination (D2H) has a device source; a host source
+                // (H2D) has a device destination
+                const bool clean = dsta ? clean_interior<U, NT, false, true>(vbase, abase, dbase)
+                                 : src_host ? clean_interior<U, NT, true, false>(vbase, abase, dbase)
+                                            : clean_interior<U, NT, false, false>(vbase, abase, dbase);
+                if (clean) continue;
+            }
+        }
 
         u32x4 v[U];
         uint32_t ok[U], un[U];
@@ -810,7 +867,7 @@ __global__ void __launch_bounds__(256) k_tile_starts(BatchArgs a)
 // k_batched: persistent kernel over the tiles of the flattened unit space
 // ---------------------------------------------------------------------------
 template <int U, bool NT, bool PROP>
-__global__ void __launch_bounds__(512) k_batched(BatchArgs a)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3))) k_batched(BatchArgs a)
 {
     const uint32_t lane = lane_id();
     const uint64_t ntiles = ufl64(a.ctl->ntiles);
