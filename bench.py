@@ -76,12 +76,12 @@ def cpu_baseline(w, hv, ha, got, target_bytes, threads):
     return gbs, text, same, dt
 
 
-def profiled_traffic(tuning, config):
-    """Bytes per launch of the scan kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (scaled by the copy-probe factor), if the kernel source and
-    launch shape are the ones profiled; else None."""
+def matching_profile(name, tuning, config):
+    """A committed rocprofv3 summary (profiles/<name>.json) of the scan kernel on
+    the 1M-record workload, if the kernel source and launch shape are the ones
+    profiled: (dict, None); else (None, the reason)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_batched_batched-1M_traffic.json")
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if config != 3 or not os.path.exists(path):
         return None, "no profile for this workload"
     prof = json.load(open(path))
@@ -90,7 +90,26 @@ def profiled_traffic(tuning, config):
         return None, "kernel changed since the counters were taken"
     if {k: tuning[k] for k in prof["tuning"]} != prof["tuning"]:
         return None, "launch shape differs from the profiled one"
+    return prof, None
+
+
+def profiled_traffic(tuning, config):
+    """Bytes per launch of the scan kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by the copy-probe factor), if the kernel source and
+    launch shape are the ones profiled; else None."""
+    prof, why = matching_profile("k_batched_batched-1M_traffic", tuning, config)
+    if prof is None:
+        return None, why
     return int(prof["traffic_bytes"]), "bytes per launch, profiles/k_batched_batched-1M_traffic.md"
+
+
+def profiled_limits(tuning, config):
+    """Issue and load-path utilisation of the scan kernel from the committed SQ /
+    TA / TCC counter passes, under the same matching rule; else None."""
+    prof, why = matching_profile("k_batched_batched-1M_counters", tuning, config)
+    if prof is None:
+        return {"note": why}
+    return dict(prof["limits"], source="profiles/k_batched_batched-1M_counters.md")
 
 
 TUNE_CACHE = os.environ.get("XC_TUNE_CACHE", os.path.join(ROOT, "paper_1310_0901_amd", "tuning_cache.jsonl"))
@@ -514,7 +533,8 @@ def main():
                           "note": "achieved counts the bytes the check examines; a large batch is worked as "
                                   "segments of its records sorted by block of source memory, so re-reads of the "
                                   "same bytes hit in L2 and traffic (L2 misses to the fabric) is below them",
-                          "algorithmic_bytes_per_launch": int(bytes_step)}
+                          "algorithmic_bytes_per_launch": int(bytes_step),
+                          "limits": profiled_limits(tun, args.config)}
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         gbs, text, same, dt = cpu_baseline(w, hv, ha, got, args.cpu_bytes, threads)

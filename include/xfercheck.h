@@ -75,7 +75,7 @@ extern "C" {
 #define CG_PLAIN           0x04u  /* one kernel launch per transfer (baseline path) */
 #define CG_DEBUG_CONFLICTS 0x08u  /* host-side verification of the no-conflict rule (synchronous) */
 #define CG_EAGER           0x10u  /* batched path without graph capture */
-#define CG_KEEP_ORDER      0x20u  /* work a large batch in the given order (no reordering by source address) */
+#define CG_KEEP_ORDER      0x20u  /* work a large batch in the given order (no source-block segments) */
 
 /*
  * One transfer record, 32 bytes, in device memory (the parameters of a
@@ -181,10 +181,12 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  * (a hipStream_t; NULL = the null stream).
  *   mode: CG_CHECK and/or CG_PROPAGATE, optionally with CG_PLAIN (one launch
  *   per record), CG_EAGER (no graph capture), CG_DEBUG_CONFLICTS or
- *   CG_KEEP_ORDER.  A batched check of 16,384 to 2^31 - 1 records is worked in
- *   ascending order of source address (records reading the same bytes run
- *   close together); verdicts are written at the records' own positions
- *   either way, and CG_KEEP_ORDER works the batch in the given order.
+ *   CG_KEEP_ORDER.  A batched check of 16,384 to 2^30 records is worked as
+ *   source-block segments: each record's bytes are cut at blocks of source
+ *   memory (a power of two of at least 1 MiB) and the pieces are worked in
+ *   block order, so that copies reading the same bytes run close together.
+ *   Verdicts are the same and are written at the records' own positions
+ *   either way; CG_KEEP_ORDER works the batch in the given order.
  * With CG_PROPAGATE every valid destination byte receives the source's V
  * byte, or 0xFF where the source byte is not valid; overlapping D2D records
  * are not propagated.  All records read the shadow as it was before the
@@ -219,7 +221,8 @@ typedef struct cg_transfer2d {
  * (byte c of row r is r*width + c): flags = OR over its rows, first_bad =
  * smallest r*width + first_bad_r, undef_bytes = sum, avail = the first row's
  * (bytes from src / dst to the end of its allocation).  A record with no
- * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers.  The
+ * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers, except
+ * that the rows are always worked in their order (CG_KEEP_ORDER).  The
  * call waits for the caller's stream once, to learn the number of rows
  * (at most 2^32 - 1024 in total).  Errors: as check_transfers, and CG_EINVAL for
  * 2^31 records or more, or too many rows.

@@ -847,7 +847,9 @@ __global__ void __launch_bounds__(256) k_prefix_tiles(BatchArgs a)
 }
 
 // One lane per tile (grid-stride): the last record whose prefix is at or
-// below the tile's first unit (prefixes strictly increase: weights >= 1).
+// below the tile's first unit.  Prefixes strictly increase (weights >= 1)
+// except over a tail of empty positions of weight 0 (a segmented batch),
+// where they equal the total, above every unit.
 __global__ void __launch_bounds__(256) k_tile_starts(BatchArgs a)
 {
     const uint64_t ntiles = a.ctl->ntiles, tu = a.ctl->tile_units;

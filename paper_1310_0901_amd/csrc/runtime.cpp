@@ -1095,7 +1095,10 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
             w.row_cap = cap;
         }
         HIPTRY(c, launch_2d_expand(recs_dev, w.first, count, nrows, w.rows, w.rec_of, s));
-        const int rc = run_check(c, w.rows, nrows, (mode & CG_CHECK) ? w.rowv : nullptr, mode, s,
+        // the rows keep their order (each record's rows ascend in memory):
+        // cutting millions of short rows into source-block segments costs
+        // more than the cache reuse it could bring
+        const int rc = run_check(c, w.rows, nrows, (mode & CG_CHECK) ? w.rowv : nullptr, mode | CG_KEEP_ORDER, s,
                                  (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
         if (rc) return rc;
     }

@@ -29,7 +29,7 @@
 //                 from segment 0's key, for the sort's pass mask
 //   (sort.hip)    stable radix sort of the segments' keys
 //   k_seg_layout  one lane per position: descriptor, record, work weight
-//                 (positions past the segments: empty, weight 1), and the
+//                 (positions past the segments: empty, weight 0), and the
 //                 block-local prefix and block sums that k_classify makes
 //                 for a batch in its given order
 #include <hip/hip_runtime.h>
@@ -223,7 +223,9 @@ __global__ void __launch_bounds__(kT) k_seg_layout(SegArgs g, const uint32_t *va
         desc[p] = o;
         perm[p] = r;
         weight[p] = o.units;
-        w = o.units ? o.units : 1;
+        // a segment weighs its units (at least 1); the empty positions past
+        // the segments weigh 0, so no unit of the scan reaches them
+        w = p < ns ? (o.units ? o.units : 1) : 0;
     }
     uint64_t tot;
     const uint64_t ex = block_excl(w, &tot);
