@@ -181,7 +181,7 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  * (a hipStream_t; NULL = the null stream).
  *   mode: CG_CHECK and/or CG_PROPAGATE, optionally with CG_PLAIN (one launch
  *   per record), CG_EAGER (no graph capture), CG_DEBUG_CONFLICTS or
- *   CG_KEEP_ORDER.  A batched check of 16,384 to 2^30 records is worked as
+ *   CG_KEEP_ORDER.  A batched check of 16,384 to 2^27 records is worked as
  *   source-block segments: each record's bytes are cut at blocks of source
  *   memory (a power of two of at least 1 MiB) and the pieces are worked in
  *   block order, so that copies reading the same bytes run close together.

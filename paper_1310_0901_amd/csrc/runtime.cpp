@@ -33,7 +33,9 @@ constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
 constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
 constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
-constexpr uint64_t kSegMaxRecords = 1ull << 30;   // largest batch worked as segments
+// largest batch worked as segments: its 3 * count positions take 96-byte
+// descriptors (about 40 GB at this size); larger batches keep their order
+constexpr uint64_t kSegMaxRecords = 1ull << 27;
 constexpr size_t kGraphsPerWs = 16;
 constexpr int kVersions = 4;             // table versions in the device ring
 
@@ -603,9 +605,8 @@ int debug_conflicts(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, hipS
 
 int note_use(cg_ctx *c, hipStream_t s);
 
-// Batches of at least reorder_min records (and at most kSegMaxRecords, so
-// that the 3 * count positions have 32-bit indices) are worked as
-// source-block segments unless the caller keeps the given order.
+// Batches of at least reorder_min records and at most kSegMaxRecords are
+// worked as source-block segments unless the caller keeps the given order.
 bool segmented(const cg_ctx *c, uint64_t count, uint32_t mode)
 {
     return !(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min && count <= kSegMaxRecords;
