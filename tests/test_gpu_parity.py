@@ -222,3 +222,30 @@ def test_segments_of_large_records(X, H, seed, monkeypatch):
         assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
     finally:
         dw.close()
+
+
+def test_segmented_graph_replays(X, H, monkeypatch):
+    """A segmented batch checked through its captured graph several times on
+    the same buffers, with the verdicts overwritten, eager checks and host
+    synchronisation between the replays: every replay equals the oracle."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SEG_MIN_LOG2", "4")
+    rng = np.random.default_rng(51)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=1 << 20, nalloc=10, max_size=200_000, dens=1e-3)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 500, max_n=40_000)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        rt = H.records_tensor(recs)
+        out = H.verdicts_tensor(recs.size)
+        s = torch.cuda.current_stream()
+        for rep in range(4):
+            out.fill_(0xAB)
+            X.check_transfers(dw.ctx, rt.data_ptr(), recs.size, out.data_ptr(), X.CG_CHECK, s.cuda_stream)
+            s.synchronize()
+            util.assert_verdicts_equal(H.verdicts_np(out, recs.size), want, f"replay {rep}")
+            # eager work on the same stream between the replays
+            util.assert_verdicts_equal(dw.check(recs[::3], X.CG_CHECK | X.CG_EAGER), want[::3], f"eager {rep}")
+    finally:
+        dw.close()
