@@ -609,7 +609,7 @@ int note_use(cg_ctx *c, hipStream_t s);
 // worked as source-block segments unless the caller keeps the given order.
 bool segmented(const cg_ctx *c, uint64_t count, uint32_t mode)
 {
-    return !(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= c->reorder_min && count <= kSegMaxRecords;
+    return !(mode & (CG_PLAIN | CG_KEEP_ORDER)) && count >= 1 && count >= c->reorder_min && count <= kSegMaxRecords;
 }
 
 // Segment buffers for `count` records; the positions (w->cap) are already
