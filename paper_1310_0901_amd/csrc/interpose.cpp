@@ -114,6 +114,16 @@ using memcpy3d_t = hipError_t (*)(const hipMemcpy3DParms *);
 using memcpy3d_async_t = hipError_t (*)(const hipMemcpy3DParms *, hipStream_t);
 using malloc_pitch_t = hipError_t (*)(void **, size_t *, size_t, size_t);
 using malloc3d_t = hipError_t (*)(hipPitchedPtr *, hipExtent);
+using memset_async_t = hipError_t (*)(void *, int, size_t, hipStream_t);
+using memset_d8_t = hipError_t (*)(hipDeviceptr_t, unsigned char, size_t);
+using memset_d8_async_t = hipError_t (*)(hipDeviceptr_t, unsigned char, size_t, hipStream_t);
+using memset_d16_t = hipError_t (*)(hipDeviceptr_t, unsigned short, size_t);
+using memset_d16_async_t = hipError_t (*)(hipDeviceptr_t, unsigned short, size_t, hipStream_t);
+using memset_d32_t = hipError_t (*)(hipDeviceptr_t, int, size_t);
+using memset_d32_async_t = hipError_t (*)(hipDeviceptr_t, int, size_t, hipStream_t);
+using htod_async_t = hipError_t (*)(hipDeviceptr_t, const void *, size_t, hipStream_t);
+using dtoh_async_t = hipError_t (*)(void *, hipDeviceptr_t, size_t, hipStream_t);
+using dtod_async_t = hipError_t (*)(hipDeviceptr_t, hipDeviceptr_t, size_t, hipStream_t);
 
 // a kernel's parameter list as far as its name tells it
 struct KernelSig {
@@ -124,9 +134,14 @@ struct KernelSig {
 };
 
 // an asynchronous copy waiting in the window
+// An asynchronous copy (or fill) in the concurrent-access window.  A fill
+// writes [dst, dst + n); it joins as a D2D record with src = dst, so every
+// pair it takes part in involves its write.
 struct WinCopy {
     cg_transfer r;
     hipStream_t stream;
+    const char *api = "hipMemcpyAsync";
+    bool fill = false;
 };
 
 // A window this long is joined at once, as if a synchronising call had come:
@@ -407,7 +422,7 @@ void window_rows(const Pitched &p, uint32_t kind, hipStream_t stream)
             G.win.push_back(WinCopy{cg_transfer{(uint64_t)(p.src + z * p.sslice + y * p.spitch),
                                                 (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width,
                                                 kind, 0},
-                                    stream});
+                                    stream, "hipMemcpy2DAsync/3DAsync row"});
     if (G.win.size() >= kWindowMax) close_window();
 }
 
@@ -430,10 +445,14 @@ Pitched pitched_3d(const hipMemcpy3DParms *q)
 
 bool meets(uint64_t a, uint64_t na, uint64_t b, uint64_t nb) { return na && nb && a < b + nb && b < a + na; }
 
-void describe(char *buf, size_t len, const cg_transfer &r, hipStream_t s)
+void describe(char *buf, size_t len, const WinCopy &c)
 {
-    snprintf(buf, len, "hipMemcpyAsync(dst=%p, src=%p, %" PRIu64 " bytes, %s) on stream %p", (void *)r.dst,
-             (void *)r.src, r.n, kind_name(r.kind), (void *)s);
+    const cg_transfer &r = c.r;
+    if (c.fill)
+        snprintf(buf, len, "%s(dst=%p, %" PRIu64 " bytes) on stream %p", c.api, (void *)r.dst, r.n, (void *)c.stream);
+    else
+        snprintf(buf, len, "%s(dst=%p, src=%p, %" PRIu64 " bytes, %s) on stream %p", c.api, (void *)r.dst,
+                 (void *)r.src, r.n, kind_name(r.kind), (void *)c.stream);
 }
 
 // Join the window's copies and report each conflicting pair once; the caller
@@ -491,8 +510,8 @@ void close_window()
         const bool ww = meets(x.dst, x.n, y.dst, y.n), wr = meets(x.dst, x.n, y.src, y.n);
         const char *va = (ww || wr) ? "writes" : "reads", *vb = (ww || !wr) ? "writes" : "reads";
         char da[256], db[256];
-        describe(da, sizeof da, x, w[a].stream);
-        describe(db, sizeof db, y, w[b].stream);
+        describe(da, sizeof da, w[a]);
+        describe(db, sizeof db, w[b]);
         fprintf(stderr,
                 "Error: Concurrent copies access the same bytes without synchronisation.\n %s\n %s bytes that\n %s\n "
                 "%s.\n",
@@ -678,6 +697,38 @@ void track_free(const char *api, void *p)
     }
 }
 
+// A fill of n bytes at dst: its bytes become defined (shadow_set); a fill
+// outside the allocations is reported and refused.  An asynchronous fill
+// also joins the concurrent-access window as a write on its stream.
+bool track_fill(const char *api, void *dst, size_t n, bool async, hipStream_t stream)
+{
+    if (inside || !n) return true;
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (!ensure_ctx()) return true;
+    Guard g;
+    if (shadow_set(G.ctx, (uint64_t)dst, n, 0) != CG_OK) {
+        ++G.errors;
+        fprintf(stderr, "Error: %s of %zu bytes at %p leaves allocated device memory.\n", api, n, dst);
+        if (!G.allow_bad) return false;
+    }
+    if (async) {
+        G.win.push_back(WinCopy{cg_transfer{(uint64_t)dst, (uint64_t)dst, (uint64_t)n, CG_D2D, 0}, stream, api, true});
+        if (G.win.size() >= kWindowMax) close_window();
+    }
+    return true;
+}
+
+// an asynchronous copy: checked when issued, then part of the window
+bool async_copy(const char *api, void *dst, const void *src, size_t n, uint32_t d, hipStream_t stream)
+{
+    if (inside || !n || d > CG_D2D) return true;
+    if (!check_copy(api, dst, src, n, d)) return false;
+    std::lock_guard<std::mutex> lk(G.mu);
+    G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream, api});
+    if (G.win.size() >= kWindowMax) close_window();
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -701,18 +752,61 @@ hipError_t hipFree(void *ptr)
 hipError_t hipMemset(void *dst, int value, size_t n)
 {
     static memset_t f = real<memset_t>("hipMemset");
-    if (!inside && n) {
-        std::lock_guard<std::mutex> lk(G.mu);
-        if (ensure_ctx()) {
-            Guard g;
-            if (shadow_set(G.ctx, (uint64_t)dst, n, 0) != CG_OK) {
-                ++G.errors;
-                fprintf(stderr, "Error: hipMemset of %zu bytes at %p leaves allocated device memory.\n", n, dst);
-                if (!G.allow_bad) return refuse();
-            }
-        }
-    }
+    if (!inside) sync_point();
+    if (!track_fill("hipMemset", dst, n, false, nullptr)) return refuse();
     return f(dst, value, n);
+}
+
+hipError_t hipMemsetAsync(void *dst, int value, size_t n, hipStream_t stream)
+{
+    static memset_async_t f = real<memset_async_t>("hipMemsetAsync");
+    if (!track_fill("hipMemsetAsync", dst, n, true, stream)) return refuse();
+    return f(dst, value, n, stream);
+}
+
+hipError_t hipMemsetD8(hipDeviceptr_t dst, unsigned char value, size_t count)
+{
+    static memset_d8_t f = real<memset_d8_t>("hipMemsetD8");
+    if (!inside) sync_point();
+    if (!track_fill("hipMemsetD8", dst, count, false, nullptr)) return refuse();
+    return f(dst, value, count);
+}
+
+hipError_t hipMemsetD8Async(hipDeviceptr_t dst, unsigned char value, size_t count, hipStream_t stream)
+{
+    static memset_d8_async_t f = real<memset_d8_async_t>("hipMemsetD8Async");
+    if (!track_fill("hipMemsetD8Async", dst, count, true, stream)) return refuse();
+    return f(dst, value, count, stream);
+}
+
+hipError_t hipMemsetD16(hipDeviceptr_t dst, unsigned short value, size_t count)
+{
+    static memset_d16_t f = real<memset_d16_t>("hipMemsetD16");
+    if (!inside) sync_point();
+    if (!track_fill("hipMemsetD16", dst, 2 * count, false, nullptr)) return refuse();
+    return f(dst, value, count);
+}
+
+hipError_t hipMemsetD16Async(hipDeviceptr_t dst, unsigned short value, size_t count, hipStream_t stream)
+{
+    static memset_d16_async_t f = real<memset_d16_async_t>("hipMemsetD16Async");
+    if (!track_fill("hipMemsetD16Async", dst, 2 * count, true, stream)) return refuse();
+    return f(dst, value, count, stream);
+}
+
+hipError_t hipMemsetD32(hipDeviceptr_t dst, int value, size_t count)
+{
+    static memset_d32_t f = real<memset_d32_t>("hipMemsetD32");
+    if (!inside) sync_point();
+    if (!track_fill("hipMemsetD32", dst, 4 * count, false, nullptr)) return refuse();
+    return f(dst, value, count);
+}
+
+hipError_t hipMemsetD32Async(hipDeviceptr_t dst, int value, size_t count, hipStream_t stream)
+{
+    static memset_d32_async_t f = real<memset_d32_async_t>("hipMemsetD32Async");
+    if (!track_fill("hipMemsetD32Async", dst, 4 * count, true, stream)) return refuse();
+    return f(dst, value, count, stream);
 }
 
 hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind kind)
@@ -753,14 +847,40 @@ hipError_t hipMemcpyDtoD(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n)
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind kind, hipStream_t stream)
 {
     static memcpy_async_t f = real<memcpy_async_t>("hipMemcpyAsync");
+    if (!inside && n && !async_copy("hipMemcpyAsync", dst, src, n, direction(dst, src, kind), stream))
+        return refuse();
+    return f(dst, src, n, kind, stream);
+}
+
+hipError_t hipMemcpyHtoDAsync(hipDeviceptr_t dst, const void *src, size_t n, hipStream_t stream)
+{
+    static htod_async_t f = real<htod_async_t>("hipMemcpyHtoDAsync");
+    if (!async_copy("hipMemcpyHtoDAsync", dst, src, n, CG_H2D, stream)) return refuse();
+    return f(dst, src, n, stream);
+}
+
+hipError_t hipMemcpyDtoHAsync(void *dst, hipDeviceptr_t src, size_t n, hipStream_t stream)
+{
+    static dtoh_async_t f = real<dtoh_async_t>("hipMemcpyDtoHAsync");
+    if (!async_copy("hipMemcpyDtoHAsync", dst, src, n, CG_D2H, stream)) return refuse();
+    return f(dst, src, n, stream);
+}
+
+hipError_t hipMemcpyDtoDAsync(hipDeviceptr_t dst, hipDeviceptr_t src, size_t n, hipStream_t stream)
+{
+    static dtod_async_t f = real<dtod_async_t>("hipMemcpyDtoDAsync");
+    if (!async_copy("hipMemcpyDtoDAsync", dst, src, n, CG_D2D, stream)) return refuse();
+    return f(dst, src, n, stream);
+}
+
+// a copy the host waits for: ordered after what came before, as hipMemcpy
+hipError_t hipMemcpyWithStream(void *dst, const void *src, size_t n, hipMemcpyKind kind, hipStream_t stream)
+{
+    static memcpy_async_t f = real<memcpy_async_t>("hipMemcpyWithStream");
+    if (!inside) sync_point();
     if (!inside && n) {
         const uint32_t d = direction(dst, src, kind);
-        if (d <= CG_D2D) {
-            if (!check_copy("hipMemcpyAsync", dst, src, n, d)) return refuse();
-            std::lock_guard<std::mutex> lk(G.mu);
-            G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream});
-            if (G.win.size() >= kWindowMax) close_window();
-        }
+        if (d <= CG_D2D && !check_copy("hipMemcpyWithStream", dst, src, n, d)) return refuse();
     }
     return f(dst, src, n, kind, stream);
 }

@@ -91,6 +91,49 @@ static int streams()
     return 0;
 }
 
+// Fills and the typed asynchronous copies: a fill racing with a download of
+// bytes it writes, a typed upload and download sharing 512 bytes; fills of
+// disjoint bytes and copies ordered on one stream stay quiet; a fill and
+// copies past the end of the allocation are refused.
+static int fills()
+{
+    const size_t MB = 1 << 20;
+    uint8_t *d = nullptr, *h1 = nullptr, *h2 = nullptr;
+    if (hipMalloc((void **)&d, 2 * MB) != hipSuccess) return 2;
+    if (hipHostMalloc((void **)&h1, MB + 64) != hipSuccess || hipHostMalloc((void **)&h2, MB) != hipSuccess) return 2;
+    hipStream_t s1, s2;
+    if (hipStreamCreate(&s1) != hipSuccess || hipStreamCreate(&s2) != hipSuccess) return 2;
+    // racing: a fill and a download of bytes it writes
+    hipMemsetAsync(d, 1, 4096, s1);
+    hipMemcpyDtoHAsync(h1, (hipDeviceptr_t)(d + 1024), 1024, s2);
+    (void)hipDeviceSynchronize();
+    // racing: typed upload and download sharing 512 bytes
+    hipMemcpyHtoDAsync((hipDeviceptr_t)(d + MB), h1, 4096, s1);
+    hipMemcpyDtoHAsync(h2, (hipDeviceptr_t)(d + MB + 3584), 4096, s2);
+    (void)hipStreamSynchronize(s2);
+    // quiet: fills of disjoint bytes on two streams, a copy ordered after a fill on one stream
+    hipMemsetD32Async((hipDeviceptr_t)d, 7, 1024, s1);            // bytes [0, 4096)
+    hipMemsetD8Async((hipDeviceptr_t)(d + 4096), 3, 4096, s2);     // bytes [4096, 8192)
+    hipMemsetD16Async((hipDeviceptr_t)(d + 8192), 5, 2048, s2);    // bytes [8192, 12288)
+    hipMemcpyDtoDAsync((hipDeviceptr_t)(d + MB), (hipDeviceptr_t)d, 4096, s1);
+    (void)hipDeviceSynchronize();
+    // refused: a fill and copies past the end of the allocation
+    const hipError_t e1 = hipMemsetD32((hipDeviceptr_t)(d + 2 * MB - 8), 0, 4);
+    const hipError_t e2 = hipMemcpyDtoDAsync((hipDeviceptr_t)(d + MB), (hipDeviceptr_t)d, MB + 1, s1);
+    const hipError_t e3 = hipMemcpyWithStream(h1, d + MB, MB + 16, hipMemcpyDeviceToHost, s1);
+    const hipError_t e4 = hipMemcpyWithStream(h1, d, MB, hipMemcpyDeviceToHost, s1);
+    (void)hipDeviceSynchronize();
+    printf("fill past the end %d, DtoD past the end %d, copy with stream past the end %d, fitting copy %d\n",
+           (int)e1, (int)e2, (int)e3, (int)e4);
+    (void)hipStreamDestroy(s1);
+    (void)hipStreamDestroy(s2);
+    hipFree(d);
+    (void)hipHostFree(h1);
+    (void)hipHostFree(h2);
+    printf("fills done\n");
+    return 0;
+}
+
 // Kernel arguments: launches with valid pointers (inside an allocation, one
 // past its end, null, pinned host memory), then with a freed pointer and with
 // a pointer to ordinary host memory.  The refused launches pass n = 0, so the
@@ -174,6 +217,7 @@ int main(int argc, char **argv)
     if (argc > 1 && strcmp(argv[1], "kernelargs") == 0) return kernel_args();
     if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
     if (argc > 1 && strcmp(argv[1], "streams") == 0) return streams();
+    if (argc > 1 && strcmp(argv[1], "fills") == 0) return fills();
     const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;
     const int size = 1000000;
     double *c, *a, *b;

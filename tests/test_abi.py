@@ -66,5 +66,9 @@ def test_preload_wraps_the_hip_calls():
     so = os.path.join(ROOT, "paper_1310_0901_amd", "libxfercheck_preload.so")
     out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True, check=True).stdout
     names = {l.split()[-1] for l in out.splitlines() if l.strip()}
-    for f in ("hipMalloc", "hipFree", "hipMemset", "hipMemcpy", "hipMemcpyHtoD", "hipMemcpyDtoH", "hipMemcpyDtoD"):
+    for f in ("hipMalloc", "hipFree", "hipMemset", "hipMemcpy", "hipMemcpyHtoD", "hipMemcpyDtoH", "hipMemcpyDtoD",
+              "hipMemcpyAsync", "hipMemcpyHtoDAsync", "hipMemcpyDtoHAsync", "hipMemcpyDtoDAsync", "hipMemcpyWithStream",
+              "hipMemsetAsync", "hipMemsetD8", "hipMemsetD8Async", "hipMemsetD16", "hipMemsetD16Async", "hipMemsetD32",
+              "hipMemsetD32Async", "hipMemcpy2D", "hipMemcpy2DAsync", "hipMemcpy3D", "hipMemcpy3DAsync",
+              "hipLaunchKernel", "hipDeviceSynchronize", "hipStreamSynchronize"):
         assert f in names, f

@@ -85,6 +85,29 @@ def test_concurrent_copies_on_streams():
     assert "12 copies checked, 2 with errors, 2 concurrent-access pairs" in err
 
 
+def test_fills_and_typed_async_copies():
+    """hipMemsetAsync / hipMemsetD8/D16/D32(Async) mark their bytes defined and
+    join the concurrent-access window as writes; hipMemcpyHtoDAsync /
+    DtoHAsync / DtoDAsync are checked when issued and join the window;
+    hipMemcpyWithStream is checked like hipMemcpy.  A fill racing with a
+    download and two typed copies sharing bytes are reported; fills of
+    disjoint bytes and copies ordered on one stream are not; a fill and
+    copies past the allocation's end are refused."""
+    r = run_example("fills")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0 and "fills done" in r.stdout
+    assert "fill past the end 1, DtoD past the end 1, copy with stream past the end 1, fitting copy 0" in r.stdout
+    err = r.stderr
+    head = "Error: Concurrent copies access the same bytes without synchronisation."
+    assert err.count(head) == 2
+    first, second = err.split(head)[1:3]
+    assert "hipMemsetAsync(dst=" in first and "4096 bytes) on stream" in first and "writes bytes that" in first
+    assert "hipMemcpyDtoHAsync(dst=" in first and "1024 bytes, hipMemcpyDeviceToHost" in first
+    assert "hipMemcpyHtoDAsync(dst=" in second and "hipMemcpyDtoHAsync(dst=" in second and "\n reads." in second
+    assert "Error: hipMemsetD32 of 16 bytes at" in err
+    assert "2 concurrent-access pairs" in err
+
+
 def test_kernel_arguments():
     """hipLaunchKernel's raw-pointer arguments are looked up among the live
     allocations (the outlook of Sec. 5.1): pointers inside an allocation, one
