@@ -49,6 +49,25 @@ def test_tiny_universe_every_case(X, H):
         dw.close()
 
 
+def test_tiny_universe_segmented(X, H, monkeypatch):
+    """Every classification case of the tiny universe (bad kinds, empty
+    records, unallocated and unaddressable sides, overruns, overlapping
+    D2D) in one batch worked as source-block segments of 16 bytes and up,
+    on the graph and eager paths."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SEG_MIN_LOG2", "4")
+    rows = all_records()
+    recs = np.array([(s, d, n, k, 0) for k, s, d, n in rows], W.RECORD_DTYPE)
+    w = tiny_workload(recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for name, mode in modes(X)[:2]:
+            util.assert_verdicts_equal(dw.check(recs, mode), want, f"segmented {name}")
+    finally:
+        dw.close()
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_small_config_parity(X, H, k):
     w = W.small_config(k)
