@@ -18,6 +18,7 @@ struct RaceWs {
     uint32_t *res = nullptr;                  // per-interval partner (or none)
     void *agg = nullptr;                      // per sweep tile: 4 monoid aggregates
     void *pre = nullptr;                      // per sweep tile: prefix / suffix of those
+    uint32_t *flag = nullptr;                 // 0 when every epoch is sorted in LDS (per-epoch path)
 };
 
 // Grow `w` to hold `intervals` intervals (frees and reallocates; the caller

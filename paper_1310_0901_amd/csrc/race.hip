@@ -11,7 +11,10 @@
 // The join is an interval sweep.  Every record gives two intervals whose key
 // is (epoch << 48 | address), so intervals of different epochs never meet.
 // The keys are sorted by the 8-bit LSD radix sort of sort.hip, which skips a
-// pass whose digit is the same in every key.  An interval then meets an
+// pass whose digit is the same in every key.  When the epochs never decrease
+// in record order and no epoch spans more than 4,096 records (a program's
+// synchronisation windows), each epoch's intervals are instead sorted in LDS
+// by one block, in place, and the radix passes all skip.  An interval then meets an
 // interval of another stream that starts no later exactly when the furthest
 // end among earlier intervals of other streams lies past its start, and one
 // that starts later exactly when the smallest start among later intervals of
@@ -35,6 +38,9 @@ constexpr uint32_t kEpochLimit = 1u << 15;
 constexpr int kT = 256;                          // threads per block
 constexpr int kWaves = kT / 64;
 constexpr int kSweepItems = 8;                   // consecutive elements per thread
+constexpr uint32_t kRunMax = 4096;               // records of one epoch sorted in LDS, at most
+constexpr int kLocalN = 2 * kRunMax;             // their intervals
+constexpr int kLT = 1024;                        // threads of the per-epoch sort
 constexpr int kSweepTile = kT * kSweepItems;
 static_assert(kT == kSortKeyBlock, "one part of the key mask per block of k_race_keys");
 
@@ -59,10 +65,11 @@ __device__ __forceinline__ uint64_t interval_key(const cg_transfer *recs, const 
 }
 
 __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const uint32_t *epochs, uint64_t m,
-                                                  uint64_t *keys, uint32_t *vals, uint64_t *parts)
+                                                  uint64_t *keys, uint32_t *vals, uint64_t *parts, uint32_t *flag)
 {
     __shared__ uint64_t part[kWaves];
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i == 0) *flag = 0;
     const uint64_t k0 = interval_key(recs, epochs, 0);
     uint64_t x = 0;
     if (i < m) {
@@ -78,6 +85,97 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
         uint64_t y = 0;
         for (int w = 0; w < kWaves; ++w) y |= part[w];
         parts[blockIdx.x] = y;
+    }
+}
+
+// ---- per-epoch sort --------------------------------------------------------
+
+// *flag becomes non-zero unless the epochs never decrease and no epoch spans
+// more than kRunMax records (without epochs: all records are one epoch).
+// Equal epochs kRunMax records apart mean a longer epoch, since they never
+// decrease.
+__global__ __launch_bounds__(kT) void k_race_local_check(const uint32_t *epochs, uint64_t count, uint32_t *flag)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    bool bad = false;
+    if (i < count) {
+        if (!epochs) bad = i == 0 && count > kRunMax;
+        else bad = (i > 0 && epochs[i] < epochs[i - 1]) || (i >= kRunMax && epochs[i] == epochs[i - kRunMax]);
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+// One block per chunk of kRunMax records sorts, in place, the intervals of
+// every epoch that starts in the chunk (at most kRunMax records, so at most
+// kLocalN intervals): each key is packed with its index in the epoch's run
+// (ties keep interval order, as the radix sort does), sorted by a bitonic
+// network in LDS, and written back with its interval id.  Unchecked intervals
+// go to the end of their epoch's run; the sweep skips them wherever they are.
+// The chunk's parts of the key mask are cleared, so every radix pass skips.
+__global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_t *vals, uint64_t *parts,
+                                                         uint64_t nparts, const uint32_t *epochs, uint64_t count,
+                                                         const uint32_t *flag)
+{
+    __shared__ uint64_t a[kLocalN];
+    __shared__ uint32_t starts[kRunMax];
+    __shared__ uint32_t nstarts, run_len;
+    if (*flag != 0) return;   // the whole grid leaves: the radix sort runs
+    const uint64_t c0 = (uint64_t)blockIdx.x * kRunMax;
+    const uint64_t c1 = c0 + kRunMax < count ? c0 + kRunMax : count;
+    // parts cover 128 records each; the chunks tile the records, so every part is cleared once
+    const uint64_t p1 = (c1 + 127) / 128 < nparts ? (c1 + 127) / 128 : nparts;
+    for (uint64_t b = c0 / 128 + threadIdx.x; b < p1; b += kLT) parts[b] = 0;
+    if (threadIdx.x == 0) nstarts = 0;
+    __syncthreads();
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += kLT) {
+        const bool st = i == 0 || (epochs && epochs[i] != epochs[i - 1]);
+        if (st) starts[atomicAdd(&nstarts, 1u)] = (uint32_t)(i - c0);
+    }
+    __syncthreads();
+    const uint32_t ns = nstarts;
+    for (uint32_t k = 0; k < ns; ++k) {
+        const uint64_t s = c0 + starts[k];
+        const uint32_t most = (uint32_t)(count - s < kRunMax ? count - s : kRunMax);
+        const uint32_t ep = epochs ? epochs[s] : 0u;
+        if (threadIdx.x == 0) run_len = most;
+        __syncthreads();
+        if (epochs)
+            for (uint32_t j = 1 + threadIdx.x; j < most; j += kLT)
+                if (epochs[s + j] != ep) atomicMin(&run_len, j);
+        __syncthreads();
+        const uint32_t n = 2 * run_len;   // intervals of this epoch
+        uint32_t P = 2;
+        while (P < n) P <<= 1;
+        const uint64_t i0 = 2 * s;
+        for (uint32_t l = threadIdx.x; l < P; l += kLT) {
+            uint64_t v = ~0ull;
+            if (l < n) {
+                const uint64_t key = keys[i0 + l];
+                const uint64_t v49 = (key >> 63) ? (1ull << 48) : (key & ((1ull << 48) - 1));
+                v = (v49 << 13) | l;
+            }
+            a[l] = v;
+        }
+        __syncthreads();
+        for (uint32_t q = 2; q <= P; q <<= 1)
+            for (uint32_t j = q >> 1; j > 0; j >>= 1) {
+                for (uint32_t t = threadIdx.x; t < P / 2; t += kLT) {
+                    const uint32_t x = ((t & ~(j - 1)) << 1) | (t & (j - 1)), y = x + j;
+                    const uint64_t u = a[x], v = a[y];
+                    if ((u > v) == ((x & q) == 0)) {
+                        a[x] = v;
+                        a[y] = u;
+                    }
+                }
+                __syncthreads();
+            }
+        for (uint32_t j = threadIdx.x; j < n; j += kLT) {
+            const uint64_t v = a[j];
+            const uint64_t v49 = v >> 13;
+            keys[i0 + j] = (v49 >> 48) ? kInvalidKey : (((uint64_t)ep << 48) | v49);
+            vals[i0 + j] = (uint32_t)(i0 + (v & (kLocalN - 1)));
+        }
+        __syncthreads();
     }
 }
 
@@ -446,6 +544,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
         if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 8);
     };
     get((void **)&w.res, intervals * sizeof(uint32_t));
+    get((void **)&w.flag, 64);
     get(&w.agg, sweeps * 4 * sizeof(Top2));
     get(&w.pre, sweeps * 4 * sizeof(Top2));
     if (e != hipSuccess) {
@@ -459,7 +558,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
 void race_release(RaceWs &w)
 {
     sort_release(w.sort);
-    void *ps[] = {w.res, w.agg, w.pre};
+    void *ps[] = {w.res, w.agg, w.pre, w.flag};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     w = RaceWs{};
@@ -473,7 +572,10 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
     const uint32_t sweeps = (uint32_t)ceil_div(m, kSweepTile);
     SortWs &q = w.sort;
     hipLaunchKernelGGL(k_race_keys, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, recs, epochs, m, q.keys[0],
-                       q.vals[0], q.parts);
+                       q.vals[0], q.parts, w.flag);
+    hipLaunchKernelGGL(k_race_local_check, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, epochs, count, w.flag);
+    hipLaunchKernelGGL(k_race_local_sort, dim3((uint32_t)ceil_div(count, kRunMax)), dim3(kLT), 0, s, q.keys[0],
+                       q.vals[0], q.parts, ceil_div(m, kT), epochs, count, w.flag);
     hipError_t e = sort_pairs(q, m, s);
     if (e != hipSuccess) return e;
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;

@@ -122,6 +122,33 @@ def test_small_race(X, ctx, count, streams, epochs):
         assert not (res["flags"] & 3).any()
 
 
+@pytest.mark.parametrize("count,run", [(20_000, 4096), (20_000, 4097), (9000, 1), (12_289, 777), (4096, None),
+                                       (4097, None), (30_000, "random"), (10_000, "decreasing")])
+def test_epoch_runs(X, ctx, count, run):
+    """Epochs that never decrease (a program's synchronisation windows), as
+    runs of a fixed length (shifted so that runs cross the 4,096-record
+    chunks), of random lengths up to 4,096, none (one epoch), or with one
+    decrease: epochs of at most 4,096 records are sorted in LDS, anything
+    else takes the radix sort; flags equal the oracle's either way and
+    every partner is valid."""
+    b = W.small_race(count=count, streams=8, epochs=1, seed=W.SEED0 + 40 + count % 97)
+    rng = np.random.default_rng(count)
+    if run is None:
+        ep = None
+    elif run == "random":
+        lengths = rng.integers(1, 4097, size=count)
+        ep = np.repeat(np.arange(count, dtype=np.uint32), lengths)[:count]
+    elif run == "decreasing":
+        ep = (np.arange(count) // 1000).astype(np.uint32)
+        ep[count // 2:] -= 1
+    else:
+        ep = ((np.arange(count) + 2000) // run).astype(np.uint32)
+    want = oracle.race(b.records, b.streams, ep, threads=8)
+    res = gpu_join(X, ctx, b.records, b.streams, ep)
+    check(res, b.records, b.streams, ep, want)
+    assert (res["flags"] & 3).any() or run == 1
+
+
 def test_no_epochs_argument(X, ctx):
     b = W.small_race(count=5000, epochs=1)
     want = oracle.race(b.records, b.streams, None, threads=8)
