@@ -12,9 +12,10 @@
 // is (epoch << 48 | address), so intervals of different epochs never meet.
 // The keys are sorted by the 8-bit LSD radix sort of sort.hip, which skips a
 // pass whose digit is the same in every key.  When the epochs never decrease
-// in record order and no epoch spans more than 4,096 records (a program's
-// synchronisation windows), each epoch's intervals are instead sorted in LDS
-// by one block, in place, and the radix passes all skip.  An interval then meets an
+// in record order, no epoch spans more than 4,096 records and they average
+// at least 256 (a program's synchronisation windows), each epoch's intervals
+// are instead sorted in LDS by one block, in place, and the global passes all
+// skip.  An interval then meets an
 // interval of another stream that starts no later exactly when the furthest
 // end among earlier intervals of other streams lies past its start, and one
 // that starts later exactly when the smallest start among later intervals of
@@ -41,6 +42,9 @@ constexpr int kSweepItems = 8;                   // consecutive elements per thr
 constexpr uint32_t kRunMax = 4096;               // records of one epoch sorted in LDS, at most
 constexpr int kLocalN = 2 * kRunMax;             // their intervals
 constexpr int kLT = 1024;                        // threads of the per-epoch sort
+constexpr int kLWaves = kLT / 64;
+constexpr int kLRounds = kLocalN / kLT;          // elements per thread
+constexpr uint64_t kRunMean = 256;               // records per epoch, on average at least
 constexpr int kSweepTile = kT * kSweepItems;
 static_assert(kT == kSortKeyBlock, "one part of the key mask per block of k_race_keys");
 
@@ -69,7 +73,10 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
 {
     __shared__ uint64_t part[kWaves];
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (i == 0) *flag = 0;
+    if (i == 0) {
+        flag[0] = 0;
+        flag[1] = 0;
+    }
     const uint64_t k0 = interval_key(recs, epochs, 0);
     uint64_t x = 0;
     if (i < m) {
@@ -90,36 +97,54 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
 
 // ---- per-epoch sort --------------------------------------------------------
 
-// *flag becomes non-zero unless the epochs never decrease and no epoch spans
-// more than kRunMax records (without epochs: all records are one epoch).
-// Equal epochs kRunMax records apart mean a longer epoch, since they never
-// decrease.
+// flag[0] becomes non-zero unless the epochs never decrease and no epoch
+// spans more than kRunMax records (equal epochs kRunMax records apart mean a
+// longer one, since they never decrease); flag[1] counts the epochs.  Without
+// epochs all records are one epoch.
 __global__ __launch_bounds__(kT) void k_race_local_check(const uint32_t *epochs, uint64_t count, uint32_t *flag)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    bool bad = false;
+    bool bad = false, start = false;
     if (i < count) {
+        start = i == 0 || (epochs && epochs[i] != epochs[i - 1]);
         if (!epochs) bad = i == 0 && count > kRunMax;
         else bad = (i > 0 && epochs[i] < epochs[i - 1]) || (i >= kRunMax && epochs[i] == epochs[i - kRunMax]);
     }
-    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+    const uint64_t b = __ballot(bad), st = __ballot(start);
+    if ((threadIdx.x & 63) == 0) {
+        if (b) atomicOr(&flag[0], 1u);
+        if (st) atomicAdd(&flag[1], (uint32_t)__popcll(st));
+    }
+}
+
+// the per-epoch path applies: see k_race_local_check
+__device__ __forceinline__ bool local_path(const uint32_t *flag, uint64_t count)
+{
+    return flag[0] == 0 && (uint64_t)flag[1] * kRunMean <= count;
 }
 
 // One block per chunk of kRunMax records sorts, in place, the intervals of
 // every epoch that starts in the chunk (at most kRunMax records, so at most
-// kLocalN intervals): each key is packed with its index in the epoch's run
-// (ties keep interval order, as the radix sort does), sorted by a bitonic
-// network in LDS, and written back with its interval id.  Unchecked intervals
-// go to the end of their epoch's run; the sweep skips them wherever they are.
-// The chunk's parts of the key mask are cleared, so every radix pass skips.
+// kLocalN intervals), by a stable LSD radix sort in LDS with 8-bit digits:
+// each key is packed with its index in the epoch's run, element e of the run
+// sits in wave e / 512, round (e / 64) % 8, lane e % 64, ranks come from
+// ballots as in the global sort, and a pass whose digit is the same in every
+// key is skipped.  Unchecked intervals go to the end of their epoch's run;
+// the sweep skips them wherever they are.  The chunk's parts of the key mask
+// are cleared, so every pass of the global sort skips.
 __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_t *vals, uint64_t *parts,
                                                          uint64_t nparts, const uint32_t *epochs, uint64_t count,
                                                          const uint32_t *flag)
 {
-    __shared__ uint64_t a[kLocalN];
+    __shared__ uint64_t buf[kLocalN];
+    __shared__ uint32_t wrun[kLWaves][256];   // per wave and digit: running count, then prefix over waves
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t wtot[kLWaves];
+    __shared__ uint64_t wor[kLWaves];
     __shared__ uint32_t starts[kRunMax];
     __shared__ uint32_t nstarts, run_len;
-    if (*flag != 0) return;   // the whole grid leaves: the radix sort runs
+    if (!local_path(flag, count)) return;   // the whole grid leaves: the global sort runs
+    const uint32_t w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const uint64_t c0 = (uint64_t)blockIdx.x * kRunMax;
     const uint64_t c1 = c0 + kRunMax < count ? c0 + kRunMax : count;
     // parts cover 128 records each; the chunks tile the records, so every part is cleared once
@@ -133,8 +158,8 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
     }
     __syncthreads();
     const uint32_t ns = nstarts;
-    for (uint32_t k = 0; k < ns; ++k) {
-        const uint64_t s = c0 + starts[k];
+    for (uint32_t r = 0; r < ns; ++r) {
+        const uint64_t s = c0 + starts[r];
         const uint32_t most = (uint32_t)(count - s < kRunMax ? count - s : kRunMax);
         const uint32_t ep = epochs ? epochs[s] : 0u;
         if (threadIdx.x == 0) run_len = most;
@@ -144,36 +169,85 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
                 if (epochs[s + j] != ep) atomicMin(&run_len, j);
         __syncthreads();
         const uint32_t n = 2 * run_len;   // intervals of this epoch
-        uint32_t P = 2;
-        while (P < n) P <<= 1;
         const uint64_t i0 = 2 * s;
-        for (uint32_t l = threadIdx.x; l < P; l += kLT) {
-            uint64_t v = ~0ull;
-            if (l < n) {
-                const uint64_t key = keys[i0 + l];
-                const uint64_t v49 = (key >> 63) ? (1ull << 48) : (key & ((1ull << 48) - 1));
-                v = (v49 << 13) | l;
-            }
-            a[l] = v;
+        auto pack = [&](uint32_t e) {
+            const uint64_t key = keys[i0 + e];
+            const uint64_t v49 = (key >> 63) ? (1ull << 48) : (key & ((1ull << 48) - 1));
+            return (v49 << 13) | e;
+        };
+        const uint64_t k0 = pack(0);
+        uint64_t k[kLRounds];
+        uint64_t x = 0;
+#pragma unroll
+        for (int i = 0; i < kLRounds; ++i) {
+            const uint32_t e = w * 512 + i * 64 + l;
+            k[i] = e < n ? pack(e) : ~0ull;
+            if (e < n) x |= k[i] ^ k0;
         }
+        for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+        if (l == 0) wor[w] = x;
         __syncthreads();
-        for (uint32_t q = 2; q <= P; q <<= 1)
-            for (uint32_t j = q >> 1; j > 0; j >>= 1) {
-                for (uint32_t t = threadIdx.x; t < P / 2; t += kLT) {
-                    const uint32_t x = ((t & ~(j - 1)) << 1) | (t & (j - 1)), y = x + j;
-                    const uint64_t u = a[x], v = a[y];
-                    if ((u > v) == ((x & q) == 0)) {
-                        a[x] = v;
-                        a[y] = u;
-                    }
-                }
-                __syncthreads();
+        uint64_t live = 0;
+        for (int j = 0; j < kLWaves; ++j) live |= wor[j];
+        for (int sh = 13; sh < 64; sh += 8) {
+            if (((live >> sh) & 0xFFu) == 0) continue;   // the same digit everywhere: skip the pass
+            for (int j = threadIdx.x; j < kLWaves * 256; j += kLT) (&wrun[0][0])[j] = 0;
+            __syncthreads();
+            uint32_t pk[kLRounds];
+#pragma unroll
+            for (int i = 0; i < kLRounds; ++i) {
+                const bool valid = w * 512 + i * 64 + l < n;
+                const uint32_t d = (uint32_t)(k[i] >> sh) & 0xFFu;
+                const uint64_t peers = match8(d, valid);
+                const uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
+                uint32_t run = 0;
+                if (valid) run = wrun[w][d];
+                if (valid && rank == 0) wrun[w][d] = run + (uint32_t)__popcll(peers);
+                pk[i] = valid ? (d << 16) | (run + rank) : 0xFFFFFFFFu;
             }
-        for (uint32_t j = threadIdx.x; j < n; j += kLT) {
-            const uint64_t v = a[j];
-            const uint64_t v49 = v >> 13;
-            keys[i0 + j] = (v49 >> 48) ? kInvalidKey : (((uint64_t)ep << 48) | v49);
-            vals[i0 + j] = (uint32_t)(i0 + (v & (kLocalN - 1)));
+            __syncthreads();
+            uint32_t tot = 0;
+            if (threadIdx.x < 256)
+                for (int j = 0; j < kLWaves; ++j) {
+                    const uint32_t c = wrun[j][threadIdx.x];
+                    wrun[j][threadIdx.x] = tot;
+                    tot += c;
+                }
+            uint32_t inc = tot;
+            for (uint32_t d = 1; d < 64u; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d);
+                if (l >= d) inc += y;
+            }
+            if (threadIdx.x < 256 && l == 63) wtot[w] = inc;
+            __syncthreads();
+            if (threadIdx.x < 256) {
+                uint32_t off = 0;
+                for (uint32_t j = 0; j < w; ++j) off += wtot[j];
+                dstart[threadIdx.x] = off + inc - tot;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kLRounds; ++i)
+                if (pk[i] != 0xFFFFFFFFu) {
+                    const uint32_t d = pk[i] >> 16;
+                    buf[dstart[d] + wrun[w][d] + (pk[i] & 0xFFFFu)] = k[i];
+                }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kLRounds; ++i) {
+                const uint32_t e = w * 512 + i * 64 + l;
+                if (e < n) k[i] = buf[e];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kLRounds; ++i) {
+            const uint32_t e = w * 512 + i * 64 + l;
+            if (e < n) {
+                const uint64_t v49 = k[i] >> 13;
+                keys[i0 + e] = (v49 >> 48) ? kInvalidKey : (((uint64_t)ep << 48) | v49);
+                vals[i0 + e] = (uint32_t)(i0 + (k[i] & (kLocalN - 1)));
+            }
         }
         __syncthreads();
     }

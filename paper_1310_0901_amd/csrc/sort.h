@@ -35,6 +35,21 @@ void sort_release(SortWs &w);
 // parts (0 for blocks past the keys).
 hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev = nullptr);
 
+// lanes of the wave whose valid 8-bit digit equals this lane's (8 ballots)
+__device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t y = __ballot(bit);
+        m &= bit ? y : ~y;
+    }
+    return valid ? m : 0ull;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
+
 // a pass over key byte `pass` is skipped when that byte is the same in every key
 __device__ __forceinline__ bool sort_pass_live(uint64_t mask, int pass) { return ((mask >> (8 * pass)) & 0xFFu) != 0; }
 

@@ -37,20 +37,6 @@ __global__ __launch_bounds__(kT) void k_sort_mask(const uint64_t *parts, uint32_
 
 // ---- radix sort ----------------------------------------------------------
 
-// lanes of the wave whose valid digit equals this lane's
-__device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
-{
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t y = __ballot(bit);
-        m &= bit ? y : ~y;
-    }
-    return valid ? m : 0ull;
-}
-
-__device__ __forceinline__ uint64_t lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
 // keys to sort: mcap, or the count held in device memory when there is one
 // (never above mcap)
