@@ -650,7 +650,11 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
     hipLaunchKernelGGL(k_race_local_check, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, epochs, count, w.flag);
     hipLaunchKernelGGL(k_race_local_sort, dim3((uint32_t)ceil_div(count, kRunMax)), dim3(kLT), 0, s, q.keys[0],
                        q.vals[0], q.parts, ceil_div(m, kT), epochs, count, w.flag);
-    hipError_t e = sort_pairs(q, m, s);
+    // without epochs, a batch of kRunMean to kRunMax records is one epoch that
+    // the per-epoch sort takes (as the device decides too): the global passes
+    // would all return at once, so they are not launched
+    const bool one_local_epoch = !epochs && count <= kRunMax && count >= kRunMean;
+    hipError_t e = one_local_epoch ? sort_mask_only(q, m, s) : sort_pairs(q, m, s);
     if (e != hipSuccess) return e;
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
     hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0],

@@ -35,6 +35,10 @@ void sort_release(SortWs &w);
 // parts (0 for blocks past the keys).
 hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev = nullptr);
 
+// Only the key-bit mask of n keys (from the parts), for pairs already in
+// order in keys[0] / vals[0] whose parts were cleared: no pass runs.
+hipError_t sort_mask_only(SortWs &w, uint64_t n, hipStream_t s);
+
 // lanes of the wave whose valid 8-bit digit equals this lane's (8 ballots)
 __device__ __forceinline__ uint64_t match8(uint32_t d, bool valid)
 {

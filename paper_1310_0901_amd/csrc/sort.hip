@@ -244,6 +244,13 @@ void sort_release(SortWs &w)
     w = SortWs{};
 }
 
+hipError_t sort_mask_only(SortWs &w, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_mask, dim3(1), dim3(kT), 0, s, w.parts, (uint32_t)ceil_div(n, kT), w.mask);
+    return hipGetLastError();
+}
+
 hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev)
 {
     if (n == 0) return hipSuccess;
