@@ -149,6 +149,22 @@ def test_epoch_runs(X, ctx, count, run):
     assert (res["flags"] & 3).any() or run == 1
 
 
+def test_epoch_runs_with_unchecked_epochs(X, ctx):
+    """The per-epoch path with epochs at and above 2^15 in the second half
+    (those records are unchecked: their intervals carry the invalid key and
+    end up at the end of their epoch's run)."""
+    count = 12_000
+    b = W.small_race(count=count, streams=4, epochs=1, seed=W.SEED0 + 77)
+    ep = (np.arange(count) // 1000).astype(np.uint32)
+    ep[count // 2:] += (1 << 15) - 6
+    want = oracle.race(b.records, b.streams, ep, threads=8)
+    res = gpu_join(X, ctx, b.records, b.streams, ep)
+    check(res, b.records, b.streams, ep, want)
+    late = np.arange(count) >= count // 2
+    assert (res["flags"][late & (b.records["n"] > 0)] == X.CG_RACE_UNCHECKED).all()   # empty records are checked
+    assert (res["flags"][: count // 2] & 3).any()
+
+
 def test_no_epochs_argument(X, ctx):
     b = W.small_race(count=5000, epochs=1)
     want = oracle.race(b.records, b.streams, None, threads=8)
