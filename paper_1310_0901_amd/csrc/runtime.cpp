@@ -33,6 +33,10 @@ constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
 constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
 constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
+// launch shape for checks of mostly short pitched rows (measured on 4 KiB and
+// 512-byte rows: 20-26 % faster than the shapes tuned for long transfers)
+constexpr cg_tuning kShortRowTuning = {256, 2, 16, 1u << 16, 0, {0, 0, 0}};
+
 // largest batch worked as segments: its 3 * count positions take 96-byte
 // descriptors (about 40 GB at this size); larger batches keep their order
 constexpr uint64_t kSegMaxRecords = 1ull << 27;
@@ -100,7 +104,7 @@ struct TableVersion {
 // Row expansion of pitched 2D copies on one stream.
 struct StridedWs {
     uint64_t rec_cap = 0, row_cap = 0;
-    uint64_t *first = nullptr, *bsum = nullptr, *total = nullptr, *h_total = nullptr;
+    uint64_t *first = nullptr, *bsum = nullptr, *bshort = nullptr, *total = nullptr, *h_total = nullptr;
     cg_transfer *rows = nullptr;
     uint32_t *rec_of = nullptr;
     cg_verdict *rowv = nullptr;
@@ -864,6 +868,7 @@ int cg_destroy(cg_ctx *c)
         StridedWs &w = kv.second;
         (void)hipFree(w.first);
         (void)hipFree(w.bsum);
+        (void)hipFree(w.bshort);
         (void)hipFree(w.total);
         (void)hipFree(w.rows);
         (void)hipFree(w.rec_of);
@@ -1064,20 +1069,22 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
         HIPTRY(c, hipStreamSynchronize(s));
         (void)hipFree(w.first);
         (void)hipFree(w.bsum);
-        w.first = w.bsum = nullptr;
+        (void)hipFree(w.bshort);
+        w.first = w.bsum = w.bshort = nullptr;
         w.rec_cap = 0;
         uint64_t cap = 1024;
         while (cap < count) cap <<= 1;
         HIPTRY(c, hipMalloc(&w.first, cap * 8));
         HIPTRY(c, hipMalloc(&w.bsum, (cap / 256 + 1) * 8));
-        if (!w.total) HIPTRY(c, hipMalloc(&w.total, 8));
-        if (!w.h_total) HIPTRY(c, hipHostMalloc(&w.h_total, 8, hipHostMallocDefault));
+        HIPTRY(c, hipMalloc(&w.bshort, (cap / 256 + 1) * 8));
+        if (!w.total) HIPTRY(c, hipMalloc(&w.total, 16));
+        if (!w.h_total) HIPTRY(c, hipHostMalloc(&w.h_total, 16, hipHostMallocDefault));
         w.rec_cap = cap;
     }
-    HIPTRY(c, launch_2d_prefix(recs_dev, count, w.first, w.bsum, w.total, s));
-    HIPTRY(c, hipMemcpyAsync(w.h_total, w.total, 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, launch_2d_prefix(recs_dev, count, w.first, w.bsum, w.bshort, w.total, s));
+    HIPTRY(c, hipMemcpyAsync(w.h_total, w.total, 16, hipMemcpyDeviceToHost, s));
     HIPTRY(c, hipStreamSynchronize(s));
-    const uint64_t nrows = *w.h_total;
+    const uint64_t nrows = w.h_total[0], nshort = w.h_total[1];
     if (nrows > (1ull << 32) - 1024) return fail(c, CG_EINVAL, "at most 2^32 - 1024 rows per call");
     if (nrows) {
         if (w.row_cap < nrows) {
@@ -1099,8 +1106,11 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
         // the rows keep their order (each record's rows ascend in memory):
         // cutting millions of short rows into source-block segments costs
         // more than the cache reuse it could bring
-        const int rc = run_check(c, w.rows, nrows, (mode & CG_CHECK) ? w.rowv : nullptr, mode | CG_KEEP_ORDER, s,
-                                 (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
+        // mostly short rows (16 KiB or less) are checked with more waves in
+        // flight and a shorter loop: their work per row is latency, not bytes
+        cg_tuning tun = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
+        if (!(mode & CG_PROPAGATE) && 2 * nshort >= nrows) tun = kShortRowTuning;
+        const int rc = run_check(c, w.rows, nrows, (mode & CG_CHECK) ? w.rowv : nullptr, mode | CG_KEEP_ORDER, s, tun);
         if (rc) return rc;
     }
     if (mode & CG_CHECK) HIPTRY(c, launch_2d_fold(recs_dev, w.first, count, w.rec_of, w.rowv, nrows, out_dev, s));

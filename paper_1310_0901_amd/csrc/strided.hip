@@ -6,8 +6,9 @@
 // rows' flags, the smallest r*width + first_bad_r, the sum of undefined bytes
 // and the first row's avail.
 //
-//   k2d_count   per block: exclusive scan of the records' row counts
-//   k2d_sums    one block: exclusive scan of the block sums; the total
+//   k2d_count   per block: exclusive scan of the records' row counts, and the
+//               rows of records with short rows (a launch-shape choice)
+//   k2d_sums    one block: exclusive scan of the block sums; the totals
 //   k2d_add     block offsets added: first row of every record
 //   k2d_expand  one lane per row: its record (binary search in the first
 //               rows), its transfer record
@@ -23,15 +24,37 @@ namespace {
 
 constexpr int kT = 256;
 
-__device__ __forceinline__ uint64_t rows_of(const cg_transfer2d &r) { return r.width ? r.rows : 0; }
+constexpr uint64_t kShortRow = 16384;   // bytes: rows this wide or less are short
+
+// a record's rows, at most 2^32 (the sum over 2^31 records cannot wrap, and a
+// batch with a record this tall is refused for too many rows)
+__device__ __forceinline__ uint64_t rows_of(const cg_transfer2d &r)
+{
+    return r.width ? (r.rows < (1ull << 32) ? r.rows : (1ull << 32)) : 0;
+}
+
+// block sum of x over the kT threads
+__device__ __forceinline__ uint64_t block_sum(uint64_t x)
+{
+    __shared__ uint64_t part[kT / 64];
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint64_t t = 0;
+    for (int k = 0; k < kT / 64; ++k) t += part[k];
+    return t;
+}
 
 __global__ void __launch_bounds__(kT) k2d_count(const cg_transfer2d *recs, uint64_t count, uint64_t *first,
-                                                uint64_t *bsum)
+                                                uint64_t *bsum, uint64_t *bshort)
 {
     __shared__ uint64_t wsum[kT / 64];
     const uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t c = t < count ? rows_of(recs[t]) : 0;
+    const cg_transfer2d r = t < count ? recs[t] : cg_transfer2d{};
+    const uint64_t c = t < count ? rows_of(r) : 0;
+    const uint64_t sh = block_sum(r.width <= kShortRow ? c : 0);
+    if (threadIdx.x == 0) bshort[blockIdx.x] = sh;
     uint64_t x = c;
     for (uint32_t d = 1; d < 64; d <<= 1) {
         const uint64_t y = __shfl_up(x, d);
@@ -45,14 +68,19 @@ __global__ void __launch_bounds__(kT) k2d_count(const cg_transfer2d *recs, uint6
     if (threadIdx.x == kT - 1) bsum[blockIdx.x] = off + x;
 }
 
-__global__ void __launch_bounds__(1024) k2d_sums(uint64_t *bsum, uint64_t nb, uint64_t *total)
+__global__ void __launch_bounds__(1024) k2d_sums(uint64_t *bsum, const uint64_t *bshort, uint64_t nb, uint64_t *total)
 {
-    __shared__ uint64_t wsum[16];
+    __shared__ uint64_t wsum[16], ssum[16];
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t per = (nb + 1023) / 1024;
     const uint64_t b0 = tid * per < nb ? tid * per : nb, b1 = b0 + per < nb ? b0 + per : nb;
-    uint64_t s = 0;
-    for (uint64_t b = b0; b < b1; ++b) s += bsum[b];
+    uint64_t s = 0, sh = 0;
+    for (uint64_t b = b0; b < b1; ++b) {
+        s += bsum[b];
+        sh += bshort[b];
+    }
+    for (int d = 32; d >= 1; d >>= 1) sh += __shfl_xor(sh, d);
+    if (lane == 0) ssum[w] = sh;
     uint64_t x = s;
     for (uint32_t d = 1; d < 64; d <<= 1) {
         const uint64_t y = __shfl_up(x, d);
@@ -68,7 +96,12 @@ __global__ void __launch_bounds__(1024) k2d_sums(uint64_t *bsum, uint64_t nb, ui
         bsum[b] = run;
         run += v;
     }
-    if (tid == 1023) *total = off + x;
+    if (tid == 1023) {
+        total[0] = off + x;
+        uint64_t t = 0;
+        for (int k = 0; k < 16; ++k) t += ssum[k];
+        total[1] = t;   // rows of records with short rows
+    }
 }
 
 __global__ void __launch_bounds__(kT) k2d_add(uint64_t *first, const uint64_t *boff, uint64_t count)
@@ -149,11 +182,11 @@ uint32_t grid_for(uint64_t n, uint64_t cap)
 }  // namespace
 
 hipError_t launch_2d_prefix(const cg_transfer2d *recs, uint64_t count, uint64_t *first, uint64_t *bsum,
-                            uint64_t *total, hipStream_t s)
+                            uint64_t *bshort, uint64_t *total, hipStream_t s)
 {
     const uint64_t nb = (count + kT - 1) / kT;
-    hipLaunchKernelGGL(k2d_count, dim3((uint32_t)nb), dim3(kT), 0, s, recs, count, first, bsum);
-    hipLaunchKernelGGL(k2d_sums, dim3(1), dim3(1024), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL(k2d_count, dim3((uint32_t)nb), dim3(kT), 0, s, recs, count, first, bsum, bshort);
+    hipLaunchKernelGGL(k2d_sums, dim3(1), dim3(1024), 0, s, bsum, bshort, nb, total);
     hipLaunchKernelGGL(k2d_add, dim3((uint32_t)nb), dim3(kT), 0, s, first, bsum, count);
     return hipGetLastError();
 }

@@ -160,7 +160,7 @@ hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
 struct SortWs;
 hipError_t launch_segments(const SegArgs &g, SortWs &sort, const BatchArgs &ap, uint32_t *perm, hipStream_t s);
 hipError_t launch_2d_prefix(const cg_transfer2d *recs, uint64_t count, uint64_t *first, uint64_t *bsum,
-                            uint64_t *total, hipStream_t s);
+                            uint64_t *bshort, uint64_t *total, hipStream_t s);
 hipError_t launch_2d_expand(const cg_transfer2d *recs, const uint64_t *first, uint64_t count, uint64_t nrows,
                             cg_transfer *rows, uint32_t *rec_of, hipStream_t s);
 hipError_t launch_2d_fold(const cg_transfer2d *recs, const uint64_t *first, uint64_t count, const uint32_t *rec_of,
