@@ -156,6 +156,17 @@ def test_no_rows_and_errors(X, H):
         with pytest.raises(X.CgError) as e:
             X.check_transfers_2d(dw.ctx, 0, 1, 16, X.CG_CHECK, 0)
         assert e.value.status == X.CG_EINVAL
+        # too many rows, also when the row counts would wrap a 64-bit sum
+        for tall in ([(1 << 64) - 1], [1 << 63, 1 << 63], [1 << 33]):
+            t = np.zeros(len(tall), W.RECORD2D_DTYPE)
+            for i, r in enumerate(tall):
+                t[i] = (W.HOST_BASE, int(bases[0]), 1, r, 1, 1, 0, (0, 0, 0))
+            tt = torch.from_numpy(t.view(np.uint8).copy()).to("cuda:0")
+            vo = torch.zeros(len(tall) * 32, dtype=torch.uint8, device="cuda:0")
+            with pytest.raises(X.CgError) as e:
+                X.check_transfers_2d(dw.ctx, tt.data_ptr(), len(tall), vo.data_ptr(), X.CG_CHECK,
+                                     torch.cuda.current_stream().cuda_stream)
+            assert e.value.status == X.CG_EINVAL, tall
         with pytest.raises(X.CgError) as e:
             X.check_transfers_2d(dw.ctx, 16, 1, 16, 0, 0)
         assert e.value.status == X.CG_EINVAL
