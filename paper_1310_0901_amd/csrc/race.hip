@@ -131,10 +131,13 @@ __device__ __forceinline__ bool local_path(const uint32_t *flag, uint64_t count)
 // ballots as in the global sort, and a pass whose digit is the same in every
 // key is skipped.  Unchecked intervals go to the end of their epoch's run;
 // the sweep skips them wherever they are.  The chunk's parts of the key mask
-// are cleared, so every pass of the global sort skips.
-__global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_t *vals, uint64_t *parts,
-                                                         uint64_t nparts, const uint32_t *epochs, uint64_t count,
-                                                         const uint32_t *flag)
+// are cleared, so every pass of the global sort skips.  The write-back also
+// puts each interval's end key and stream into the spare buffers (ends,
+// strm), which k_race_gather fills on the global path.
+__global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_t *vals, uint64_t *ends,
+                                                         uint32_t *strm, uint64_t *parts, uint64_t nparts,
+                                                         const cg_transfer *recs, const uint32_t *streams,
+                                                         const uint32_t *epochs, uint64_t count, const uint32_t *flag)
 {
     __shared__ uint64_t buf[kLocalN];
     __shared__ uint32_t wrun[kLWaves][256];   // per wave and digit: running count, then prefix over waves
@@ -245,8 +248,13 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
             const uint32_t e = w * 512 + i * 64 + l;
             if (e < n) {
                 const uint64_t v49 = k[i] >> 13;
-                keys[i0 + e] = (v49 >> 48) ? kInvalidKey : (((uint64_t)ep << 48) | v49);
-                vals[i0 + e] = (uint32_t)(i0 + (k[i] & (kLocalN - 1)));
+                const uint64_t iv = i0 + (k[i] & (kLocalN - 1));
+                const bool valid = !(v49 >> 48);
+                const uint64_t key = valid ? (((uint64_t)ep << 48) | v49) : kInvalidKey;
+                keys[i0 + e] = key;
+                vals[i0 + e] = (uint32_t)iv;
+                ends[i0 + e] = valid ? key + recs[iv >> 1].n : 0;
+                strm[i0 + e] = valid ? streams[iv >> 1] : kNoStream;
             }
         }
         __syncthreads();
@@ -410,10 +418,11 @@ __device__ __forceinline__ Elem load_elem(const Sorted &o, uint64_t p, uint64_t 
 // buffers that do not hold the sorted order
 __global__ __launch_bounds__(kT) void k_race_gather(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
                                                     const uint64_t *maskp, const cg_transfer *recs,
-                                                    const uint32_t *streams, uint64_t m)
+                                                    const uint32_t *streams, uint64_t m, const uint32_t *flag,
+                                                    uint64_t count)
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (p >= m) return;
+    if (p >= m || local_path(flag, count)) return;   // the per-epoch sort wrote them
     const bool b = sort_parity(*maskp) != 0;
     const uint64_t k = (b ? kb : ka)[p];
     const uint32_t iv = (b ? vb : va)[p];
@@ -649,7 +658,7 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
                        q.vals[0], q.parts, w.flag);
     hipLaunchKernelGGL(k_race_local_check, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, epochs, count, w.flag);
     hipLaunchKernelGGL(k_race_local_sort, dim3((uint32_t)ceil_div(count, kRunMax)), dim3(kLT), 0, s, q.keys[0],
-                       q.vals[0], q.parts, ceil_div(m, kT), epochs, count, w.flag);
+                       q.vals[0], q.keys[1], q.vals[1], q.parts, ceil_div(m, kT), recs, streams, epochs, count, w.flag);
     // without epochs, a batch of kRunMean to kRunMax records is one epoch that
     // the per-epoch sort takes (as the device decides too): the global passes
     // would all return at once, so they are not launched
@@ -658,7 +667,7 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
     if (e != hipSuccess) return e;
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
     hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0],
-                       q.vals[1], q.mask, recs, streams, m);
+                       q.vals[1], q.mask, recs, streams, m, w.flag, count);
     hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1],
                        q.mask, m, agg);
     hipLaunchKernelGGL(k_race_sweep_scan, dim3(1), dim3(kT), 0, s, agg, sweeps, pre);
