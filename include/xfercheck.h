@@ -222,7 +222,10 @@ typedef struct cg_transfer2d {
  * smallest r*width + first_bad_r, undef_bytes = sum, avail = the first row's
  * (bytes from src / dst to the end of its allocation).  A record with no
  * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers, except
- * that the rows are always worked in their order (CG_KEEP_ORDER).  The
+ * that the rows are always worked in their order (CG_KEEP_ORDER), and that a
+ * check without CG_PROPAGATE whose rows are mostly 16 KiB wide or less runs
+ * with a fixed launch shape (256-thread blocks, unroll 2, 16 blocks per CU)
+ * instead of the context's tuning.  The
  * call waits for the caller's stream once, to learn the number of rows
  * (at most 2^32 - 1024 in total).  Errors: as check_transfers, and CG_EINVAL for
  * 2^31 records or more, or too many rows.
