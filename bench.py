@@ -281,11 +281,13 @@ def serving_leg(plain_seconds):
            "admission_cap_bytes": 16 << 30}
     dw = S.serve_world(sw, host_arrays=(hv, ha))
     try:
-        cfg = S.config(streams=4, max_batch=512)
+        # micro-batches hold 2-3 requests on average at this load: padding them to
+        # 64 records rather than 512 cuts the p50 by about a third
+        cfg = S.config(streams=4, max_batch=64)
         res, summ = S.run(dw, sw, cfg)
     finally:
         dw.close()
-    out["batched"] = dict(summ, streams=4, max_batch=512)
+    out["batched"] = dict(summ, streams=4, max_batch=64)
     log(f"[bench] serving batched: {summ}")
     # plain path on the first `plain_seconds` of the same log (it cannot keep up
     # with the full offered load), and the batched loop on the same prefix

@@ -1426,11 +1426,22 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
     uint64_t nreq = 0;
     for (uint64_t i = 0; i < n; ++i) ridx[i] = ev[i].type == CG_EV_CHECK ? nreq++ : ~0ull;
 
+    // Completion times are GPU event times after ev0; arrival times are host
+    // times after T0.  Every slot stream has run a command before (so no
+    // first-use set-up delays ev0), and T0 is taken once the device has
+    // executed ev0: the device clock cannot start after the host clock, and
+    // a latency is at most overstated by the few microseconds of that wait.
+    for (auto &sl : slots)
+        if (hipEventRecord(sl.done, sl.s) != hipSuccess || hipEventSynchronize(sl.done) != hipSuccess)
+            return bail(fail(c, CG_EHIP, "serve: stream warm-up"));
     hipEvent_t ev0;
     if (hipEventCreate(&ev0) != hipSuccess) return bail(fail(c, CG_EHIP, "serve: event"));
     using clk = std::chrono::steady_clock;
+    if (hipEventRecord(ev0, slots[0].s) != hipSuccess || hipEventSynchronize(ev0) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return bail(fail(c, CG_EHIP, "serve: clock start"));
+    }
     const auto T0 = clk::now();
-    if (hipEventRecord(ev0, slots[0].s) != hipSuccess) { (void)hipEventDestroy(ev0); return bail(CG_EHIP); }
     auto now = [&] { return std::chrono::duration<double>(clk::now() - T0).count(); };
 
     std::deque<uint64_t> fifo;
