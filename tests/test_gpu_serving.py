@@ -53,3 +53,10 @@ def test_serving_mix_alone_and_oracle(S):
     big = float(np.max(sw.requests["n"]) * 1.125)
     assert runs["capped"][1]["max_inflight_GB"] * 1e9 <= max(4 << 20, big) + 1
     assert runs["mix"][1]["mean_batch"] >= 1.0
+    # latencies of the open-loop runs, several in this process: a completion
+    # never comes before its scheduled arrival (the device clock starts no
+    # later than the host clock)
+    for name in ("mix", "alone", "plain", "capped"):
+        res = runs[name][0]
+        lat = res["t_done"] - res["t_arrive"]
+        assert np.isfinite(lat).all() and (lat >= 0).all(), name
