@@ -1306,6 +1306,20 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
             for (uint32_t bpc : {1u, 2u, 4u, 8u}) { cg_tuning t = cur; t.block = b; t.blocks_per_cu = bpc; cands.push_back(t); }
         rc = try_set(cands);
     }
+    if (!rc) {
+        // batches of short records are per-record latency: many waves with a
+        // short loop can beat deep unrolling (measured on 4 KiB rows: -20 %)
+        cands.clear();
+        for (uint32_t u : {1u, 2u})
+            for (uint32_t bpc : {8u, 16u}) {
+                cg_tuning t = cur;
+                t.block = 256;
+                t.unroll = u;
+                t.blocks_per_cu = bpc;
+                cands.push_back(t);
+            }
+        rc = try_set(cands);
+    }
     c->timing = was_timing;
     if (rc) return rc;
     target = cur;
