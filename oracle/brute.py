@@ -136,18 +136,24 @@ def race_flags(rows, streams, epochs=None):
     one of its bytes is also written (for its reads) or read or written (for
     its writes) by a record of another stream in the same epoch.  rows are
     (kind, src, dst, n) tuples as in run_snapshot; flags use 1 = source,
-    2 = destination, 4 = not checked (see oracle.c for the reading)."""
+    2 = destination, 4 = not checked (see oracle.c for the reading).
+
+    Ranges are sets of integers (they may run past 2^64).  So that ranges of
+    any length can be enumerated, the bytes are taken piece by piece: between
+    two consecutive range ends every byte lies in the same ranges, so one byte
+    per piece stands for all of them."""
     epochs = epochs or [0] * len(rows)
-    unchecked = set()
+    unchecked = {t for t, row in enumerate(rows) if row[0] > 2}
+    cuts = sorted({x for t, (kind, src, dst, n) in enumerate(rows) if t not in unchecked
+                   for x in (src, src + n, dst, dst + n)})
     touched = {}
     for t, (kind, src, dst, n) in enumerate(rows):
-        if kind > 2 or (n > 0 and (src + n > 1 << 48 or dst + n > 1 << 48 or epochs[t] >= 1 << 15)):
-            unchecked.add(t)
+        if t in unchecked:
             continue
-        for x in range(src, src + n):
-            touched.setdefault(x, []).append((t, "r"))
-        for x in range(dst, dst + n):
-            touched.setdefault(x, []).append((t, "w"))
+        for lo, hi, how in ((src, src + n, "r"), (dst, dst + n, "w")):
+            for x in cuts:
+                if lo <= x < hi:   # x starts a piece that lies inside [lo, hi)
+                    touched.setdefault(x, []).append((t, how))
     flags = [4 if t in unchecked else 0 for t in range(len(rows))]
     for x, acc in touched.items():
         for t, how in acc:

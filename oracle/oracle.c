@@ -220,23 +220,16 @@ int oracle_run(uint64_t hb, uint64_t hl, uint8_t *hv, const uint64_t *ha,
  *     conflict);
  *   - flags of a: RACE_SRC when R_a meets W_b of a conflicting b, RACE_DST
  *     when W_a meets W_b or R_b of a conflicting b;
- *   - a record is not checked (RACE_UNCHECKED, and it meets nothing) when
- *     its kind is not 0, 1 or 2, or when n > 0 and src + n or dst + n
- *     exceeds 2^48 or its epoch is 2^15 or more.  n == 0 touches no byte.
+ *   - byte ranges are sets of integers: [src, src + n) never wraps, even
+ *     where src + n exceeds 2^64; any 32-bit epoch and any address count;
+ *   - a record whose kind is not 0, 1 or 2 names no ranges: it is not
+ *     checked (RACE_UNCHECKED) and meets nothing.  n == 0 touches no byte.
  * Each requested record is compared with every other record, one pair at a
  * time.
  */
 enum { OR_RACE_SRC = 1u, OR_RACE_DST = 2u, OR_RACE_UNCHECKED = 4u };
-#define OR_ADDR_LIMIT (1ull << 48)
-#define OR_EPOCH_LIMIT (1u << 15)
 
-static int race_unchecked(const or_record *r, uint32_t epoch)
-{
-    if (r->kind > OR_D2D) return 1;
-    if (r->n == 0) return 0;
-    if ((wide)r->src + r->n > OR_ADDR_LIMIT || (wide)r->dst + r->n > OR_ADDR_LIMIT) return 1;
-    return epoch >= OR_EPOCH_LIMIT;
-}
+static int race_unchecked(const or_record *r) { return r->kind > OR_D2D; }
 
 /* do [a, a + na) and [b, b + nb) share a byte? */
 static int meets(uint64_t a, uint64_t na, uint64_t b, uint64_t nb)
@@ -253,7 +246,7 @@ void oracle_race(uint64_t count, const or_record *recs, const uint32_t *streams,
         const or_record *ra = &recs[a];
         uint32_t ea = epochs ? epochs[a] : 0;
         uint32_t f = 0;
-        if (race_unchecked(ra, ea)) {
+        if (race_unchecked(ra)) {
             flags[k] = OR_RACE_UNCHECKED;
             continue;
         }
@@ -261,7 +254,7 @@ void oracle_race(uint64_t count, const or_record *recs, const uint32_t *streams,
             if (b == a) continue;
             const or_record *rb = &recs[b];
             uint32_t eb = epochs ? epochs[b] : 0;
-            if (race_unchecked(rb, eb)) continue;
+            if (race_unchecked(rb)) continue;
             if (eb != ea || streams[b] == streams[a]) continue;
             if (meets(ra->dst, ra->n, rb->dst, rb->n) || meets(ra->dst, ra->n, rb->src, rb->n))
                 f |= OR_RACE_DST;

@@ -25,7 +25,6 @@ MODE_CHECK, MODE_PROPAGATE = 1, 2
 RACE_SRC, RACE_DST, RACE_UNCHECKED = 1, 2, 4
 PTR_UNALLOC = 1
 PTR = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("base", "<u8"), ("avail", "<u8")])
-ADDR_LIMIT, EPOCH_LIMIT = 1 << 48, 1 << 15
 REC = np.dtype([("src", "<u8"), ("dst", "<u8"), ("n", "<u8"), ("kind", "<u4"), ("reserved", "<u4")])
 VER = np.dtype([("flags", "<u4"), ("reserved", "<u4"), ("first_bad", "<u8"),
                 ("undef_bytes", "<u8"), ("avail", "<u8")])
@@ -209,17 +208,13 @@ def conflict(ra, rb, sa, sb, ea=0, eb=0):
     a's written bytes meet b's read or written bytes, and whether a's read
     bytes meet b's written bytes, when the two are unordered (different
     streams, same epoch) and both are checked.  One pair, by definition."""
-    def checked(r, e):
-        if int(r["kind"]) > 2:
-            return False
-        n = int(r["n"])
-        return n == 0 or (int(r["src"]) + n <= ADDR_LIMIT and int(r["dst"]) + n <= ADDR_LIMIT
-                          and int(e) < EPOCH_LIMIT)
+    def checked(r):
+        return int(r["kind"]) <= 2
 
     def meets(a, na, b, nb):
         return na > 0 and nb > 0 and a < b + nb and b < a + na
 
-    if not (checked(ra, ea) and checked(rb, eb)) or int(ea) != int(eb) or int(sa) == int(sb):
+    if not (checked(ra) and checked(rb)) or int(ea) != int(eb) or int(sa) == int(sb):
         return False, False
     n_a, n_b = int(ra["n"]), int(rb["n"])
     dst = meets(int(ra["dst"]), n_a, int(rb["dst"]), n_b) or meets(int(ra["dst"]), n_a, int(rb["src"]), n_b)

@@ -32,9 +32,13 @@ MUTANTS = {
                                   "if (meets(ra->src, ra->n, rb->dst, rb->n) || meets(ra->src, ra->n, rb->src, rb->n))"),
     "race ranges end inclusive": ("(wide)a < (wide)b + nb && (wide)b < (wide)a + na",
                                   "(wide)a <= (wide)b + nb && (wide)b <= (wide)a + na"),
-    "race address limit inclusive": ("(wide)r->src + r->n > OR_ADDR_LIMIT || (wide)r->dst + r->n > OR_ADDR_LIMIT",
-                                     "(wide)r->src + r->n >= OR_ADDR_LIMIT || (wide)r->dst + r->n >= OR_ADDR_LIMIT"),
-    "unchecked records still meet": ("            if (race_unchecked(rb, eb)) continue;\n", ""),
+    "race ranges wrap at 2^64": ("(wide)a < (wide)b + nb && (wide)b < (wide)a + na", "a < b + nb && b < a + na"),
+    "race epochs cut to 15 bits": ("if (eb != ea || streams[b] == streams[a]) continue;",
+                                   "if ((eb & 0x7FFFu) != (ea & 0x7FFFu) || streams[b] == streams[a]) continue;"),
+    "race unchecked above 2^48": ("static int race_unchecked(const or_record *r) { return r->kind > OR_D2D; }",
+                                  "static int race_unchecked(const or_record *r) { return r->kind > OR_D2D || "
+                                  "(r->n && (wide)r->dst + r->n > ((wide)1 << 48)); }"),
+    "unchecked records still meet": ("            if (race_unchecked(rb)) continue;\n", ""),
     "write-write conflicts missed": ("meets(ra->dst, ra->n, rb->dst, rb->n) || ", ""),
     "pointer one past the end rejected": ("            else if ((wide)p == end) past = (int64_t)j;\n", ""),
     "pointer one past wins over holding": ("int64_t j = hold >= 0 ? hold : past;", "int64_t j = past >= 0 ? past : hold;"),

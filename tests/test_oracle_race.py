@@ -12,6 +12,7 @@ D = 0x7000_0000_0000      # a device address
 H = 0x5000_0000           # a host address
 H2D, D2H, D2D = 0, 1, 2
 L48 = 1 << 48
+TOP = 1 << 64       # one past the last address
 
 # (rows (kind, src, dst, n), streams, epochs, expected flags); flags derived by hand
 PINS = [
@@ -35,12 +36,25 @@ PINS = [
     ([(D2H, D, H, 50), (H2D, H + 25, D + 5000, 50)], [3, 4], [7, 7], [2, 1]),
     # bad kind: not checked, and meets nothing
     ([(3, H, D, 100), (H2D, H + 1000, D, 100)], [1, 2], [0, 0], [4, 0]),
-    # address limit: ending exactly at 2^48 is checked, beyond is not
+    # any address: ranges ending at, crossing and lying above 2^48 meet as integers do
     ([(H2D, H, L48 - 100, 100), (H2D, H + 200, L48 - 50, 50)], [1, 2], [0, 0], [2, 2]),
-    ([(H2D, H, L48 - 50, 100), (H2D, H + 200, L48 - 100, 100)], [1, 2], [0, 0], [4, 0]),
-    # epoch limit: 2^15 - 1 is checked, 2^15 is not
+    ([(H2D, H, L48 - 50, 100), (H2D, H + 200, L48 - 100, 100)], [1, 2], [0, 0], [2, 2]),
+    ([(H2D, H, L48 - 50, 50), (D2H, L48, H + 500, 10)], [1, 2], [0, 0], [0, 0]),
+    ([(D2D, 3 * L48, 5 * L48, 64), (D2H, 5 * L48 + 63, H, 1), (H2D, H + 900, 3 * L48 + 64, 8)],
+     [1, 2, 3], [0, 0, 0], [2, 1, 0]),
+    # any 32-bit epoch: only equality matters
     ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [(1 << 15) - 1] * 2, [2, 2]),
-    ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [1 << 15, 1 << 15], [4, 4]),
+    ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [1 << 15, 1 << 15], [2, 2]),
+    ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [(1 << 32) - 1, (1 << 32) - 2], [0, 0]),
+    ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [5, 5 + (1 << 15)], [0, 0]),
+    ([(H2D, H, D, 8), (H2D, H + 8, D, 8)], [1, 2], [7, 7 + (1 << 31)], [0, 0]),
+    ([(H2D, H, D, 8), (H2D, H + 8, D, 8), (D2H, D + 4, H + 100, 2)], [1, 2, 3],
+     [(1 << 32) - 1, (1 << 32) - 1, 1 << 16], [2, 2, 0]),
+    # ranges that run past 2^64 are integer ranges: they meet the top bytes, never address 0
+    ([(D2D, TOP - 300, TOP - 10, 100), (H2D, H, TOP - 1, 1), (H2D, H + 500, 0, 50)], [1, 2, 3], [0, 0, 0],
+     [2, 2, 0]),
+    ([(H2D, H, TOP - 1, TOP - 1), (D2H, TOP - 1, H + 100, 1), (D2H, 0, H + 300, 100)], [1, 2, 3], [0, 0, 0],
+     [3, 3, 2]),
     # zero-length records touch nothing
     ([(H2D, H, D, 0), (H2D, H + 8, D, 8)], [1, 2], [0, 0], [0, 0]),
     # one device copy overlapping itself is no race
@@ -63,11 +77,16 @@ def check_pins(lib=None):
     for seed in range(40):
         rows, st, ep = random_batch(np.random.default_rng(seed), 12)
         assert run_oracle(rows, st, ep, lib=lib) == brute.race_flags(rows, st, ep), f"race brute seed {seed}"
+    for seed in range(12):
+        rows, st, ep = random_batch(np.random.default_rng(seed), 12, **HIGH[seed % len(HIGH)])
+        assert run_oracle(rows, st, ep, lib=lib) == brute.race_flags(rows, st, ep), f"race brute high seed {seed}"
 
 
-def random_batch(rng, count, universe=160, streams=3, epochs=2):
-    """Tiny batch over two small address windows (device at D, host at H)
-    with many overlaps, some bad kinds and zero lengths."""
+def random_batch(rng, count, universe=160, streams=3, epochs=2, dbase=D, hbase=H, epoch0=0):
+    """Tiny batch over two small address windows (device at dbase, host at
+    hbase) with many overlaps, some bad kinds and zero lengths; epochs are
+    epoch0 + 0 .. epochs - 1."""
+    D, H = dbase, hbase
     rows = []
     for _ in range(count):
         kind = int(rng.choice([0, 1, 2, 3], p=[0.35, 0.3, 0.3, 0.05]))
@@ -83,8 +102,15 @@ def random_batch(rng, count, universe=160, streams=3, epochs=2):
         else:
             rows.append((kind, H + h_off, D + d_off, n))
     st = [int(x) for x in rng.integers(0, streams, count)]
-    ep = [int(x) for x in rng.integers(0, epochs, count)]
+    ep = [epoch0 + int(x) for x in rng.integers(0, epochs, count)]
     return rows, st, ep
+
+
+# windows at the top of the key space: device bytes around 2^48 and up to the
+# last address (ranges there run past 2^64), epochs just below 2^32
+HIGH = [dict(dbase=L48 - 80, hbase=H, epoch0=(1 << 15) - 1),
+        dict(dbase=TOP - 200, hbase=L48 - 100, epoch0=(1 << 32) - 3),
+        dict(dbase=TOP - 161, hbase=TOP - 330, epoch0=1 << 31)]
 
 
 @pytest.mark.parametrize("i", range(len(PINS)))
@@ -98,6 +124,13 @@ def test_pin(i):
 def test_oracle_matches_byte_sets(seed):
     rng = np.random.default_rng(1000 + seed)
     rows, st, ep = random_batch(rng, int(rng.integers(1, 20)))
+    assert run_oracle(rows, st, ep) == brute.race_flags(rows, st, ep)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_oracle_matches_byte_sets_high(seed):
+    rng = np.random.default_rng(3000 + seed)
+    rows, st, ep = random_batch(rng, int(rng.integers(1, 20)), epochs=3, **HIGH[seed % len(HIGH)])
     assert run_oracle(rows, st, ep) == brute.race_flags(rows, st, ep)
 
 
