@@ -266,11 +266,13 @@ int cg_stats(cg_ctx *ctx, uint64_t *live_allocs, uint64_t *pool_used);
  * was issued on, epochs[i] the number of synchronising calls made before it.
  * Records on one stream, or in different epochs, are ordered.  Two distinct
  * unordered records conflict when a written range of one meets a read or
- * written range of the other; two reads never conflict.
+ * written range of the other; two reads never conflict.  Every address,
+ * length and epoch is decided: [src, src + n) is a range of integers that
+ * does not wrap past 2^64, and only equality of epochs matters.
  */
 #define CG_RACE_SRC       0x1u  /* the source bytes are written by a conflicting record */
 #define CG_RACE_DST       0x2u  /* the destination bytes are read or written by a conflicting record */
-#define CG_RACE_UNCHECKED 0x4u  /* kind not 0/1/2, or n > 0 with src + n or dst + n > 2^48 or epoch >= 2^15 */
+#define CG_RACE_UNCHECKED 0x4u  /* kind not 0/1/2: the record names no ranges and meets nothing */
 
 /* One result, 16 bytes, in device memory: the flags above, and the index of
  * one record this one conflicts with (CG_NONE when there is none).  When

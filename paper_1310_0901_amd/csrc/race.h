@@ -10,12 +10,14 @@
 namespace xc {
 
 // Device buffers of one join, sized for `cap` intervals (two per record).
-// After the sort, the sort's spare pair of buffers holds each sorted
-// interval's end key and stream.
+// After the sorts, keys/vals hold each sorted interval's epoch and id, the
+// sort's spare pair of buffers its last byte and stream, `first` its first
+// byte.
 struct RaceWs {
     uint64_t cap = 0;
     SortWs sort;
     uint32_t *res = nullptr;                  // per-interval partner (or none)
+    uint64_t *first = nullptr;                // per sorted interval: first byte
     void *agg = nullptr;                      // per sweep tile: 4 monoid aggregates
     void *pre = nullptr;                      // per sweep tile: prefix / suffix of those
     uint32_t *flag = nullptr;                 // 0 when every epoch is sorted in LDS (per-epoch path)

@@ -6,21 +6,24 @@
 // process's one address space, and carries the stream it was issued on and an
 // epoch (the synchronising calls made before it).  Two records conflict when
 // they share the epoch, run on different streams, and a written range of one
-// meets a read or written range of the other.
+// meets a read or written range of the other.  Any 64-bit address, any length
+// and any 32-bit epoch is decided; ranges are integer ranges that do not wrap.
 //
-// The join is an interval sweep.  Every record gives two intervals whose key
-// is (epoch << 48 | address), so intervals of different epochs never meet.
-// The keys are sorted by the 8-bit LSD radix sort of sort.hip, which skips a
-// pass whose digit is the same in every key.  When the epochs never decrease
-// in record order, no epoch spans more than 4,096 records and they average
-// at least 256 (a program's synchronisation windows), each epoch's intervals
-// are instead sorted in LDS by one block, in place, and the global passes all
-// skip.  An interval then meets an
-// interval of another stream that starts no later exactly when the furthest
-// end among earlier intervals of other streams lies past its start, and one
-// that starts later exactly when the smallest start among later intervals of
-// other streams lies before its end.  "Best among other streams" is kept as
-// the best two entries of distinct streams; that combine is associative and
+// The join is an interval sweep.  Every record gives two intervals, ordered
+// by (epoch, first byte).  The order comes from two stable passes of the
+// 8-bit LSD radix sort of sort.hip, which skips a pass whose digit is the same
+// in every key: the first sorts on the 64-bit first byte, the second on the
+// 32-bit epoch.  When the epochs never decrease in record order, no epoch
+// spans more than 4,096 records and they average at least 256 (a program's
+// synchronisation windows), each epoch's intervals are instead sorted in LDS
+// by one block, in place, and the global passes all skip.  An interval then
+// meets an interval of another stream that starts no later exactly when the
+// furthest last byte among earlier intervals of other streams of its epoch
+// reaches its first byte, and one that starts later exactly when the smallest
+// first byte among later intervals of other streams of its epoch reaches no
+// further than its last.  Comparing (epoch, byte) pairs keeps the epochs
+// apart without a segmented scan.  "Best among other streams" is kept as the
+// best two entries of distinct streams; that combine is associative and
 // commutative, so both directions are one reduce-then-scan over tiles.
 #include <hip/hip_runtime.h>
 
@@ -32,9 +35,8 @@ namespace {
 
 constexpr uint32_t kNoRec = 0xFFFFFFFFu;
 constexpr uint32_t kNoStream = 0xFFFFFFFFu;
-constexpr uint64_t kInvalidKey = 1ull << 63;
-constexpr uint64_t kAddrLimit = 1ull << 48;
-constexpr uint32_t kEpochLimit = 1u << 15;
+constexpr uint32_t kDead = 0x80000000u;         // interval-id bit: the interval touches no byte
+constexpr uint64_t kHere = 1ull << 32;          // high word of every real sweep value (none is 0)
 
 constexpr int kT = 256;                          // threads per block
 constexpr int kWaves = kT / 64;
@@ -50,26 +52,30 @@ static_assert(kT == kSortKeyBlock, "one part of the key mask per block of k_race
 
 // ---- records -------------------------------------------------------------
 
-__device__ __forceinline__ bool rec_checked(const cg_transfer &t, uint32_t e)
+__device__ __forceinline__ bool rec_checked(const cg_transfer &t) { return t.kind <= CG_D2D; }
+
+// Interval i of record i / 2: the source range for even i, the destination
+// range for odd i, as its first and last byte.  A range that runs past 2^64
+// is cut at 2^64 - 1: two ranges that meet above it both hold that byte, so
+// no meeting is lost or added.  `live` is false when it touches no byte.
+struct Iv {
+    uint64_t first, last;
+    bool live;
+};
+
+__device__ __forceinline__ Iv interval_of(const cg_transfer &t, uint64_t i)
 {
-    if (t.kind > CG_D2D) return false;
-    if (t.n == 0) return true;
-    return t.src <= kAddrLimit && t.n <= kAddrLimit - t.src && t.dst <= kAddrLimit &&
-           t.n <= kAddrLimit - t.dst && e < kEpochLimit;
+    Iv v;
+    v.first = (i & 1) ? t.dst : t.src;
+    v.live = rec_checked(t) && t.n > 0;
+    v.last = v.live && t.n - 1 <= ~v.first ? v.first + (t.n - 1) : ~0ull;
+    return v;
 }
 
-// interval i of record i / 2: the source range for even i, the destination
-// range for odd i; empty and unchecked ranges sort last
-__device__ __forceinline__ uint64_t interval_key(const cg_transfer *recs, const uint32_t *epochs, uint64_t i)
-{
-    const cg_transfer t = recs[i >> 1];
-    const uint32_t e = epochs ? epochs[i >> 1] : 0u;
-    if (t.n == 0 || !rec_checked(t, e)) return kInvalidKey;
-    return ((uint64_t)e << 48) | ((i & 1) ? t.dst : t.src);
-}
-
-__global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const uint32_t *epochs, uint64_t m,
-                                                  uint64_t *keys, uint32_t *vals, uint64_t *parts, uint32_t *flag)
+// first pass keys: every interval's first byte (dead ones too, where they
+// land does not matter), its id with kDead when it touches nothing
+__global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, uint64_t m, uint64_t *keys, uint32_t *vals,
+                                                  uint64_t *parts, uint32_t *flag)
 {
     __shared__ uint64_t part[kWaves];
     const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
@@ -77,13 +83,13 @@ __global__ __launch_bounds__(kT) void k_race_keys(const cg_transfer *recs, const
         flag[0] = 0;
         flag[1] = 0;
     }
-    const uint64_t k0 = interval_key(recs, epochs, 0);
+    const uint64_t k0 = recs[0].src;
     uint64_t x = 0;
     if (i < m) {
-        const uint64_t k = interval_key(recs, epochs, i);
-        keys[i] = k;
-        vals[i] = (uint32_t)i;
-        x = k ^ k0;
+        const Iv v = interval_of(recs[i >> 1], i);
+        keys[i] = v.first;
+        vals[i] = (uint32_t)i | (v.live ? 0u : kDead);
+        x = v.first ^ k0;
     }
     for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
@@ -125,21 +131,24 @@ __device__ __forceinline__ bool local_path(const uint32_t *flag, uint64_t count)
 
 // One block per chunk of kRunMax records sorts, in place, the intervals of
 // every epoch that starts in the chunk (at most kRunMax records, so at most
-// kLocalN intervals), by a stable LSD radix sort in LDS with 8-bit digits:
-// each key is packed with its index in the epoch's run, element e of the run
-// sits in wave e / 512, round (e / 64) % 8, lane e % 64, ranks come from
-// ballots as in the global sort, and a pass whose digit is the same in every
-// key is skipped.  Unchecked intervals go to the end of their epoch's run;
-// the sweep skips them wherever they are.  The chunk's parts of the key mask
-// are cleared, so every pass of the global sort skips.  The write-back also
-// puts each interval's end key and stream into the spare buffers (ends,
-// strm), which k_race_gather fills on the global path.
+// kLocalN intervals) by first byte, with a stable LSD radix sort in LDS and
+// 8-bit digits: each key travels with its index in the epoch's run, element
+// e of the run sits in wave e / 512, round (e / 64) % 8, lane e % 64, ranks
+// come from ballots as in the global sort, and a pass whose digit is the same
+// in every key is skipped.  Dead intervals sort by their address like the
+// others; the sweep skips them wherever they are.  The chunk's parts of the
+// key mask are cleared, so every pass of both global sorts skips.  The
+// write-back leaves what the sweep reads: the epoch as the key, the interval
+// id, and in the spare buffers and `first` each interval's last byte, stream
+// and first byte (k_race_gather fills them on the global path).
 __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_t *vals, uint64_t *ends,
-                                                         uint32_t *strm, uint64_t *parts, uint64_t nparts,
-                                                         const cg_transfer *recs, const uint32_t *streams,
-                                                         const uint32_t *epochs, uint64_t count, const uint32_t *flag)
+                                                         uint32_t *strm, uint64_t *first, uint64_t *parts,
+                                                         uint64_t nparts, const cg_transfer *recs,
+                                                         const uint32_t *streams, const uint32_t *epochs,
+                                                         uint64_t count, const uint32_t *flag)
 {
     __shared__ uint64_t buf[kLocalN];
+    __shared__ uint16_t bix[kLocalN];
     __shared__ uint32_t wrun[kLWaves][256];   // per wave and digit: running count, then prefix over waves
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t wtot[kLWaves];
@@ -173,18 +182,15 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
         __syncthreads();
         const uint32_t n = 2 * run_len;   // intervals of this epoch
         const uint64_t i0 = 2 * s;
-        auto pack = [&](uint32_t e) {
-            const uint64_t key = keys[i0 + e];
-            const uint64_t v49 = (key >> 63) ? (1ull << 48) : (key & ((1ull << 48) - 1));
-            return (v49 << 13) | e;
-        };
-        const uint64_t k0 = pack(0);
+        const uint64_t k0 = keys[i0];
         uint64_t k[kLRounds];
+        uint32_t ix[kLRounds];
         uint64_t x = 0;
 #pragma unroll
         for (int i = 0; i < kLRounds; ++i) {
             const uint32_t e = w * 512 + i * 64 + l;
-            k[i] = e < n ? pack(e) : ~0ull;
+            k[i] = e < n ? keys[i0 + e] : ~0ull;
+            ix[i] = e;
             if (e < n) x |= k[i] ^ k0;
         }
         for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
         __syncthreads();
         uint64_t live = 0;
         for (int j = 0; j < kLWaves; ++j) live |= wor[j];
-        for (int sh = 13; sh < 64; sh += 8) {
+        for (int sh = 0; sh < 64; sh += 8) {
             if (((live >> sh) & 0xFFu) == 0) continue;   // the same digit everywhere: skip the pass
             for (int j = threadIdx.x; j < kLWaves * 256; j += kLT) (&wrun[0][0])[j] = 0;
             __syncthreads();
@@ -233,13 +239,18 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
             for (int i = 0; i < kLRounds; ++i)
                 if (pk[i] != 0xFFFFFFFFu) {
                     const uint32_t d = pk[i] >> 16;
-                    buf[dstart[d] + wrun[w][d] + (pk[i] & 0xFFFFu)] = k[i];
+                    const uint32_t pos = dstart[d] + wrun[w][d] + (pk[i] & 0xFFFFu);
+                    buf[pos] = k[i];
+                    bix[pos] = (uint16_t)ix[i];
                 }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < kLRounds; ++i) {
                 const uint32_t e = w * 512 + i * 64 + l;
-                if (e < n) k[i] = buf[e];
+                if (e < n) {
+                    k[i] = buf[e];
+                    ix[i] = bix[e];
+                }
             }
             __syncthreads();
         }
@@ -247,57 +258,99 @@ __global__ __launch_bounds__(kLT) void k_race_local_sort(uint64_t *keys, uint32_
         for (int i = 0; i < kLRounds; ++i) {
             const uint32_t e = w * 512 + i * 64 + l;
             if (e < n) {
-                const uint64_t v49 = k[i] >> 13;
-                const uint64_t iv = i0 + (k[i] & (kLocalN - 1));
-                const bool valid = !(v49 >> 48);
-                const uint64_t key = valid ? (((uint64_t)ep << 48) | v49) : kInvalidKey;
-                keys[i0 + e] = key;
-                vals[i0 + e] = (uint32_t)iv;
-                ends[i0 + e] = valid ? key + recs[iv >> 1].n : 0;
-                strm[i0 + e] = valid ? streams[iv >> 1] : kNoStream;
+                const uint64_t iv = i0 + ix[i];
+                const Iv v = interval_of(recs[iv >> 1], iv);
+                keys[i0 + e] = ep;
+                vals[i0 + e] = (uint32_t)iv | (v.live ? 0u : kDead);
+                first[i0 + e] = v.first;
+                ends[i0 + e] = v.last;
+                strm[i0 + e] = streams[iv >> 1];
             }
         }
         __syncthreads();
     }
 }
 
+// Second pass keys (global path): the epoch of each interval, in the order of
+// the first pass, moved into keys[0] / vals[0] with the key-bit parts of the
+// second sort.  On the per-epoch path the keys already hold the epochs and the
+// parts stay cleared.
+__global__ __launch_bounds__(kT) void k_race_rekey(uint64_t *ka, uint32_t *va, const uint32_t *vb,
+                                                   const uint64_t *maskp, const uint32_t *epochs, uint64_t m,
+                                                   uint64_t *parts, const uint32_t *flag, uint64_t count)
+{
+    __shared__ uint64_t part[kWaves];
+    if (local_path(flag, count)) return;
+    const uint32_t *vin = sort_parity(*maskp) ? vb : va;   // va[i] is rewritten with its own value only
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t k0 = epochs ? epochs[(vin[0] & ~kDead) >> 1] : 0u;
+    uint64_t x = 0;
+    if (i < m) {
+        const uint32_t v = vin[i];
+        const uint64_t k = epochs ? epochs[(v & ~kDead) >> 1] : 0u;
+        ka[i] = k;
+        va[i] = v;
+        x = k ^ k0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t y = 0;
+        for (int w = 0; w < kWaves; ++w) y |= part[w];
+        parts[blockIdx.x] = y;
+    }
+}
+
 // ---- sweep ---------------------------------------------------------------
+
+// A sweep value: (epoch tag, byte) compared as one 128-bit number.  Real
+// values have kHere in the high word, so the empty value 0 is below all of
+// them.  Forward values are (kHere | epoch, last byte): the largest among
+// earlier intervals belongs to the latest epoch, and within it to the
+// furthest-reaching interval.  Backward values are (kHere | ~epoch, ~first
+// byte), so that the largest is the smallest (epoch, first byte).
+struct Val {
+    uint64_t h, l;
+};
+
+__device__ __forceinline__ bool v_ge(const Val &a, const Val &b) { return a.h > b.h || (a.h == b.h && a.l >= b.l); }
+__device__ __forceinline__ bool v_gt(const Val &a, const Val &b) { return a.h > b.h || (a.h == b.h && a.l > b.l); }
 
 // The best two entries (value, record) of distinct streams: (v1, s1, r1) has
 // the largest value, (v2, r2) the largest value of any stream other than s1.
-// Ends are kept as they are (furthest end wins), starts as their complement
-// (smallest start wins).  Between equal values either entry may be kept: the
-// values, which decide every conflict, come out the same, and any entry kept
-// names a valid partner; the combining order is fixed, so results repeat.
+// Between equal values either entry may be kept: the values, which decide
+// every conflict, come out the same, and any entry kept names a valid
+// partner; the combining order is fixed, so results repeat.
 struct Top2 {
-    uint64_t v1, v2;
+    Val v1, v2;
     uint32_t s1, r1, r2;
 };
 
-__device__ __forceinline__ Top2 t2_none() { return Top2{0, 0, kNoStream, kNoRec, kNoRec}; }
+__device__ __forceinline__ Top2 t2_none() { return Top2{{0, 0}, {0, 0}, kNoStream, kNoRec, kNoRec}; }
 
 __device__ __forceinline__ Top2 t2_combine(const Top2 &x, const Top2 &y)
 {
-    const bool xw = x.v1 >= y.v1;
+    const bool xw = v_ge(x.v1, y.v1);
     const Top2 a = xw ? x : y, b = xw ? y : x;
     Top2 o;
     o.v1 = a.v1;
     o.s1 = a.s1;
     o.r1 = a.r1;
     const bool other = b.s1 != a.s1;
-    const uint64_t cv = other ? b.v1 : b.v2;
+    const Val cv = other ? b.v1 : b.v2;
     const uint32_t cr = other ? b.r1 : b.r2;
-    const bool keep = a.v2 >= cv;
+    const bool keep = v_ge(a.v2, cv);
     o.v2 = keep ? a.v2 : cv;
     o.r2 = keep ? a.r2 : cr;
     return o;
 }
 
 // insert one entry
-__device__ __forceinline__ Top2 t2_add(const Top2 &x, uint64_t v, uint32_t s, uint32_t r)
+__device__ __forceinline__ Top2 t2_add(const Top2 &x, const Val &v, uint32_t s, uint32_t r)
 {
     Top2 o = x;
-    if (v > x.v1) {
+    if (v_gt(v, x.v1)) {
         // the old best stays as the second unless it has this stream
         const bool other = x.s1 != s;
         o.v2 = other ? x.v1 : x.v2;
@@ -305,7 +358,7 @@ __device__ __forceinline__ Top2 t2_add(const Top2 &x, uint64_t v, uint32_t s, ui
         o.v1 = v;
         o.s1 = s;
         o.r1 = r;
-    } else if (s != x.s1 && v > x.v2) {
+    } else if (s != x.s1 && v_gt(v, x.v2)) {
         o.v2 = v;
         o.r2 = r;
     }
@@ -313,22 +366,36 @@ __device__ __forceinline__ Top2 t2_add(const Top2 &x, uint64_t v, uint32_t s, ui
 }
 
 // the best entry of a stream other than s
-__device__ __forceinline__ void t2_other(const Top2 &x, uint32_t s, uint64_t *v, uint32_t *r)
+__device__ __forceinline__ void t2_other(const Top2 &x, uint32_t s, Val *v, uint32_t *r)
 {
     const bool first = x.s1 != s;
     *v = first ? x.v1 : x.v2;
     *r = first ? x.r1 : x.r2;
 }
 
-template <bool UP>
+template <int MODE>   // 0: up, 1: down, 2: xor
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int d)
+{
+    return MODE == 0 ? __shfl_up(x, d) : MODE == 1 ? __shfl_down(x, d) : __shfl_xor(x, d);
+}
+
+template <int MODE>
+__device__ __forceinline__ uint32_t shfl32(uint32_t x, int d)
+{
+    return MODE == 0 ? __shfl_up(x, d) : MODE == 1 ? __shfl_down(x, d) : __shfl_xor(x, d);
+}
+
+template <int MODE>
 __device__ __forceinline__ Top2 t2_shfl(const Top2 &x, int d)
 {
     Top2 y;
-    y.v1 = UP ? __shfl_up(x.v1, d) : __shfl_down(x.v1, d);
-    y.v2 = UP ? __shfl_up(x.v2, d) : __shfl_down(x.v2, d);
-    y.s1 = UP ? __shfl_up(x.s1, d) : __shfl_down(x.s1, d);
-    y.r1 = UP ? __shfl_up(x.r1, d) : __shfl_down(x.r1, d);
-    y.r2 = UP ? __shfl_up(x.r2, d) : __shfl_down(x.r2, d);
+    y.v1.h = shfl64<MODE>(x.v1.h, d);
+    y.v1.l = shfl64<MODE>(x.v1.l, d);
+    y.v2.h = shfl64<MODE>(x.v2.h, d);
+    y.v2.l = shfl64<MODE>(x.v2.l, d);
+    y.s1 = shfl32<MODE>(x.s1, d);
+    y.r1 = shfl32<MODE>(x.r1, d);
+    y.r2 = shfl32<MODE>(x.r2, d);
     return y;
 }
 
@@ -340,10 +407,10 @@ __device__ Top2 block_excl(const Top2 &x)
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     Top2 inc = x;
     for (int d = 1; d < 64; d <<= 1) {
-        const Top2 y = t2_shfl<FWD>(inc, d);
+        const Top2 y = t2_shfl<FWD ? 0 : 1>(inc, d);
         if (FWD ? l >= d : l + d < 64) inc = t2_combine(inc, y);
     }
-    Top2 ex = t2_shfl<FWD>(inc, 1);
+    Top2 ex = t2_shfl<FWD ? 0 : 1>(inc, 1);
     if (FWD ? l == 0 : l == 63) ex = t2_none();
     if (FWD ? l == 63 : l == 0) wtot[w] = inc;
     __syncthreads();
@@ -357,15 +424,7 @@ __device__ Top2 block_all(const Top2 &x)
 {
     __shared__ Top2 wtot[kWaves];
     Top2 a = x;
-    for (int d = 32; d >= 1; d >>= 1) {
-        Top2 y;
-        y.v1 = __shfl_xor(a.v1, d);
-        y.v2 = __shfl_xor(a.v2, d);
-        y.s1 = __shfl_xor(a.s1, d);
-        y.r1 = __shfl_xor(a.r1, d);
-        y.r2 = __shfl_xor(a.r2, d);
-        a = t2_combine(a, y);
-    }
+    for (int d = 32; d >= 1; d >>= 1) a = t2_combine(a, t2_shfl<2>(a, d));
     if ((threadIdx.x & 63) == 0) wtot[threadIdx.x >> 6] = a;
     __syncthreads();
     Top2 o = wtot[0];
@@ -376,90 +435,96 @@ __device__ Top2 block_all(const Top2 &x)
 
 // one interval of the sorted order
 struct Elem {
-    uint64_t start, end;
-    uint32_t s, r, iv;
+    uint64_t first, last;
+    uint32_t ep, s, r, iv;
     bool valid, w, present;
 };
 
-// The sorted order's keys K and interval ids V, with the end keys E and
-// streams S that k_race_gather laid out beside them.
-struct Sorted {
-    const uint64_t *K, *E;
-    const uint32_t *V, *S;
-};
-
-__device__ __forceinline__ Sorted sorted_view(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
-                                              const uint32_t *vb, uint64_t mask)
+// an interval id slot as read from the sorted order (kNoRec: a padding slot)
+__device__ __forceinline__ Elem make_elem(uint32_t raw, uint32_t ep, uint64_t first, uint64_t last, uint32_t s)
 {
-    const bool b = sort_parity(mask) != 0;
-    return Sorted{b ? kb : ka, b ? ka : kb, b ? vb : va, b ? va : vb};
-}
-
-__device__ __forceinline__ Elem load_elem(const Sorted &o, uint64_t p, uint64_t m)
-{
-    Elem e{kInvalidKey, 0, kNoStream, kNoRec, 0, false, false, false};
-    if (p < m) {
-        const uint64_t k = o.K[p];
-        e.iv = o.V[p];
-        e.present = e.iv < m;
-        if (e.present && !(k >> 63)) {
-            e.valid = true;
-            e.r = e.iv >> 1;
-            e.w = (e.iv & 1u) != 0;
-            e.start = k;
-            e.end = o.E[p];
-            e.s = o.S[p];
-        }
+    Elem e{0, 0, 0, kNoStream, kNoRec, raw & ~kDead, false, false, raw != kNoRec};
+    if (e.present && !(raw & kDead)) {
+        e.valid = true;
+        e.r = e.iv >> 1;
+        e.w = (e.iv & 1u) != 0;
+        e.ep = ep;
+        e.first = first;
+        e.last = last;
+        e.s = s;
     }
     return e;
 }
 
-// end key and stream of every sorted interval, written into the ping-pong
-// buffers that do not hold the sorted order
+// The sorted order: epochs K and interval ids V, with the last bytes E and
+// streams S in the spare buffers and the first bytes F.
+struct Sorted {
+    const uint64_t *K, *E, *F;
+    const uint32_t *V, *S;
+};
+
+__device__ __forceinline__ Sorted sorted_view(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
+                                              const uint32_t *vb, const uint64_t *first, uint64_t mask)
+{
+    const bool b = sort_parity(mask) != 0;
+    return Sorted{b ? kb : ka, b ? ka : kb, first, b ? vb : va, b ? va : vb};
+}
+
+__device__ __forceinline__ Elem load_elem(const Sorted &o, uint64_t p, uint64_t m)
+{
+    if (p >= m) return make_elem(kNoRec, 0, 0, 0, kNoStream);
+    const uint32_t raw = o.V[p];
+    if (raw & kDead) return make_elem(raw, 0, 0, 0, kNoStream);
+    return make_elem(raw, (uint32_t)o.K[p], o.F[p], o.E[p], o.S[p]);
+}
+
+// first byte, last byte and stream of every sorted interval, written into
+// `first` and the ping-pong buffers that do not hold the sorted order
 __global__ __launch_bounds__(kT) void k_race_gather(uint64_t *ka, uint64_t *kb, uint32_t *va, uint32_t *vb,
-                                                    const uint64_t *maskp, const cg_transfer *recs,
+                                                    uint64_t *first, const uint64_t *maskp, const cg_transfer *recs,
                                                     const uint32_t *streams, uint64_t m, const uint32_t *flag,
                                                     uint64_t count)
 {
     const uint64_t p = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (p >= m || local_path(flag, count)) return;   // the per-epoch sort wrote them
     const bool b = sort_parity(*maskp) != 0;
-    const uint64_t k = (b ? kb : ka)[p];
-    const uint32_t iv = (b ? vb : va)[p];
-    uint64_t end = 0;
-    uint32_t s = kNoStream;
-    if (!(k >> 63) && iv < m) {
-        end = k + recs[iv >> 1].n;
-        s = streams[iv >> 1];
-    }
-    (b ? ka : kb)[p] = end;
-    (b ? va : vb)[p] = s;
+    const uint32_t iv = (b ? vb : va)[p] & ~kDead;
+    const Iv v = interval_of(recs[iv >> 1], iv);
+    first[p] = v.first;
+    (b ? ka : kb)[p] = v.last;
+    (b ? va : vb)[p] = streams[iv >> 1];
 }
 
-// the four running combines: ends and starts, of all intervals and of writes
+// the four running combines: forward (last bytes) and backward (first
+// bytes), of all intervals and of writes
 struct Sweep {
     Top2 fa, fw, ba, bw;
 };
 
+__device__ __forceinline__ Val fwd_val(const Elem &e) { return Val{kHere | e.ep, e.last}; }
+__device__ __forceinline__ Val bwd_val(const Elem &e) { return Val{kHere | (uint32_t)~e.ep, ~e.first}; }
+
 __device__ __forceinline__ void sweep_add_fwd(Sweep &x, const Elem &e)
 {
     if (!e.valid) return;
-    x.fa = t2_add(x.fa, e.end, e.s, e.r);
-    if (e.w) x.fw = t2_add(x.fw, e.end, e.s, e.r);
+    const Val v = fwd_val(e);
+    x.fa = t2_add(x.fa, v, e.s, e.r);
+    if (e.w) x.fw = t2_add(x.fw, v, e.s, e.r);
 }
 
 __device__ __forceinline__ void sweep_add_bwd(Sweep &x, const Elem &e)
 {
     if (!e.valid) return;
-    x.ba = t2_add(x.ba, ~e.start, e.s, e.r);
-    if (e.w) x.bw = t2_add(x.bw, ~e.start, e.s, e.r);
+    const Val v = bwd_val(e);
+    x.ba = t2_add(x.ba, v, e.s, e.r);
+    if (e.w) x.bw = t2_add(x.bw, v, e.s, e.r);
 }
 
 __global__ __launch_bounds__(kT) void k_race_sweep_reduce(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
-                                                          const uint32_t *vb, const uint64_t *maskp, uint64_t m,
-                                                          Top2 *agg)
+                                                          const uint32_t *vb, const uint64_t *first,
+                                                          const uint64_t *maskp, uint64_t m, Top2 *agg)
 {
-    const Sorted o = sorted_view(ka, kb, va, vb, *maskp);
+    const Sorted o = sorted_view(ka, kb, va, vb, first, *maskp);
     // the combines do not depend on order: read the tile lane-contiguously
     const uint64_t base = (uint64_t)blockIdx.x * kSweepTile + threadIdx.x;
     Sweep x{t2_none(), t2_none(), t2_none(), t2_none()};
@@ -478,7 +543,7 @@ __global__ __launch_bounds__(kT) void k_race_sweep_reduce(const uint64_t *ka, co
     }
 }
 
-// per sweep tile: combine of the tiles before it (ends) and after it (starts)
+// per sweep tile: combine of the tiles before it (forward) and after it (backward)
 __global__ __launch_bounds__(kT) void k_race_sweep_scan(const Top2 *agg, uint32_t tiles, Top2 *pre)
 {
     const uint32_t per = (tiles + kT - 1) / kT;
@@ -514,44 +579,38 @@ __device__ __forceinline__ int pad_slot(int i) { return i + i / kSweepItems; }
 constexpr int kSweepSlots = kSweepTile + kSweepTile / kSweepItems;
 
 __global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, const uint64_t *kb, const uint32_t *va,
-                                                         const uint32_t *vb, const uint64_t *maskp, uint64_t m,
-                                                         const Top2 *pre, uint32_t *res)
+                                                         const uint32_t *vb, const uint64_t *first,
+                                                         const uint64_t *maskp, uint64_t m, const Top2 *pre,
+                                                         uint32_t *res)
 {
-    __shared__ uint64_t sk[kSweepSlots], se[kSweepSlots];
-    __shared__ uint32_t sv[kSweepSlots], ss[kSweepSlots];
-    const Sorted o = sorted_view(ka, kb, va, vb, *maskp);
+    __shared__ uint64_t sf[kSweepSlots], se[kSweepSlots];
+    __shared__ uint32_t sk[kSweepSlots], sv[kSweepSlots], ss[kSweepSlots];
+    const Sorted o = sorted_view(ka, kb, va, vb, first, *maskp);
     const uint64_t tile = (uint64_t)blockIdx.x * kSweepTile;
     // stage the tile through LDS: read lane-contiguously, walk per thread
     for (int j = 0; j < kSweepItems; ++j) {
         const int i = j * kT + threadIdx.x;
         const uint64_t p = tile + i;
         const int q = pad_slot(i);
+        sv[q] = kNoRec;
         if (p < m) {
-            sk[q] = o.K[p];
-            se[q] = o.E[p];
-            sv[q] = o.V[p];
-            ss[q] = o.S[p];
-        } else {
-            sk[q] = kInvalidKey;
-            sv[q] = kNoRec;
+            const uint32_t raw = o.V[p];
+            sv[q] = raw;
+            if (!(raw & kDead)) {
+                sk[q] = (uint32_t)o.K[p];
+                sf[q] = o.F[p];
+                se[q] = o.E[p];
+                ss[q] = o.S[p];
+            }
         }
     }
     __syncthreads();
-    const int first = threadIdx.x * kSweepItems;
+    const int base = threadIdx.x * kSweepItems;
     auto elem = [&](int j) {
-        const int q = pad_slot(first + j);
-        Elem e{kInvalidKey, 0, kNoStream, kNoRec, sv[q], false, false, false};
-        e.present = e.iv < m;
-        const uint64_t k = sk[q];
-        if (e.present && !(k >> 63)) {
-            e.valid = true;
-            e.r = e.iv >> 1;
-            e.w = (e.iv & 1u) != 0;
-            e.start = k;
-            e.end = se[q];
-            e.s = ss[q];
-        }
-        return e;
+        const int q = pad_slot(base + j);
+        const uint32_t raw = sv[q];
+        if (raw & kDead) return make_elem(raw, 0, 0, 0, kNoStream);
+        return make_elem(raw, sk[q], sf[q], se[q], ss[q]);
     };
     Sweep own{t2_none(), t2_none(), t2_none(), t2_none()};
     for (int j = 0; j < kSweepItems; ++j) {
@@ -571,10 +630,13 @@ __global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, con
         const Elem e = elem(j);
         hit[j] = kNoRec;
         if (e.valid) {
-            uint64_t v;
-            uint32_t r;
-            t2_other(e.w ? x.fa : x.fw, e.s, &v, &r);
-            if (v > e.start) hit[j] = r;
+            // an earlier interval of another stream, in this epoch, reaching this one's first byte
+            Val va, vw;
+            uint32_t ra, rw;
+            t2_other(x.fa, e.s, &va, &ra);
+            t2_other(x.fw, e.s, &vw, &rw);
+            const Val v = e.w ? va : vw;
+            if (v.h == (kHere | e.ep) && v.l >= e.first) hit[j] = e.w ? ra : rw;
         }
         sweep_add_fwd(x, e);
     }
@@ -582,26 +644,28 @@ __global__ __launch_bounds__(kT) void k_race_sweep_apply(const uint64_t *ka, con
     for (int j = kSweepItems - 1; j >= 0; --j) {
         const Elem e = elem(j);
         if (e.valid && hit[j] == kNoRec) {
-            uint64_t v;
-            uint32_t r;
-            t2_other(e.w ? x.ba : x.bw, e.s, &v, &r);
-            if (~v < e.end) hit[j] = r;
+            // a later interval of another stream, in this epoch, starting at or before this one's last byte
+            Val va, vw;
+            uint32_t ra, rw;
+            t2_other(x.ba, e.s, &va, &ra);
+            t2_other(x.bw, e.s, &vw, &rw);
+            const Val v = e.w ? va : vw;
+            if (v.h == (kHere | (uint32_t)~e.ep) && ~v.l <= e.last) hit[j] = e.w ? ra : rw;
         }
         sweep_add_bwd(x, e);
         if (e.present) res[e.iv] = hit[j];
     }
 }
 
-__global__ __launch_bounds__(kT) void k_race_finalize(const cg_transfer *recs, const uint32_t *epochs,
-                                                      uint64_t count, const uint32_t *res, cg_race *out)
+__global__ __launch_bounds__(kT) void k_race_finalize(const cg_transfer *recs, uint64_t count, const uint32_t *res,
+                                                      cg_race *out)
 {
     const uint64_t r = (uint64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= count) return;
     const cg_transfer t = recs[r];
-    const uint32_t e = epochs ? epochs[r] : 0u;
     cg_race o;
     o.reserved = 0;
-    if (!rec_checked(t, e)) {
+    if (!rec_checked(t)) {
         o.flags = CG_RACE_UNCHECKED;
         o.partner = CG_NONE;
     } else {
@@ -627,6 +691,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
         if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 8);
     };
     get((void **)&w.res, intervals * sizeof(uint32_t));
+    get((void **)&w.first, intervals * sizeof(uint64_t));
     get((void **)&w.flag, 64);
     get(&w.agg, sweeps * 4 * sizeof(Top2));
     get(&w.pre, sweeps * 4 * sizeof(Top2));
@@ -641,7 +706,7 @@ hipError_t race_reserve(RaceWs &w, uint64_t intervals)
 void race_release(RaceWs &w)
 {
     sort_release(w.sort);
-    void *ps[] = {w.res, w.agg, w.pre, w.flag};
+    void *ps[] = {w.res, w.first, w.agg, w.pre, w.flag};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     w = RaceWs{};
@@ -653,28 +718,36 @@ hipError_t race_launch(RaceWs &w, const cg_transfer *recs, const uint32_t *strea
     if (count == 0) return hipSuccess;
     const uint64_t m = 2 * count;
     const uint32_t sweeps = (uint32_t)ceil_div(m, kSweepTile);
+    const uint32_t blocks = (uint32_t)ceil_div(m, kT);
     SortWs &q = w.sort;
-    hipLaunchKernelGGL(k_race_keys, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, recs, epochs, m, q.keys[0],
-                       q.vals[0], q.parts, w.flag);
+    hipLaunchKernelGGL(k_race_keys, dim3(blocks), dim3(kT), 0, s, recs, m, q.keys[0], q.vals[0], q.parts, w.flag);
     hipLaunchKernelGGL(k_race_local_check, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, epochs, count, w.flag);
     hipLaunchKernelGGL(k_race_local_sort, dim3((uint32_t)ceil_div(count, kRunMax)), dim3(kLT), 0, s, q.keys[0],
-                       q.vals[0], q.keys[1], q.vals[1], q.parts, ceil_div(m, kT), recs, streams, epochs, count, w.flag);
+                       q.vals[0], q.keys[1], q.vals[1], w.first, q.parts, ceil_div(m, kT), recs, streams, epochs, count,
+                       w.flag);
     // without epochs, a batch of kRunMean to kRunMax records is one epoch that
     // the per-epoch sort takes (as the device decides too): the global passes
     // would all return at once, so they are not launched
     const bool one_local_epoch = !epochs && count <= kRunMax && count >= kRunMean;
+    // first sort: by first byte
     hipError_t e = one_local_epoch ? sort_mask_only(q, m, s) : sort_pairs(q, m, s);
     if (e != hipSuccess) return e;
+    // second sort, stable: by epoch (all 0 without epochs: only the mask is taken,
+    // which then names keys[0] / vals[0], where the rekey moved the order)
+    if (!one_local_epoch)
+        hipLaunchKernelGGL(k_race_rekey, dim3(blocks), dim3(kT), 0, s, q.keys[0], q.vals[0], q.vals[1], q.mask, epochs,
+                           m, q.parts, w.flag, count);
+    e = epochs ? sort_pairs(q, m, s, nullptr, 4) : sort_mask_only(q, m, s);
+    if (e != hipSuccess) return e;
     Top2 *agg = (Top2 *)w.agg, *pre = (Top2 *)w.pre;
-    hipLaunchKernelGGL(k_race_gather, dim3((uint32_t)ceil_div(m, kT)), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0],
-                       q.vals[1], q.mask, recs, streams, m, w.flag, count);
+    hipLaunchKernelGGL(k_race_gather, dim3(blocks), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1], w.first,
+                       q.mask, recs, streams, m, w.flag, count);
     hipLaunchKernelGGL(k_race_sweep_reduce, dim3(sweeps), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1],
-                       q.mask, m, agg);
+                       w.first, q.mask, m, agg);
     hipLaunchKernelGGL(k_race_sweep_scan, dim3(1), dim3(kT), 0, s, agg, sweeps, pre);
     hipLaunchKernelGGL(k_race_sweep_apply, dim3(sweeps), dim3(kT), 0, s, q.keys[0], q.keys[1], q.vals[0], q.vals[1],
-                       q.mask, m, pre, w.res);
-    hipLaunchKernelGGL(k_race_finalize, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, recs, epochs, count,
-                       w.res, out);
+                       w.first, q.mask, m, pre, w.res);
+    hipLaunchKernelGGL(k_race_finalize, dim3((uint32_t)ceil_div(count, kT)), dim3(kT), 0, s, recs, count, w.res, out);
     return hipGetLastError();
 }
 

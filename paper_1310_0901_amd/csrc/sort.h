@@ -32,8 +32,10 @@ void sort_release(SortWs &w);
 // given, the count in device memory at n_dev (at most n; read when the
 // kernels run, so that a count computed on the device needs no copy back).
 // parts[0 .. ceil(n / kSortKeyBlock)) must hold the key-building blocks'
-// parts (0 for blocks past the keys).
-hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev = nullptr);
+// parts (0 for blocks past the keys).  Only `bytes` passes are launched:
+// every key must be below 2^(8 * bytes), so that the higher bytes are all
+// equal (the mask, and so the parity, then hold no bits above them).
+hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev = nullptr, int bytes = 8);
 
 // Only the key-bit mask of n keys (from the parts), for pairs already in
 // order in keys[0] / vals[0] whose parts were cleared: no pass runs.

@@ -251,12 +251,13 @@ hipError_t sort_mask_only(SortWs &w, uint64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev)
+hipError_t sort_pairs(SortWs &w, uint64_t n, hipStream_t s, const uint64_t *n_dev, int bytes)
 {
     if (n == 0) return hipSuccess;
+    if (bytes < 1 || bytes > 8) return hipErrorInvalidValue;
     const uint32_t tiles = (uint32_t)ceil_div(n, kSortTile);
     hipLaunchKernelGGL(k_sort_mask, dim3(1), dim3(kT), 0, s, w.parts, (uint32_t)ceil_div(n, kT), w.mask);
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = 0; pass < bytes; ++pass) {
         hipLaunchKernelGGL(k_sort_count, dim3(tiles), dim3(kT), 0, s, w.keys[0], w.keys[1], n, n_dev, tiles, w.mask,
                            pass, w.counts);
         hipLaunchKernelGGL(k_sort_scan_digits, dim3(256), dim3(kT), 0, s, w.counts, tiles, w.dtot, w.mask, pass);

@@ -149,20 +149,58 @@ def test_epoch_runs(X, ctx, count, run):
     assert (res["flags"] & 3).any() or run == 1
 
 
-def test_epoch_runs_with_unchecked_epochs(X, ctx):
-    """The per-epoch path with epochs at and above 2^15 in the second half
-    (those records are unchecked: their intervals carry the invalid key and
-    end up at the end of their epoch's run)."""
+def test_epoch_runs_with_high_epochs(X, ctx):
+    """The per-epoch path with epochs at and above 2^15, and up to 2^32 - 1,
+    in the second half: every epoch is decided like any other."""
     count = 12_000
     b = W.small_race(count=count, streams=4, epochs=1, seed=W.SEED0 + 77)
     ep = (np.arange(count) // 1000).astype(np.uint32)
     ep[count // 2:] += (1 << 15) - 6
+    ep[-1000:] = (1 << 32) - 1
     want = oracle.race(b.records, b.streams, ep, threads=8)
     res = gpu_join(X, ctx, b.records, b.streams, ep)
     check(res, b.records, b.streams, ep, want)
-    late = np.arange(count) >= count // 2
-    assert (res["flags"][late & (b.records["n"] > 0)] == X.CG_RACE_UNCHECKED).all()   # empty records are checked
-    assert (res["flags"][: count // 2] & 3).any()
+    assert (res["flags"][count // 2:] & 3).any() and (res["flags"][-1000:] & 3).any()
+    assert ((res["flags"] & X.CG_RACE_UNCHECKED) != 0).sum() == (b.records["kind"] > 2).sum()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_tiny_high(X, ctx, seed):
+    """Tiny batches at the top of the address space (ranges above 2^48, up to
+    the last byte and past 2^64) with epochs near 2^15, 2^31 and 2^32."""
+    from tests.test_oracle_race import HIGH
+    rng = np.random.default_rng(900 + seed)
+    for j in range(8):
+        rows, st, ep = random_batch(rng, int(rng.integers(1, 60)), epochs=3, **HIGH[(seed + j) % len(HIGH)])
+        r = tiny_recs(rows)
+        check(gpu_join(X, ctx, r, st, ep), r, st, ep, oracle.race(r, st, ep))
+
+
+@pytest.mark.parametrize("shift,run", [(1 << 48, 1000), ((1 << 64) - (1 << 16), "decreasing"),
+                                       (1 << 60, None), ((1 << 64) - (1 << 16), 3000)])
+def test_high_addresses(X, ctx, shift, run):
+    """A dense batch moved above 2^48 or to the top of the address space (its
+    device ranges run past 2^64 there), on the per-epoch path (epoch runs
+    of 1,000 or 3,000 records near 2^31) and the radix-sort path (decreasing
+    epochs, or none at 5,000 records)."""
+    count = 9000 if run is not None else 5000
+    b = W.small_race(count=count, streams=6, epochs=1, seed=W.SEED0 + 91 + count)
+    r = b.records.copy()
+    # the host window goes 1 MiB below `shift`, the device window to `shift`
+    for f in ("src", "dst"):
+        a = r[f].astype(object)
+        r[f] = [(x - W.HOST_BASE + shift - (1 << 20)) % (1 << 64) if x >= W.HOST_BASE else x - W.DEV_BASE + shift
+                for x in a]
+    if run is None:
+        ep = None
+    elif run == "decreasing":
+        ep = ((1 << 32) - 1 - np.arange(count) // 700).astype(np.uint32)
+    else:
+        ep = ((1 << 31) + np.arange(count) // run).astype(np.uint32)
+    want = oracle.race(r, b.streams, ep, threads=8)
+    res = gpu_join(X, ctx, r, b.streams, ep)
+    check(res, r, b.streams, ep, want)
+    assert (res["flags"] & 3).any()
 
 
 def test_no_epochs_argument(X, ctx):
@@ -184,12 +222,13 @@ def test_edges(X, ctx):
     r = W.make_records(np.full(T, 2), D + np.arange(T), D + 1000 + np.arange(T), np.full(T, 3))
     st = (np.arange(T) % 2).astype(np.uint32)
     check(gpu_join(X, ctx, r, st), r, st, None, oracle.race(r, st))
-    # the limits: end exactly at 2^48, beyond it, epochs 2^15 - 1 and 2^15, high epochs in the key
+    # ranges ending at and crossing 2^48; epochs 2^15 - 1 and 2^15, and epochs that differ above bit 15
     rows = [(0, W.HOST_BASE, L - 100, 100), (0, W.HOST_BASE + 500, L - 50, 50), (0, W.HOST_BASE, L - 50, 100),
             (2, D, D + 10_000, 64), (2, D + 10_000, D, 64), (1, D, W.HOST_BASE, 0), (7, D, D, 10)]
     r = tiny_recs([(k, s, d, n) for k, s, d, n in rows])
     for ep in ([0] * 7, [(1 << 15) - 1] * 7, [1 << 15] * 7, [300, 300, 300, 40000, 40000, 5, 5],
-               [65535, 257, 257, 258, 258, 1, 1]):
+               [65535, 257, 257, 258, 258, 1, 1], [5, 5 + (1 << 15), 5, 5 + (1 << 16), 5, 5, 5],
+               [(1 << 32) - 1] * 3 + [(1 << 31)] * 4):
         st = [1, 2, 3, 1, 2, 3, 4]
         check(gpu_join(X, ctx, r, st, ep), r, st, ep, oracle.race(r, st, ep))
 
