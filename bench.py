@@ -47,7 +47,7 @@ def algo_bytes(recs, propagate=False):
 
 def cpu_baseline(w, hv, ha, got, target_bytes, threads):
     """Oracle on the first records of the workload up to ~target_bytes of
-    transfer data, on `threads` host threads; returns (GB/s, sample text, ok)."""
+    transfer data, on `threads` host threads; returns (GB/s, sample text, ok, s)."""
     import numpy as np
     from oracle.oracle import OracleState
     from paper_1310_0901_amd import workloads as W
@@ -72,8 +72,34 @@ def cpu_baseline(w, hv, ha, got, target_bytes, threads):
     same = all(np.array_equal(v[f], got[f][:m]) for f in ("flags", "first_bad", "undef_bytes", "avail"))
     gbs = algo_bytes(sample) / dt / 1e9
     text = (f"first {m} of {w.count} records ({int(n[:m].sum()) / 1e9:.2f} GB of transfers, "
-            f"{idx.size} allocations materialised), check-only, {threads} threads, {dt:.2f} s wall")
+            f"{idx.size} allocations materialised), check-only, {threads} thread(s), {dt:.2f} s wall; "
+            f"the rate is per algorithmic byte, so it scales to the whole batch")
     return gbs, text, same, dt
+
+
+def cpu_cores():
+    """Host cores this process may run on, and how many the oracle uses: all
+    of them, up to the 16-core share a one-GPU machine gives a process."""
+    aff = sorted(os.sched_getaffinity(0))
+    return aff, min(len(aff), 16)
+
+
+def cpu_baseline_legs(w, hv, ha, got, all_bytes, one_bytes):
+    """The oracle on one thread and on every allowed core (cpu_cores)."""
+    aff, n_all = cpu_cores()
+    legs = {}
+    for name, threads, b in (("one_thread", 1, one_bytes), ("all_cores", n_all, all_bytes)):
+        gbs, text, same, dt = cpu_baseline(w, hv, ha, got, b, threads)
+        legs[name] = {"value": round(gbs, 3), "cores": threads, "sample": text, "seconds": round(dt, 2),
+                      "verdicts_identical_to_gpu": bool(same)}
+        log(f"[bench] oracle {name}: {gbs:.2f} GB/s on {threads} thread(s), identical: {same}")
+    top = legs["all_cores"]
+    return {"value": top["value"], "unit": "GB/s", "cores": top["cores"], "kind": "oracle", "sample": top["sample"],
+            "verdicts_identical_to_gpu": top["verdicts_identical_to_gpu"] and legs["one_thread"]["verdicts_identical_to_gpu"],
+            "one_thread": legs["one_thread"], "all_cores": legs["all_cores"],
+            "host": {"affinity_cores": len(aff), "affinity": f"{aff[0]}-{aff[-1]}" if aff else "",
+                     "os_cpu_count": os.cpu_count(),
+                     "note": "all_cores uses every core of the affinity set up to 16, the CPU share of a one-GPU box"}}
 
 
 def matching_profile(name, tuning, config):
@@ -110,6 +136,63 @@ def profiled_limits(tuning, config):
     if prof is None:
         return {"note": why}
     return dict(prof["limits"], source="profiles/k_batched_batched-1M_counters.md")
+
+
+def given_order_leg(X, ctx, w, recs_t, got, T, stream, dev, bytes_step, steps=2):
+    """The same batch worked in the given order (CG_KEEP_ORDER: no source-block
+    segments, so almost no byte is re-read from cache): every examined byte
+    comes from HBM, and the algorithmic rate is an HBM rate."""
+    import numpy as np
+    import torch
+    from paper_1310_0901_amd.harness import verdicts_tensor, verdicts_np
+    mode = X.CG_CHECK | X.CG_KEEP_ORDER
+    out = verdicts_tensor(T, dev)
+    tun = X.cg_autotune(ctx, recs_t.data_ptr(), T, out.data_ptr(), mode, stream, TUNE_CACHE).as_dict()
+    X.check_transfers(ctx, recs_t.data_ptr(), T, out.data_ptr(), mode, stream)   # warm-up
+    torch.cuda.synchronize(dev)
+    X.cg_kernel_ms(ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X.check_transfers(ctx, recs_t.data_ptr(), T, out.data_ptr(), mode, stream)
+    torch.cuda.synchronize(dev)
+    wall = (time.perf_counter() - t0) / steps
+    kms, nk = X.cg_kernel_ms(ctx)
+    k = kms / max(nk, 1)
+    v = verdicts_np(out, T)
+    same = all(np.array_equal(v[f], got[f]) for f in ("flags", "first_bad", "undef_bytes", "avail"))
+    o = {"ms_per_step": round(wall * 1e3, 3), "scan_ms": round(k, 3),
+         "GBps": round(bytes_step / wall / 1e9, 1), "scan_GBps": round(bytes_step / (k / 1e3) / 1e9, 1),
+         "scan_pct_hbm_peak": round(100 * bytes_step / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
+         "verdicts_identical_to_batched": bool(same), "tuning": tun,
+         "note": "check-only, records in their given order: traffic behind L2 is about 1.0x the algorithmic bytes "
+                 "(profiles/k_batched_given-order_traffic.md), so this rate is bound by HBM"}
+    log(f"[bench] given order: {o}")
+    return o
+
+
+def probe_l2(X, dev, stream, cus=256):
+    """L2-resident read ceiling (cg_probe_l2): 8 slices, one per XCD, each
+    re-read by 8 blocks per CU with the scan kernel's cached 16-byte loads;
+    the best of three slice sizes that fit the 4 MB L2 of an XCD."""
+    import torch
+    best, rates = 0.0, {}
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    for mib in (1, 2, 3):
+        sl = mib << 20
+        buf = torch.zeros(8 * sl, dtype=torch.uint8, device=dev)
+        blocks, passes = 8 * cus, 16
+        X.cg_probe_l2(buf.data_ptr(), sl, passes, blocks, sink.data_ptr(), stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            X.cg_probe_l2(buf.data_ptr(), sl, passes, blocks, sink.data_ptr(), stream)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        r = blocks * sl * passes * 3 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        rates[f"{mib}MiB"] = round(r, 1)
+        best = max(best, r)
+        del buf
+    return {"GBps": round(best, 1), "by_slice": rates}
 
 
 TUNE_CACHE = os.environ.get("XC_TUNE_CACHE", os.path.join(ROOT, "paper_1310_0901_amd", "tuning_cache.jsonl"))
@@ -394,9 +477,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-given-order", dest="given_order", action="store_false",
+                    help="skip the given-order (CG_KEEP_ORDER) run of the same batch")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the launch-shape autotuner (by default its cached choice is used, or it tunes)")
-    ap.add_argument("--cpu-bytes", type=float, default=12e9)
+    ap.add_argument("--cpu-bytes", type=float, default=12e9, help="sample of the all-core oracle leg")
+    ap.add_argument("--cpu-bytes-one", type=float, default=2e9, help="sample of the one-thread oracle leg")
     ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg (configuration 5)")
     ap.add_argument("--plain-serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-legs", dest="legs", action="store_false",
@@ -499,6 +585,9 @@ def main():
         result["speedup_batched_over_plain"] = round(pwall / (wall / args.steps), 2)
         log(f"[bench] plain: {pwall * 1e3:.0f} ms, identical verdicts: {same}")
 
+    if args.given_order:
+        result["given_order"] = given_order_leg(X, ctx, w, recs_t, got, T, stream, dev, bytes_step)
+
     if not args.no_probe:
         sink = torch.zeros(1, dtype=torch.int64, device=dev)
         nb = (dw.hv.numel() // 16) * 16
@@ -523,10 +612,11 @@ def main():
         # read + write bytes: the practical ceiling of the propagating variant
         cp = 2 * cp_bytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
         del dst
+        l2 = probe_l2(X, dev, stream)
         result["probe_read_GBps"] = round(rd, 1)
-        result["pct_of_probe_read"] = round(100 * value / rd, 2)
         result["probe_copy_GBps"] = round(cp, 1)
-        log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write)")
+        result["probe_l2_read"] = l2
+        log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write), L2-resident read {l2}")
 
     traffic, traffic_note = profiled_traffic(tun, args.config)
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -538,11 +628,7 @@ def main():
                           "algorithmic_bytes_per_launch": int(bytes_step),
                           "limits": profiled_limits(tun, args.config)}
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        gbs, text, same, dt = cpu_baseline(w, hv, ha, got, args.cpu_bytes, threads)
-        result["cpu_baseline"] = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-                                  "sample": text, "verdicts_identical_to_gpu": bool(same)}
-        log(f"[bench] oracle sample {gbs:.2f} GB/s on {threads} threads, identical: {same}")
+        result["cpu_baseline"] = cpu_baseline_legs(w, hv, ha, got, args.cpu_bytes, args.cpu_bytes_one)
     dw.close()
     if args.legs:
         result["concurrency"] = concurrency_leg(w.records)

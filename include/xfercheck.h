@@ -256,6 +256,23 @@ int cg_sync(cg_ctx *ctx);
 /* Number of live allocations and bytes of shadow pool in use. */
 int cg_stats(cg_ctx *ctx, uint64_t *live_allocs, uint64_t *pool_used);
 
+/*
+ * Test hook: the device copy of the allocation list (Sec. 2, Fig. 2 caption)
+ * as the next check will read it, copied to host memory.  A new table version
+ * is made first if allocations or frees are pending (by device merge of the
+ * previous version with the changes, or by full upload when the changes are
+ * many).  base/end/off get the n live allocations sorted by base: their
+ * [base, end) and the byte offset of their V bytes in the shadow pool (cap
+ * entries at most); top gets every 2^shift-th base (ntop entries, top_cap at
+ * most).  pool, merges and full_uploads (each may be NULL) get the pool's
+ * device address and how many versions were made by device merge and by full
+ * upload so far.  Synchronous; host buffers are the caller's.
+ * Errors: CG_EINVAL (null arguments, buffers too small), CG_EHIP.
+ */
+int cg_table_read(cg_ctx *ctx, uint64_t *base, uint64_t *end, uint64_t *off, uint64_t cap, uint64_t *n,
+                  uint64_t *top, uint32_t top_cap, uint32_t *ntop, uint32_t *shift, uint64_t *pool,
+                  uint64_t *merges, uint64_t *full_uploads);
+
 /* ---- concurrent accesses ------------------------------------------------- */
 /*
  * Sec. 2 counts some concurrent accesses, when a program uses several
@@ -363,6 +380,13 @@ int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
 int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip_stream);
 /* Copy `bytes` (multiple of 16) from src to dst. */
 int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
+/* L2-resident read ceiling: dev holds 8 slices of slice_bytes (a multiple of
+ * 16 KiB, at least 16 KiB); `blocks` blocks of 256 threads each read slice
+ * (block mod 8), the XCD the block runs on, `passes` times with cached
+ * 16-byte loads, each block from its own offset.  Bytes read =
+ * blocks * slice_bytes * passes.  Errors: CG_EINVAL, CG_EHIP. */
+int cg_probe_l2(const void *dev, uint64_t slice_bytes, uint32_t passes, uint32_t blocks, uint64_t *sink_dev,
+                void *hip_stream);
 
 
 /* ---- serving: continuous batching of check requests ----------------------- */

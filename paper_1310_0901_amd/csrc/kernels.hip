@@ -1051,6 +1051,28 @@ __global__ void __launch_bounds__(256) k_probe_read(const u32x4 *p, uint64_t n16
     if (x == 0x9E3779B9u) atomicXor((unsigned long long *)sink, (unsigned long long)x);
 }
 
+// L2-resident read ceiling: block b reads slice b mod 8 (the XCD it runs on)
+// `passes` times with the same cached 16-byte loads as the scan kernel, each
+// block from its own starting offset, so that the blocks sharing a CU do not
+// hit in its L1 on each other's lines; a slice that fits its XCD's L2 is then
+// served from L2 to the L1s.
+__global__ void __launch_bounds__(256) k_probe_l2(const u32x4 *p, uint64_t slice16, uint32_t passes, uint64_t *sink)
+{
+    const u32x4 *q = p + (uint64_t)(blockIdx.x % kXcds) * slice16;
+    const uint64_t step = 4ull * blockDim.x;
+    const uint64_t groups = slice16 / step;   // whole groups of 4 loads per thread
+    uint64_t g = ((uint64_t)(blockIdx.x / kXcds) * 37u) % (groups ? groups : 1);
+    u32x4 acc{0u, 0u, 0u, 0u};
+    for (uint64_t k = 0; k < groups * passes; ++k) {
+        const u32x4 *r = q + g * step + threadIdx.x;
+        const u32x4 a = r[0], b = r[blockDim.x], c = r[2 * blockDim.x], d = r[3 * blockDim.x];
+        acc ^= a ^ b ^ c ^ d;
+        g = g + 1 == groups ? 0 : g + 1;
+    }
+    const uint32_t x = acc.x ^ acc.y ^ acc.z ^ acc.w;
+    if (x == 0x9E3779B9u) atomicXor((unsigned long long *)sink, (unsigned long long)x);
+}
+
 __global__ void __launch_bounds__(256) k_probe_copy(u32x4 *d, const u32x4 *p, uint64_t n16)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1149,6 +1171,14 @@ hipError_t launch_probe_read(const void *p, uint64_t bytes, uint64_t *sink, hipS
 {
     hipLaunchKernelGGL(k_probe_read, dim3(8192), dim3(256), 0, s, reinterpret_cast<const u32x4 *>(p), bytes / 16,
                        sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_l2(const void *p, uint64_t slice_bytes, uint32_t passes, uint32_t blocks, uint64_t *sink,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_probe_l2, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const u32x4 *>(p), slice_bytes / 16,
+                       passes, sink);
     return hipGetLastError();
 }
 

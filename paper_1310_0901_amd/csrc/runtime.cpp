@@ -1171,6 +1171,34 @@ int cg_stats(cg_ctx *c, uint64_t *live, uint64_t *used)
     return CG_OK;
 }
 
+int cg_table_read(cg_ctx *c, uint64_t *base, uint64_t *end, uint64_t *off, uint64_t cap, uint64_t *n, uint64_t *top,
+                  uint32_t top_cap, uint32_t *ntop, uint32_t *shift, uint64_t *pool, uint64_t *merges,
+                  uint64_t *full_uploads)
+{
+    if (!c || !base || !end || !off || !n || !top || !ntop || !shift) return CG_EINVAL;
+    int rc = ctx_begin(c);
+    if (!rc) rc = materialize(c);
+    if (rc) return rc;
+    const TableVersion &v = c->ver[c->cur];
+    const DevState &st = *c->h_state;
+    const uint64_t M = c->max_allocs;
+    if (v.n > cap || st.table.ntop > top_cap) return fail(c, CG_EINVAL, "cg_table_read: buffers too small");
+    HIPTRY(c, hipStreamSynchronize(c->s));
+    if (v.n) {
+        HIPTRY(c, hipMemcpy(base, v.tab, v.n * 8, hipMemcpyDeviceToHost));
+        HIPTRY(c, hipMemcpy(end, v.tab + M, v.n * 8, hipMemcpyDeviceToHost));
+        HIPTRY(c, hipMemcpy(off, v.tab + 2 * M, v.n * 8, hipMemcpyDeviceToHost));
+        HIPTRY(c, hipMemcpy(top, v.tab + 3 * M, st.table.ntop * 8ull, hipMemcpyDeviceToHost));
+    }
+    *n = v.n;
+    *ntop = v.n ? st.table.ntop : 0;
+    *shift = st.table.top_shift;
+    if (pool) *pool = (uint64_t)c->pool;
+    if (merges) *merges = c->merges;
+    if (full_uploads) *full_uploads = c->full_uploads;
+    return CG_OK;
+}
+
 int cg_get_tuning(cg_ctx *c, cg_tuning *t)
 {
     if (!c || !t) return CG_EINVAL;
@@ -1335,6 +1363,16 @@ int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip
 {
     if (!dev || !sink_dev || (bytes & 15u) || ((uint64_t)dev & 15u)) return CG_EINVAL;
     return launch_probe_read(dev, bytes, sink_dev, (hipStream_t)hip_stream) == hipSuccess ? CG_OK : CG_EHIP;
+}
+
+int cg_probe_l2(const void *dev, uint64_t slice_bytes, uint32_t passes, uint32_t blocks, uint64_t *sink_dev,
+                void *hip_stream)
+{
+    if (!dev || !sink_dev || ((uint64_t)dev & 15u) || slice_bytes < 16384 || (slice_bytes & 16383u) || passes == 0 ||
+        blocks == 0)
+        return CG_EINVAL;
+    return launch_probe_l2(dev, slice_bytes, passes, blocks, sink_dev, (hipStream_t)hip_stream) == hipSuccess ? CG_OK
+                                                                                                           : CG_EHIP;
 }
 
 int cg_probe_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream)

@@ -168,5 +168,7 @@ hipError_t launch_2d_fold(const cg_transfer2d *recs, const uint64_t *first, uint
 hipError_t launch_pointers(const DevState *st, const uint64_t *ptrs, uint64_t count, cg_ptr_check *out, hipStream_t s);
 hipError_t launch_probe_read(const void *p, uint64_t bytes, uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_copy(void *d, const void *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_probe_l2(const void *p, uint64_t slice_bytes, uint32_t passes, uint32_t blocks, uint64_t *sink,
+                           hipStream_t s);
 
 }  // namespace xc

@@ -98,6 +98,8 @@ _PROTOS = {
     "cg_last_error": (ctypes.c_char_p, [P]),
     "cg_sync": (I32, [P]),
     "cg_stats": (I32, [P, PU64, PU64]),
+    "cg_table_read": (I32, [P, P, P, P, U64, PU64, P, U32, ctypes.POINTER(U32), ctypes.POINTER(U32), PU64, PU64,
+                            PU64]),
     "cg_get_tuning": (I32, [P, ctypes.POINTER(cg_tuning)]),
     "cg_set_tuning": (I32, [P, ctypes.POINTER(cg_tuning)]),
     "cg_autotune": (I32, [P, P, U64, P, U32, P, ctypes.c_char_p, ctypes.POINTER(cg_tuning)]),
@@ -105,6 +107,7 @@ _PROTOS = {
     "cg_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double), PU64]),
     "cg_probe_read": (I32, [P, U64, P, P]),
     "cg_probe_copy": (I32, [P, P, U64, P]),
+    "cg_probe_l2": (I32, [P, U64, U32, U32, P, P]),
     "cg_serve_run": (I32, [P, P, U64, ctypes.POINTER(cg_serve_config), P, ctypes.POINTER(cg_serve_stats)]),
 }
 
@@ -234,6 +237,22 @@ def cg_sync(ctx) -> None:
     _chk(ctx, lib().cg_sync(ctx), "cg_sync")
 
 
+def cg_table_read(ctx, cap, top_cap=1024) -> dict:
+    """Host copy of the device table (test hook): base, end, off, top arrays,
+    shift, pool address, merges and full uploads so far."""
+    import numpy as np
+    b, e, o = (np.zeros(cap, np.uint64) for _ in range(3))
+    t = np.zeros(top_cap, np.uint64)
+    n, pool, merges, full = (ctypes.c_uint64() for _ in range(4))
+    ntop, shift = ctypes.c_uint32(), ctypes.c_uint32()
+    _chk(ctx, lib().cg_table_read(ctx, b.ctypes.data, e.ctypes.data, o.ctypes.data, cap, ctypes.byref(n),
+                                  t.ctypes.data, top_cap, ctypes.byref(ntop), ctypes.byref(shift), ctypes.byref(pool),
+                                  ctypes.byref(merges), ctypes.byref(full)), "cg_table_read")
+    k = n.value
+    return {"base": b[:k], "end": e[:k], "off": o[:k], "top": t[:ntop.value], "shift": shift.value,
+            "pool": pool.value, "merges": merges.value, "full_uploads": full.value}
+
+
 def cg_stats(ctx):
     a, b = ctypes.c_uint64(), ctypes.c_uint64()
     _chk(ctx, lib().cg_stats(ctx, ctypes.byref(a), ctypes.byref(b)), "cg_stats")
@@ -273,6 +292,10 @@ def cg_probe_read(dev, nbytes, sink_dev, stream=0) -> None:
 
 def cg_probe_copy(dst, src, nbytes, stream=0) -> None:
     _chk(None, lib().cg_probe_copy(dst, src, nbytes, stream), "cg_probe_copy")
+
+
+def cg_probe_l2(dev, slice_bytes, passes, blocks, sink_dev, stream=0) -> None:
+    _chk(None, lib().cg_probe_l2(dev, slice_bytes, passes, blocks, sink_dev, stream), "cg_probe_l2")
 
 
 def cg_serve_run(ctx, events, cfg: cg_serve_config):

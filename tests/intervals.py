@@ -209,3 +209,21 @@ def expected(w, records=None):
     fb = np.where(first >= big, NONE, first.astype(np.uint64))
     fb = np.where(bad_kind | zero, NONE, fb)
     return flags.astype(np.uint32), fb.astype(np.uint64), undef.astype(np.uint64), avail.astype(np.uint64)
+
+
+def piece_closed_form(w, stage):
+    """Undefined bytes and first undefined offset of each piece [a, b) of the
+    2 GiB region (pieces cut at the same offsets in every stage): the padding
+    bytes 13..15 of every 16-byte record, plus the one payload byte of each
+    payload record, counted by arithmetic rather than by a byte loop."""
+    a = (stage["src"] - stage["src"][0]).astype(np.int64)
+    b = a + stage["n"].astype(np.int64)
+    pad = lambda x: 3 * (x // 16) + np.maximum(0, x % 16 - 13)     # padding bytes in [0, x)
+    pos = np.sort(16 * np.asarray(w.payload_records, np.int64) + np.asarray(w.payload_byte, np.int64))
+    lo, hi = np.searchsorted(pos, a), np.searchsorted(pos, b)
+    und = (pad(b) - pad(a) + (hi - lo)).astype(np.uint64)
+    first_pad = np.where(a % 16 <= 13, 13 - a % 16, 0)
+    first_pay = np.where(hi > lo, pos[np.minimum(lo, pos.size - 1)] - a, np.iinfo(np.int64).max)
+    first = np.minimum(first_pad, first_pay)
+    first = np.where(first < b - a, first, -1).astype(np.int64).astype(np.uint64)   # -1: none (~0)
+    return und, first

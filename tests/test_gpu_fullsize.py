@@ -125,6 +125,10 @@ def test_config4_full_chain(X, H, pieces):
             else:
                 assert np.all(got["flags"] == X.CG_SRC_UNDEF)
                 assert np.all(got["avail"] == stage["n"] + (w.host.length - (stage["src"] - stage["src"][0]) - stage["n"]))
+                # each piece [a, b) of the region against its closed form
+                und, first = intervals.piece_closed_form(w, stage)
+                assert np.array_equal(got["undef_bytes"], und), h
+                assert np.array_equal(got["first_bad"], first), h
         last = w.dev.live_idx[-1]
         dv = H.device_view(X.shadow_ptr(dw.ctx, int(w.dev.base[last])), w.host.length)
         assert torch.equal(dv, dw.hv[: w.host.length]), "final shadow differs from host V"

@@ -116,6 +116,7 @@ def test_full_table_sampled(X):
     b = W.pointer_batch()
     ctx = make_ctx(X, b.bases, b.sizes)
     try:
+        gpu_check(X, ctx, b.ptrs[:16])   # the table is on the device, so the frees below are merged
         X.shadow_free_batch(ctx, b.bases[b.freed])
         live = np.setdiff1d(np.arange(b.bases.size), b.freed)
         got = gpu_check(X, ctx, b.ptrs)
@@ -130,5 +131,61 @@ def test_full_table_sampled(X):
         assert (got["avail"][ok] <= b.sizes[pos]).all()
         assert (got["base"][ok] + b.sizes[pos] - got["avail"][ok] == b.ptrs[ok]).all()
         assert ((got["base"][~ok] == 0) & (got["avail"][~ok] == 0)).all()
+    finally:
+        X.cg_destroy(ctx)
+
+
+def test_table_merges_at_full_size(X):
+    """The device table at 975,000 entries after 30 rounds of frees and new
+    allocations, each round made into a new version by the device merge (the
+    list is updated on every allocation and free, Sec. 2 / Fig. 2 caption):
+    every base, end, shadow offset and top-level entry read back equals the
+    host's sorted list, and sampled lookups equal the oracle's."""
+    b = W.pointer_batch()
+    ctx = make_ctx(X, b.bases, b.sizes)
+    rng = np.random.default_rng(77)
+    try:
+        gpu_check(X, ctx, b.ptrs[:16])                      # first version: a full upload
+        full0 = X.cg_table_read(ctx, b.bases.size + 16)["full_uploads"]
+        live = {int(x): int(z) for x, z in zip(b.bases, b.sizes)}
+        freed = []
+        for r in range(30):
+            keys = np.array(sorted(live), np.uint64)
+            kill = np.sort(rng.choice(keys.size, 2000, replace=False))
+            X.shadow_free_batch(ctx, keys[kill])
+            for k in keys[kill]:
+                freed.append((int(k), live.pop(int(k))))
+            # re-allocate earlier freed blocks at their base, with a size no larger
+            rng.shuffle(freed)
+            take, freed = freed[:1500], freed[1500:]
+            nb = np.array([f[0] for f in take], np.uint64)
+            ns = np.array([max(1, int(rng.integers(1, f[1] + 1))) for f in take], np.uint64)
+            X.shadow_alloc_batch(ctx, nb, ns)
+            live.update({int(x): int(z) for x, z in zip(nb, ns)})
+            if r % 3 == 2:
+                gpu_check(X, ctx, b.ptrs[r * 1000:(r + 1) * 1000])   # a check makes the version
+            if r % 10 == 9:
+                t = X.cg_table_read(ctx, len(live) + 16)
+                keys = np.array(sorted(live), np.uint64)
+                sizes = np.array([live[int(k)] for k in keys], np.uint64)
+                assert np.array_equal(t["base"], keys), f"round {r}: bases"
+                assert np.array_equal(t["end"], keys + sizes), f"round {r}: ends"
+                top = t["base"][:: 1 << t["shift"]]
+                assert t["top"].size <= 1024 and np.array_equal(t["top"], top), f"round {r}: top level"
+                # shadow slots: 256-byte aligned, disjoint, and where shadow_ptr says
+                o = t["off"]
+                order = np.argsort(o)
+                assert (o % 256 == 0).all()
+                assert (o[order][:-1] + (sizes[order][:-1] + 255) // 256 * 256 <= o[order][1:]).all()
+                for j in rng.choice(keys.size, 3000, replace=False):
+                    assert X.shadow_ptr(ctx, int(keys[j])) == t["pool"] + int(o[j])
+        # every version after the first was a device merge
+        assert t["full_uploads"] == full0 and t["merges"] >= 10, (t["merges"], t["full_uploads"], full0)
+        keys = np.array(sorted(live), np.uint64)
+        sizes = np.array([live[int(k)] for k in keys], np.uint64)
+        idx = np.sort(rng.choice(b.ptrs.size, 3000, replace=False))
+        probe = np.concatenate([b.ptrs[idx], keys[:500], keys[:500] + sizes[:500], np.array([f[0] for f in freed[:500]],
+                                                                                          np.uint64)])
+        assert same(gpu_check(X, ctx, probe), oracle.pointers(keys, sizes, probe))
     finally:
         X.cg_destroy(ctx)

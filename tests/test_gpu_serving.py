@@ -6,7 +6,7 @@ import pytest
 
 from paper_1310_0901_amd import workloads as W
 from tests import util
-from tests.serve_replay import replay
+from tests.serve_replay import replay, replay_sampled
 
 pytestmark = pytest.mark.gpu
 
@@ -60,3 +60,33 @@ def test_serving_mix_alone_and_oracle(S):
         res = runs[name][0]
         lat = res["t_done"] - res["t_arrive"]
         assert np.isfinite(lat).all() and (lat >= 0).all(), name
+
+
+@pytest.mark.slow
+def test_serving_full_log_sampled(S):
+    """The full serving configuration (500k requests at 50k/s, 975k initial
+    allocations, one alloc/free per 10 requests, so the device table is
+    re-merged tens of thousands of times) against a host replay of the log on
+    a sample: every 500th request, and the 20 requests after each of 200 table
+    events spread over the log."""
+    sw = W.config5()
+    hv, ha = W.host_v(sw.host), W.host_a(sw.host)
+    dw = S.serve_world(sw, host_arrays=(hv, ha))
+    try:
+        res, summ = S.run(dw, sw, S.config(streams=4, max_batch=64))
+    finally:
+        dw.close()
+    print(summ, flush=True)
+    assert summ["table_versions"] > 10_000
+    ev = sw.events
+    is_req = ev["type"] == W.EV_CHECK
+    req_before = np.cumsum(is_req) - is_req            # requests before each event
+    table_ev = np.flatnonzero(~is_req)
+    picks = table_ev[np.linspace(0, table_ev.size - 1, 200).astype(np.int64)]
+    after = (req_before[picks][:, None] + np.arange(20)[None, :]).ravel()
+    n_req = int(is_req.sum())
+    which = np.unique(np.concatenate([np.arange(0, n_req, 500), after[after < n_req]]))
+    want = replay_sampled(sw, which, hv, ha)
+    util.assert_verdicts_equal(verdicts(res)[which], want, "serving full log, sampled")
+    # the sample holds clean requests and requests into unallocated memory
+    assert (want["flags"] == 0).any() and (want["flags"] & (0x4 | 0x20)).any()

@@ -90,3 +90,36 @@ def test_generators_are_seeded_and_shaped():
     n = w.records["n"].astype(np.float64)
     # log-uniform sizes: median near sqrt(8 * 16 MiB)
     assert 0.8 < np.median(n) / np.sqrt(8 * 16 * 2 ** 20) < 1.25
+
+
+def test_sampled_serving_replay_equals_full_replay():
+    """The sampled replay (live set tracked by event index, V materialised
+    only for the allocations each request touches) gives the full sequential
+    replay's verdicts on a small log, for every request."""
+    from tests.serve_replay import replay, replay_sampled
+    sw = W.small_serve()
+    want = replay(sw)
+    n = want.size
+    which = np.arange(n)
+    got = replay_sampled(sw, which, W.host_v(sw.host), W.host_a(sw.host))
+    for f in ("flags", "first_bad", "undef_bytes", "avail"):
+        assert np.array_equal(got[f], want[f]), f
+    # the log makes and frees allocations that requests then hit
+    assert (want["flags"] & (DST_UNALLOC | SRC_UNALLOC)).any()
+
+
+@pytest.mark.parametrize("pieces", [1, 7, 64])
+def test_config4_piece_closed_form_matches_oracle(pieces):
+    """The per-piece closed form used at full size (padding bytes by
+    arithmetic, payload bytes by search) equals the oracle on a 1 MiB region
+    cut into pieces, on the first stage and on a device-to-device hop."""
+    w = W.config4(host_len=1 << 20, pieces=pieces)
+    st = oracle_for(w)
+    for h in (0, 1):
+        stage = w.stages[h]
+        if h == 1:
+            st.run(w.stages[0], check=False, propagate=True)
+        got = st.run(stage)
+        und, first = intervals.piece_closed_form(w, stage)
+        assert np.array_equal(got["undef_bytes"], und)
+        assert np.array_equal(got["first_bad"], first)
