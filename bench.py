@@ -212,7 +212,9 @@ def plain_tiny_leg():
     from paper_1310_0901_amd.harness import DeviceWorld, records_tensor, verdicts_tensor, verdicts_np
     w = W.config1()
     dw = DeviceWorld(w)
-    out = {"workload": f"{w.name} (configuration 1): {w.note}"}
+    out = {"workload": f"{w.name} (configuration 1): {w.note}",
+           "path": f"batches of up to 256 records run in one launch (k_small); larger ones as classify, scans and "
+                   f"the persistent kernel"}
     try:
         ctx, T, s = dw.ctx, w.count, torch.cuda.current_stream().cuda_stream
         rt, ob = records_tensor(w.records), verdicts_tensor(T)
@@ -229,6 +231,14 @@ def plain_tiny_leg():
                     ts.append(time.perf_counter() - t0)
             res[name] = verdicts_np(ob, T)
             out[name] = {"median_us_per_call": round(float(np.median(ts)) * 1e6, 1)}
+            # device time of the check's kernels (events around them on the stream)
+            X.cg_timing(ctx, True)
+            X.cg_kernel_ms(ctx)
+            for _ in range(20):
+                X.check_transfers(ctx, rt.data_ptr(), T, ob.data_ptr(), mode, s)
+            ms, k = X.cg_kernel_ms(ctx)
+            X.cg_timing(ctx, False)
+            out[name]["kernel_us_per_call"] = round(ms * 1e3 / 20, 1)
         out["verdicts_identical"] = bool(all(np.array_equal(res["plain"][f], res["batched_graph"][f])
                                              for f in ("flags", "first_bad", "undef_bytes", "avail")))
     finally:

@@ -35,6 +35,11 @@
 // is reported.  Copies of one window are taken as unordered unless they share
 // a stream; copies in different windows as ordered, so a race across a
 // synchronising call is not reported (no false reports, possibly missed ones).
+// Work on the null stream (stream 0) waits for all earlier work on blocking
+// streams and all later work on them waits for it, so an asynchronous copy,
+// fill or kernel launch on stream 0 also closes the window, before and after
+// its own copy; copies on non-blocking streams (hipStreamNonBlocking) are not
+// ordered by it and stay in the window, and a pair is reported once.
 //
 // Kernel arguments (the outlook of Sec. 5.1): hipLaunchKernel is wrapped, the
 // kernel's parameter list is recovered by demangling its name, and every
@@ -142,6 +147,7 @@ struct WinCopy {
     hipStream_t stream;
     const char *api = "hipMemcpyAsync";
     bool fill = false;
+    uint64_t seq = 0;   // issue order, names the copy in reported pairs
 };
 
 // A window this long is joined at once, as if a synchronising call had come:
@@ -168,6 +174,8 @@ struct State {
     uint64_t copies = 0, errors = 0;
     // the window of asynchronous copies since the last synchronising call
     std::vector<WinCopy> win;
+    uint64_t win_seq = 0;
+    std::set<std::pair<uint64_t, uint64_t>> reported;   // pairs (by seq) reported while their copies stay in the window
     cg_transfer *d_wrec = nullptr;
     uint32_t *d_wsid = nullptr;
     cg_race *d_wres = nullptr;
@@ -412,18 +420,21 @@ bool check_copy(const char *api, void *dst, const void *src, size_t n, uint32_t 
 }
 
 // the rows of a pitched asynchronous copy join the concurrent-access window
-void close_window();
+void close_window(bool keep_non_blocking = false);
+void window_push(WinCopy c);
+void null_stream_point(hipStream_t stream);
 
 void window_rows(const Pitched &p, uint32_t kind, hipStream_t stream)
 {
     std::lock_guard<std::mutex> lk(G.mu);
+    null_stream_point(stream);
     for (size_t z = 0; z < p.depth; ++z)
         for (size_t y = 0; y < p.height; ++y)
-            G.win.push_back(WinCopy{cg_transfer{(uint64_t)(p.src + z * p.sslice + y * p.spitch),
-                                                (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width,
-                                                kind, 0},
-                                    stream, "hipMemcpy2DAsync/3DAsync row"});
-    if (G.win.size() >= kWindowMax) close_window();
+            window_push(WinCopy{cg_transfer{(uint64_t)(p.src + z * p.sslice + y * p.spitch),
+                                            (uint64_t)(p.dst + z * p.dslice + y * p.dpitch), (uint64_t)p.width, kind,
+                                            0},
+                                stream, "hipMemcpy2DAsync/3DAsync row"});
+    null_stream_point(stream);
 }
 
 // a 3D copy of linear memory as a Pitched copy
@@ -455,12 +466,46 @@ void describe(char *buf, size_t len, const WinCopy &c)
                  (void *)r.src, r.n, kind_name(r.kind), (void *)c.stream);
 }
 
+bool non_blocking(hipStream_t s)
+{
+    unsigned int f = 0;
+    return s != nullptr && hipStreamGetFlags(s, &f) == hipSuccess && (f & hipStreamNonBlocking);
+}
+
+void join_window(const std::vector<WinCopy> &w);
+
 // Join the window's copies and report each conflicting pair once; the caller
-// holds G.mu.  The window is emptied.
-void close_window()
+// holds G.mu.  The window is emptied, or, at work on the null stream
+// (keep_non_blocking), keeps the copies of non-blocking streams, which that
+// work does not order.
+void close_window(bool keep_non_blocking)
 {
     std::vector<WinCopy> w;
     w.swap(G.win);
+    join_window(w);
+    if (keep_non_blocking)
+        for (const WinCopy &c : w)
+            if (non_blocking(c.stream)) G.win.push_back(c);
+    if (G.win.empty()) G.reported.clear();
+}
+
+// a copy joins the window
+void window_push(WinCopy c)
+{
+    c.seq = G.win_seq++;
+    G.win.push_back(c);
+    if (G.win.size() >= kWindowMax) close_window();
+}
+
+// asynchronous work on `stream`: on the null stream it is ordered after the
+// window's copies on blocking streams, and later work on them after it
+void null_stream_point(hipStream_t stream)
+{
+    if (stream == nullptr && !G.win.empty()) close_window(true);
+}
+
+void join_window(const std::vector<WinCopy> &w)
+{
     if (w.size() < 2 || !G.ctx) return;
     std::map<hipStream_t, uint32_t> ids;
     std::vector<uint32_t> sid(w.size());
@@ -500,11 +545,11 @@ void close_window()
         fprintf(stderr, "==xfercheck== concurrent-access check failed: %s\n", cg_last_error(G.ctx));
         return;
     }
-    std::set<std::pair<uint64_t, uint64_t>> seen;
     for (uint64_t a = 0; a < n; ++a) {
         if (!(res[a].flags & (CG_RACE_SRC | CG_RACE_DST)) || res[a].partner >= n) continue;
         const uint64_t b = res[a].partner;
-        if (!seen.insert({std::min(a, b), std::max(a, b)}).second) continue;
+        const uint64_t qa = w[a].seq, qb = w[b].seq;
+        if (!G.reported.insert({std::min(qa, qb), std::max(qa, qb)}).second) continue;
         const cg_transfer &x = r[a], &y = r[b];
         // what the first copy does to the shared bytes, and what the second does
         const bool ww = meets(x.dst, x.n, y.dst, y.n), wr = meets(x.dst, x.n, y.src, y.n);
@@ -712,8 +757,9 @@ bool track_fill(const char *api, void *dst, size_t n, bool async, hipStream_t st
         if (!G.allow_bad) return false;
     }
     if (async) {
-        G.win.push_back(WinCopy{cg_transfer{(uint64_t)dst, (uint64_t)dst, (uint64_t)n, CG_D2D, 0}, stream, api, true});
-        if (G.win.size() >= kWindowMax) close_window();
+        null_stream_point(stream);
+        window_push(WinCopy{cg_transfer{(uint64_t)dst, (uint64_t)dst, (uint64_t)n, CG_D2D, 0}, stream, api, true});
+        null_stream_point(stream);
     }
     return true;
 }
@@ -724,8 +770,9 @@ bool async_copy(const char *api, void *dst, const void *src, size_t n, uint32_t 
     if (inside || !n || d > CG_D2D) return true;
     if (!check_copy(api, dst, src, n, d)) return false;
     std::lock_guard<std::mutex> lk(G.mu);
-    G.win.push_back(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream, api});
-    if (G.win.size() >= kWindowMax) close_window();
+    null_stream_point(stream);
+    window_push(WinCopy{cg_transfer{(uint64_t)src, (uint64_t)dst, (uint64_t)n, d, 0}, stream, api});
+    null_stream_point(stream);
     return true;
 }
 
@@ -890,6 +937,11 @@ hipError_t hipLaunchKernel(const void *fn, dim3 grid, dim3 block, void **args, s
     static launch_t f = real<launch_t>("hipLaunchKernel");
     if (!inside && args && G.kernel_args && !check_launch("hipLaunchKernel", fn, args, stream))
         return refuse();
+    if (!inside && stream == nullptr) {
+        // a kernel on the null stream orders the blocking streams' copies around it
+        std::lock_guard<std::mutex> lk(G.mu);
+        null_stream_point(stream);
+    }
     return f(fn, grid, block, args, shmem, stream);
 }
 

@@ -610,16 +610,22 @@ __device__ __forceinline__ void region_clip(uint64_t p, uint64_t n, uint64_t hb,
 
 __device__ __forceinline__ uint64_t clamp_scan(uint64_t x) { return x < kScanLimit ? x : kScanLimit; }
 
-// Decode record t; write its verdict's range-derived fields and its
-// descriptor; return its number of units.
-__device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
+// does the record have a device source / destination to look up?
+__device__ __forceinline__ bool dev_src(const cg_transfer &r) { return r.kind <= CG_D2D && r.n && r.kind != CG_H2D; }
+__device__ __forceinline__ bool dev_dst(const cg_transfer &r) { return r.kind <= CG_D2D && r.n && r.kind != CG_D2H; }
+
+// Decode record r, given the table entries holding its device source and
+// destination pointers (js, jd: -1 when none, or when the side is on the
+// host): its descriptor, its verdict's range-derived fields, and its number
+// of units (returned).
+__device__ uint64_t classify_rec(const cg_transfer &r, uint32_t mode, const DevState &st, int64_t js, int64_t jd,
+                                 Desc &ds, cg_verdict &v)
 {
-    const cg_transfer r = a.recs[t];
     const uint64_t n = r.n;
-    Desc ds = {};
+    ds = Desc{};
     uint32_t flags = 0;
     uint64_t first = NONE, avail = 0;
-    const bool check = (a.mode & CG_CHECK) != 0;
+    const bool check = (mode & CG_CHECK) != 0;
     uint64_t units = 0;
 
     if (r.kind > CG_D2D) {
@@ -641,7 +647,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
             phi = (uint32_t)((r.src - R.hb) & 15u);
             ds.a_src = (int64_t)((r.src - R.hb) - phi);
         } else {
-            const int64_t j = table_lookup(st.table, top, r.src);
+            const int64_t j = js;
             if (j < 0) { flags |= CG_SRC_UNALLOC; first = 0; }
             else {
                 avail_s = st.table.end[j] - r.src;
@@ -662,7 +668,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
             psi = (uint32_t)((r.dst - R.hb) & 15u);
             ds.a_dst = (int64_t)((r.dst - R.hb) - psi);
         } else {
-            const int64_t j = table_lookup(st.table, top, r.dst);
+            const int64_t j = jd;
             if (j < 0) { flags |= CG_DST_UNALLOC; first = 0; }
             else {
                 avail_d = st.table.end[j] - r.dst;
@@ -681,7 +687,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
         }
         avail = src_host ? avail_d : (dst_host ? avail_s : (avail_s < avail_d ? avail_s : avail_d));
 
-        const bool prop = (a.mode & CG_PROPAGATE) && !overlap;
+        const bool prop = (mode & CG_PROPAGATE) && !overlap;
         const bool dsta = check && dst_host;
         const bool dstwork = (prop || dsta) && dst_ok;
         vlo = clamp_scan(vlo); vhi = clamp_scan(vhi);
@@ -713,17 +719,27 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
                  (phi << CTL_PHI_SHIFT) | (psi << CTL_PSI_SHIFT) | (delta ? CTL_DELTA : 0u);
         if (!src_ok) { ds.v_lo = 0; ds.v_hi = 0; }
     }
+    v.flags = flags;
+    v.reserved = 0;
+    v.first_bad = first;
+    v.undef_bytes = 0;
+    v.avail = avail;
+    return units;
+}
+
+// Record t of a batch: its descriptor and work weight, and its verdict's
+// range-derived fields; returns its number of units.
+__device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
+{
+    const cg_transfer r = a.recs[t];
+    const int64_t js = dev_src(r) ? table_lookup(st.table, top, r.src) : -1;
+    const int64_t jd = dev_dst(r) ? table_lookup(st.table, top, r.dst) : -1;
+    Desc ds;
+    cg_verdict v;
+    const uint64_t units = classify_rec(r, a.mode, st, js, jd, ds, v);
     a.desc[t] = ds;
     a.weight[t] = units;
-    if (a.out && check) {
-        cg_verdict v;
-        v.flags = flags;
-        v.reserved = 0;
-        v.first_bad = first;
-        v.undef_bytes = 0;
-        v.avail = avail;
-        a.out[t] = v;
-    }
+    if (a.out && (a.mode & CG_CHECK)) a.out[t] = v;
     return units;
 }
 
@@ -1012,6 +1028,153 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t
 }
 
 // ---------------------------------------------------------------------------
+// k_small: a small batch in one launch
+// ---------------------------------------------------------------------------
+
+// wave-wide sum of a 32-bit value (every lane active)
+__device__ __forceinline__ uint32_t wave_add32(uint32_t x)
+{
+    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d);
+    return x;
+}
+
+// The table search of table_lookup done by one wave (every lane active): the
+// top level, then the segment of 2^top_shift entries it picks, are each
+// compared 64 entries at a time, so two rounds of independent loads take the
+// place of a chain of dependent ones.  Entries are sorted by base, so the
+// number of them at or below p is one past the last of them.
+__device__ int64_t table_lookup_wave(const TableView &tb, uint64_t p)
+{
+    if (tb.n == 0) return -1;
+    const uint32_t lane = lane_id();
+    uint32_t c = 0;
+    for (uint32_t k = lane; k < tb.ntop; k += 64) c += tb.top[k] <= p ? 1u : 0u;
+    c = wave_add32(c);
+    if (c == 0) return -1;
+    const uint64_t a0 = (uint64_t)(c - 1) << tb.top_shift;
+    const uint64_t a1 = a0 + (1ull << tb.top_shift) < tb.n ? a0 + (1ull << tb.top_shift) : tb.n;
+    uint32_t c2 = 0;
+    for (uint64_t k = a0 + lane; k < a1; k += 64) c2 += tb.base[k] <= p ? 1u : 0u;
+    c2 = wave_add32(c2);
+    const uint64_t j = a0 + c2 - 1;   // base[a0] is top[c - 1] <= p, so c2 >= 1
+    return p < tb.end[j] ? (int64_t)j : -1;
+}
+
+// A batch of few records in one launch, up to `bpr` blocks per record.  The
+// blocks a record uses follow from its byte count alone (at most one per
+// kSmallUnits units), so that every block of the record agrees on them and
+// the unused ones leave after one load.  Block b of record t: wave 0 looks up
+// the record's device pointers and classifies it; the record's units are
+// split evenly over its blocks, and a block's share over its waves (the
+// wave-uniform loop).  A record of one block gets its whole verdict from that
+// block.  Otherwise a block that finds something merges it into the record's
+// accumulator with atomics; the last of the record's blocks to finish (the
+// accumulator's counter) writes the whole verdict -- the range-derived fields
+// of its own classification and the findings of all blocks -- and puts the
+// accumulator back to its starting state {NONE, 0, 0, 0}, so that the next
+// call needs no clearing.
+constexpr uint64_t kSmallUnits = 8192;
+
+template <int U, bool NT, bool PROP>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3)))
+k_small(BatchArgs a, SmallAcc *acc, uint32_t bpr)
+{
+    __shared__ Desc sd;
+    __shared__ cg_verdict sv;
+    __shared__ uint64_t su;
+    __shared__ uint64_t wfirst[8], wund[8];
+    __shared__ uint32_t wfl[8];
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t t = blockIdx.x / bpr;
+    const uint32_t b = blockIdx.x % bpr;
+    const cg_transfer r = a.recs[t];
+    // units never exceed n / 16 + 2 (one per 16-byte chunk the bytes touch)
+    const uint64_t most = r.kind <= CG_D2D && r.n ? r.n / 16 + 2 : 1;
+    const uint64_t want = (most + kSmallUnits - 1) / kSmallUnits;
+    const uint32_t nb = want < bpr ? (uint32_t)want : bpr;   // blocks of this record, at least 1
+    if (b >= nb) return;
+    const DevState *st = a.st;
+    if (wid == 0) {
+        const int64_t js = dev_src(r) ? table_lookup_wave(st->table, r.src) : -1;
+        const int64_t jd = dev_dst(r) ? table_lookup_wave(st->table, r.dst) : -1;
+        if (lane == 0) {
+            Desc ds;
+            cg_verdict v;
+            su = classify_rec(r, a.mode, *st, js, jd, ds, v);
+            sd = ds;
+            sv = v;
+        }
+    }
+    __syncthreads();
+    const uint64_t units = su;
+    // this block's units, then this wave's, in whole iterations of 64 units
+    const uint64_t per_b = ((units + nb - 1) / nb + 63) & ~63ull;
+    const uint64_t b0 = (uint64_t)b * per_b < units ? (uint64_t)b * per_b : units;
+    const uint64_t b1 = b0 + per_b < units ? b0 + per_b : units;
+    const uint64_t per_w = ((b1 - b0 + nw - 1) / nw + 63) & ~63ull;
+    const uint64_t k0 = b0 + wid * per_w < b1 ? b0 + wid * per_w : b1;
+    const uint64_t k1 = k0 + per_w < b1 ? k0 + per_w : b1;
+    Acc ac;
+    acc_reset(ac);
+    if (k1 > k0) {
+        const DV d = load_desc_uniform(&sd, 0);
+        run_uniform<U, NT, PROP>(d, st->region, k0, k1, ac);
+    }
+    if (!a.out) return;   // propagation only: no verdict (uniform over the grid)
+    uint64_t f = NONE, u = 0;
+    uint32_t fl = 0;
+    if (__ballot(ac.flags != 0u)) {
+        f = wave_min64(ac.first);
+        u = wave_sum64(ac.undef);
+        fl = wave_or32(ac.flags);
+    }
+    if (lane == 0) {
+        wfirst[wid] = f;
+        wund[wid] = u;
+        wfl[wid] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (uint32_t w = 1; w < nw; ++w) {
+        f = wfirst[w] < f ? wfirst[w] : f;
+        u += wund[w];
+        fl |= wfl[w];
+    }
+    cg_verdict v = sv;
+    if (nb > 1) {
+        SmallAcc &x = acc[t];
+        if (fl) {
+            atomicOr(&x.flags, fl);
+            if (f != NONE) atomicMin((unsigned long long *)&x.first, (unsigned long long)f);
+            if (u) atomicAdd((unsigned long long *)&x.undef, (unsigned long long)u);
+        }
+        __threadfence();
+        if (atomicAdd(&x.done, 1u) != nb - 1) return;
+        __threadfence();
+        // the last block of the record: every other block's findings are in
+        fl |= __hip_atomic_load(&x.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t af = __hip_atomic_load(&x.first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u = __hip_atomic_load(&x.undef, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        f = af < f ? af : f;
+        __hip_atomic_store(&x.flags, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&x.first, NONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&x.undef, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&x.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    v.flags |= fl;
+    v.first_bad = f < v.first_bad ? f : v.first_bad;
+    v.undef_bytes = u;
+    a.out[t] = v;
+}
+
+// accumulators to their starting state
+__global__ void __launch_bounds__(256) k_small_reset(SmallAcc *acc, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) acc[i] = SmallAcc{NONE, 0, 0, 0};
+}
+
+// ---------------------------------------------------------------------------
 // shadow fills and bandwidth probes
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_fill(const FillRange *ranges, uint64_t k)
@@ -1139,6 +1302,31 @@ static void launch_plain_t(const BatchArgs &a, uint64_t t, uint64_t units, uint3
 hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
 {
     XC_DISPATCH(launch_batched_t, a, sh, s);
+    return hipGetLastError();
+}
+
+template <int U, bool NT>
+static void launch_small_t(const BatchArgs &a, SmallAcc *acc, uint32_t bpr, uint32_t block, hipStream_t s)
+{
+    const dim3 grid((uint32_t)(a.count * bpr));
+    if (a.mode & CG_PROPAGATE)
+        hipLaunchKernelGGL((k_small<U, NT, true>), grid, dim3(block), 0, s, a, acc, bpr);
+    else
+        hipLaunchKernelGGL((k_small<U, NT, false>), grid, dim3(block), 0, s, a, acc, bpr);
+}
+
+hipError_t launch_small(const BatchArgs &a, SmallAcc *acc, uint32_t bpr, const LaunchShape &sh, hipStream_t s)
+{
+    if (a.count == 0 || bpr == 0 || a.count * bpr > 0x7FFFFFFFull || sh.block > 512 || sh.block % 64)
+        return hipErrorInvalidValue;
+    XC_DISPATCH(launch_small_t, a, acc, bpr, sh.block, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_reset(SmallAcc *acc, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_small_reset, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, acc, n);
     return hipGetLastError();
 }
 

@@ -41,6 +41,9 @@ constexpr cg_tuning kShortRowTuning = {256, 2, 16, 1u << 16, 0, {0, 0, 0}};
 // descriptors (about 40 GB at this size); larger batches keep their order
 constexpr uint64_t kSegMaxRecords = 1ull << 27;
 constexpr size_t kGraphsPerWs = 16;
+// batches of at most this many records are worked in one launch (k_small),
+// unless XC_SMALL_MAX sets another limit
+constexpr uint64_t kSmallMax = 256;
 constexpr int kVersions = 4;             // table versions in the device ring
 
 // A captured batched check.  With kernel timing on, the scan kernel is kept in
@@ -72,6 +75,7 @@ struct Workspace {
     uint32_t *tile_start = nullptr;
     Ctl *ctl = nullptr;
     uint64_t *h_weight = nullptr;   // pinned copy of weights (plain path)
+    SmallAcc *small = nullptr;      // small_max accumulators of the one-launch path (k_small)
     hipEvent_t done = nullptr;      // recorded after every check issued on this stream
     bool used = false;
     std::vector<GraphEntry> graphs;
@@ -173,6 +177,7 @@ struct cg_ctx {
     std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
     uint64_t reorder_min = 16384;            // batches this large are worked as source-block segments
     uint32_t seg_min_log2 = 20;              // smallest source block of the segments, log2
+    uint64_t small_max = kSmallMax;          // batches this small run in one launch (k_small); 0: never
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
@@ -379,6 +384,8 @@ void free_ws(Workspace *w)
     (void)hipFree(w->tile_start);
     (void)hipFree(w->ctl);
     if (w->h_weight) (void)hipHostFree(w->h_weight);
+    (void)hipFree(w->small);
+    w->small = nullptr;
     free_seg(w);
     w->desc = nullptr;
     w->weight = w->local = w->bsum = w->boff = w->prefix = nullptr;
@@ -415,6 +422,8 @@ int get_ws(cg_ctx *c, hipStream_t s, uint64_t count, Workspace **out)
         HIPTRY(c, hipMalloc(&w->tile_start, kTilesCap * 4));
         HIPTRY(c, hipMalloc(&w->ctl, sizeof(Ctl)));
         HIPTRY(c, hipHostMalloc(&w->h_weight, cap * 8, hipHostMallocDefault));
+        HIPTRY(c, hipMalloc(&w->small, std::max<uint64_t>(c->small_max, 1) * sizeof(SmallAcc)));
+        HIPTRY(c, launch_small_reset(w->small, std::max<uint64_t>(c->small_max, 1), s));
         w->cap = cap;
     }
     *out = w;
@@ -643,8 +652,20 @@ int reserve_segments(cg_ctx *c, Workspace *w, uint64_t count, hipStream_t s)
     return CG_OK;
 }
 
+// Blocks per record of a small batch, at most: `hint`, or else about 8
+// blocks of 256 threads per CU over the whole batch (a record uses fewer
+// when it is small, k_small).
+uint32_t small_bpr(const cg_ctx *c, uint64_t count, const LaunchShape &sh, uint32_t hint)
+{
+    const uint64_t grid = (uint64_t)c->cu_count * 8 * 256 / (sh.block ? sh.block : 256);
+    uint64_t bpr = hint ? hint : grid / (count ? count : 1);
+    if (bpr < 1) bpr = 1;
+    if (bpr > grid) bpr = grid;
+    return (uint32_t)bpr;
+}
+
 int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *out, uint32_t mode,
-              hipStream_t s, const cg_tuning &tun)
+              hipStream_t s, const cg_tuning &tun, uint32_t bpr = 0)
 {
     Workspace *w;
     const bool seg = segmented(c, count, mode);
@@ -681,7 +702,13 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         sp = &plan;
     }
     const LaunchShape sh = shape_of(c, tun);
-    if (mode & CG_PLAIN) {
+    if (!(mode & CG_PLAIN) && count <= c->small_max) {
+        // few records: one launch, no preparation kernels
+        TimingPair *tp = c->timing ? next_pair(c) : nullptr;
+        if (tp) HIPTRY(c, hipEventRecord(tp->a, s));
+        HIPTRY(c, launch_small(a, w->small, small_bpr(c, count, sh, bpr), sh, s));
+        if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
+    } else if (mode & CG_PLAIN) {
         HIPTRY(c, launch_classify(a, s));
         HIPTRY(c, hipMemcpyAsync(w->h_weight, w->weight, count * 8, hipMemcpyDeviceToHost, s));
         HIPTRY(c, hipStreamSynchronize(s));
@@ -842,6 +869,7 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_REORDER_MIN")) c->reorder_min = strtoull(e, nullptr, 0);
     if (const char *e = getenv("XC_SEG_MIN_LOG2")) c->seg_min_log2 = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_SMALL_MAX")) c->small_max = std::min<uint64_t>(strtoull(e, nullptr, 0), 1ull << 20);
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
@@ -1428,6 +1456,9 @@ int prewarm(cg_ctx *c, hipStream_t s, const cg_transfer *recs, uint64_t count, c
     Workspace *w;
     int rc = get_ws(c, s, count, &w);
     if (rc) return rc;
+    // micro-batches of this size run in one launch: run it once on the
+    // padding records (bad kinds), so that its code is on the device
+    if (count <= c->small_max) return run_check(c, recs, count, out, CG_CHECK | CG_KEEP_ORDER, s, tun, 1);
     const LaunchShape sh = shape_of(c, tun);
     for (int v = 0; v < kVersions && !rc; ++v) {
         BatchArgs a = make_args(c, w, recs, count, out, CG_CHECK);
@@ -1462,6 +1493,8 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             return bail(fail(c, CG_ENOMEM, "serve: slot buffers"));
         for (uint32_t k = 0; k < B; ++k) sl.h_recs[k] = cg_transfer{0, 0, 0, 0xFFFFFFFFu, 0};
         sl.filled = B;
+        if (hipMemcpy(sl.d_recs, sl.h_recs, B * sizeof(cg_transfer), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(c, CG_EHIP, "serve: slot records"));
     }
     {
         // the table as it stands now, and the code of every kernel the loop
@@ -1571,7 +1604,10 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             sl.filled = cnt;
             const double ta = now();
             for (uint64_t r : sl.reqs) res[r].t_admit = ta;
-            const uint32_t count = cfg->plain ? cnt : B;   // graph shape: fixed count, padded
+            // graph shape: a fixed count, padded; micro-batches that run in one
+            // launch take their own count
+            const bool one_launch = !cfg->plain && B <= c->small_max;
+            const uint32_t count = cfg->plain || one_launch ? cnt : B;
             hipError_t e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
             if (e1 != hipSuccess) { rc = hip_fail(c, "serve: records upload", e1); break; }
             // micro-batches keep their order (their graphs are captured before the clock starts)

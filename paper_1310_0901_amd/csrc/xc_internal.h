@@ -121,6 +121,15 @@ struct SegArgs {
     uint32_t min_log2;      // smallest block size, log2
 };
 
+// Per record of a batch worked by k_small: the findings of its blocks so
+// far, and how many of its blocks have finished.  Starting state (and the
+// state every call leaves): first = CG_NONE, the rest 0.
+struct SmallAcc {
+    uint64_t first, undef;
+    uint32_t flags, done;
+};
+static_assert(sizeof(SmallAcc) == 24, "small-batch accumulator layout");
+
 struct LaunchShape {
     uint32_t block, unroll, grid, nontemporal;
     uint32_t tile_units;
@@ -153,6 +162,9 @@ hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
                         hipStream_t s);
 hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
+// a batch of a.count records in one launch of a.count * bpr blocks of sh.block threads
+hipError_t launch_small(const BatchArgs &a, SmallAcc *acc, uint32_t bpr, const LaunchShape &sh, hipStream_t s);
+hipError_t launch_small_reset(SmallAcc *acc, uint64_t n, hipStream_t s);
 
 // segment.hip: segments of the records described by g, sorted by source
 // block, written as the positions of ap (desc, weight, local, bsum) with

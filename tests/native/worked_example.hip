@@ -91,6 +91,53 @@ static int streams()
     return 0;
 }
 
+// The null stream (stream 0): its work waits for earlier work on blocking
+// streams, and later work on them waits for it, so copies on two blocking
+// streams on either side of a fill or a copy on stream 0 are ordered; copies
+// on non-blocking streams are not ordered by it.  Exactly two pairs race: an
+// upload and a download on two non-blocking streams around a fill on stream 0,
+// and an upload on a non-blocking stream with a download on stream 0.
+static int null_stream()
+{
+    const size_t KB = 1 << 10;
+    uint8_t *d = nullptr, *h1 = nullptr, *h2 = nullptr;
+    if (hipMalloc((void **)&d, 64 * KB) != hipSuccess) return 2;
+    if (hipHostMalloc((void **)&h1, 64 * KB) != hipSuccess || hipHostMalloc((void **)&h2, 64 * KB) != hipSuccess) return 2;
+    hipMemset(d, 0, 64 * KB);
+    hipStream_t b1, b2, n1, n2;
+    if (hipStreamCreate(&b1) != hipSuccess || hipStreamCreate(&b2) != hipSuccess ||
+        hipStreamCreateWithFlags(&n1, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&n2, hipStreamNonBlocking) != hipSuccess)
+        return 2;
+    // quiet: blocking streams on either side of a fill on stream 0
+    hipMemcpyAsync(d, h1, 4 * KB, hipMemcpyHostToDevice, b1);
+    hipMemsetAsync(d + 32 * KB, 0, 16, 0);
+    hipMemcpyAsync(h2, d, 4 * KB, hipMemcpyDeviceToHost, b2);
+    (void)hipDeviceSynchronize();
+    // quiet: an upload on a blocking stream, then a download of its bytes on stream 0
+    hipMemcpyAsync(d + 8 * KB, h1, 4 * KB, hipMemcpyHostToDevice, b1);
+    hipMemcpyAsync(h2, d + 8 * KB, 4 * KB, hipMemcpyDeviceToHost, 0);
+    (void)hipDeviceSynchronize();
+    // racing: non-blocking streams on either side of a fill on stream 0
+    hipMemcpyAsync(d + 16 * KB, h1, 4 * KB, hipMemcpyHostToDevice, n1);
+    hipMemsetAsync(d + 32 * KB, 0, 16, 0);
+    hipMemcpyAsync(h2, d + 16 * KB, 4 * KB, hipMemcpyDeviceToHost, n2);
+    (void)hipDeviceSynchronize();
+    // racing: an upload on a non-blocking stream, a download of its bytes on stream 0
+    hipMemcpyAsync(d + 24 * KB, h1, 4 * KB, hipMemcpyHostToDevice, n1);
+    hipMemcpyAsync(h2 + 8 * KB, d + 24 * KB, 4 * KB, hipMemcpyDeviceToHost, 0);
+    (void)hipDeviceSynchronize();
+    (void)hipStreamDestroy(b1);
+    (void)hipStreamDestroy(b2);
+    (void)hipStreamDestroy(n1);
+    (void)hipStreamDestroy(n2);
+    hipFree(d);
+    (void)hipHostFree(h1);
+    (void)hipHostFree(h2);
+    printf("null stream done\n");
+    return 0;
+}
+
 // Fills and the typed asynchronous copies: a fill racing with a download of
 // bytes it writes, a typed upload and download sharing 512 bytes; fills of
 // disjoint bytes and copies ordered on one stream stay quiet; a fill and
@@ -218,6 +265,7 @@ int main(int argc, char **argv)
     if (argc > 1 && strcmp(argv[1], "pitched") == 0) return pitched_and_async();
     if (argc > 1 && strcmp(argv[1], "streams") == 0) return streams();
     if (argc > 1 && strcmp(argv[1], "fills") == 0) return fills();
+    if (argc > 1 && strcmp(argv[1], "nullstream") == 0) return null_stream();
     const bool correct = argc > 1 && strcmp(argv[1], "correct") == 0;
     const int size = 1000000;
     double *c, *a, *b;

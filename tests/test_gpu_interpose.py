@@ -85,6 +85,24 @@ def test_concurrent_copies_on_streams():
     assert "12 copies checked, 2 with errors, 2 concurrent-access pairs" in err
 
 
+def test_null_stream_orders_blocking_streams():
+    """Work on stream 0 orders the copies of blocking streams around it (no
+    report), but not those of non-blocking streams: an upload and a download
+    on two non-blocking streams around a fill on stream 0, and an upload on a
+    non-blocking stream with a download of its bytes on stream 0, are each
+    reported once."""
+    r = run_example("nullstream")
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0 and "null stream done" in r.stdout
+    err = r.stderr
+    head = "Error: Concurrent copies access the same bytes without synchronisation."
+    assert err.count(head) == 2
+    first, second = err.split(head)[1:3]
+    assert "hipMemcpyHostToDevice) on stream" in first and "hipMemcpyDeviceToHost) on stream" in first
+    assert "on stream (nil)" not in first and "on stream (nil)" in second
+    assert "2 concurrent-access pairs" in err
+
+
 def test_fills_and_typed_async_copies():
     """hipMemsetAsync / hipMemsetD8/D16/D32(Async) mark their bytes defined and
     join the concurrent-access window as writes; hipMemcpyHtoDAsync /

@@ -26,6 +26,15 @@ def H(X):
     return harness
 
 
+@pytest.fixture(params=["one-launch", "multi-kernel"])
+def batch_path(request, monkeypatch):
+    """Batches worked by the one-launch kernel (any batch of up to 2^20
+    records) or by the classify / scan / persistent-kernel chain (no batch):
+    the limit is read when a context is created."""
+    monkeypatch.setenv("XC_SMALL_MAX", str(1 << 20) if request.param == "one-launch" else "0")
+    return request.param
+
+
 def modes(X):
     return [("graph", X.CG_CHECK), ("eager", X.CG_CHECK | X.CG_EAGER), ("plain", X.CG_CHECK | X.CG_PLAIN)]
 
@@ -36,7 +45,7 @@ def tiny_workload(records):
                                      [ALLOCS[b] for b in bases], records)
 
 
-def test_tiny_universe_every_case(X, H):
+def test_tiny_universe_every_case(X, H, batch_path):
     rows = all_records()
     recs = np.array([(s, d, n, k, 0) for k, s, d, n in rows], W.RECORD_DTYPE)
     w = tiny_workload(recs)
@@ -69,7 +78,7 @@ def test_tiny_universe_segmented(X, H, monkeypatch):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_small_config_parity(X, H, k):
+def test_small_config_parity(X, H, batch_path, k):
     w = W.small_config(k)
     want = util.oracle_for(w).run(w.records)
     dw = H.DeviceWorld(w)
@@ -101,7 +110,7 @@ def test_small_tiles_and_ragged_tails(X, H):
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13, 14, 15])
-def test_random_worlds_check(X, H, seed):
+def test_random_worlds_check(X, H, batch_path, seed):
     rng = np.random.default_rng(seed)
     hl, hv, a, bases, sizes, vs = util.random_world(rng)
     recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 300)
@@ -117,7 +126,7 @@ def test_random_worlds_check(X, H, seed):
 
 @pytest.mark.parametrize("seed", [21, 22, 23, 24])
 @pytest.mark.parametrize("path", ["graph", "plain"])
-def test_random_worlds_propagation(X, H, seed, path):
+def test_random_worlds_propagation(X, H, batch_path, seed, path):
     """Check + propagate on conflict-free batches: verdicts and every shadow
     byte (device allocations and host region) equal the oracle's."""
     rng = np.random.default_rng(seed)
@@ -141,7 +150,7 @@ def test_random_worlds_propagation(X, H, seed, path):
         dw.close()
 
 
-def test_config4_small_chain(X, H):
+def test_config4_small_chain(X, H, batch_path):
     """Struct padding and single payload bits, H2D then D2D hops with
     propagation: verdicts and shadows bit-exact after every hop."""
     w = W.small_config(4)

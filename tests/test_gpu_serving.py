@@ -33,6 +33,7 @@ def test_serving_mix_alone_and_oracle(S):
     want = replay(sw)
     runs = {}
     for name, cfg in (("mix", S.config(streams=4, max_batch=256)),
+                      ("mix-graphs", S.config(streams=4, max_batch=512)),
                       ("alone", S.config(streams=1, max_batch=1)),
                       ("closed", S.config(streams=3, max_batch=64, open_loop=False)),
                       ("plain", S.config(plain=True)),
