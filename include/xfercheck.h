@@ -237,6 +237,28 @@ int check_transfers_2d(cg_ctx *ctx, const cg_transfer2d *recs_dev, uint64_t coun
 int propagate_shadow(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ * check_transfers for a batch of at most CG_NOALLOC_MAX records, with the same
+ * arguments, results (verdicts, and destination shadows with CG_PROPAGATE)
+ * and stream order.  The batch is worked in one launch; its per-record
+ * accumulators live in a fixed device array of the library, one per GPU
+ * (CG_NOALLOC_MAX * 24 bytes, set up by cg_create for its device and held
+ * until the process ends), which every call leaves in its starting state.
+ * The call makes no device allocation or free and no graph; its completion
+ * events were made by cg_create.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap in time on one GPU (other streams, threads or
+ * contexts) race and give wrong verdicts: the caller orders them.
+ * mode: CG_CHECK and/or CG_PROPAGATE (CG_EAGER and CG_KEEP_ORDER are
+ * accepted and change nothing).  Errors: CG_EINVAL (count above
+ * CG_NOALLOC_MAX, CG_PLAIN or CG_DEBUG_CONFLICTS or unknown mode bits, null
+ * pointers), CG_ESTATE (no array on this device), CG_EHIP.
+ */
+#define CG_NOALLOC_MAX 4096u
+int check_transfers_noalloc(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, cg_verdict *out_dev,
+                            uint32_t mode, void *hip_stream);
+
+/*
  * Paper-style text for one verdict (the report of Sec. 4.5, Listing 6), for
  * host copies of a record and its verdict.  Writes at most len bytes,
  * NUL-terminated; returns the length of the full text (like snprintf), or a

@@ -14,6 +14,7 @@
 #include <deque>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <set>
 #include <sstream>
 #include <string>
@@ -33,6 +34,7 @@ constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
 constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
 constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
+constexpr int kPooledEvents = 16;             // completion events made at set-up
 // launch shape for checks of mostly short pitched rows (measured on 4 KiB and
 // 512-byte rows: 20-26 % faster than the shapes tuned for long transfers)
 constexpr cg_tuning kShortRowTuning = {256, 2, 16, 1u << 16, 0, {0, 0, 0}};
@@ -103,6 +105,8 @@ struct TableVersion {
     DevState *st = nullptr;
     uint64_t n = 0;
     std::map<hipStream_t, hipEvent_t> uses;
+    hipEvent_t fixed_use = nullptr;   // after the last check_transfers_noalloc call that read this version
+    bool fixed_used = false;
 };
 
 // Row expansion of pitched 2D copies on one stream.
@@ -237,6 +241,7 @@ int materialize(cg_ctx *c)
     const int t = (c->cur + 1) % kVersions;
     TableVersion &nv = c->ver[t], &ov = c->ver[c->cur];
     for (auto &kv : nv.uses) HIPTRY(c, hipStreamWaitEvent(c->s, kv.second, 0));
+    if (nv.fixed_used) HIPTRY(c, hipStreamWaitEvent(c->s, nv.fixed_use, 0));
     const uint64_t n = c->table.size();
     const uint64_t M = c->max_allocs;
     uint32_t shift = 0;
@@ -794,6 +799,62 @@ bool parse_field(const std::string &line, const char *name, uint32_t *v)
 
 }  // namespace
 
+// ---- the no-allocation entry point's device array -----------------------------
+// Accumulators of check_transfers_noalloc: a fixed array on every GPU the
+// library runs on, held until the process ends.  In host code `scratch` is
+// only a stand-in for the array; its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device at set-up with that device
+// current, and is the only thing passed to kernels.
+static __device__ __align__(256) SmallAcc scratch[CG_NOALLOC_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+SmallAcc *g_scratch[kMaxDevices] = {};
+
+// Once per device, with that device current: the array's address there, and
+// every accumulator put in its starting state.
+int scratch_setup(cg_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (c->dev < 0 || c->dev >= kMaxDevices) return fail(c, CG_EINVAL, "device index above 63");
+    if (g_scratch[c->dev]) return CG_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(c, "hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorUnknown);
+    e = launch_small_reset(static_cast<SmallAcc *>(p), CG_NOALLOC_MAX, c->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) return hip_fail(c, "scratch reset", e);
+    g_scratch[c->dev] = static_cast<SmallAcc *>(p);
+    return CG_OK;
+}
+
+SmallAcc *scratch_of(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < kMaxDevices ? g_scratch[dev] : nullptr;
+}
+
+// note_use for check_transfers_noalloc: the version's own event, and an event
+// from the pool (made by cg_create) for the pool blocks' quarantine; when the
+// pool is empty, finished checks give theirs back first
+int note_use_fixed(cg_ctx *c, hipStream_t s)
+{
+    TableVersion &v = c->ver[c->cur];
+    HIPTRY(c, hipEventRecord(v.fixed_use, s));
+    v.fixed_used = true;
+    if (c->ev_pool.empty()) retire(c, false);
+    if (c->ev_pool.empty()) retire(c, true);
+    if (c->ev_pool.empty()) return fail(c, CG_ESTATE, "no pooled event");
+    const hipEvent_t ev = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    HIPTRY(c, hipEventRecord(ev, s));
+    c->inflight.push_back(InFlight{++c->check_seq, ev});
+    if (c->inflight.size() > 256) retire(c, false);
+    return CG_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -874,6 +935,15 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
     c->tuning_prop.unroll = 2;
+    // events that check_transfers_noalloc records, made here so that it makes none
+    for (auto &v : c->ver)
+        if (hipEventCreateWithFlags(&v.fixed_use, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+    for (int k = 0; k < kPooledEvents; ++k) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
+        c->ev_pool.push_back(e);
+    }
+    if (scratch_setup(c) != CG_OK) return bail(CG_EHIP);
     // an empty table and region, so that checks before any allocation work
     if (materialize(c) != CG_OK) return bail(CG_EHIP);
     if (hipStreamSynchronize(c->s) != hipSuccess) return bail(CG_EHIP);
@@ -914,6 +984,7 @@ int cg_destroy(cg_ctx *c)
         (void)hipFree(v.tab);
         (void)hipFree(v.st);
         for (auto &kv : v.uses) (void)hipEventDestroy(kv.second);
+        if (v.fixed_use) (void)hipEventDestroy(v.fixed_use);
     }
     for (auto &f : c->inflight) (void)hipEventDestroy(f.ev);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1071,6 +1142,36 @@ int check_transfers(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_v
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
     return run_check(c, recs_dev, count, out_dev, mode, (hipStream_t)hip_stream,
                      (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
+}
+
+int check_transfers_noalloc(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdict *out_dev,
+                            uint32_t mode, void *hip_stream)
+{
+    if (!c) return CG_EINVAL;
+    if (!(mode & (CG_CHECK | CG_PROPAGATE))) return fail(c, CG_EINVAL, "mode needs CG_CHECK or CG_PROPAGATE");
+    if (mode & ~(CG_CHECK | CG_PROPAGATE | CG_EAGER | CG_KEEP_ORDER))
+        return fail(c, CG_EINVAL, "check_transfers_noalloc: mode bits other than CG_CHECK, CG_PROPAGATE, CG_EAGER, "
+                                  "CG_KEEP_ORDER");
+    if (count > CG_NOALLOC_MAX) return fail(c, CG_EINVAL, "check_transfers_noalloc: more than CG_NOALLOC_MAX records");
+    if (count == 0) return CG_OK;
+    if (!recs_dev) return fail(c, CG_EINVAL, "null records");
+    if ((mode & CG_CHECK) && !out_dev) return fail(c, CG_EINVAL, "null verdicts with CG_CHECK");
+    SmallAcc *acc = scratch_of(c->dev);
+    if (!acc) return fail(c, CG_ESTATE, "check_transfers_noalloc: no device array for this device");
+    if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int rc = materialize(c);
+    if (rc) return rc;
+    HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+    BatchArgs a{};
+    a.recs = recs_dev;
+    a.count = count;
+    a.out = (mode & CG_CHECK) ? out_dev : nullptr;
+    a.mode = mode & (CG_CHECK | CG_PROPAGATE);
+    a.st = c->ver[c->cur].st;
+    const LaunchShape sh = shape_of(c, (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning);
+    HIPTRY(c, launch_small(a, acc, small_bpr(c, count, sh, 0), sh, s));
+    return note_use_fixed(c, s);
 }
 
 int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, void *hip_stream)

@@ -28,6 +28,7 @@ CG_RACE_SRC, CG_RACE_DST, CG_RACE_UNCHECKED = 0x1, 0x2, 0x4
 CG_PTR_UNALLOC = 0x1
 # modes
 CG_CHECK, CG_PROPAGATE, CG_PLAIN, CG_DEBUG_CONFLICTS, CG_EAGER, CG_KEEP_ORDER = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+CG_NOALLOC_MAX = 4096
 
 
 class CgError(RuntimeError):
@@ -89,6 +90,7 @@ _PROTOS = {
     "shadow_set_batch": (I32, [P, P, P, P, U64]),
     "shadow_ptr": (I32, [P, U64, ctypes.POINTER(P)]),
     "check_transfers": (I32, [P, P, U64, P, U32, P]),
+    "check_transfers_noalloc": (I32, [P, P, U64, P, U32, P]),
     "propagate_shadow": (I32, [P, P, U64, P]),
     "check_concurrent": (I32, [P, P, P, P, U64, P, P]),
     "check_pointers": (I32, [P, P, U64, P, P]),
@@ -197,6 +199,10 @@ def shadow_ptr(ctx, dev_addr) -> int:
 
 def check_transfers(ctx, recs_dev, count, out_dev, mode, stream=0) -> None:
     _chk(ctx, lib().check_transfers(ctx, recs_dev, count, out_dev, mode, stream), "check_transfers")
+
+
+def check_transfers_noalloc(ctx, recs_dev, count, out_dev, mode, stream=0) -> None:
+    _chk(ctx, lib().check_transfers_noalloc(ctx, recs_dev, count, out_dev, mode, stream), "check_transfers_noalloc")
 
 
 def propagate_shadow(ctx, recs_dev, count, stream=0) -> None:
