@@ -847,7 +847,10 @@ __global__ void __launch_bounds__(1024) k_scan_sums(BatchArgs a, uint32_t tile_u
         a.ctl->total_units = total;
         a.ctl->tile_units = tu;
         a.ctl->ntiles = (total + tu - 1) / tu;
-        for (int x = 0; x < kXcds; ++x) a.ctl->counter[x] = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            a.ctl->counter[x] = 0;
+            a.ctl->lds_counter[x] = 0;
+        }
         a.prefix[a.count] = total;
     }
 }
@@ -884,8 +887,27 @@ __global__ void __launch_bounds__(256) k_tile_starts(BatchArgs a)
 // ---------------------------------------------------------------------------
 // k_batched: persistent kernel over the tiles of the flattened unit space
 // ---------------------------------------------------------------------------
+
+// Blocks b = x, x + nch, x + 2 nch, ... of the grid run on XCD x; b / nch is
+// their rank there.  A work queue split into nch chunks gives each claiming
+// block of XCD x a first item of chunk x by rank, without an atomic.  claim
+// 0: every block claims; 1: the blocks of even rank; 2: those of odd rank.
+__device__ __forceinline__ uint32_t claimers_on(uint32_t x, uint32_t nch, int claim)
+{
+    const uint32_t n = (gridDim.x + nch - 1 - x) / nch;
+    return claim == 0 ? n : (claim == 1 ? (n + 1) / 2 : n / 2);
+}
+
+__device__ __forceinline__ int64_t claim_rank(uint32_t nch, int claim)
+{
+    const uint32_t r = blockIdx.x / nch;
+    if (claim == 0) return r;
+    return (int)(r & 1u) == claim - 1 ? (int64_t)(r >> 1) : -1;
+}
+
+// The waves' loop of the scan kernel (claim: which blocks take first tiles).
 template <int U, bool NT, bool PROP>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3))) k_batched(BatchArgs a)
+__device__ void batched_loop(const BatchArgs &a, int claim)
 {
     const uint32_t lane = lane_id();
     const uint64_t ntiles = ufl64(a.ctl->ntiles);
@@ -908,9 +930,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ?
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t xcd = blockIdx.x % nch;
     auto chunk_lo = [&](uint32_t x) { return ntiles * x / nch; };
-    auto waves_on = [&](uint32_t x) { return (uint64_t)((gridDim.x + nch - 1 - x) / nch) * wpb; };
-    uint64_t jn = chunk_lo(xcd) + (uint64_t)(blockIdx.x / nch) * wpb + (threadIdx.x >> 6);
-    if (jn >= chunk_lo(xcd + 1)) jn = kNoTile;
+    auto waves_on = [&](uint32_t x) { return (uint64_t)claimers_on(x, nch, claim) * wpb; };
+    const int64_t rank = claim_rank(nch, claim);
+    uint64_t jn = kNoTile;
+    if (rank >= 0) {
+        jn = chunk_lo(xcd) + (uint64_t)rank * wpb + (threadIdx.x >> 6);
+        if (jn >= chunk_lo(xcd + 1)) jn = kNoTile;
+    }
     uint32_t y = xcd, left = nch;
     for (;;) {
         while (jn == kNoTile && left > 0) {
@@ -1004,6 +1030,235 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ?
             }
             u = g_end;
         }
+    }
+}
+
+template <int U, bool NT, bool PROP>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3))) k_batched(BatchArgs a)
+{
+    batched_loop<U, NT, PROP>(a, 0);
+}
+
+// ---------------------------------------------------------------------------
+// k_host_lds: host-source segments with their source bytes staged in LDS
+// ---------------------------------------------------------------------------
+// A batch worked as segments reads each host byte many times (about 160 on
+// the 1M-record configuration), and through the vector memory path every
+// re-read costs an address and an L2-to-L1 transfer.  Here the host-source
+// positions (sorted last, by block of source memory) are taken in tasks of
+// kTaskPos consecutive positions, each by one workgroup: for every window of
+// kWinChunks chunks that the task's segments of one block touch, the window's
+// V bytes and A bits are copied into LDS once, and every segment overlapping
+// it is checked from there by one wave.  Only check-only host-to-device
+// records have host sources worked here: their destination needs no check
+// of its own.  Findings go to each position's record with the same atomics
+// as in k_batched.  Tasks are split into one contiguous range per XCD, like
+// k_batched's tiles, so that the tasks of one block stage it from one L2.
+constexpr uint32_t kWinChunks = 2048;   // 32 KiB of V bytes per window
+constexpr uint32_t kTaskPos = 256;      // positions per task, at most
+
+// One position of a task, as the waves need it: absolute chunk indices (the
+// shadow address over 16) of the segment's chunks [c_lo, c_hi), the record
+// byte index i0 of chunk c_lo's first byte, the record's valid source bytes
+// [v_lo, v_hi), and the verdict it reports to.
+struct HostPos {
+    int64_t c_lo, c_hi, i0, v_lo, v_hi;
+    uint64_t blk;
+    uint32_t rec, pad;
+};
+
+template <int U>
+__device__ __forceinline__ void lds_segment(const HostPos &P, int64_t wc0, int64_t wc1, const u32x4 *sv,
+                                            const uint16_t *sa, Acc &acc)
+{
+    const int64_t ca = P.c_lo > wc0 ? P.c_lo : wc0;
+    const int64_t cb = P.c_hi < wc1 ? P.c_hi : wc1;
+    const int32_t lane = (int32_t)lane_id();
+    for (int64_t c = ca; c < cb; c += 64 * U) {
+        const int64_t i0f = P.i0 + 16 * (c - P.c_lo);
+        const int32_t base = (int32_t)(c - wc0);
+        const int32_t n = (int32_t)(cb - c < 64 * U ? cb - c : 64 * U);
+        // all U reads issued back to back: lanes past the segment's chunks in
+        // this window read its last chunk again and ignore it
+        u32x4 v[U];
+        uint32_t av[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t k = 64 * j + lane;
+            const int32_t kk = k < n ? k : n - 1;
+            v[j] = sv[base + kk];
+            av[j] = sa[base + kk];
+        }
+        // every chunk of the iteration wholly valid: one test over them
+        if (i0f >= P.v_lo && i0f + 16 * n <= P.v_hi) {
+            uint32_t bad = 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) bad |= v[j].x | v[j].y | v[j].z | v[j].w | (av[j] ^ 0xFFFFu);
+            if (__ballot(bad != 0u) == 0) continue;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t k = 64 * j + lane;
+            const int64_t i0 = i0f + 16 * k;
+            const uint32_t m = k < n ? rmask(P.v_lo - i0, P.v_hi - i0) : 0u;
+            src_findings(acc, i0, v[j], m & av[j], m & ~av[j]);
+        }
+    }
+}
+
+// The workgroups' loop over the host-source tasks (claim: which blocks take
+// first tasks, as in batched_loop); sv / sa / sp / s_task / s_next / s_list
+// are the block's LDS.
+template <int U>
+__device__ void host_loop(const BatchArgs &a, const uint64_t *meta, int claim, u32x4 *sv, uint16_t *sa, HostPos *sp,
+                          uint64_t *s_task, uint32_t *s_next, uint16_t *s_list)
+{
+    const uint64_t p_begin = meta[2], p_end = meta[0];
+    if (p_begin >= p_end) return;
+    const uint32_t lb = (uint32_t)meta[1];
+    const uint32_t tp = a.task_pos ? a.task_pos : kTaskPos;   // positions per task, at most kTaskPos
+    const uint64_t ntasks = (p_end - p_begin + tp - 1) / tp;
+    const Region R = a.st->region;
+    const int64_t vbase = (int64_t)((uint64_t)R.v >> 4);     // V is 16-byte aligned
+    const int64_t nvch = (int64_t)((R.hl + 15) >> 4);         // chunks of V
+    const int64_t nach = (int64_t)(((R.hl + 63) >> 6) * 4);   // 16-bit A words
+    const gcptr<u32x4> gv = reinterpret_cast<gcptr<u32x4>>((uint64_t)R.v);
+    const gcptr<uint16_t> ga = reinterpret_cast<gcptr<uint16_t>>((uint64_t)R.a16);
+    // tasks in kXcds contiguous chunks, chunk x taken by the workgroups on XCD x
+    auto chunk_lo = [&](uint32_t x) { return ntasks * x / kXcds; };
+    auto groups_on = [&](uint32_t x) { return (uint64_t)claimers_on(x, kXcds, claim); };
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const int64_t rank = claim_rank(kXcds, claim);
+    uint64_t jn = kNoTile;
+    if (rank >= 0) {
+        jn = chunk_lo(xcd) + (uint64_t)rank;
+        if (jn >= chunk_lo(xcd + 1)) jn = kNoTile;
+    }
+    uint32_t y = xcd, left = kXcds;
+    Acc acc;
+    acc_reset(acc);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            while (jn == kNoTile && left > 0) {
+                const uint64_t lo = chunk_lo(y), hi = chunk_lo(y + 1);
+                uint64_t c = hi;
+                if (hi - lo > groups_on(y)) c = lo + groups_on(y) + atomicAdd(&a.ctl->lds_counter[y], 1u);
+                if (c < hi) jn = c;
+                else {
+                    y = (y + 1) % kXcds;
+                    --left;
+                }
+            }
+            *s_task = jn;
+        }
+        __syncthreads();
+        const uint64_t j = *s_task;
+        jn = kNoTile;
+        __syncthreads();
+        if (j == kNoTile) break;
+        const uint64_t q0 = p_begin + j * tp;
+        const uint32_t np = (uint32_t)(p_end - q0 < tp ? p_end - q0 : tp);
+        for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
+            const Desc d = a.desc[q0 + t];
+            const uint32_t phi = (d.ctl >> CTL_PHI_SHIFT) & 15u;
+            const int64_t e = (int64_t)d.e0 - ((d.ctl & CTL_DELTA) ? 1 : 0);
+            HostPos h;
+            h.c_lo = (int64_t)(d.src_sh >> 4) + e;
+            h.c_hi = h.c_lo + (int64_t)d.units;
+            h.i0 = 16 * e - (int64_t)phi;
+            h.v_lo = d.v_lo;
+            h.v_hi = d.v_hi;
+            h.blk = (uint64_t)h.c_lo >> (lb - 4);
+            h.rec = a.perm[q0 + t];
+            h.pad = 0;
+            sp[t] = h;
+        }
+        __syncthreads();
+        // the task's positions by block (they are sorted by block)
+        for (uint32_t g0 = 0; g0 < np;) {
+            const uint64_t blk = sp[g0].blk;
+            uint32_t g1 = g0 + 1;
+            int64_t cmin = sp[g0].c_lo, cmax = sp[g0].c_hi;
+            while (g1 < np && sp[g1].blk == blk) {
+                cmin = sp[g1].c_lo < cmin ? sp[g1].c_lo : cmin;
+                cmax = sp[g1].c_hi > cmax ? sp[g1].c_hi : cmax;
+                ++g1;
+            }
+            for (int64_t wc0 = (cmin / kWinChunks) * kWinChunks; wc0 < cmax; wc0 += kWinChunks) {
+                const int64_t wc1 = wc0 + kWinChunks;
+                // stage the window: V chunks and A words inside the buffers,
+                // zeros elsewhere; every load is issued (at a clamped index,
+                // inside the buffer) before the first is used
+                // (passes of 4 chunks per thread: 2 for 256 threads, 1 for 512)
+                for (uint32_t k0 = 0; k0 < kWinChunks; k0 += 4 * blockDim.x) {
+                    u32x4 gvv[4];
+                    uint32_t gav[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t c = wc0 + k0 + threadIdx.x + i * blockDim.x - vbase;
+                        gvv[i] = gv[c < 0 ? 0 : (c < nvch ? c : nvch - 1)];
+                        gav[i] = ga[c < 0 ? 0 : (c < nach ? c : nach - 1)];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t k = k0 + threadIdx.x + i * blockDim.x;
+                        const int64_t c = wc0 + k - vbase;
+                        sv[k] = (c >= 0 && c < nvch) ? gvv[i] : u32x4{0u, 0u, 0u, 0u};
+                        sa[k] = (uint16_t)((c >= 0 && c < nach) ? gav[i] : 0u);
+                    }
+                }
+                // the group's positions that overlap the window, listed once
+                if (threadIdx.x == 0) {
+                    s_next[0] = 0;
+                    s_next[1] = 0;
+                }
+                __syncthreads();
+                for (uint32_t t = threadIdx.x; t < g1 - g0; t += blockDim.x) {
+                    const HostPos &P = sp[g0 + t];
+                    if (P.c_hi > wc0 && P.c_lo < wc1) s_list[atomicAdd(&s_next[1], 1u)] = (uint16_t)(g0 + t);
+                }
+                __syncthreads();
+                const uint32_t nlist = s_next[1];
+                // listed positions taken one at a time by whichever wave is
+                // free, so that a few long segments do not hold up the others
+                for (;;) {
+                    uint32_t q = 0;
+                    if (lane_id() == 0) q = atomicAdd(&s_next[0], 1u);
+                    q = ufl32(__shfl(q, 0));
+                    if (q >= nlist) break;
+                    const HostPos P = sp[s_list[q]];
+                    lds_segment<U>(P, wc0, wc1, sv, sa, acc);
+                    if (a.out) flush_wave(acc, a.out, P.rec);
+                }
+                __syncthreads();
+            }
+            g0 = g1;
+        }
+    }
+}
+
+// A check-only batch worked as segments with its host-source positions left
+// to LDS: blocks of even rank on their XCD start with the scan kernel's tiles,
+// blocks of odd rank with the host-source tasks, and each turns to the other
+// queue when its own is used up, so that the HBM-bound device-source work and
+// the LDS-bound host-source work run side by side to the end.
+template <int U, bool NT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_batched_lds(BatchArgs a)
+{
+    __shared__ u32x4 sv[kWinChunks];
+    __shared__ uint16_t sa[kWinChunks];
+    __shared__ HostPos sp[kTaskPos];
+    __shared__ uint64_t s_task;
+    __shared__ uint32_t s_next[2];
+    __shared__ uint16_t s_list[kTaskPos];
+    if (((blockIdx.x / kXcds) & 1u) != 0) {
+        host_loop<4>(a, a.lds_meta, 2, sv, sa, sp, &s_task, s_next, s_list);
+        __syncthreads();
+        batched_loop<U, NT, false>(a, 1);
+    } else {
+        batched_loop<U, NT, false>(a, 1);
+        __syncthreads();
+        host_loop<4>(a, a.lds_meta, 2, sv, sa, sp, &s_task, s_next, s_list);
     }
 }
 
@@ -1269,10 +1524,29 @@ hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// the host-source tasks alone (the LDS path run after the scan kernel)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_host_lds(BatchArgs a)
+{
+    __shared__ u32x4 sv[kWinChunks];
+    __shared__ uint16_t sa[kWinChunks];
+    __shared__ HostPos sp[kTaskPos];
+    __shared__ uint64_t s_task;
+    __shared__ uint32_t s_next[2];
+    __shared__ uint16_t s_list[kTaskPos];
+    host_loop<4>(a, a.lds_meta, 0, sv, sa, sp, &s_task, s_next, s_list);
+}
+
 template <int U, bool NT>
 static void launch_batched_t(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
 {
-    if (a.mode & CG_PROPAGATE)
+    if (a.lds_meta && sh.lds_after) {
+        BatchArgs d = a;
+        d.lds_meta = nullptr;
+        hipLaunchKernelGGL((k_batched<U, NT, false>), dim3(sh.grid), dim3(sh.block), 0, s, d);
+        hipLaunchKernelGGL(k_host_lds, dim3(sh.cus * 3), dim3(256), 0, s, a);
+    } else if (a.lds_meta)
+        hipLaunchKernelGGL((k_batched_lds<U, NT>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+    else if (a.mode & CG_PROPAGATE)
         hipLaunchKernelGGL((k_batched<U, NT, true>), dim3(sh.grid), dim3(sh.block), 0, s, a);
     else
         hipLaunchKernelGGL((k_batched<U, NT, false>), dim3(sh.grid), dim3(sh.block), 0, s, a);
@@ -1301,6 +1575,7 @@ static void launch_plain_t(const BatchArgs &a, uint64_t t, uint64_t units, uint3
 
 hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
 {
+    if (a.lds_meta && (a.mode & CG_PROPAGATE)) return hipErrorInvalidValue;   // check-only
     XC_DISPATCH(launch_batched_t, a, sh, s);
     return hipGetLastError();
 }

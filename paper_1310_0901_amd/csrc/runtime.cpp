@@ -182,6 +182,9 @@ struct cg_ctx {
     uint64_t reorder_min = 16384;            // batches this large are worked as source-block segments
     uint32_t seg_min_log2 = 20;              // smallest source block of the segments, log2
     uint64_t small_max = kSmallMax;          // batches this small run in one launch (k_small); 0: never
+    uint32_t task_pos = 0;                   // positions per host-source task (0: the kernel's default)
+    int host_lds = 1;                        // check-only segments of host sources worked from LDS: 1 in the
+                                             // scan kernel's blocks, 2 in a kernel of their own after it, 0 not
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
     cg_tuning tuning{};        // check-only launch shape
     cg_tuning tuning_prop{};   // launch shape when propagating (more registers per lane)
@@ -464,6 +467,8 @@ LaunchShape shape_of(cg_ctx *c, const cg_tuning &t)
     sh.grid = (uint32_t)c->cu_count * t.blocks_per_cu;
     sh.nontemporal = t.nontemporal;
     sh.tile_units = t.tile_units;
+    sh.cus = (uint32_t)c->cu_count;
+    sh.lds_after = c->host_lds == 2 ? 1u : 0u;
     return sh;
 }
 
@@ -701,9 +706,14 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         plan.ar.prefix = nullptr;
         plan.ar.tile_start = nullptr;
         plan.ar.ctl = nullptr;
-        plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2};
+        // check-only: the host-source segments sort last and are worked from LDS
+        const bool host_last = c->host_lds && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK;
+        plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2,
+                         host_last ? 1u : 0u};
         plan.sort = &w->sort;
         a.perm = w->perm;
+        a.lds_meta = host_last ? w->meta : nullptr;
+        a.task_pos = c->task_pos;
         sp = &plan;
     }
     const LaunchShape sh = shape_of(c, tun);
@@ -928,9 +938,12 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_BLOCK")) c->tuning.block = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_BLOCKS_PER_CU")) c->tuning.blocks_per_cu = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_TILE_UNITS")) c->tuning.tile_units = (uint32_t)atoi(e);
+    if (const char *e = getenv("XC_NONTEMPORAL")) c->tuning.nontemporal = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_REORDER_MIN")) c->reorder_min = strtoull(e, nullptr, 0);
     if (const char *e = getenv("XC_SEG_MIN_LOG2")) c->seg_min_log2 = (uint32_t)atoi(e);
     if (const char *e = getenv("XC_SMALL_MAX")) c->small_max = std::min<uint64_t>(strtoull(e, nullptr, 0), 1ull << 20);
+    if (const char *e = getenv("XC_HOST_LDS")) c->host_lds = atoi(e);
+    if (const char *e = getenv("XC_TASK_POS")) c->task_pos = std::min<uint32_t>((uint32_t)atoi(e), 256);
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
@@ -1444,7 +1457,12 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     if (!rc) {
         cands.clear();
         for (uint32_t b : {256u, 512u})
-            for (uint32_t bpc : {1u, 2u, 4u, 8u}) { cg_tuning t = cur; t.block = b; t.blocks_per_cu = bpc; cands.push_back(t); }
+            for (uint32_t bpc : {1u, 2u, 3u, 4u, 6u, 8u}) {
+                cg_tuning t = cur;
+                t.block = b;
+                t.blocks_per_cu = bpc;
+                cands.push_back(t);
+            }
         rc = try_set(cands);
     }
     if (!rc) {
@@ -1460,7 +1478,12 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
         // the occupancy that suits a tile size may differ from the first pick
         cands.clear();
         for (uint32_t b : {256u, 512u})
-            for (uint32_t bpc : {1u, 2u, 4u, 8u}) { cg_tuning t = cur; t.block = b; t.blocks_per_cu = bpc; cands.push_back(t); }
+            for (uint32_t bpc : {1u, 2u, 3u, 4u, 6u, 8u}) {
+                cg_tuning t = cur;
+                t.block = b;
+                t.blocks_per_cu = bpc;
+                cands.push_back(t);
+            }
         rc = try_set(cands);
     }
     if (!rc) {

@@ -61,9 +61,14 @@ __device__ __forceinline__ uint64_t seg_count(const Desc &d, uint32_t lb)
     return (a1 >> lb) - (a0 >> lb) + 1;
 }
 
-__device__ __forceinline__ uint64_t seg_key(const Desc &d, uint32_t lb, uint64_t j)
+// a segment of a record whose source is the host region
+__device__ __forceinline__ bool seg_host(const Desc &d) { return seg_split(d) && (d.ctl & CTL_SRC_HOST); }
+
+// the block of segment j; with host_last, host-source segments after all others
+__device__ __forceinline__ uint64_t seg_key(const Desc &d, uint32_t lb, uint64_t j, uint32_t host_last)
 {
-    return seg_split(d) ? (seg_a0(d) >> lb) + j : 0ull;
+    if (!seg_split(d)) return 0ull;
+    return ((seg_a0(d) >> lb) + j) | (host_last && (d.ctl & CTL_SRC_HOST) ? 1ull << 63 : 0ull);
 }
 
 // units [u0, u1) of segment j
@@ -157,6 +162,7 @@ __global__ void __launch_bounds__(1024) k_seg_scan(SegArgs g, uint64_t nbr)
     if (tid == 1023) {
         const uint64_t total = off + x;
         g.meta[0] = total < g.npos ? total : g.npos;   // total <= 3 * count = npos by the choice of B
+        g.meta[2] = g.meta[0];                           // no host-source position yet (k_seg_layout)
     }
 }
 
@@ -172,7 +178,7 @@ __global__ void __launch_bounds__(kT) k_seg_keys(SegArgs g, uint64_t *keys, uint
     const uint64_t ns = g.meta[0];
     const uint32_t lb = (uint32_t)g.meta[1];
     const uint64_t q = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    const uint64_t key0 = seg_key(g.rdesc[0], lb, 0);   // segment 0 is record 0's first
+    const uint64_t key0 = seg_key(g.rdesc[0], lb, 0, g.host_last);   // segment 0 is record 0's first
     uint64_t x = 0;
     if (q < ns) {
         // the record holding segment q: the last r with first[r] <= q (every
@@ -182,7 +188,7 @@ __global__ void __launch_bounds__(kT) k_seg_keys(SegArgs g, uint64_t *keys, uint
             const uint64_t mid = (lo + hi + 1) >> 1;
             if (g.first[mid] <= q) lo = mid; else hi = mid - 1;
         }
-        const uint64_t key = seg_key(g.rdesc[lo], lb, q - g.first[lo]);
+        const uint64_t key = seg_key(g.rdesc[lo], lb, q - g.first[lo], g.host_last);
         keys[q] = key;
         vals[q] = (uint32_t)q;
         g.srec[q] = (uint32_t)lo;
@@ -210,6 +216,7 @@ __global__ void __launch_bounds__(kT) k_seg_layout(SegArgs g, const uint32_t *va
     if (p < g.npos) {
         Desc o = {};
         uint32_t r = 0;
+        bool host = false;
         if (p < ns) {
             const uint32_t q = sorted[p];
             r = g.srec[q];
@@ -219,13 +226,17 @@ __global__ void __launch_bounds__(kT) k_seg_layout(SegArgs g, const uint32_t *va
             o = d;
             o.e0 = d.e0 + u0;
             o.units = u1 - u0;
+            host = g.host_last && seg_host(d);
+            // the first host-source position (they sort last)
+            if (host && (p == 0 || !seg_host(g.rdesc[g.srec[sorted[p - 1]]]))) g.meta[2] = p;
         }
         desc[p] = o;
         perm[p] = r;
         weight[p] = o.units;
         // a segment weighs its units (at least 1); the empty positions past
-        // the segments weigh 0, so no unit of the scan reaches them
-        w = p < ns ? (o.units ? o.units : 1) : 0;
+        // the segments, and with host_last the host-source ones (worked by
+        // k_host_lds), weigh 0, so no unit of the scan kernel reaches them
+        w = p < ns && !host ? (o.units ? o.units : 1) : 0;
     }
     uint64_t tot;
     const uint64_t ex = block_excl(w, &tot);

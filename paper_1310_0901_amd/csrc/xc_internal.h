@@ -50,8 +50,10 @@ struct alignas(64) Ctl {
     uint64_t tile_units;    // units per tile actually used
     uint32_t counter[8];    // per XCD: tiles taken from its chunk beyond the first tiles
     uint64_t pad[1];
+    uint32_t lds_counter[8];  // per XCD: host-source tasks taken beyond the first ones (k_host_lds)
+    uint64_t pad2[4];
 };
-static_assert(sizeof(Ctl) == 64, "control block layout");
+static_assert(sizeof(Ctl) == 128, "control block layout");
 
 struct Region {
     uint64_t hb, hl;
@@ -104,6 +106,11 @@ struct BatchArgs {
     // that record's verdict (descriptors, weights and prefixes are by
     // position; the positions are source-block segments, segment.hip)
     const uint32_t *perm;
+    // when not null (a check-only batch worked as segments), the host-source
+    // positions [lds_meta[2], lds_meta[0]) weigh 0 in the scan kernel's
+    // prefix and are worked by k_host_lds from LDS
+    const uint64_t *lds_meta;
+    uint32_t task_pos;   // positions per task of k_host_lds (0: its default)
 };
 
 // Cutting a batch's records into source-block segments (segment.hip).
@@ -117,8 +124,9 @@ struct SegArgs {
     uint64_t *first;        // per record: first segment
     uint64_t *sbsum;        // per record block: segment sums, then their prefix
     uint32_t *srec;         // per segment: its record
-    uint64_t *meta;         // [0] segments, [1] log2 of the block size
+    uint64_t *meta;         // [0] segments, [1] log2 of the block size, [2] first host-source position
     uint32_t min_log2;      // smallest block size, log2
+    uint32_t host_last;     // host-source segments sort after the others and weigh 0: k_host_lds works them
 };
 
 // Per record of a batch worked by k_small: the findings of its blocks so
@@ -133,6 +141,8 @@ static_assert(sizeof(SmallAcc) == 24, "small-batch accumulator layout");
 struct LaunchShape {
     uint32_t block, unroll, grid, nontemporal;
     uint32_t tile_units;
+    uint32_t cus;   // compute units of the device
+    uint32_t lds_after;   // host-source positions in a kernel of their own after the scan kernel (else side by side)
 };
 
 // Merge of a table version with the frees and allocations made since
@@ -158,6 +168,7 @@ hipError_t launch_merge_warm(hipStream_t s);
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s);
 hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);
+// the persistent scan kernel, then (a.lds_meta) the host-source positions in LDS
 hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s);
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
                         hipStream_t s);

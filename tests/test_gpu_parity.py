@@ -35,6 +35,15 @@ def batch_path(request, monkeypatch):
     return request.param
 
 
+@pytest.fixture(params=["host-lds", "host-lds-after", "scan-only"])
+def host_lds(request, monkeypatch):
+    """Check-only batches worked as segments with their host-source segments
+    staged in LDS, by the scan kernel's own blocks or by a kernel of their
+    own after it, or all of them in the persistent scan kernel."""
+    monkeypatch.setenv("XC_HOST_LDS", {"host-lds": "1", "host-lds-after": "2", "scan-only": "0"}[request.param])
+    return request.param
+
+
 def modes(X):
     return [("graph", X.CG_CHECK), ("eager", X.CG_CHECK | X.CG_EAGER), ("plain", X.CG_CHECK | X.CG_PLAIN)]
 
@@ -58,7 +67,7 @@ def test_tiny_universe_every_case(X, H, batch_path):
         dw.close()
 
 
-def test_tiny_universe_segmented(X, H, monkeypatch):
+def test_tiny_universe_segmented(X, H, host_lds, monkeypatch):
     """Every classification case of the tiny universe (bad kinds, empty
     records, unallocated and unaddressable sides, overruns, overlapping
     D2D) in one batch worked as source-block segments of 16 bytes and up,
@@ -183,7 +192,7 @@ def test_conflicting_batch_is_refused(X, H):
 
 @pytest.mark.parametrize("seg_log2", ["20", "4"])
 @pytest.mark.parametrize("seed", [31, 32, 33])
-def test_reordered_batches(X, H, seed, seg_log2, monkeypatch):
+def test_reordered_batches(X, H, seed, seg_log2, host_lds, monkeypatch):
     """Batches worked as source-block segments (forced here for small
     batches; with a 16-byte floor on the block size, records are cut into
     several segments each): verdicts and every shadow byte equal the
@@ -217,7 +226,7 @@ def test_reordered_batches(X, H, seed, seg_log2, monkeypatch):
 
 
 @pytest.mark.parametrize("seed", [41, 42])
-def test_segments_of_large_records(X, H, seed, monkeypatch):
+def test_segments_of_large_records(X, H, seed, host_lds, monkeypatch):
     """Records of up to 3 MB beside small ones, worked as segments: the block
     size follows the mean record size, so large records are cut into many
     segments (some of them in blocks other records also read), and single
@@ -252,7 +261,7 @@ def test_segments_of_large_records(X, H, seed, monkeypatch):
         dw.close()
 
 
-def test_segmented_graph_replays(X, H, monkeypatch):
+def test_segmented_graph_replays(X, H, host_lds, monkeypatch):
     """A segmented batch checked through its captured graph several times on
     the same buffers, with the verdicts overwritten, eager checks and host
     synchronisation between the replays: every replay equals the oracle."""
