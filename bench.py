@@ -103,8 +103,8 @@ def cpu_baseline_legs(w, hv, ha, got, all_bytes, one_bytes):
 
 
 def matching_profile(name, tuning, config):
-    """A committed rocprofv3 summary (profiles/<name>.json) of the scan kernel on
-    the 1M-record workload, if the kernel source and launch shape are the ones
+    """A committed rocprofv3 summary (profiles/<name>.json) of a kernel on the
+    1M-record workload, if the kernel source and launch shape are the ones
     profiled: (dict, None); else (None, the reason)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name + ".json")
@@ -114,28 +114,39 @@ def matching_profile(name, tuning, config):
     src = os.path.join(ROOT, "paper_1310_0901_amd", "csrc", "kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != prof["kernels_hip_sha256"]:
         return None, "kernel changed since the counters were taken"
-    if {k: tuning[k] for k in prof["tuning"]} != prof["tuning"]:
+    if tuning is not None and {k: tuning[k] for k in prof["tuning"]} != prof["tuning"]:
         return None, "launch shape differs from the profiled one"
     return prof, None
 
 
-def profiled_traffic(tuning, config):
-    """Bytes per launch of the scan kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (scaled by the copy-probe factor), if the kernel source and
-    launch shape are the ones profiled; else None."""
-    prof, why = matching_profile("k_batched_batched-1M_traffic", tuning, config)
+def roofline(tun, config, k_avg_ms, bytes_step, l2_probe_GBps):
+    """The scan kernel's roofline from its committed counters and its live
+    duration: the bytes the L2 returns to the L1s per launch (L1 -> L2 read
+    requests x 128 B) over the launch, against the L2-resident read probe
+    measured in this run; HBM traffic (FETCH_SIZE + WRITE_SIZE, scaled by the
+    copy probe) beside it."""
+    prof, why = matching_profile("k_batched_lds_batched-1M_counters", tun, config)
+    t = k_avg_ms / 1e3
+    out = {"kernel": "k_batched_lds", "kernel_avg_ms": round(k_avg_ms, 3),
+           "effective_algorithmic_GBps": round(bytes_step / t / 1e9, 1),
+           "algorithmic_bytes_per_launch": int(bytes_step)}
     if prof is None:
-        return None, why
-    return int(prof["traffic_bytes"]), "bytes per launch, profiles/k_batched_batched-1M_traffic.md"
-
-
-def profiled_limits(tuning, config):
-    """Issue and load-path utilisation of the scan kernel from the committed SQ /
-    TA / TCC counter passes, under the same matching rule; else None."""
-    prof, why = matching_profile("k_batched_batched-1M_counters", tuning, config)
-    if prof is None:
-        return {"note": why}
-    return dict(prof["limits"], source="profiles/k_batched_batched-1M_counters.md")
+        return dict(out, bound=None, achieved=None, peak=None, unit="GB/s", frac=None, traffic=None, note=why)
+    lim = prof["limits"]
+    peak = l2_probe_GBps or None
+    achieved = lim["l2_to_l1_bytes"] / t / 1e9
+    traffic = int(lim["traffic_bytes"])
+    return dict(bound=prof["bound"], achieved=round(achieved, 1), peak=round(peak, 1) if peak else None, unit="GB/s",
+                frac=round(achieved / peak, 4) if peak else None, traffic=traffic,
+                hbm_GBps=round(traffic / t / 1e9, 1), hbm_frac=round(traffic / t / 1e9 / HBM_PEAK_GBS, 4),
+                **out,
+                note="achieved = bytes the L2 returns to the L1s per launch (counted L1 -> L2 read requests x 128 B, "
+                     "profiles/k_batched_lds_batched-1M_counters.md) over this run's kernel time; peak = this run's "
+                     "L2-resident read probe (cg_probe_l2). Host-source segments are checked from LDS, so the "
+                     "algorithmic bytes exceed what crosses L2; traffic = HBM-side bytes per launch from FETCH_SIZE + "
+                     "WRITE_SIZE; effective_algorithmic_GBps counts every byte the check examines",
+                limits=dict({k: v for k, v in lim.items() if k not in ("traffic_bytes", "l2_to_l1_bytes")},
+                            source="profiles/k_batched_lds_batched-1M_counters.md"))
 
 
 def given_order_leg(X, ctx, w, recs_t, got, T, stream, dev, bytes_step, steps=2):
@@ -164,8 +175,17 @@ def given_order_leg(X, ctx, w, recs_t, got, T, stream, dev, bytes_step, steps=2)
          "GBps": round(bytes_step / wall / 1e9, 1), "scan_GBps": round(bytes_step / (k / 1e3) / 1e9, 1),
          "scan_pct_hbm_peak": round(100 * bytes_step / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 2),
          "verdicts_identical_to_batched": bool(same), "tuning": tun,
-         "note": "check-only, records in their given order: traffic behind L2 is about 1.0x the algorithmic bytes "
-                 "(profiles/k_batched_given-order_traffic.md), so this rate is bound by HBM"}
+         "note": "check-only, records in their given order: almost no re-read hits in L2, so this rate is bound "
+                 "by HBM"}
+    prof, why = matching_profile("k_batched_given-order_batched-1M_counters", tun, 3)
+    if prof is not None:
+        tb = prof["limits"]["traffic_bytes"]
+        o["roofline"] = {"bound": "hbm", "achieved": round(tb / (k / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(tb / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": tb,
+                         "traffic_over_algorithmic": round(tb / bytes_step, 4),
+                         "source": "profiles/k_batched_given-order_batched-1M_counters.md"}
+    else:
+        o["roofline"] = {"note": why}
     log(f"[bench] given order: {o}")
     return o
 
@@ -574,7 +594,6 @@ def main():
                    "mode": "check", "path": "batched: classify + source-block segments + scan + persistent scan kernel, "
                            "hipGraph replay",
                    "tuning": tun},
-        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "transfers_per_s": round(T / (wall / args.steps), 1),
         "algorithmic_bytes_per_step": int(bytes_step),
     }
@@ -628,15 +647,8 @@ def main():
         result["probe_l2_read"] = l2
         log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write), L2-resident read {l2}")
 
-    traffic, traffic_note = profiled_traffic(tun, args.config)
-    result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_note": traffic_note,
-                          "kernel": "k_batched", "kernel_avg_ms": round(k_avg_ms, 3),
-                          "note": "achieved counts the bytes the check examines; a large batch is worked as "
-                                  "segments of its records sorted by block of source memory, so re-reads of the "
-                                  "same bytes hit in L2 and traffic (L2 misses to the fabric) is below them",
-                          "algorithmic_bytes_per_launch": int(bytes_step),
-                          "limits": profiled_limits(tun, args.config)}
+    result["roofline"] = roofline(tun, args.config, k_avg_ms, bytes_step,
+                                  result.get("probe_l2_read", {}).get("GBps"))
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline_legs(w, hv, ha, got, args.cpu_bytes, args.cpu_bytes_one)
     dw.close()
