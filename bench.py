@@ -328,6 +328,35 @@ def plain_at_scale_leg():
         wall = (time.perf_counter() - t0) / 3
         out["pitched_2d"] = {"records": T, "rows": int(rows.sum()), "ms": round(wall * 1e3, 3),
                              "GBps": round(b2 / wall / 1e9, 1), "algorithmic_bytes": b2}
+        # strided: the same rows narrowed to 4,032 bytes at the 4 KiB pitch (a sub-matrix copy)
+        r2["width"] = 4032
+        b3 = int((rows * 4032).sum()) * 9 // 8
+        rt3 = torch.from_numpy(r2.view(np.uint8).copy()).to(rt.device)
+        X.check_transfers_2d(ctx, rt3.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            X.check_transfers_2d(ctx, rt3.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 3
+        out["pitched_2d_strided"] = {"records": T, "rows": int(rows.sum()), "width": 4032, "pitch": 4096,
+                                     "ms": round(wall * 1e3, 3), "GBps": round(b3 / wall / 1e9, 1),
+                                     "algorithmic_bytes": b3}
+        # short strided rows: 240 bytes at a 256-byte pitch over the same spans
+        rows_s = w.records["n"] // 256
+        r2["width"], r2["rows"], r2["spitch"], r2["dpitch"] = 240, rows_s, 256, 256
+        b4 = int((rows_s * 240).sum()) * 9 // 8
+        rt4 = torch.from_numpy(r2.view(np.uint8).copy()).to(rt.device)
+        X.check_transfers_2d(ctx, rt4.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            X.check_transfers_2d(ctx, rt4.data_ptr(), T, ob.data_ptr(), X.CG_CHECK, s)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / 3
+        out["pitched_2d_short"] = {"records": T, "rows": int(rows_s.sum()), "width": 240, "pitch": 256,
+                                   "ms": round(wall * 1e3, 3), "GBps": round(b4 / wall / 1e9, 1),
+                                   "algorithmic_bytes": b4}
     finally:
         dw.close()
     log(f"[bench] plain at scale: {out}")

@@ -67,6 +67,7 @@ extern "C" {
 #define CG_DST_OVERRUN  0x040u  /* n exceeds the bytes left in the destination allocation */
 #define CG_OVERLAP      0x080u  /* device->device copy whose ranges intersect (not propagated) */
 #define CG_BAD_KIND     0x100u  /* kind is not 0, 1 or 2 */
+#define CG_ROWS_LIMIT   0x200u  /* pitched 2D copy: not every row was checked (see check_transfers_2d) */
 #define CG_NONE 0xFFFFFFFFFFFFFFFFull /* first_bad when the transfer is clean */
 
 /* ---- modes of check_transfers ------------------------------------------ */
@@ -221,14 +222,22 @@ typedef struct cg_transfer2d {
  * (byte c of row r is r*width + c): flags = OR over its rows, first_bad =
  * smallest r*width + first_bad_r, undef_bytes = sum, avail = the first row's
  * (bytes from src / dst to the end of its allocation).  A record with no
- * rows or width 0 gives {0, CG_NONE, 0, 0}.  Modes as check_transfers, except
- * that the rows are always worked in their order (CG_KEEP_ORDER), and that a
- * check without CG_PROPAGATE whose rows are mostly 16 KiB wide or less runs
- * with a fixed launch shape (256-thread blocks, unroll 2, 16 blocks per CU)
- * instead of the context's tuning.  The
- * call waits for the caller's stream once, to learn the number of rows
- * (at most 2^32 - 1024 in total).  Errors: as check_transfers, and CG_EINVAL for
- * 2^31 records or more, or too many rows.
+ * rows or width 0 gives {0, CG_NONE, 0, 0}.
+ * Every record is one work item whose rows are stepped through on the device,
+ * so the call does not wait for the stream and can be captured in a graph:
+ * under capture it needs an earlier call on the same stream, of at least this
+ * count, made after the last change of allocations or host region
+ * (CG_ESTATE otherwise), and a replay reads the allocations as they were at
+ * capture, so the caller replays it only while they are unchanged.
+ * The rows of a record checked are those below index 2^32 that start below
+ * byte 2^62 of the copy; a record with more rows gets CG_ROWS_LIMIT in its
+ * flags (its other fields cover the rows checked).
+ * With CG_PLAIN or CG_DEBUG_CONFLICTS the rows are instead expanded into
+ * transfer records (a launch per row, or the host-side conflict check on the
+ * rows): that call waits for the stream once, to learn the number of rows, and
+ * fails with CG_EINVAL above 2^32 - 1024 rows in total.
+ * Modes as check_transfers otherwise; the context's tuning applies.
+ * Errors: as check_transfers, and CG_EINVAL for 2^31 records or more.
  */
 int check_transfers_2d(cg_ctx *ctx, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev,
                        uint32_t mode, void *hip_stream);

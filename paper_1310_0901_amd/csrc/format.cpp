@@ -66,6 +66,7 @@ extern "C" int cg_format_verdict(const cg_transfer *rec, const cg_verdict *v, ch
         if (f & CG_OVERLAP)
             line(s, "Warning: Source and destination of %s copy overlap; definedness not propagated.", dir);
     }
+    if (f & CG_ROWS_LIMIT) line(s, "Note: not every row of the pitched %s copy was checked.", dir);
     if (len) {
         const size_t k = s.size() < len - 1 ? s.size() : (size_t)len - 1;
         s.copy(buf, k);

@@ -82,8 +82,16 @@ int AllocTable::erase(uint64_t base, AllocEntry *out)
     auto it = m_.find(base);
     if (it == m_.end()) return CG_ENOTFOUND;
     if (out) *out = it->second;
+    --by_bits_[bits(it->second.size)];
     m_.erase(it);
     return CG_OK;
+}
+
+uint64_t AllocTable::size_bound() const
+{
+    for (int k = 64; k > 0; --k)
+        if (by_bits_[k]) return k == 64 ? ~0ull : (1ull << k) - 1;
+    return 0;
 }
 
 const AllocEntry *AllocTable::find(uint64_t p, uint64_t *base) const

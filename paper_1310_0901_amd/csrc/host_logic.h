@@ -43,7 +43,11 @@ class AllocTable {
 public:
     // CG_OK, CG_EINVAL (size 0 or end beyond 2^64 - 1) or CG_EOVERLAP
     int check_insert(uint64_t base, uint64_t size) const;
-    void insert(uint64_t base, uint64_t size, uint64_t off) { m_[base] = AllocEntry{size, off}; }
+    void insert(uint64_t base, uint64_t size, uint64_t off)
+    {
+        m_[base] = AllocEntry{size, off};
+        ++by_bits_[bits(size)];
+    }
     // CG_OK or CG_ENOTFOUND (not the base of a live allocation)
     int erase(uint64_t base, AllocEntry *out);
     // live allocation containing p, or nullptr
@@ -51,9 +55,14 @@ public:
     size_t size() const { return m_.size(); }
     // sorted arrays of bases, ends and pool offsets (each size() long)
     void export_sorted(uint64_t *base, uint64_t *end, uint64_t *off) const;
+    // a bound of every live allocation's size, within a factor of two:
+    // 2^k - 1 for the smallest k that covers them all (0 when there is none)
+    uint64_t size_bound() const;
 
 private:
+    static int bits(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
     std::map<uint64_t, AllocEntry> m_;
+    uint64_t by_bits_[65] = {};   // live allocations by the bit length of their size
 };
 
 }  // namespace xc

@@ -589,6 +589,35 @@ __device__ __forceinline__ int64_t table_lookup(const TableView &tb, const uint6
     return p < tb.end[a] ? (int64_t)a : -1;
 }
 
+// wave-wide sum of a 32-bit value (every lane active)
+__device__ __forceinline__ uint32_t wave_add32(uint32_t x)
+{
+    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d);
+    return x;
+}
+
+// The table search of table_lookup done by one wave (every lane active): the
+// top level, then the segment of 2^top_shift entries it picks, are each
+// compared 64 entries at a time, so two rounds of independent loads take the
+// place of a chain of dependent ones.  Entries are sorted by base, so the
+// number of them at or below p is one past the last of them.
+__device__ int64_t table_lookup_wave(const TableView &tb, uint64_t p)
+{
+    if (tb.n == 0) return -1;
+    const uint32_t lane = lane_id();
+    uint32_t c = 0;
+    for (uint32_t k = lane; k < tb.ntop; k += 64) c += tb.top[k] <= p ? 1u : 0u;
+    c = wave_add32(c);
+    if (c == 0) return -1;
+    const uint64_t a0 = (uint64_t)(c - 1) << tb.top_shift;
+    const uint64_t a1 = a0 + (1ull << tb.top_shift) < tb.n ? a0 + (1ull << tb.top_shift) : tb.n;
+    uint32_t c2 = 0;
+    for (uint64_t k = a0 + lane; k < a1; k += 64) c2 += tb.base[k] <= p ? 1u : 0u;
+    c2 = wave_add32(c2);
+    const uint64_t j = a0 + c2 - 1;   // base[a0] is top[c - 1] <= p, so c2 >= 1
+    return p < tb.end[j] ? (int64_t)j : -1;
+}
+
 // Byte indices i in [0, n) with hb <= p + i < hb + hl, as [lo, hi) (empty: 0, 0).
 __device__ __forceinline__ void region_clip(uint64_t p, uint64_t n, uint64_t hb, uint64_t hl,
                                             uint64_t &lo, uint64_t &hi)
@@ -773,6 +802,207 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// pitched 2D records (check_transfers_2d) as positions of their own
+// ---------------------------------------------------------------------------
+
+// Pitch::uniform: rows follow row 0 (kRowsUniform), and also keep its 16-byte
+// phases, so that every row has row 0's units and upr is that number
+// (kRowsStep); or, in a check without propagation, the rows' sources (and a
+// host destination) lie back to back, so that the record is worked as one
+// transfer of rows * width bytes, whose descriptor is the position's and whose
+// units are upr (kRowsContig): its byte indices are the record's own.
+constexpr uint32_t kRowsUniform = 1u, kRowsStep = 3u, kRowsContig = 7u;
+
+// rows of a 2D record that are worked: every row below index 2^32 that
+// starts below byte 2^62 of the record (its bytes are numbered row by row)
+__device__ __forceinline__ uint64_t rows_worked(const cg_transfer2d &r)
+{
+    if (r.width == 0 || r.rows == 0) return 0;
+    const uint64_t lim = r.width >= kScanLimit ? 1 : (kScanLimit + r.width - 1) / r.width;
+    uint64_t n = r.rows < lim ? r.rows : lim;
+    return n < (1ull << 32) ? n : (1ull << 32);
+}
+
+// A bound of the bytes from any row's start to the end of that row's valid
+// source and destination parts, for a record whose rows do not follow row 0:
+// a device side ends within its allocation (none is larger than
+// st.size_bound); a host side ends within the region, at most `gap + hl`
+// bytes from a row that starts `gap` bytes below it.  The host side's rows
+// start no lower than row 0 unless their addresses wrap past 2^64.
+__device__ __forceinline__ uint64_t row_extent_bound(const Pitch &P, uint64_t rows, const DevState &st)
+{
+    uint64_t e = st.size_bound;
+    if (P.kind == CG_H2D || P.kind == CG_D2H) {
+        const Region &R = st.region;
+        const uint64_t p = P.kind == CG_H2D ? P.src : P.dst, q = P.kind == CG_H2D ? P.spitch : P.dpitch;
+        const bool wraps = q != 0 && rows > 1 && rows - 1 > (~0ull - p) / q;
+        const uint64_t gap = wraps ? R.hb : (p < R.hb ? R.hb - p : 0);
+        const uint64_t h = gap + R.hl;
+        e = e > h ? e : h;
+    }
+    return e;
+}
+
+// do rows 0 .. n-1 of one side, starting at p with pitch q and `w` bytes
+// long, all lie in [lo, hi)?  (p >= lo is known)
+__device__ __forceinline__ bool rows_inside(uint64_t p, uint64_t q, uint64_t w, uint64_t n, uint64_t lo, uint64_t hi)
+{
+    (void)lo;
+    if (p >= hi || w > hi - p) return false;
+    if (n <= 1 || q == 0) return true;
+    return n - 1 <= (hi - p - w) / q;   // p + (n-1) q + w <= hi
+}
+
+// the transfer record of row r
+__device__ __forceinline__ cg_transfer row_record(const Pitch &P, uint64_t r)
+{
+    return cg_transfer{P.src + r * P.spitch, P.dst + r * P.dpitch, P.width, P.kind, 0u};
+}
+
+// One lane per pitched 2D record: row 0 looked up and classified (its
+// descriptor is the position's), whether every row follows from it, the
+// units (rows * upr) and the verdict before any row is worked: row 0's when
+// the rows are uniform, else {0, NONE, 0, row 0's avail} (the rows bring
+// their own flags), with ROWS_LIMIT when not every row is worked.  A record
+// with no rows or width 0 gives {0, NONE, 0, 0}, one with rows and a bad
+// kind {BAD_KIND, NONE, 0, 0}; both weigh 1 and have no units.  upr bounds
+// the units of every row: a uniform row's follow from the width, any other
+// row's from the extent of its valid parts (so a bogus width costs no more
+// than the memory its rows can reach).
+__global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, const cg_transfer2d *recs2d, Pitch *pitch)
+{
+    __shared__ uint64_t top[kMaxTop];
+    __shared__ uint64_t wsum[kClassifyBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    const DevState st = *a.st;
+    for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
+    uint64_t w = 0;
+    if (t < a.count) {
+        const cg_transfer2d R2 = recs2d[t];
+        Pitch P{R2.src, R2.dst, R2.width, R2.rows, R2.spitch, R2.dpitch, 0, R2.kind, 0};
+        Desc ds = {};
+        cg_verdict v{0u, 0u, NONE, 0, 0};
+        uint64_t units = 0;
+        const uint64_t rows = rows_worked(R2);
+        if (rows == 0) {
+            // nothing to check
+        } else if (R2.kind > CG_D2D) {
+            v.flags = CG_BAD_KIND;
+        } else {
+            const cg_transfer r0 = row_record(P, 0);
+            const int64_t js = dev_src(r0) ? table_lookup(st.table, top, r0.src) : -1;
+            const int64_t jd = dev_dst(r0) ? table_lookup(st.table, top, r0.dst) : -1;
+            cg_verdict v0;
+            const uint64_t u0 = classify_rec(r0, a.mode, st, js, jd, ds, v0);
+            const Region &R = st.region;
+            auto side_ok = [&](bool host, int64_t j, uint64_t p, uint64_t q) {
+                if (host) return R.hl > 0 && p >= R.hb && rows_inside(p, q, P.width, rows, R.hb, R.hb + R.hl);
+                return j >= 0 && rows_inside(p, q, P.width, rows, st.table.base[j], st.table.end[j]);
+            };
+            const bool uniform = (v0.flags & ~CG_OVERLAP) == 0 && (R2.kind != CG_D2D || R2.spitch == R2.dpitch) &&
+                                 side_ok(R2.kind == CG_H2D, js, P.src, P.spitch) &&
+                                 side_ok(R2.kind == CG_D2H, jd, P.dst, P.dpitch);
+            P.rows = rows;
+            uint64_t ext = P.width < kScanLimit ? P.width : kScanLimit;
+            if (!uniform) {
+                const uint64_t b = row_extent_bound(P, rows, st);
+                ext = b < ext ? b : ext;
+            }
+            // rows that follow row 0 at pitches that keep the 16-byte phases
+            // all have row 0's units: no padding between rows
+            const bool step = uniform && ((P.spitch | P.dpitch) & 15u) == 0 && u0 > 0;
+            P.upr = step ? u0 : (ext + 14) / 16 + 2;
+            P.uniform = uniform ? (step ? kRowsStep : kRowsUniform) : 0u;
+            // rows back to back on every side the check reads: one transfer
+            // (in the rows' allocations, so its lookups are row 0's)
+            if (step && !(a.mode & CG_PROPAGATE) && R2.spitch == R2.width &&
+                (R2.kind != CG_D2H || R2.dpitch == R2.width)) {
+                const cg_transfer rc{P.src, P.dst, rows * P.width, P.kind, 0u};
+                cg_verdict vc;
+                P.upr = classify_rec(rc, a.mode, st, js, jd, ds, vc);
+                P.uniform = kRowsContig;
+            }
+            units = P.uniform == kRowsContig ? P.upr : rows * P.upr;
+            v = uniform ? v0 : cg_verdict{0u, 0u, NONE, 0, v0.avail};
+            if (rows < R2.rows) v.flags |= CG_ROWS_LIMIT;
+        }
+        pitch[t] = P;
+        a.desc[t] = ds;
+        a.weight[t] = units;
+        if (a.out && (a.mode & CG_CHECK)) a.out[t] = v;
+        w = units ? units : 1;
+    }
+    const uint32_t lane = lane_id(), wid = tid >> 6;
+    uint64_t x = w;
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63u) wsum[wid] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
+    if (t < a.count) a.local[t] = off + x - w;
+    if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
+}
+
+// Row r's descriptor when the rows are uniform: row 0's shifted by the
+// pitches; the phases, and so the realignment and the unit range, are row r's.
+__device__ Desc row_desc(const Desc &d0, const Pitch &P, uint64_t r)
+{
+    const uint32_t phi0 = (d0.ctl >> CTL_PHI_SHIFT) & 15u, psi0 = (d0.ctl >> CTL_PSI_SHIFT) & 15u;
+    const uint64_t src0 = d0.src_sh + phi0 + r * P.spitch, dst0 = d0.dst_sh + psi0 + r * P.dpitch;
+    const uint32_t phi = (uint32_t)(src0 & 15u), psi = (uint32_t)(dst0 & 15u);
+    const bool dstwork = (d0.ctl & (CTL_PROP | CTL_DST_A)) != 0;
+    const uint32_t delta = (dstwork && phi < psi) ? 1u : 0u;
+    const uint64_t w = P.width;
+    uint64_t e_lo = delta, e_hi = ((w - 1 + phi) >> 4) + 1 + delta;
+    if (dstwork) {
+        const uint64_t f_hi = ((w - 1 + psi) >> 4) + 1;
+        e_lo = 0;
+        e_hi = f_hi > e_hi ? f_hi : e_hi;
+    }
+    Desc x = d0;
+    x.src_sh = src0 - phi;
+    x.dst_sh = dst0 - psi;
+    x.v_lo = 0;
+    x.v_hi = (int64_t)w;
+    x.d_lo = 0;
+    x.d_hi = (int64_t)w;
+    x.a_src = d0.a_src + (int64_t)phi0 + (int64_t)(r * P.spitch) - (int64_t)phi;
+    x.a_dst = d0.a_dst + (int64_t)psi0 + (int64_t)(r * P.dpitch) - (int64_t)psi;
+    x.e0 = e_lo;
+    x.units = e_hi - e_lo;
+    x.ctl = (d0.ctl & ~((15u << CTL_PHI_SHIFT) | (15u << CTL_PSI_SHIFT) | CTL_DELTA)) | (phi << CTL_PHI_SHIFT) |
+            (psi << CTL_PSI_SHIFT) | (delta ? CTL_DELTA : 0u);
+    return x;
+}
+
+// every field of a wave-uniform descriptor in scalar registers
+__device__ __forceinline__ DV dv_uniform(const Desc &x)
+{
+    Desc u;
+    u.src_sh = ufl64(x.src_sh); u.dst_sh = ufl64(x.dst_sh);
+    u.v_lo = (int64_t)ufl64((uint64_t)x.v_lo); u.v_hi = (int64_t)ufl64((uint64_t)x.v_hi);
+    u.d_lo = (int64_t)ufl64((uint64_t)x.d_lo); u.d_hi = (int64_t)ufl64((uint64_t)x.d_hi);
+    u.a_src = (int64_t)ufl64((uint64_t)x.a_src); u.a_dst = (int64_t)ufl64((uint64_t)x.a_dst);
+    u.e0 = ufl64(x.e0); u.units = ufl64(x.units); u.ctl = ufl32(x.ctl);
+    return make_dv(u);
+}
+
+// findings of one row (row-relative byte indices) into a record's
+// accumulator: byte c of row r is byte r * width + c of the record
+__device__ __forceinline__ void acc_add_row(Acc &acc, const Acc &ra, uint32_t rflags, uint64_t rfirst, uint64_t base)
+{
+    acc.flags |= ra.flags | rflags;
+    acc.undef += ra.undef;
+    if (ra.first != NONE) acc_min(acc, (int64_t)(base + ra.first));
+    if (rfirst != NONE) acc_min(acc, (int64_t)(base + rfirst));
+}
+
+// ---------------------------------------------------------------------------
 // k_pointers: pointer queries (kernel arguments) against the live allocations,
 // through the same table lookup as the transfers
 // ---------------------------------------------------------------------------
@@ -888,6 +1118,170 @@ __global__ void __launch_bounds__(256) k_tile_starts(BatchArgs a)
 // k_batched: persistent kernel over the tiles of the flattened unit space
 // ---------------------------------------------------------------------------
 
+// Units [k0, k1) of a pitched record whose rows step by the pitches with row
+// 0's phases (kRowsStep), checked without propagation, by the whole wave:
+// the rows' units follow each other with no gap (upr is a row's units), and
+// each lane works its own unit of an iteration in whichever row it falls, so
+// that short rows and row ends share iterations.  d is row 0's descriptor;
+// row r's source and destination lie r * spitch and r * dpitch further on.
+template <int U, bool NT>
+__device__ void run_rows_flat(const DV &d, const Pitch &P, const Region &R, uint64_t k0, uint64_t k1, Acc &acc)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t ur = P.upr;
+    const bool src_host = (d.ctl & CTL_SRC_HOST) != 0;
+    const bool dsta = (d.ctl & CTL_DST_A) != 0;
+    const uint64_t a16b = (uint64_t)R.a16;
+    uint64_t rb = k0 / ur, jb = k0 - rb * ur;   // row and unit of the iteration's first unit
+    for (uint64_t kb = k0; kb < k1; kb += 64u * U) {
+        u32x4 v[U];
+        uint32_t ms[U], as[U], md[U], ad[U];
+        int64_t fs[U], fd[U] = {};   // record byte index of byte 0 of the source / destination chunk
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t c = 64u * j + lane;
+            uint64_t r = rb, q = jb + c;
+            if (q >= ur) {
+                // ur >= 64 U: q < 2 ur; else q < ur + 64 U, small
+                const uint64_t x = ur >= 64u * U ? 1u : (uint64_t)((uint32_t)q / (uint32_t)ur);
+                r += x;
+                q -= x * ur;
+            }
+            const bool live = kb + c < k1;
+            const int64_t cs = (int64_t)(d.e0 + q) - (int64_t)d.delta;
+            const int64_t i0 = 16 * cs - (int64_t)d.phi;
+            const int64_t base = (int64_t)(r * P.width);
+            fs[j] = base + i0;
+            ms[j] = live ? rmask(d.v_lo - i0, d.v_hi - i0) : 0u;
+            v[j] = u32x4{0u, 0u, 0u, 0u};
+            as[j] = 0xFFFFu;
+            if (ms[j]) {
+                v[j] = ld16<NT>(d.src_sh + r * P.spitch + (uint64_t)(16 * cs));
+                if (src_host) as[j] = ld_u16(a16b + (((uint64_t)(d.a_src + 16 * cs) + r * P.spitch) >> 3));
+            }
+            md[j] = 0u;
+            ad[j] = 0xFFFFu;
+            if (dsta) {
+                const int64_t e = (int64_t)(d.e0 + q);
+                const int64_t i0d = 16 * e - (int64_t)d.psi;
+                fd[j] = base + i0d;
+                md[j] = live ? rmask(d.d_lo - i0d, d.d_hi - i0d) : 0u;
+                if (md[j]) ad[j] = ld_u16(a16b + (((uint64_t)(d.a_dst + 16 * e) + r * P.dpitch) >> 3));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            src_findings(acc, fs[j], v[j], ms[j] & as[j], ms[j] & ~as[j]);
+            const uint32_t ud = md[j] & ~ad[j];
+            if (dsta && ud) {
+                acc.flags |= CG_DST_UNADDR;
+                acc_min(acc, fd[j] + __builtin_ctz(ud));
+            }
+        }
+        jb += 64u * U;
+        if (jb >= ur) {
+            const uint64_t x = ur >= 64u * U ? 1u : (uint64_t)((uint32_t)jb / (uint32_t)ur);
+            rb += x;
+            jb -= x * ur;
+        }
+    }
+}
+
+// Units [k0, k1) of pitched position t, by the whole wave: row by row, each
+// row's own units through the wave-uniform loop; rows that do not follow row
+// 0 are looked up (64 table entries per step) and classified here, and their
+// range-derived flags join the record's (OR and min: a row worked in parts by
+// several waves adds them more than once to the same effect).
+template <int U, bool NT, bool PROP>
+__device__ void run_pitched(const BatchArgs &a, const DevState *st, uint64_t t, uint64_t k0, uint64_t k1, Acc &acc)
+{
+    const Pitch &Pg = a.pitch[t];
+    Pitch P;
+    P.src = ufl64(Pg.src); P.dst = ufl64(Pg.dst); P.width = ufl64(Pg.width); P.rows = ufl64(Pg.rows);
+    P.spitch = ufl64(Pg.spitch); P.dpitch = ufl64(Pg.dpitch); P.upr = ufl64(Pg.upr);
+    P.kind = ufl32(Pg.kind); P.uniform = ufl32(Pg.uniform);
+    const Desc d0 = a.desc[t];
+    if (!PROP && P.uniform == kRowsContig) {   // (made only for checks without propagation)
+        run_uniform<U, NT, false>(dv_uniform(d0), st->region, k0, k1, acc);
+        return;
+    }
+    // rows shorter than 64 units share iterations (at most 4 chunks per
+    // lane: every lane keeps a row's worth of indices for each); longer rows
+    // go row by row, their interiors through the unmasked loads
+    constexpr int UF = U > 4 ? 4 : U;
+    if (!PROP && P.uniform == kRowsStep && P.upr < 64u) {
+        run_rows_flat<UF, NT>(dv_uniform(d0), P, st->region, k0, k1, acc);
+        return;
+    }
+    const uint64_t r0 = k0 / P.upr;
+    // kRowsStep: each next row's descriptor is the last one's moved by the pitches
+    DV ds = dv_uniform(row_desc(d0, P, r0));
+    for (uint64_t r = r0; r * P.upr < k1; ++r) {
+        const uint64_t j0 = (k0 > r * P.upr ? k0 : r * P.upr) - r * P.upr;
+        const uint64_t j1 = (k1 < (r + 1) * P.upr ? k1 : (r + 1) * P.upr) - r * P.upr;
+        uint32_t rflags = 0;
+        uint64_t rfirst = NONE;
+        DV d;
+        if (P.uniform == kRowsStep) {
+            d = ds;
+            ds.src_sh += P.spitch;
+            ds.dst_sh += P.dpitch;
+            ds.a_src += (int64_t)P.spitch;
+            ds.a_dst += (int64_t)P.dpitch;
+        } else if (P.uniform) {
+            d = dv_uniform(row_desc(d0, P, r));
+        } else {
+            const cg_transfer row = row_record(P, r);
+            const int64_t js = dev_src(row) ? table_lookup_wave(st->table, row.src) : -1;
+            const int64_t jd = dev_dst(row) ? table_lookup_wave(st->table, row.dst) : -1;
+            Desc x;
+            cg_verdict v;
+            classify_rec(row, a.mode, *st, js, jd, x, v);
+            rflags = ufl32(v.flags);
+            rfirst = ufl64(v.first_bad);
+            d = dv_uniform(x);
+        }
+        Acc ra;
+        acc_reset(ra);
+        const uint64_t e = j1 < d.units ? j1 : d.units;
+        if (e > j0) run_uniform<U, NT, PROP>(d, st->region, j0, e, ra);
+        acc_add_row(acc, ra, rflags, rfirst, r * P.width);
+    }
+}
+
+// Unit k of pitched position t, by one lane (short rows, tile ends).
+template <bool NT, bool PROP>
+__device__ void run_unit_pitched(const BatchArgs &a, const DevState *st, uint64_t t, uint64_t k, Acc &acc)
+{
+    const Pitch P = a.pitch[t];
+    if (P.upr == 0) return;   // no rows, or a bad kind: nothing to work
+    if (!PROP && P.uniform == kRowsContig) {
+        const DV d = load_desc(a.desc, t);
+        if (k < d.units) run_unit<NT, false>(d, st->region, k, acc);
+        return;
+    }
+    const uint64_t r = k / P.upr, j = k - r * P.upr;
+    uint32_t rflags = 0;
+    uint64_t rfirst = NONE;
+    Desc x;
+    if (P.uniform) {
+        x = row_desc(a.desc[t], P, r);
+    } else {
+        const cg_transfer row = row_record(P, r);
+        const int64_t js = dev_src(row) ? table_lookup(st->table, st->table.top, row.src) : -1;
+        const int64_t jd = dev_dst(row) ? table_lookup(st->table, st->table.top, row.dst) : -1;
+        cg_verdict v;
+        classify_rec(row, a.mode, *st, js, jd, x, v);
+        rflags = v.flags;
+        rfirst = v.first_bad;
+    }
+    const DV d = make_dv(x);
+    Acc ra;
+    acc_reset(ra);
+    if (j < d.units) run_unit<NT, PROP>(d, st->region, j, ra);
+    acc_add_row(acc, ra, rflags, rfirst, r * P.width);
+}
+
 // Blocks b = x, x + nch, x + 2 nch, ... of the grid run on XCD x; b / nch is
 // their rank there.  A work queue split into nch chunks gives each claiming
 // block of XCD x a first item of chunk x by rank, without an atomic.  claim
@@ -905,9 +1299,10 @@ __device__ __forceinline__ int64_t claim_rank(uint32_t nch, int claim)
     return (int)(r & 1u) == claim - 1 ? (int64_t)(r >> 1) : -1;
 }
 
-// The waves' loop of the scan kernel (claim: which blocks take first tiles).
-template <int U, bool NT, bool PROP>
-__device__ void batched_loop(const BatchArgs &a, int claim)
+// The waves' loop of the scan kernel (claim: which blocks take first tiles;
+// PITCH: the positions are pitched 2D records, a.pitch).
+template <int U, bool NT, bool PROP, bool PITCH, int CLAIM>
+__device__ void batched_loop(const BatchArgs &a)
 {
     const uint32_t lane = lane_id();
     const uint64_t ntiles = ufl64(a.ctl->ntiles);
@@ -930,8 +1325,8 @@ __device__ void batched_loop(const BatchArgs &a, int claim)
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t xcd = blockIdx.x % nch;
     auto chunk_lo = [&](uint32_t x) { return ntiles * x / nch; };
-    auto waves_on = [&](uint32_t x) { return (uint64_t)claimers_on(x, nch, claim) * wpb; };
-    const int64_t rank = claim_rank(nch, claim);
+    auto waves_on = [&](uint32_t x) { return (uint64_t)claimers_on(x, nch, CLAIM) * wpb; };
+    const int64_t rank = claim_rank(nch, CLAIM);
     uint64_t jn = kNoTile;
     if (rank >= 0) {
         jn = chunk_lo(xcd) + (uint64_t)rank * wpb + (threadIdx.x >> 6);
@@ -974,7 +1369,14 @@ __device__ void batched_loop(const BatchArgs &a, int claim)
             // (its last iteration may be partial); shorter runs, which may hold
             // several records, go one unit per lane
             const uint64_t seg_end = pt1 < u_end ? pt1 : u_end;
-            const uint64_t nfull = seg_end - u >= 64 ? seg_end - u : 0;
+            uint64_t nfull = seg_end - u >= 64 ? seg_end - u : 0;
+            // pitched positions of short rows go one unit per lane (many rows
+            // per wave), unless their rows share the wave's iterations
+            if constexpr (PITCH) {
+                const uint32_t un = ufl32(a.pitch[t].uniform);
+                if (nfull && ufl64(a.pitch[t].upr) < 64 && un != kRowsContig && (PROP || un != kRowsStep))
+                    nfull = 0;
+            }
             if (nfull) {
                 if (!have_d) d = load_desc_uniform(a.desc, t);
                 const bool ahead = u + nfull == pt1 && u + nfull < u_end && t + 1 < T;
@@ -984,7 +1386,8 @@ __device__ void batched_loop(const BatchArgs &a, int claim)
                     npt1 = ufl64(a.prefix[t + 2]);
                     nd = load_desc_uniform(a.desc, t + 1);
                 }
-                run_uniform<U, NT, PROP>(d, R, u - pt, u - pt + nfull, acc);
+                if constexpr (PITCH) run_pitched<U, NT, PROP>(a, a.st, t, u - pt, u - pt + nfull, acc);
+                else run_uniform<U, NT, PROP>(d, R, u - pt, u - pt + nfull, acc);
                 if (a.out) flush_wave(acc, a.out, a.perm ? ufl32(a.perm[t]) : t);
                 u += nfull;
                 if (u == pt1) {
@@ -1013,7 +1416,9 @@ __device__ void batched_loop(const BatchArgs &a, int claim)
                 if (a.prefix[mid] <= ul) lo = mid; else hi = mid - 1;
             }
             const uint64_t tl = lo;
-            if (act) {
+            if (PITCH && act) {
+                run_unit_pitched<NT, PROP>(a, a.st, tl, ul - a.prefix[tl], acc);
+            } else if (act) {
                 const DV d = load_desc(a.desc, tl);
                 const uint64_t k = ul - a.prefix[tl];
                 if (k < d.units) run_unit<NT, PROP>(d, R, k, acc);
@@ -1036,7 +1441,14 @@ __device__ void batched_loop(const BatchArgs &a, int claim)
 template <int U, bool NT, bool PROP>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3))) k_batched(BatchArgs a)
 {
-    batched_loop<U, NT, PROP>(a, 0);
+    batched_loop<U, NT, PROP, false, 0>(a);
+}
+
+// the scan kernel over pitched 2D records (check_transfers_2d)
+template <int U, bool NT, bool PROP>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3))) k_batched_2d(BatchArgs a)
+{
+    batched_loop<U, NT, PROP, true, 0>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1254,9 +1666,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k
     if (((blockIdx.x / kXcds) & 1u) != 0) {
         host_loop<4>(a, a.lds_meta, 2, sv, sa, sp, &s_task, s_next, s_list);
         __syncthreads();
-        batched_loop<U, NT, false>(a, 1);
+        batched_loop<U, NT, false, false, 1>(a);
     } else {
-        batched_loop<U, NT, false>(a, 1);
+        batched_loop<U, NT, false, false, 1>(a);
         __syncthreads();
         host_loop<4>(a, a.lds_meta, 2, sv, sa, sp, &s_task, s_next, s_list);
     }
@@ -1285,35 +1697,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t
 // ---------------------------------------------------------------------------
 // k_small: a small batch in one launch
 // ---------------------------------------------------------------------------
-
-// wave-wide sum of a 32-bit value (every lane active)
-__device__ __forceinline__ uint32_t wave_add32(uint32_t x)
-{
-    for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d);
-    return x;
-}
-
-// The table search of table_lookup done by one wave (every lane active): the
-// top level, then the segment of 2^top_shift entries it picks, are each
-// compared 64 entries at a time, so two rounds of independent loads take the
-// place of a chain of dependent ones.  Entries are sorted by base, so the
-// number of them at or below p is one past the last of them.
-__device__ int64_t table_lookup_wave(const TableView &tb, uint64_t p)
-{
-    if (tb.n == 0) return -1;
-    const uint32_t lane = lane_id();
-    uint32_t c = 0;
-    for (uint32_t k = lane; k < tb.ntop; k += 64) c += tb.top[k] <= p ? 1u : 0u;
-    c = wave_add32(c);
-    if (c == 0) return -1;
-    const uint64_t a0 = (uint64_t)(c - 1) << tb.top_shift;
-    const uint64_t a1 = a0 + (1ull << tb.top_shift) < tb.n ? a0 + (1ull << tb.top_shift) : tb.n;
-    uint32_t c2 = 0;
-    for (uint64_t k = a0 + lane; k < a1; k += 64) c2 += tb.base[k] <= p ? 1u : 0u;
-    c2 = wave_add32(c2);
-    const uint64_t j = a0 + c2 - 1;   // base[a0] is top[c - 1] <= p, so c2 >= 1
-    return p < tb.end[j] ? (int64_t)j : -1;
-}
 
 // A batch of few records in one launch, up to `bpr` blocks per record.  The
 // blocks a record uses follow from its byte count alone (at most one per
@@ -1510,6 +1893,13 @@ hipError_t launch_classify(const BatchArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_classify_2d(const BatchArgs &a, const cg_transfer2d *recs2d, Pitch *pitch, hipStream_t s)
+{
+    const uint64_t blocks = (a.count + kClassifyBlock - 1) / kClassifyBlock;
+    hipLaunchKernelGGL(k_classify_2d, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, a, recs2d, pitch);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, a, tile_units, waves);
@@ -1539,7 +1929,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 template <int U, bool NT>
 static void launch_batched_t(const BatchArgs &a, const LaunchShape &sh, hipStream_t s)
 {
-    if (a.lds_meta && sh.lds_after) {
+    if (a.pitch && (a.mode & CG_PROPAGATE)) {
+        hipLaunchKernelGGL((k_batched_2d<U, NT, true>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+    } else if (a.pitch) {
+        hipLaunchKernelGGL((k_batched_2d<U, NT, false>), dim3(sh.grid), dim3(sh.block), 0, s, a);
+    } else if (a.lds_meta && sh.lds_after) {
         BatchArgs d = a;
         d.lds_meta = nullptr;
         hipLaunchKernelGGL((k_batched<U, NT, false>), dim3(sh.grid), dim3(sh.block), 0, s, d);

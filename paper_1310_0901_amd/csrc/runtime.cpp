@@ -77,7 +77,10 @@ struct Workspace {
     uint32_t *tile_start = nullptr;
     Ctl *ctl = nullptr;
     uint64_t *h_weight = nullptr;   // pinned copy of weights (plain path)
+    uint64_t ctx_seen = ~0ull;      // ctx_seq when this stream last waited for ev_ctx (2D path)
     SmallAcc *small = nullptr;      // small_max accumulators of the one-launch path (k_small)
+    Pitch *pitch = nullptr;         // per position of a pitched 2D batch (allocated on first use)
+    uint64_t pitch_cap = 0;
     hipEvent_t done = nullptr;      // recorded after every check issued on this stream
     bool used = false;
     std::vector<GraphEntry> graphs;
@@ -177,12 +180,14 @@ struct cg_ctx {
     int fill_next = 0;
     // ordering
     hipEvent_t ev_ctx = nullptr;
+    uint64_t ctx_seq = 0;          // records of ev_ctx so far
     std::map<hipStream_t, Workspace *> ws;
     std::map<hipStream_t, RaceWs> race_ws;   // concurrent-access joins, per stream
     uint64_t reorder_min = 16384;            // batches this large are worked as source-block segments
     uint32_t seg_min_log2 = 20;              // smallest source block of the segments, log2
     uint64_t small_max = kSmallMax;          // batches this small run in one launch (k_small); 0: never
     uint32_t task_pos = 0;                   // positions per host-source task (0: the kernel's default)
+    bool pitched_2d = true;                  // 2D records as pitched positions (else rows expanded, one wait)
     int host_lds = 1;                        // check-only segments of host sources worked from LDS: 1 in the
                                              // scan kernel's blocks, 2 in a kernel of their own after it, 0 not
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
@@ -226,6 +231,7 @@ int ctx_begin(cg_ctx *c)
 int ctx_end(cg_ctx *c)
 {
     HIPTRY(c, hipEventRecord(c->ev_ctx, c->s));
+    ++c->ctx_seq;
     return CG_OK;
 }
 
@@ -298,6 +304,7 @@ int materialize(cg_ctx *c)
     st.table.ntop = ntop;
     st.region = c->region;
     st.pool = (uint64_t)c->pool;
+    st.size_bound = c->table.size_bound();
     HIPTRY(c, hipMemcpyAsync(nv.st, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
     HIPTRY(c, hipEventRecord(c->ev_stage, c->s));
     c->stage_busy = true;
@@ -394,6 +401,9 @@ void free_ws(Workspace *w)
     if (w->h_weight) (void)hipHostFree(w->h_weight);
     (void)hipFree(w->small);
     w->small = nullptr;
+    (void)hipFree(w->pitch);
+    w->pitch = nullptr;
+    w->pitch_cap = 0;
     free_seg(w);
     w->desc = nullptr;
     w->weight = w->local = w->bsum = w->boff = w->prefix = nullptr;
@@ -944,6 +954,7 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_SMALL_MAX")) c->small_max = std::min<uint64_t>(strtoull(e, nullptr, 0), 1ull << 20);
     if (const char *e = getenv("XC_HOST_LDS")) c->host_lds = atoi(e);
     if (const char *e = getenv("XC_TASK_POS")) c->task_pos = std::min<uint32_t>((uint32_t)atoi(e), 256);
+    if (const char *e = getenv("XC_PITCHED_2D")) c->pitched_2d = atoi(e) != 0;
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
@@ -1192,6 +1203,63 @@ int propagate_shadow(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, voi
     return check_transfers(c, recs_dev, count, nullptr, CG_PROPAGATE, hip_stream);
 }
 
+// check_transfers_2d without a wait: every 2D record is one position whose
+// units step through its rows (k_classify_2d, then the scan kernel over
+// pitched positions); no row count is needed on the host.  Under a caller's
+// stream capture only the four kernels are enqueued: the stream must already
+// wait for every table upload (an eager call on it since the last change),
+// and the bookkeeping events are left out (a replay reads the table of the
+// capture's time).
+int check_2d_pitched(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev, uint32_t mode,
+                     hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPTRY(c, hipStreamIsCapturing(s, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    Workspace *w;
+    auto it = c->ws.find(s);
+    if (capturing && (it == c->ws.end() || it->second->cap < count || it->second->pitch_cap < it->second->cap))
+        return fail(c, CG_ESTATE, "check_transfers_2d under capture: make one call of this size on the stream first");
+    int rc = get_ws(c, s, count, &w);
+    if (rc) return rc;
+    if (w->pitch_cap < w->cap) {
+        if (w->pitch) HIPTRY(c, hipStreamSynchronize(s));   // an earlier call on this stream may still read it
+        (void)hipFree(w->pitch);
+        w->pitch = nullptr;
+        w->pitch_cap = 0;
+        HIPTRY(c, hipMalloc(&w->pitch, w->cap * sizeof(Pitch)));
+        w->pitch_cap = w->cap;
+    }
+    if (capturing) {
+        if (c->full_dirty || !c->pend_del.empty() || !c->pend_ins.empty() || w->ctx_seen != c->ctx_seq)
+            return fail(c, CG_ESTATE, "check_transfers_2d under capture: the table changed since the last call on "
+                                      "this stream; make one call outside the capture first");
+    } else {
+        rc = materialize(c);
+        if (rc) return rc;
+        HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+        w->ctx_seen = c->ctx_seq;
+    }
+    BatchArgs a = make_args(c, w, nullptr, count, out_dev, mode);
+    a.pitch = w->pitch;
+    const cg_tuning &tun = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
+    const LaunchShape sh = shape_of(c, tun);
+    HIPTRY(c, launch_classify_2d(a, recs_dev, w->pitch, s));
+    HIPTRY(c, launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s));
+    HIPTRY(c, launch_prefix_tiles(a, s));
+    if (capturing) {
+        HIPTRY(c, launch_batched(a, sh, s));
+        return CG_OK;
+    }
+    TimingPair *tp = c->timing ? next_pair(c) : nullptr;
+    if (tp) HIPTRY(c, hipEventRecord(tp->a, s));
+    HIPTRY(c, launch_batched(a, sh, s));
+    if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
+    HIPTRY(c, hipEventRecord(w->done, s));
+    w->used = true;
+    return note_use(c, s);
+}
+
 int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, cg_verdict *out_dev, uint32_t mode,
                        void *hip_stream)
 {
@@ -1205,6 +1273,10 @@ int check_transfers_2d(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count,
     if (count >= (1ull << 31)) return fail(c, CG_EINVAL, "at most 2^31 - 1 records per call");
     if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
     const hipStream_t s = (hipStream_t)hip_stream;
+    // the plain path (a launch per row) and the host-side conflict check need
+    // the rows themselves: those modes expand them, after one wait for the count
+    if (!(mode & (CG_PLAIN | CG_DEBUG_CONFLICTS)) && c->pitched_2d)
+        return check_2d_pitched(c, recs_dev, count, out_dev, mode & (CG_CHECK | CG_PROPAGATE), s);
     StridedWs &w = c->strided_ws[s];
     if (w.rec_cap < count) {
         // the buffers may still be in use by an earlier call on this stream

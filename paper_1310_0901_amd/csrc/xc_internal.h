@@ -75,6 +75,7 @@ struct DevState {
     TableView table;
     Region region;
     uint64_t pool;          // device address of the shadow pool
+    uint64_t size_bound;    // no live allocation is larger (within a factor of two)
 };
 
 struct FillRange {
@@ -86,6 +87,21 @@ constexpr int kMaxTop = 1024;        // LDS-staged top level of the table
 constexpr uint64_t kMinTile = 1024;  // smallest work tile, in 16-byte units
 constexpr int kClassifyBlock = 256;  // records per classify block
 constexpr uint64_t kScanLimit = 1ull << 62;  // byte indices scanned per record
+
+// A pitched 2D record worked as one position (check_transfers_2d): row r is
+// the transfer {src + r*spitch, dst + r*dpitch, width, kind}, its units are
+// [r*upr, (r+1)*upr) of the position (upr bounds the units of any row; the
+// units past a row's own are empty), and the position's Desc is row 0's.
+// When `uniform` is non-zero, every row lies in row 0's allocation or in the
+// host region on each side, fully valid, so row r's descriptor follows from
+// row 0's by the pitches (with pitches that keep the 16-byte phases, every
+// row has exactly upr units); otherwise each row is looked up and classified
+// where it is worked.
+struct Pitch {
+    uint64_t src, dst, width, rows, spitch, dpitch, upr;
+    uint32_t kind, uniform;
+};
+static_assert(sizeof(Pitch) == 64, "pitched record layout");
 
 struct BatchArgs {
     const cg_transfer *recs;
@@ -111,6 +127,9 @@ struct BatchArgs {
     // prefix and are worked by k_host_lds from LDS
     const uint64_t *lds_meta;
     uint32_t task_pos;   // positions per task of k_host_lds (0: its default)
+    // when not null, position t is the pitched 2D record pitch[t] (desc[t] is
+    // its row 0; check_transfers_2d), and findings are offset by row * width
+    const Pitch *pitch;
 };
 
 // Cutting a batch's records into source-block segments (segment.hip).
@@ -166,6 +185,9 @@ hipError_t launch_merge_warm(hipStream_t s);
 
 // kernel launchers (kernels.hip); all asynchronous on `s`
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
+// one lane per pitched 2D record: row 0 classified, Pitch, weight rows * upr,
+// verdict before any row is worked (check_transfers_2d)
+hipError_t launch_classify_2d(const BatchArgs &a, const cg_transfer2d *recs2d, Pitch *pitch, hipStream_t s);
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s);
 hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);
 // the persistent scan kernel, then (a.lds_meta) the host-source positions in LDS

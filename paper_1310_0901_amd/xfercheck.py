@@ -22,7 +22,7 @@ CG_H2D, CG_D2H, CG_D2D = 0, 1, 2
 # flags
 CG_SRC_UNADDR, CG_SRC_UNDEF, CG_SRC_UNALLOC, CG_SRC_OVERRUN = 0x1, 0x2, 0x4, 0x8
 CG_DST_UNADDR, CG_DST_UNALLOC, CG_DST_OVERRUN = 0x10, 0x20, 0x40
-CG_OVERLAP, CG_BAD_KIND = 0x80, 0x100
+CG_OVERLAP, CG_BAD_KIND, CG_ROWS_LIMIT = 0x80, 0x100, 0x200
 CG_NONE = 0xFFFF_FFFF_FFFF_FFFF
 CG_RACE_SRC, CG_RACE_DST, CG_RACE_UNCHECKED = 0x1, 0x2, 0x4
 CG_PTR_UNALLOC = 0x1

@@ -1,7 +1,9 @@
 """check_transfers_2d (pitched 2D copies, the strided copies of the footnote
 to Sec. 2's error list) on the GPU against the oracle: the closed-form pins,
-random 2D batches on the graph, eager and plain paths, and check + propagate
-on conflict-free batches with every shadow byte compared."""
+random 2D batches through the no-wait path (rows stepped on the device) and
+the expanded path (CG_PLAIN), wide rows worked by whole waves, check +
+propagate on conflict-free batches with every shadow byte compared, the row
+limit, and a captured call replayed."""
 import numpy as np
 import pytest
 
@@ -123,6 +125,208 @@ def test_random_propagate(X, H, seed):
         assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
     finally:
         dw.close()
+    # the same through the no-wait path (rows stepped on the device)
+    dw = H.DeviceWorld(w)
+    try:
+        got = check2d(X, dw, recs, X.CG_CHECK | X.CG_PROPAGATE)
+        util.assert_verdicts_equal(got, want, f"seed {seed}, rows stepped on the device")
+        for j in range(bases.size):
+            assert np.array_equal(dw.alloc_shadow(bases[j], sizes[j]), o.vs[j]), f"allocation {j}"
+        assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
+    finally:
+        dw.close()
+
+
+def wide_2d(rng, hb, hl, bases, sizes, count):
+    """2D copies of 1-9 KiB rows (whole-wave work per row), most of them with
+    every row inside one allocation or the host region (rows that follow row
+    0), some running past it, at pitches equal to and above the width."""
+    out = np.zeros(count, W.RECORD2D_DTYPE)
+    for i in range(count):
+        kind = int(rng.choice([0, 1, 2]))
+        width = int(rng.integers(1024, 9 * 1024))
+        rows = int(rng.integers(1, 40))
+        sp, dp = (width + int(rng.choice([0, 0, 16, 37, 512])) for _ in range(2))
+        if kind == 2 and rng.random() < 0.5:
+            dp = sp
+        inside = rng.random() < 0.8
+
+        def place(host, pitch):
+            span = (rows - 1) * pitch + width
+            if host:
+                room = hl - span
+                return hb + (int(rng.integers(0, room + 1)) if inside and room >= 0 else int(rng.integers(0, hl)))
+            j = int(rng.integers(0, bases.size))
+            room = int(sizes[j]) - span
+            if inside and room >= 0:
+                return int(bases[j]) + int(rng.integers(0, room + 1))
+            return int(bases[j]) + int(rng.integers(0, int(sizes[j])))
+        out[i] = (place(kind == 0, sp), place(kind == 1, dp), width, rows, sp, dp, kind, (0, 0, 0))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_wide_rows(X, H, seed):
+    """Rows of 1-9 KiB: check on the no-wait path and the expanded path, both
+    against the oracle; then check + propagate of a conflict-free subset on
+    the no-wait path with every shadow byte compared."""
+    rng = np.random.default_rng(900 + seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=2 << 20, nalloc=6, max_size=1 << 20,
+                                                     dens=[1e-4, 0.01, 0.0][seed])
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    recs = wide_2d(rng, W.HOST_BASE, hl, bases, sizes, 400)
+    want = util.oracle_for(w).run2d(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_PLAIN):
+            util.assert_verdicts_equal(check2d(X, dw, recs, mode), want, f"seed {seed} mode {mode}")
+    finally:
+        dw.close()
+    keep = []
+    for i in range(recs.size):
+        rows, _, _ = oracle.expand_rows(recs[keep + [i]])
+        if len(util.conflict_free(rows, W.HOST_BASE, hl, bases, sizes)) == rows.size:
+            keep.append(i)
+    sub = recs[keep]
+    assert sub.size >= 10
+    o = util.oracle_for(w)
+    want = o.run2d(sub, propagate=True)
+    dw = H.DeviceWorld(w)
+    try:
+        util.assert_verdicts_equal(check2d(X, dw, sub, X.CG_CHECK | X.CG_PROPAGATE), want, f"seed {seed} propagate")
+        for j in range(bases.size):
+            assert np.array_equal(dw.alloc_shadow(bases[j], sizes[j]), o.vs[j]), f"allocation {j}"
+        assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
+    finally:
+        dw.close()
+
+
+def spans_apart(recs):
+    """Greedy subset of 2D records (each with pitches at or above its width)
+    whose written address span, first row to last, meets no other kept
+    record's read or written span, nor its own read span: a conflict-free
+    batch, since disjoint addresses have disjoint shadow bytes."""
+    keep, reads, writes = [], [], []
+
+    def span(p, pitch, r):
+        return (int(r["rows"]) - 1) * pitch + int(r["width"])
+
+    def meets(a, lst):
+        return any(a[0] < y and x < a[1] for x, y in lst)
+    for i, r in enumerate(recs):
+        rs = (int(r["src"]), int(r["src"]) + span(r["src"], int(r["spitch"]), r))
+        ws = (int(r["dst"]), int(r["dst"]) + span(r["dst"], int(r["dpitch"]), r))
+        if meets(ws, reads) or meets(ws, writes) or meets(rs, writes) or meets(ws, [rs]):
+            continue
+        keep.append(i)
+        reads.append(rs)
+        writes.append(ws)
+    return recs[keep]
+
+
+def step_2d(rng, hb, hl, bases, sizes, count):
+    """2D copies at pitches that are multiples of 16 (each row keeps row 0's
+    16-byte phase), rows of 1 byte to 5 KB, 1-300 rows, nearly all inside one
+    allocation or the host region on each side; a third with rows back to
+    back (pitch = width, a multiple of 16) on the source side, and on the
+    destination side too for half of those."""
+    out = np.zeros(count, W.RECORD2D_DTYPE)
+    for i in range(count):
+        kind = int(rng.choice([0, 1, 2]))
+        width = int(rng.choice([int(rng.integers(1, 64)), int(rng.integers(64, 5000))]))
+        rows = int(rng.integers(1, 300))
+        sp, dp = ((width + 15) // 16 * 16 + 16 * int(rng.choice([0, 0, 1, 5])) for _ in range(2))
+        if kind == 2 and rng.random() < 0.5:
+            dp = sp
+        if rng.random() < 1 / 3:
+            width = 16 * int(rng.integers(1, 300))
+            sp = width
+            dp = width if rng.random() < 0.5 else width + 16 * int(rng.integers(1, 4))
+
+        def place(host, pitch):
+            span = (rows - 1) * pitch + width
+            if host:
+                room = hl - span
+                return hb + int(rng.integers(0, room + 1)) if room >= 0 and rng.random() < 0.95 else hb + int(rng.integers(0, hl))
+            j = int(rng.integers(0, bases.size))
+            room = int(sizes[j]) - span
+            if room >= 0 and rng.random() < 0.95:
+                return int(bases[j]) + int(rng.integers(0, room + 1))
+            return int(bases[j]) + int(rng.integers(0, int(sizes[j])))
+        out[i] = (place(kind == 0, sp), place(kind == 1, dp), width, rows, sp, dp, kind, (0, 0, 0))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_step_rows(X, H, seed):
+    """Rows at pitches that keep the 16-byte phase, worked with several rows
+    per wave iteration: check (host A holes included, so device->host rows
+    meet unaddressable destination bytes) against the oracle, on the no-wait
+    and expanded paths; then check + propagate of a conflict-free subset with
+    every shadow byte compared."""
+    rng = np.random.default_rng(950 + seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=4 << 20, nalloc=8, max_size=2 << 20,
+                                                     dens=[1e-4, 0.01, 0.001][seed])
+    a = (rng.random(hl) > 2e-4).astype(np.uint8)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    recs = step_2d(rng, W.HOST_BASE, hl, bases, sizes, 300)
+    want = util.oracle_for(w).run2d(recs)
+    assert (want["flags"] & X.CG_DST_UNADDR).any() and (want["flags"] & X.CG_SRC_UNDEF).any()
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_PLAIN):
+            util.assert_verdicts_equal(check2d(X, dw, recs, mode), want, f"seed {seed} mode {mode}")
+    finally:
+        dw.close()
+    sub = spans_apart(recs)
+    assert sub.size >= 20
+    o = util.oracle_for(w)
+    want = o.run2d(sub, propagate=True)
+    dw = H.DeviceWorld(w)
+    try:
+        util.assert_verdicts_equal(check2d(X, dw, sub, X.CG_CHECK | X.CG_PROPAGATE), want, f"seed {seed} propagate")
+        for j in range(bases.size):
+            assert np.array_equal(dw.alloc_shadow(bases[j], sizes[j]), o.vs[j]), f"allocation {j}"
+        assert np.array_equal(dw.host_shadow(), o.hv), "host region shadow"
+    finally:
+        dw.close()
+
+
+def test_captured_call_replays(X, H):
+    """check_transfers_2d captured in a graph (after one call of that size on
+    the stream) and replayed several times, with other eager work and
+    synchronisations between the replays: every replay equals the eager call."""
+    rng = np.random.default_rng(31)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=1 << 20, nalloc=6, max_size=1 << 20, dens=0.01)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    recs = np.concatenate([wide_2d(rng, W.HOST_BASE, hl, bases, sizes, 100),
+                           random_2d(rng, W.HOST_BASE, hl, bases, sizes, 200)])
+    want = util.oracle_for(w).run2d(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        side = torch.cuda.Stream()
+        r = np.ascontiguousarray(recs, W.RECORD2D_DTYPE)
+        rt = torch.from_numpy(r.view(np.uint8).copy()).to("cuda:0")
+        out = torch.full((r.size * 32,), 0xAB, dtype=torch.uint8, device="cuda:0")
+        torch.cuda.synchronize()
+        X.check_transfers_2d(dw.ctx, rt.data_ptr(), r.size, out.data_ptr(), X.CG_CHECK, side.cuda_stream)
+        side.synchronize()
+        util.assert_verdicts_equal(out.cpu().numpy().view(W.VERDICT_DTYPE), want, "eager call")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            X.check_transfers_2d(dw.ctx, rt.data_ptr(), r.size, out.data_ptr(), X.CG_CHECK, side.cuda_stream)
+        other = random_2d(rng, W.HOST_BASE, hl, bases, sizes, 50)
+        want_other = util.oracle_for(w).run2d(other)
+        for rep in range(3):
+            out.fill_(0xAB)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            util.assert_verdicts_equal(out.cpu().numpy().view(W.VERDICT_DTYPE), want, f"replay {rep}")
+            util.assert_verdicts_equal(check2d(X, dw, other, X.CG_CHECK), want_other, f"eager between {rep}")
+        del g
+    finally:
+        dw.close()
 
 
 def test_many_rows(X, H):
@@ -156,7 +360,8 @@ def test_no_rows_and_errors(X, H):
         with pytest.raises(X.CgError) as e:
             X.check_transfers_2d(dw.ctx, 0, 1, 16, X.CG_CHECK, 0)
         assert e.value.status == X.CG_EINVAL
-        # too many rows, also when the row counts would wrap a 64-bit sum
+        # the expanded path: too many rows, also when the row counts would
+        # wrap a 64-bit sum
         for tall in ([(1 << 64) - 1], [1 << 63, 1 << 63], [1 << 33]):
             t = np.zeros(len(tall), W.RECORD2D_DTYPE)
             for i, r in enumerate(tall):
@@ -164,11 +369,46 @@ def test_no_rows_and_errors(X, H):
             tt = torch.from_numpy(t.view(np.uint8).copy()).to("cuda:0")
             vo = torch.zeros(len(tall) * 32, dtype=torch.uint8, device="cuda:0")
             with pytest.raises(X.CgError) as e:
-                X.check_transfers_2d(dw.ctx, tt.data_ptr(), len(tall), vo.data_ptr(), X.CG_CHECK,
+                X.check_transfers_2d(dw.ctx, tt.data_ptr(), len(tall), vo.data_ptr(), X.CG_CHECK | X.CG_PLAIN,
                                      torch.cuda.current_stream().cuda_stream)
             assert e.value.status == X.CG_EINVAL, tall
         with pytest.raises(X.CgError) as e:
             X.check_transfers_2d(dw.ctx, 16, 1, 16, 0, 0)
         assert e.value.status == X.CG_EINVAL
+    finally:
+        dw.close()
+
+
+def test_row_limit(X, H):
+    """The no-wait path works the rows below index 2^32 that start below byte
+    2^62 of the copy and flags a record with more rows CG_ROWS_LIMIT; its
+    other fields cover the rows worked.  Rows here repeat one row (pitch 0),
+    so the expected verdict is that row's (from the oracle) scaled by the rows
+    worked; a bogus width costs only what its rows can reach."""
+    rng = np.random.default_rng(5)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=5000, nalloc=2, max_size=3000, dens=0.3)
+    a[:] = 1
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    o = util.oracle_for(w)
+    undef_at = int(np.flatnonzero(hv)[0])
+    cases = []
+    # 2^33 one-byte rows reading one undefined host byte into one device byte (rows follow row 0)
+    one = np.zeros(1, W.RECORD_DTYPE)
+    one[0] = (W.HOST_BASE + undef_at, int(bases[0]), 1, 0, 0)
+    cases.append(((W.HOST_BASE + undef_at, int(bases[0]), 1, 1 << 33, 0, 0, 0), o.run(one)[0], 1 << 32))
+    # every row 2^50 bytes from the host region's start (past the region and the allocation): 2^12 rows worked
+    n_eq = max(hl, int(sizes[0])) + 1   # a row of this length has the same verdict
+    eq = np.zeros(1, W.RECORD_DTYPE)
+    eq[0] = (W.HOST_BASE, int(bases[0]), n_eq, 0, 0)
+    cases.append(((W.HOST_BASE, int(bases[0]), 1 << 50, (1 << 64) - 1, 0, 0, 0), o.run(eq)[0], 1 << 12))
+    dw = H.DeviceWorld(w)
+    try:
+        for rec, row, worked in cases:
+            r = np.zeros(1, W.RECORD2D_DTYPE)
+            r[0] = rec + ((0, 0, 0),)
+            v = check2d(X, dw, r, X.CG_CHECK)[0]
+            got = (int(v["flags"]), int(v["first_bad"]), int(v["undef_bytes"]), int(v["avail"]))
+            assert got == (int(row["flags"]) | X.CG_ROWS_LIMIT, int(row["first_bad"]),
+                           worked * int(row["undef_bytes"]), int(row["avail"])), rec
     finally:
         dw.close()
