@@ -56,9 +56,15 @@ def test_config2_full_plain_and_batched(X, H):
         want = expected_all(w)
         for name, mode in (("graph", X.CG_CHECK), ("plain", X.CG_CHECK | X.CG_PLAIN)):
             util.assert_verdicts_equal(dw.check(w.records, mode), want, f"config 2 {name}")
+        # every record against the byte oracle, 256 records (and their
+        # allocations' shadows) at a time, on 8 host threads
+        for c0 in range(0, w.count, 256):
+            part = w.records[c0:c0 + 256]
+            o = util.oracle_subset(w, part, hv, ha)
+            util.assert_verdicts_equal(o.run_threads(part, 8), want[c0:c0 + 256], f"config 2 oracle, from {c0}")
+            del o
+        say(f"config 2: all {w.count} records equal the oracle ({time.time() - t0:.1f} s)")
         idx = sample_idx(w, 40, 1 << 22)
-        o = util.oracle_subset(w, w.records[idx], hv, ha)
-        util.assert_verdicts_equal(o.run(w.records[idx]), want[idx], "config 2 oracle sample")
         # propagation: every allocation receives its host source's V bytes,
         # 0xFF where the host byte is not addressable
         got = dw.check(w.records, X.CG_CHECK | X.CG_PROPAGATE)
