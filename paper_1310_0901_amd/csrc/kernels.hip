@@ -757,8 +757,10 @@ __device__ uint64_t classify_rec(const cg_transfer &r, uint32_t mode, const DevS
 }
 
 // Record t of a batch: its descriptor and work weight, and its verdict's
-// range-derived fields; returns its number of units.
-__device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top)
+// range-derived fields; returns its number of units (and in *host its valid
+// host-source bytes).
+__device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top,
+                                 uint64_t *host = nullptr)
 {
     const cg_transfer r = a.recs[t];
     const int64_t js = dev_src(r) ? table_lookup(st.table, top, r.src) : -1;
@@ -766,6 +768,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
     Desc ds;
     cg_verdict v;
     const uint64_t units = classify_rec(r, a.mode, st, js, jd, ds, v);
+    if (host) *host = (ds.ctl & CTL_SRC_HOST) && ds.v_hi > ds.v_lo ? (uint64_t)(ds.v_hi - ds.v_lo) : 0;
     a.desc[t] = ds;
     a.weight[t] = units;
     if (a.out && (a.mode & CG_CHECK)) a.out[t] = v;
@@ -781,13 +784,18 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
     __syncthreads();
     const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
-    uint64_t w = 0;
+    uint64_t w = 0, hb = 0;
     if (t < a.count) {
-        const uint64_t u = classify_one(a, st, t, top);
+        const uint64_t u = classify_one(a, st, t, top, &hb);
         w = u ? u : 1;
     }
-    // block exclusive scan of w
     const uint32_t lane = lane_id(), wid = tid >> 6;
+    if (a.host_bytes) {
+        // the batch's valid host-source bytes (the host index's cost test)
+        for (int d = 32; d >= 1; d >>= 1) hb += __shfl_xor(hb, d);
+        if (lane == 0 && hb) atomicAdd((unsigned long long *)a.host_bytes, (unsigned long long)hb);
+    }
+    // block exclusive scan of w
     uint64_t x = w;
     for (uint32_t d = 1; d < 64u; d <<= 1) {
         const uint64_t y = __shfl_up(x, d);

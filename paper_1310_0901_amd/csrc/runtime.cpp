@@ -94,6 +94,8 @@ struct Workspace {
     uint32_t *srec = nullptr;
     SortWs sort;
     uint32_t *perm = nullptr;
+    // host index of check-only segmented batches (hostindex.hip; allocated on first use)
+    HostIndex hidx{};
 };
 
 struct TimingPair {
@@ -188,6 +190,9 @@ struct cg_ctx {
     uint64_t small_max = kSmallMax;          // batches this small run in one launch (k_small); 0: never
     uint32_t task_pos = 0;                   // positions per host-source task (0: the kernel's default)
     bool pitched_2d = true;                  // 2D records as pitched positions (else rows expanded, one wait)
+    int host_index = 1;                      // host index of check-only segmented batches: 0 off, 1 when it pays, 2 always
+    uint32_t hidx_ratio = 4;                 // it pays from this many host-source bytes per region byte
+    uint64_t hidx_cap = 1ull << 22;          // entries per list of the host index
     int host_lds = 1;                        // check-only segments of host sources worked from LDS: 1 in the
                                              // scan kernel's blocks, 2 in a kernel of their own after it, 0 not
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
@@ -384,6 +389,11 @@ void free_seg(Workspace *w)
     w->rweight = w->rlocal = w->rbsum = w->sfirst = w->sbsum = w->meta = nullptr;
     w->srec = w->perm = nullptr;
     w->seg_cap = 0;
+    void *hs[] = {w->hidx.uchunk, w->hidx.umask, w->hidx.ucum, w->hidx.nchunk, w->hidx.nmask, w->hidx.bcnt,
+                  w->hidx.state};
+    for (void *p : hs)
+        if (p) (void)hipFree(p);
+    w->hidx = HostIndex{};
 }
 
 void free_ws(Workspace *w)
@@ -488,13 +498,19 @@ struct SegPlan {
     BatchArgs ar;
     SegArgs g;
     SortWs *sort;
+    const HostIndex *hidx;   // not null: build the host index and answer the host-source records from it
 };
 
 hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp)
 {
     hipError_t e;
     if (sp) {
+        if (sp->hidx && (e = launch_hidx_reset(*sp->hidx, s)) != hipSuccess) return e;
         if ((e = launch_classify(sp->ar, s)) != hipSuccess) return e;
+        if (sp->hidx) {
+            if ((e = launch_hidx_build(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
+            if ((e = launch_hidx_query(sp->ar, *sp->hidx, sp->ar.bsum, s)) != hipSuccess) return e;
+        }
         if ((e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess) return e;
     } else if ((e = launch_classify(a, s)) != hipSuccess) {
         return e;
@@ -672,6 +688,24 @@ int reserve_segments(cg_ctx *c, Workspace *w, uint64_t count, hipStream_t s)
     return CG_OK;
 }
 
+// The host index's buffers: lists of hidx_cap entries, block counts for a
+// grid of 8 blocks per CU.
+int reserve_hidx(cg_ctx *c, Workspace *w)
+{
+    if (w->hidx.state) return CG_OK;
+    HostIndex &x = w->hidx;
+    x.cap_u = x.cap_n = c->hidx_cap;
+    x.grid = (uint32_t)std::max(c->cu_count, 1) * 8u;
+    HIPTRY(c, hipMalloc(&x.uchunk, (x.cap_u + 1) * 8));
+    HIPTRY(c, hipMalloc(&x.umask, x.cap_u * 4));
+    HIPTRY(c, hipMalloc(&x.ucum, (x.cap_u + 1) * 8));
+    HIPTRY(c, hipMalloc(&x.nchunk, x.cap_n * 8));
+    HIPTRY(c, hipMalloc(&x.nmask, x.cap_n * 4));
+    HIPTRY(c, hipMalloc(&x.bcnt, 6ull * x.grid * 8));
+    HIPTRY(c, hipMalloc(&x.state, 4 * 8));
+    return CG_OK;
+}
+
 // Blocks per record of a small batch, at most: `hint`, or else about 8
 // blocks of 256 threads per CU over the whole batch (a record uses fewer
 // when it is small, k_small).
@@ -721,6 +755,14 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2,
                          host_last ? 1u : 0u};
         plan.sort = &w->sort;
+        plan.hidx = nullptr;
+        if (c->host_index && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK && c->region.hl > 0) {
+            rc = reserve_hidx(c, w);
+            if (rc) return rc;
+            w->hidx.ratio = c->host_index == 2 ? 0u : c->hidx_ratio;
+            plan.hidx = &w->hidx;
+            plan.ar.host_bytes = w->hidx.state;
+        }
         a.perm = w->perm;
         a.lds_meta = host_last ? w->meta : nullptr;
         a.task_pos = c->task_pos;
@@ -955,6 +997,8 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_HOST_LDS")) c->host_lds = atoi(e);
     if (const char *e = getenv("XC_TASK_POS")) c->task_pos = std::min<uint32_t>((uint32_t)atoi(e), 256);
     if (const char *e = getenv("XC_PITCHED_2D")) c->pitched_2d = atoi(e) != 0;
+    if (const char *e = getenv("XC_HOST_INDEX")) c->host_index = std::min(std::max(atoi(e), 0), 2);
+    if (const char *e = getenv("XC_HIDX_CAP")) c->hidx_cap = std::max<uint64_t>(strtoull(e, nullptr, 0), 1);
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;

@@ -35,13 +35,20 @@ def batch_path(request, monkeypatch):
     return request.param
 
 
-@pytest.fixture(params=["host-lds", "host-lds-after", "scan-only"])
+@pytest.fixture(params=["host-index", "host-index-overflow", "host-lds", "host-lds-after", "scan-only"])
 def host_lds(request, monkeypatch):
-    """Check-only batches worked as segments with their host-source segments
-    staged in LDS, by the scan kernel's own blocks or by a kernel of their
-    own after it, or all of them in the persistent scan kernel."""
-    monkeypatch.setenv("XC_HOST_LDS", {"host-lds": "1", "host-lds-after": "2", "scan-only": "0"}[request.param])
-    return request.param
+    """Check-only batches worked as segments: host-to-device records answered
+    from the host index (built for every such batch; and with lists of 4
+    entries, which these worlds overflow, so that the index stays invalid and
+    the records are scanned), or with their host-source segments staged in
+    LDS by the scan kernel's own blocks or by a kernel of their own after it,
+    or all of them in the persistent scan kernel."""
+    p = request.param
+    monkeypatch.setenv("XC_HOST_INDEX", "2" if p.startswith("host-index") else "0")
+    if p == "host-index-overflow":
+        monkeypatch.setenv("XC_HIDX_CAP", "4")
+    monkeypatch.setenv("XC_HOST_LDS", {"host-lds-after": "2", "scan-only": "0"}.get(p, "1"))
+    return p
 
 
 def modes(X):
@@ -284,5 +291,65 @@ def test_segmented_graph_replays(X, H, host_lds, monkeypatch):
             util.assert_verdicts_equal(H.verdicts_np(out, recs.size), want, f"replay {rep}")
             # eager work on the same stream between the replays
             util.assert_verdicts_equal(dw.check(recs[::3], X.CG_CHECK | X.CG_EAGER), want[::3], f"eager {rep}")
+    finally:
+        dw.close()
+
+
+@pytest.mark.parametrize("cap", ["4096", "64"])
+def test_host_index_edges(X, H, cap, monkeypatch):
+    """Host-to-device records answered from the host index, against the
+    oracle: a region whose length is not a multiple of 16, undefined bytes and
+    A holes on both edges of chunks and at the region's last bytes, records
+    starting below the region, ending past it, lying wholly outside it, empty,
+    and starting and ending at every offset of a chunk; the lists hold every
+    faulty chunk (cap 4096) or overflow (cap 64: the records are scanned)."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SEG_MIN_LOG2", "4")
+    monkeypatch.setenv("XC_HOST_INDEX", "2")
+    monkeypatch.setenv("XC_HIDX_CAP", cap)
+    rng = np.random.default_rng(61)
+    hl = 4000 + 7
+    hv = np.zeros(hl, np.uint8)
+    for o in (0, 15, 16, 31, 32, 47, 100, 101, 102, 1000, 2047, 2048, hl - 17, hl - 1):
+        hv[o] = 0x40
+    hv[rng.integers(0, hl, 60)] = 0xFF
+    a = np.ones(hl, np.uint8)
+    for o in (17, 40, 41, 42, 43, 44, 45, 46, 47, 63, 64, 1500, hl - 2):
+        a[o] = 0
+    a[rng.integers(0, hl, 30)] = 0
+    bases = np.array([W.DEV_BASE, W.DEV_BASE + 100_000], np.uint64)
+    sizes = np.array([90_000, 5_000], np.uint64)
+    vs = [np.zeros(int(z), np.uint8) for z in sizes]
+    recs = []
+    for start in list(range(-40, 80)) + list(range(hl - 80, hl + 20)) + list(rng.integers(-100, hl + 50, 300)):
+        for n in (0, 1, 2, 15, 16, 17, 33, 100, 1000, int(rng.integers(1, hl + 200))):
+            recs.append((W.HOST_BASE + int(start), int(bases[0]) + int(rng.integers(0, 80_000)), n, 0, 0))
+    # a few device-source records in the same batch
+    recs += [(int(bases[1]) + 10, int(bases[0]) + 500, 3000, 2, 0), (int(bases[1]), W.HOST_BASE + 5, 4000, 1, 0)]
+    recs = np.array(recs, W.RECORD_DTYPE)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_EAGER):
+            util.assert_verdicts_equal(dw.check(recs, mode), want, f"cap {cap} mode {mode}")
+    finally:
+        dw.close()
+
+
+def test_host_index_dense_world(X, H, monkeypatch):
+    """A region with 30 % undefined bytes and 1 % A holes (most chunks are
+    listed): the host index answers every host-to-device record exactly."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_HOST_INDEX", "2")
+    rng = np.random.default_rng(62)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=200_003, nalloc=6, max_size=100_000, dens=0.3)
+    a = (rng.random(hl) > 0.01).astype(np.uint8)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 2000, max_n=50_000, kinds=(0, 0, 0, 1, 2))
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    want = util.oracle_for(w).run(recs)
+    dw = H.DeviceWorld(w)
+    try:
+        util.assert_verdicts_equal(dw.check(recs, X.CG_CHECK), want, "dense world")
     finally:
         dw.close()
