@@ -119,12 +119,34 @@ def matching_profile(name, tuning, config):
     return prof, None
 
 
-def roofline(tun, config, k_avg_ms, bytes_step, l2_probe_GBps):
-    """The scan kernel's roofline from its committed counters and its live
-    duration: the bytes the L2 returns to the L1s per launch (L1 -> L2 read
-    requests x 128 B) over the launch, against the L2-resident read probe
-    measured in this run; HBM traffic (FETCH_SIZE + WRITE_SIZE, scaled by the
-    copy probe) beside it."""
+def roofline(tun, config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step, l2_probe_GBps):
+    """The dominant kernel's roofline.  When the shadow indexes answer the
+    check-only records, that is the shadow pool index's counting pass
+    (k_sidx_count<1>): it reads every V byte of the pool once (its algorithmic
+    bytes: 1 B per pool byte), so HBM bounds it; achieved = pool bytes over
+    its live duration, traffic from its committed counters.  Otherwise it is
+    the scan kernel: the bytes the L2 returns to the L1s per launch (L1 -> L2
+    read requests x 128 B, from its counters) over the launch, against the
+    L2-resident read probe measured in this run, HBM traffic beside it."""
+    if i_avg_ms and i_avg_ms >= k_avg_ms:
+        t = i_avg_ms / 1e3
+        achieved = pool_bytes / t / 1e9
+        out = {"kernel": "k_sidx_count<1>", "kernel_avg_ms": round(i_avg_ms, 3), "bound": "hbm",
+               "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+               "algorithmic_bytes_per_launch": int(pool_bytes), "scan_kernel_avg_ms": round(k_avg_ms, 3),
+               "note": "the shadow pool index's counting pass reads each V byte of the pool once (16-byte loads; "
+                       "the pool holds no A bits); achieved = pool bytes over its live duration (HIP events around "
+                       "it on the check's stream); traffic = HBM-side bytes per launch from FETCH_SIZE + WRITE_SIZE, "
+                       "profiles/k_sidx_count_pool_batched-1M_counters.md"}
+        prof, why = matching_profile("k_sidx_count_pool_batched-1M_counters", None, config)
+        if prof is not None:
+            tb = int(prof["limits"]["traffic_bytes"])
+            out.update(traffic=tb, hbm_traffic_GBps=round(tb / t / 1e9, 1),
+                       traffic_over_algorithmic=round(tb / pool_bytes, 4))
+        else:
+            out["traffic_note"] = why
+        return out
     prof, why = matching_profile("k_batched_lds_batched-1M_counters", tun, config)
     t = k_avg_ms / 1e3
     out = {"kernel": "k_batched_lds", "kernel_avg_ms": round(k_avg_ms, 3),
@@ -597,6 +619,7 @@ def main():
         X.check_transfers(ctx, recs_t.data_ptr(), T, out_t.data_ptr(), X.CG_CHECK, stream)
     torch.cuda.synchronize(dev)
     X.cg_kernel_ms(ctx)   # forget warm-up pairs
+    X.cg_index_ms(ctx)
     log(f"[bench] warm-up done ({args.warmup} steps)")
 
     torch.cuda.synchronize(dev)
@@ -606,12 +629,15 @@ def main():
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     kms, nk = X.cg_kernel_ms(ctx)
+    ims, ni = X.cg_index_ms(ctx)
     got = verdicts_np(out_t, T)
     ms_step = wall * 1e3 / args.steps
     value = bytes_step * args.steps / wall / 1e9
     k_avg_ms = kms / max(nk, 1)
-    achieved = bytes_step / (k_avg_ms / 1e3) / 1e9
-    log(f"[bench] batched: {ms_step:.2f} ms/step, {value:.0f} GB/s; scan kernel {k_avg_ms:.2f} ms ({achieved:.0f} GB/s)")
+    i_avg_ms = ims / ni if ni else None
+    pool_bytes = X.cg_stats(ctx)[1]   # allocated once, in one go: the pool's used bytes are its length
+    log(f"[bench] batched: {ms_step:.2f} ms/step, {value:.0f} GB/s; scan kernel {k_avg_ms:.2f} ms; pool index "
+        f"pass {i_avg_ms if i_avg_ms is None else round(i_avg_ms, 2)} ms over {pool_bytes / 1e9:.1f} GB")
 
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -620,11 +646,15 @@ def main():
         "config": {"workload": f"{w.name} (configuration {args.config}): {w.note}",
                    "records": T, "live_allocations": int(w.dev.live_idx.size),
                    "host_region_bytes": int(w.host.length), "transfer_bytes": int(w.records["n"].sum()),
-                   "mode": "check", "path": "batched: classify + source-block segments + scan + persistent scan kernel, "
-                           "hipGraph replay",
+                   "mode": "check", "path": "batched: classify; indexes of the faulty chunks of the host region and "
+                           "of the shadow pool, read once each, answering the check-only records; source-block "
+                           "segments and the persistent scan kernel for any record left; hipGraph replay",
                    "tuning": tun},
         "transfers_per_s": round(T / (wall / args.steps), 1),
         "algorithmic_bytes_per_step": int(bytes_step),
+        "scan_kernel_ms": round(k_avg_ms, 3),
+        "pool_index_pass_ms": None if i_avg_ms is None else round(i_avg_ms, 3),
+        "pool_bytes": int(pool_bytes),
     }
 
     if not args.no_plain:
@@ -676,7 +706,7 @@ def main():
         result["probe_l2_read"] = l2
         log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write), L2-resident read {l2}")
 
-    result["roofline"] = roofline(tun, args.config, k_avg_ms, bytes_step,
+    result["roofline"] = roofline(tun, args.config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step,
                                   result.get("probe_l2_read", {}).get("GBps"))
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline_legs(w, hv, ha, got, args.cpu_bytes, args.cpu_bytes_one)

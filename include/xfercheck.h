@@ -406,6 +406,14 @@ int cg_autotune(cg_ctx *ctx, const cg_transfer *recs_dev, uint64_t count, cg_ver
 int cg_timing(cg_ctx *ctx, int enable);
 int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
 
+/*
+ * As cg_kernel_ms, for the counting pass of the shadow pool's index (one
+ * launch per large check-only batch that builds the index, bracketed by
+ * events while timing is on): its summed time in ms since the last call, and
+ * the number of timed passes.  Errors: CG_EINVAL, CG_EHIP.
+ */
+int cg_index_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
+
 /* ---- bandwidth probes (roofline reference) -------------------------------- */
 /* Read `bytes` (multiple of 16) at dev and fold them into *sink_dev (u64). */
 int cg_probe_read(const void *dev, uint64_t bytes, uint64_t *sink_dev, void *hip_stream);

@@ -24,7 +24,7 @@ ARCH = os.environ.get("XC_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
-SOURCES = ["kernels.hip", "table.hip", "sort.hip", "segment.hip", "hostindex.hip", "race.hip", "strided.hip", "runtime.cpp",
+SOURCES = ["kernels.hip", "table.hip", "sort.hip", "segment.hip", "shadowindex.hip", "race.hip", "strided.hip", "runtime.cpp",
            "host_logic.cpp", "format.cpp"]
 
 

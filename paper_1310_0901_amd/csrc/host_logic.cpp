@@ -39,6 +39,7 @@ bool PoolAllocator::alloc(uint64_t size, uint64_t *off)
     by_off_.erase(boff);
     if (blen > need) insert_free(boff + need, blen - need);
     used_ += need;
+    high_ = boff + need > high_ ? boff + need : high_;
     *off = boff;
     return true;
 }

@@ -22,13 +22,15 @@ public:
     void release(uint64_t off, uint64_t size);
     uint64_t used() const { return used_; }
     uint64_t capacity() const { return bytes_; }
+    // end of the highest block ever handed out (no byte past it was ever used)
+    uint64_t high() const { return high_; }
     uint64_t rounded(uint64_t size) const { return (size + align_ - 1) / align_ * align_; }
     size_t free_blocks() const { return by_off_.size(); }
 
 private:
     void insert_free(uint64_t off, uint64_t len);
     void erase_free(std::map<uint64_t, uint64_t>::iterator it);
-    uint64_t bytes_, align_, used_ = 0;
+    uint64_t bytes_, align_, used_ = 0, high_ = 0;
     std::map<uint64_t, uint64_t> by_off_;            // free: offset -> length
     std::multimap<uint64_t, uint64_t> by_len_;       // free: length -> offset
 };

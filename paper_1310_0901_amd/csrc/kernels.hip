@@ -757,10 +757,10 @@ __device__ uint64_t classify_rec(const cg_transfer &r, uint32_t mode, const DevS
 }
 
 // Record t of a batch: its descriptor and work weight, and its verdict's
-// range-derived fields; returns its number of units (and in *host its valid
-// host-source bytes).
+// range-derived fields; returns its number of units (and in sp[0], sp[1] its
+// valid bytes in the host region and in the shadow pool, when sp is given).
 __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_t t, const uint64_t *top,
-                                 uint64_t *host = nullptr)
+                                 uint64_t *sp = nullptr)
 {
     const cg_transfer r = a.recs[t];
     const int64_t js = dev_src(r) ? table_lookup(st.table, top, r.src) : -1;
@@ -768,7 +768,12 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
     Desc ds;
     cg_verdict v;
     const uint64_t units = classify_rec(r, a.mode, st, js, jd, ds, v);
-    if (host) *host = (ds.ctl & CTL_SRC_HOST) && ds.v_hi > ds.v_lo ? (uint64_t)(ds.v_hi - ds.v_lo) : 0;
+    if (sp) {
+        const uint64_t src = ds.v_hi > ds.v_lo ? (uint64_t)(ds.v_hi - ds.v_lo) : 0;
+        const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? (uint64_t)(ds.d_hi - ds.d_lo) : 0;
+        sp[0] = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst;
+        sp[1] = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
+    }
     a.desc[t] = ds;
     a.weight[t] = units;
     if (a.out && (a.mode & CG_CHECK)) a.out[t] = v;
@@ -784,16 +789,19 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
     __syncthreads();
     const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
-    uint64_t w = 0, hb = 0;
+    uint64_t w = 0, sp[2] = {0, 0};
     if (t < a.count) {
-        const uint64_t u = classify_one(a, st, t, top, &hb);
+        const uint64_t u = classify_one(a, st, t, top, sp);
         w = u ? u : 1;
     }
     const uint32_t lane = lane_id(), wid = tid >> 6;
-    if (a.host_bytes) {
-        // the batch's valid host-source bytes (the host index's cost test)
-        for (int d = 32; d >= 1; d >>= 1) hb += __shfl_xor(hb, d);
-        if (lane == 0 && hb) atomicAdd((unsigned long long *)a.host_bytes, (unsigned long long)hb);
+    if (a.index_bytes[0]) {
+        // the batch's valid bytes per shadow space (the shadow indexes' cost test)
+        for (int k = 0; k < 2; ++k) {
+            uint64_t x = sp[k];
+            for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+            if (lane == 0 && x) atomicAdd((unsigned long long *)a.index_bytes[k], (unsigned long long)x);
+        }
     }
     // block exclusive scan of w
     uint64_t x = w;

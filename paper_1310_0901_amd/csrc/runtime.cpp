@@ -58,16 +58,19 @@ struct GraphEntry {
     uint32_t mode;
     cg_tuning tun;
     bool split;
-    hipGraph_t graph, graph2;
-    hipGraphExec_t exec, exec2;
+    // whole check (or, split for timing: the preparation, the scan kernel);
+    // a split check with shadow indexes has its preparation in three parts,
+    // the pool index's counting pass alone in the middle one
+    hipGraph_t graph, graph2, graph3, graph4;
+    hipGraphExec_t exec, exec2, exec3, exec4;
 };
 
 void destroy_graph(GraphEntry &g)
 {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-    if (g.exec2) (void)hipGraphExecDestroy(g.exec2);
-    if (g.graph2) (void)hipGraphDestroy(g.graph2);
+    for (hipGraphExec_t x : {g.exec, g.exec2, g.exec3, g.exec4})
+        if (x) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t x : {g.graph, g.graph2, g.graph3, g.graph4})
+        if (x) (void)hipGraphDestroy(x);
 }
 
 struct Workspace {
@@ -94,8 +97,9 @@ struct Workspace {
     uint32_t *srec = nullptr;
     SortWs sort;
     uint32_t *perm = nullptr;
-    // host index of check-only segmented batches (hostindex.hip; allocated on first use)
-    HostIndex hidx{};
+    // shadow indexes of check-only segmented batches, host region and pool
+    // (shadowindex.hip; allocated on first use)
+    ShadowIndex hidx{}, pidx{};
 };
 
 struct TimingPair {
@@ -190,9 +194,9 @@ struct cg_ctx {
     uint64_t small_max = kSmallMax;          // batches this small run in one launch (k_small); 0: never
     uint32_t task_pos = 0;                   // positions per host-source task (0: the kernel's default)
     bool pitched_2d = true;                  // 2D records as pitched positions (else rows expanded, one wait)
-    int host_index = 1;                      // host index of check-only segmented batches: 0 off, 1 when it pays, 2 always
-    uint32_t hidx_ratio = 4;                 // it pays from this many host-source bytes per region byte
-    uint64_t hidx_cap = 1ull << 22;          // entries per list of the host index
+    int shadow_index = 1;                    // shadow indexes of check-only segmented batches: 0 off, 1 when they pay, 2 always
+    uint32_t sidx_ratio = 4;                 // one pays from this many of the batch's bytes per byte of its space
+    uint64_t sidx_cap = 1ull << 22;          // entries per list of a shadow index
     int host_lds = 1;                        // check-only segments of host sources worked from LDS: 1 in the
                                              // scan kernel's blocks, 2 in a kernel of their own after it, 0 not
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
@@ -201,6 +205,8 @@ struct cg_ctx {
     // timing
     bool timing = false;
     std::vector<TimingPair> tpairs;   // pairs of the last check
+    std::vector<TimingPair> ipairs;   // pairs around the pool index's counting pass
+    size_t iused = 0;
     size_t tused = 0;
     std::string last_error;
 };
@@ -310,6 +316,7 @@ int materialize(cg_ctx *c)
     st.region = c->region;
     st.pool = (uint64_t)c->pool;
     st.size_bound = c->table.size_bound();
+    st.pool_len = c->palloc->high();
     HIPTRY(c, hipMemcpyAsync(nv.st, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
     HIPTRY(c, hipEventRecord(c->ev_stage, c->s));
     c->stage_busy = true;
@@ -389,11 +396,12 @@ void free_seg(Workspace *w)
     w->rweight = w->rlocal = w->rbsum = w->sfirst = w->sbsum = w->meta = nullptr;
     w->srec = w->perm = nullptr;
     w->seg_cap = 0;
-    void *hs[] = {w->hidx.uchunk, w->hidx.umask, w->hidx.ucum, w->hidx.nchunk, w->hidx.nmask, w->hidx.bcnt,
-                  w->hidx.state};
-    for (void *p : hs)
-        if (p) (void)hipFree(p);
-    w->hidx = HostIndex{};
+    for (ShadowIndex *x : {&w->hidx, &w->pidx}) {
+        void *hs[] = {x->uchunk, x->umask, x->ucum, x->nchunk, x->nmask, x->bcnt, x->sflag, x->state};
+        for (void *p : hs)
+            if (p) (void)hipFree(p);
+        *x = ShadowIndex{};
+    }
 }
 
 void free_ws(Workspace *w)
@@ -498,32 +506,54 @@ struct SegPlan {
     BatchArgs ar;
     SegArgs g;
     SortWs *sort;
-    const HostIndex *hidx;   // not null: build the host index and answer the host-source records from it
+    // not null: build the shadow indexes (host region, pool) and answer the
+    // records whose spaces are indexed from them
+    const ShadowIndex *hidx, *pidx;
 };
 
-hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp)
+// The preparation of a batched check, in three stages around the shadow pool
+// index's counting pass (stage 1, empty without indexes), so that timing can
+// bracket that pass.
+hipError_t prepare_stage(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp, int stage)
 {
     hipError_t e;
-    if (sp) {
-        if (sp->hidx && (e = launch_hidx_reset(*sp->hidx, s)) != hipSuccess) return e;
+    const bool idx = sp && sp->hidx;
+    if (stage == 0) {
+        if (!sp) return launch_classify(a, s);
+        if (idx && (e = launch_sidx_reset(*sp->hidx, *sp->pidx, s)) != hipSuccess) return e;
         if ((e = launch_classify(sp->ar, s)) != hipSuccess) return e;
-        if (sp->hidx) {
-            if ((e = launch_hidx_build(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
-            if ((e = launch_hidx_query(sp->ar, *sp->hidx, sp->ar.bsum, s)) != hipSuccess) return e;
-        }
-        if ((e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess) return e;
-    } else if ((e = launch_classify(a, s)) != hipSuccess) {
-        return e;
+        if (idx && (e = launch_sidx_build(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
+        return hipSuccess;
     }
+    if (stage == 1) return idx ? launch_sidx_count(*sp->pidx, sp->ar.st, s) : hipSuccess;
+    if (idx) {
+        if ((e = launch_sidx_finish(*sp->pidx, sp->ar.st, s)) != hipSuccess) return e;
+        if ((e = launch_sidx_query(sp->ar, *sp->hidx, *sp->pidx, sp->ar.bsum, s)) != hipSuccess) return e;
+    }
+    if (sp && (e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess) return e;
     if ((e = launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s)) != hipSuccess) return e;
     return launch_prefix_tiles(a, s);
 }
 
-hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp,
-                           const SegPlan *sp)
+hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp)
 {
     hipError_t e;
-    if ((e = enqueue_prepare(a, sh, s, sp)) != hipSuccess) return e;
+    for (int k = 0; k < 3; ++k)
+        if ((e = prepare_stage(a, sh, s, sp, k)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// The whole check; with tp, events around the scan kernel, and with ip
+// around the pool index's counting pass.
+hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp,
+                           const SegPlan *sp, TimingPair *ip = nullptr)
+{
+    hipError_t e;
+    if ((e = prepare_stage(a, sh, s, sp, 0)) != hipSuccess) return e;
+    if (ip && (e = hipEventRecord(ip->a, s)) != hipSuccess) return e;
+    if ((e = prepare_stage(a, sh, s, sp, 1)) != hipSuccess) return e;
+    if (ip && (e = hipEventRecord(ip->b, s)) != hipSuccess) return e;
+    if ((e = prepare_stage(a, sh, s, sp, 2)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->a, s)) != hipSuccess) return e;
     if ((e = launch_batched(a, sh, s)) != hipSuccess) return e;
     if (tp && (e = hipEventRecord(tp->b, s)) != hipSuccess) return e;
@@ -550,9 +580,13 @@ int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const SegPlan *sp, c
         destroy_graph(w->graphs.front());
         w->graphs.erase(w->graphs.begin());
     }
-    GraphEntry g{a.st, a.recs, a.out, a.count, mode, tun, split, nullptr, nullptr, nullptr, nullptr};
-    int rc = capture(c, &g.graph, &g.exec, a, sh, split ? 1 : 0, sp);
+    GraphEntry g{a.st, a.recs, a.out, a.count, mode, tun, split, nullptr, nullptr, nullptr, nullptr,
+                 nullptr, nullptr, nullptr, nullptr};
+    const bool three = split && sp && sp->pidx;
+    int rc = capture(c, &g.graph, &g.exec, a, sh, !split ? 0 : three ? 3 : 1, sp);
     if (!rc && split) rc = capture(c, &g.graph2, &g.exec2, a, sh, 2, sp);
+    if (!rc && three) rc = capture(c, &g.graph3, &g.exec3, a, sh, 4, sp);
+    if (!rc && three) rc = capture(c, &g.graph4, &g.exec4, a, sh, 5, sp);
     if (rc) {
         destroy_graph(g);
         return rc;
@@ -571,6 +605,17 @@ TimingPair *next_pair(cg_ctx *c)
         c->tpairs.push_back(p);
     }
     return &c->tpairs[c->tused++];
+}
+
+TimingPair *next_ipair(cg_ctx *c)
+{
+    if (c->iused == c->ipairs.size()) {
+        TimingPair p;
+        (void)hipEventCreate(&p.a);
+        (void)hipEventCreate(&p.b);
+        c->ipairs.push_back(p);
+    }
+    return &c->ipairs[c->iused++];
 }
 
 int valid_tuning(const cg_tuning &t)
@@ -688,21 +733,31 @@ int reserve_segments(cg_ctx *c, Workspace *w, uint64_t count, hipStream_t s)
     return CG_OK;
 }
 
-// The host index's buffers: lists of hidx_cap entries, block counts for a
-// grid of 8 blocks per CU.
-int reserve_hidx(cg_ctx *c, Workspace *w)
+// The shadow indexes' buffers: lists of sidx_cap entries (the pool's
+// unaddressable list stays empty: one entry), block counts for a grid of 8
+// blocks per CU.
+int reserve_sidx(cg_ctx *c, Workspace *w)
 {
-    if (w->hidx.state) return CG_OK;
-    HostIndex &x = w->hidx;
-    x.cap_u = x.cap_n = c->hidx_cap;
-    x.grid = (uint32_t)std::max(c->cu_count, 1) * 8u;
-    HIPTRY(c, hipMalloc(&x.uchunk, (x.cap_u + 1) * 8));
-    HIPTRY(c, hipMalloc(&x.umask, x.cap_u * 4));
-    HIPTRY(c, hipMalloc(&x.ucum, (x.cap_u + 1) * 8));
-    HIPTRY(c, hipMalloc(&x.nchunk, x.cap_n * 8));
-    HIPTRY(c, hipMalloc(&x.nmask, x.cap_n * 4));
-    HIPTRY(c, hipMalloc(&x.bcnt, 6ull * x.grid * 8));
-    HIPTRY(c, hipMalloc(&x.state, 4 * 8));
+    if (w->pidx.state) return CG_OK;
+    for (uint32_t space : {0u, 1u}) {
+        ShadowIndex &x = space ? w->pidx : w->hidx;
+        x.space = space;
+        x.cap_u = c->sidx_cap;
+        x.cap_n = space ? 1 : c->sidx_cap;
+        x.grid = (uint32_t)std::max(c->cu_count, 1) * 8u;
+        HIPTRY(c, hipMalloc(&x.uchunk, (x.cap_u + 1) * 8));
+        HIPTRY(c, hipMalloc(&x.umask, x.cap_u * 4));
+        HIPTRY(c, hipMalloc(&x.ucum, (x.cap_u + 1) * 8));
+        HIPTRY(c, hipMalloc(&x.nchunk, x.cap_n * 8));
+        HIPTRY(c, hipMalloc(&x.nmask, x.cap_n * 4));
+        HIPTRY(c, hipMalloc(&x.bcnt, 6ull * x.grid * 8));
+        // a flag per step of 4,096 chunks (64 KiB) of the pool, or of a host
+        // region of up to 64 GiB; a larger space is filled without them
+        const uint64_t len = space ? c->palloc->capacity() : std::max<uint64_t>(c->region.hl, 64ull << 30);
+        x.steps_cap = (len >> 16) + x.grid;
+        HIPTRY(c, hipMalloc(&x.sflag, 4 * x.steps_cap));
+        HIPTRY(c, hipMalloc(&x.state, 4 * 8));
+    }
     return CG_OK;
 }
 
@@ -755,13 +810,15 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2,
                          host_last ? 1u : 0u};
         plan.sort = &w->sort;
-        plan.hidx = nullptr;
-        if (c->host_index && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK && c->region.hl > 0) {
-            rc = reserve_hidx(c, w);
+        plan.hidx = plan.pidx = nullptr;
+        if (c->shadow_index && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK) {
+            rc = reserve_sidx(c, w);
             if (rc) return rc;
-            w->hidx.ratio = c->host_index == 2 ? 0u : c->hidx_ratio;
+            w->hidx.ratio = w->pidx.ratio = c->shadow_index == 2 ? 0u : c->sidx_ratio;
             plan.hidx = &w->hidx;
-            plan.ar.host_bytes = w->hidx.state;
+            plan.pidx = &w->pidx;
+            plan.ar.index_bytes[0] = w->hidx.state;
+            plan.ar.index_bytes[1] = w->pidx.state;
         }
         a.perm = w->perm;
         a.lds_meta = host_last ? w->meta : nullptr;
@@ -788,7 +845,8 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
     } else if (mode & CG_EAGER) {
         TimingPair *tp = c->timing ? next_pair(c) : nullptr;
-        HIPTRY(c, enqueue_batched(a, sh, s, tp, sp));
+        TimingPair *ip = c->timing && sp && sp->pidx ? next_ipair(c) : nullptr;
+        HIPTRY(c, enqueue_batched(a, sh, s, tp, sp, ip));
     } else {
         const bool split = c->timing;
         GraphEntry *ge = nullptr;
@@ -797,6 +855,13 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (split) {
             TimingPair *tp = next_pair(c);
             HIPTRY(c, hipGraphLaunch(ge->exec, s));
+            if (ge->exec3) {
+                TimingPair *ip = next_ipair(c);
+                HIPTRY(c, hipEventRecord(ip->a, s));
+                HIPTRY(c, hipGraphLaunch(ge->exec3, s));
+                HIPTRY(c, hipEventRecord(ip->b, s));
+                HIPTRY(c, hipGraphLaunch(ge->exec4, s));
+            }
             HIPTRY(c, hipEventRecord(tp->a, s));
             HIPTRY(c, hipGraphLaunch(ge->exec2, s));
             HIPTRY(c, hipEventRecord(tp->b, s));
@@ -832,9 +897,12 @@ int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, con
             const SegPlan *sp)
 {
     HIPTRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    // 0: all; 1: the preparation; 2: the scan kernel; 3, 4, 5: the
+    // preparation's stages 0, 1 (the pool index's counting pass), 2
     hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr, sp)
                  : part == 1 ? enqueue_prepare(a, sh, c->cap, sp)
-                             : launch_batched(a, sh, c->cap);
+                 : part == 2 ? launch_batched(a, sh, c->cap)
+                             : prepare_stage(a, sh, c->cap, sp, part - 3);
     hipError_t e2 = hipStreamEndCapture(c->cap, g);
     if (e != hipSuccess) return hip_fail(c, "graph capture", e);
     if (e2 != hipSuccess) return hip_fail(c, "hipStreamEndCapture", e2);
@@ -997,8 +1065,8 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_HOST_LDS")) c->host_lds = atoi(e);
     if (const char *e = getenv("XC_TASK_POS")) c->task_pos = std::min<uint32_t>((uint32_t)atoi(e), 256);
     if (const char *e = getenv("XC_PITCHED_2D")) c->pitched_2d = atoi(e) != 0;
-    if (const char *e = getenv("XC_HOST_INDEX")) c->host_index = std::min(std::max(atoi(e), 0), 2);
-    if (const char *e = getenv("XC_HIDX_CAP")) c->hidx_cap = std::max<uint64_t>(strtoull(e, nullptr, 0), 1);
+    if (const char *e = getenv("XC_SHADOW_INDEX")) c->shadow_index = std::min(std::max(atoi(e), 0), 2);
+    if (const char *e = getenv("XC_SIDX_CAP")) c->sidx_cap = std::max<uint64_t>(strtoull(e, nullptr, 0), 1);
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;
@@ -1493,6 +1561,22 @@ int cg_kernel_ms(cg_ctx *c, double *ms, uint64_t *launches)
     *ms = sum;
     if (launches) *launches = c->tused;
     c->tused = 0;
+    return CG_OK;
+}
+
+int cg_index_ms(cg_ctx *c, double *ms, uint64_t *launches)
+{
+    if (!c || !ms) return CG_EINVAL;
+    double sum = 0;
+    for (size_t i = 0; i < c->iused; ++i) {
+        HIPTRY(c, hipEventSynchronize(c->ipairs[i].b));
+        float x = 0;
+        HIPTRY(c, hipEventElapsedTime(&x, c->ipairs[i].a, c->ipairs[i].b));
+        sum += x;
+    }
+    *ms = sum;
+    if (launches) *launches = c->iused;
+    c->iused = 0;
     return CG_OK;
 }
 

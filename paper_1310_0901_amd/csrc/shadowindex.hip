@@ -1,0 +1,471 @@
+// Indexes of the faulty shadow chunks for large check-only batches (gfx950).
+//
+// A batch worked as segments reads the same shadow bytes many times (each
+// host byte about 160 times, each device byte about 15 times on the
+// 1M-record configuration).  A record checked without propagation needs few
+// facts about the bytes it reads: for its valid source bytes, how many are
+// undefined (V != 0 where A = 1), the first undefined one and the first
+// unaddressable one (A = 0, host sources only); for the valid bytes of a host
+// destination, the first unaddressable one.  The ranges themselves were
+// judged by k_classify's lookups.  Here each shadow space the batch reads
+// heavily is read once into two sorted lists: the chunks holding an undefined
+// byte, with its mask and the undefined bytes of all chunks before it, and
+// the chunks holding an unaddressable byte, with its mask.  A record's facts
+// then come from two binary searches per list and the masks of its edge
+// chunks.  The spaces are the host region (V and A bits) and the shadow pool
+// (V only; addressability there is the allocation table's).  An index is
+// built when the batch's valid bytes in its space reach `ratio` times the
+// space's length, and is valid when both lists fit their capacity; a record
+// whose spaces all have a valid index is answered and leaves the scan, any
+// other is scanned as before.  The facts are exact, so verdicts do not depend
+// on the choice.
+//
+//   k_sidx_reset   one lane: both states = {0, 0, 0, 0}
+//   (k_classify adds the batch's valid bytes per space to state[0])
+//   k_sidx_count   block b over its contiguous range of chunks: list entries
+//                  and undefined bytes
+//   k_sidx_scan    one block: the blocks' offsets, the totals, validity
+//   k_sidx_fill    block b writes its entries in chunk order (a block with
+//                  none returns at once)
+//   k_sidx_query   one lane per record: answers the records of a check
+//                  without propagation whose spaces are indexed, and takes
+//                  their units out of the scan
+#include <hip/hip_runtime.h>
+
+#include "xc_internal.h"
+
+namespace xc {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> using gcptr = const __attribute__((address_space(1))) T *;
+
+constexpr int kT = 256;
+constexpr uint32_t kPer = 16;                          // chunks per thread per step
+constexpr uint64_t kStep = (uint64_t)kT * kPer;        // chunks per block per step
+
+// one bit per non-zero byte of w (SWAR: no carry crosses a byte)
+__device__ __forceinline__ uint32_t nz4(uint32_t w)
+{
+    const uint32_t t = (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
+    return ((t >> 7) | (t >> 14) | (t >> 21) | (t >> 28)) & 0xFu;
+}
+
+__device__ __forceinline__ uint32_t nz16(u32x4 v)
+{
+    return nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+}
+
+// one shadow space as the kernels read it: V bytes (16-byte aligned), A bits
+// as 16-bit words (none for the pool), length in bytes
+struct Space {
+    const uint8_t *v;
+    const uint16_t *a16;
+    uint64_t len;
+};
+
+__device__ __forceinline__ Space space_of(uint32_t space, const DevState *st)
+{
+    if (space == 0) return Space{st->region.v, st->region.a16, st->region.hl};
+    return Space{reinterpret_cast<const uint8_t *>(st->pool), nullptr, st->pool_len};
+}
+
+__device__ __forceinline__ Space space_of(const ShadowIndex &x, const DevState *st) { return space_of(x.space, st); }
+
+__device__ __forceinline__ uint64_t space_chunks(const Space &S) { return (S.len + 15) >> 4; }
+
+// the index is built for this batch: a space, and enough of the batch's bytes in it
+__device__ __forceinline__ bool worth(const ShadowIndex &x, const Space &S)
+{
+    return S.len > 0 && (x.ratio == 0 || x.state[0] / x.ratio >= S.len);
+}
+
+// steps of kStep chunks per block
+__device__ __forceinline__ uint64_t block_steps(const Space &S, uint32_t grid)
+{
+    const uint64_t n = space_chunks(S);
+    return (n + (uint64_t)grid * kStep - 1) / ((uint64_t)grid * kStep);
+}
+
+// chunks [lo, hi) of block b
+__device__ __forceinline__ void block_range(const Space &S, uint32_t grid, uint32_t b, uint64_t *lo, uint64_t *hi)
+{
+    const uint64_t n = space_chunks(S);
+    const uint64_t span = block_steps(S, grid) * kStep;
+    *lo = (uint64_t)b * span < n ? (uint64_t)b * span : n;
+    *hi = *lo + span < n ? *lo + span : n;
+}
+
+// undefined (V != 0, A = 1) and unaddressable (A = 0) bytes of chunk c < the
+// space's chunks; bits of bytes past the space's end are clear
+__device__ __forceinline__ void chunk_faults(const Space &S, uint64_t c, uint32_t *und, uint32_t *un)
+{
+    const u32x4 v = *reinterpret_cast<const u32x4 *>(S.v + 16 * c);
+    const uint32_t a = S.a16 ? (uint32_t)S.a16[c] : 0xFFFFu;
+    const uint64_t left = S.len - 16 * c;
+    const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
+    *und = nz16(v) & a & live;
+    *un = ~a & live;
+}
+
+// block-wide exclusive scan of three values; tot receives the block's sums
+__device__ void block_scan3(uint64_t x[3], uint64_t ex[3], uint64_t tot[3])
+{
+    __shared__ uint64_t ws[kT / 64][3];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint64_t inc[3] = {x[0], x[1], x[2]};
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        uint64_t y[3];
+        for (int k = 0; k < 3; ++k) y[k] = __shfl_up(inc[k], d);
+        if (lane >= d)
+            for (int k = 0; k < 3; ++k) inc[k] += y[k];
+    }
+    if (lane == 63u)
+        for (int k = 0; k < 3; ++k) ws[w][k] = inc[k];
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+        uint64_t off = 0, all = 0;
+        for (uint32_t q = 0; q < kT / 64; ++q) {
+            if (q < w) off += ws[q][k];
+            all += ws[q][k];
+        }
+        ex[k] = off + inc[k] - x[k];
+        tot[k] = all;
+    }
+    __syncthreads();   // ws is reused by the next call
+}
+
+__global__ void k_sidx_reset(ShadowIndex h, ShadowIndex p)
+{
+    for (int k = 0; k < 4; ++k) {
+        h.state[k] = 0;
+        p.state[k] = 0;
+    }
+}
+
+// (one instance per space, so that a trace tells them apart).  A step's 16
+// chunks per thread are loaded back to back (non-temporal: each byte is read
+// once), then examined; each wave flags the steps where it met a faulty
+// chunk, so that the fill reads only those.
+template <uint32_t SPACE>
+__global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState *stp)
+{
+    const Space S = space_of(SPACE, stp);
+    if (!worth(x, S)) return;
+    uint64_t lo, hi;
+    block_range(S, x.grid, blockIdx.x, &lo, &hi);
+    const uint64_t spb = block_steps(S, x.grid);
+    const bool flags = spb * x.grid <= x.steps_cap;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const gcptr<u32x4> vp = reinterpret_cast<gcptr<u32x4>>(reinterpret_cast<uint64_t>(S.v));
+    uint64_t c3[3] = {0, 0, 0};
+    uint64_t step = (uint64_t)blockIdx.x * spb;
+    for (uint64_t base = lo; base < hi; base += kStep, ++step) {
+        u32x4 v[kPer];
+        uint32_t a[kPer];
+        if (base + kStep <= hi) {
+#pragma unroll
+            for (uint32_t j = 0; j < kPer; ++j) {
+                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+                v[j] = __builtin_nontemporal_load(vp + c);
+                a[j] = SPACE == 0 ? (uint32_t)S.a16[c] : 0xFFFFu;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < kPer; ++j) {
+                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+                v[j] = u32x4{0u, 0u, 0u, 0u};
+                a[j] = 0xFFFFu;
+                if (c < hi) {
+                    v[j] = __builtin_nontemporal_load(vp + c);
+                    if (SPACE == 0) a[j] = S.a16[c];
+                }
+            }
+        }
+        uint32_t any = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+            // bytes past the space's end (its last chunk, or none) are clear
+            const uint64_t left = c < hi ? S.len - 16 * c : 0;
+            const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
+            const uint32_t und = nz16(v[j]) & a[j] & live, un = ~a[j] & live;
+            c3[0] += und ? 1u : 0u;
+            c3[1] += un ? 1u : 0u;
+            c3[2] += (uint32_t)__builtin_popcount(und);
+            any |= und | un;
+        }
+        if (flags) {
+            const uint64_t seen = __ballot(any != 0);
+            if (lane == 0) x.sflag[4 * step + wave] = seen ? 1u : 0u;
+        }
+    }
+    uint64_t ex[3], tot[3];
+    block_scan3(c3, ex, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) x.bcnt[3 * blockIdx.x + k] = tot[k];
+}
+
+// offsets of the blocks' entries into [3 grid, 6 grid) of bcnt
+__global__ void __launch_bounds__(1024) k_sidx_scan(ShadowIndex x, const DevState *stp)
+{
+    __shared__ uint64_t ws[16][3];
+    const Space S = space_of(x, stp);
+    if (!worth(x, S)) {
+        if (threadIdx.x == 0) x.state[1] = 0;
+        return;
+    }
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t per = (x.grid + 1023) / 1024;
+    const uint32_t b0 = tid * per < x.grid ? tid * per : x.grid, b1 = b0 + per < x.grid ? b0 + per : x.grid;
+    uint64_t s[3] = {0, 0, 0};
+    for (uint32_t b = b0; b < b1; ++b)
+        for (int k = 0; k < 3; ++k) s[k] += x.bcnt[3 * b + k];
+    uint64_t inc[3] = {s[0], s[1], s[2]};
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        uint64_t y[3];
+        for (int k = 0; k < 3; ++k) y[k] = __shfl_up(inc[k], d);
+        if (lane >= d)
+            for (int k = 0; k < 3; ++k) inc[k] += y[k];
+    }
+    if (lane == 63u)
+        for (int k = 0; k < 3; ++k) ws[w][k] = inc[k];
+    __syncthreads();
+    uint64_t run[3];
+    for (int k = 0; k < 3; ++k) {
+        uint64_t off = 0;
+        for (uint32_t q = 0; q < w; ++q) off += ws[q][k];
+        run[k] = off + inc[k] - s[k];
+    }
+    for (uint32_t b = b0; b < b1; ++b)
+        for (int k = 0; k < 3; ++k) {
+            x.bcnt[3 * (x.grid + b) + k] = run[k];
+            run[k] += x.bcnt[3 * b + k];
+        }
+    if (tid == 0) {
+        uint64_t tot[3];
+        for (int k = 0; k < 3; ++k) {
+            uint64_t all = 0;
+            for (uint32_t q = 0; q < 16; ++q) all += ws[q][k];
+            tot[k] = all;
+        }
+        const bool valid = tot[0] <= x.cap_u && tot[1] <= x.cap_n;
+        x.state[1] = valid ? 1u : 0u;
+        x.state[2] = tot[0];
+        x.state[3] = tot[1];
+        if (valid) {
+            x.uchunk[tot[0]] = ~0ull;
+            x.ucum[tot[0]] = tot[2];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState *stp)
+{
+    if (!x.state[1]) return;
+    const Space S = space_of(x, stp);
+    const uint32_t b = blockIdx.x;
+    if (x.bcnt[3 * b] == 0 && x.bcnt[3 * b + 1] == 0) return;
+    uint64_t lo, hi;
+    block_range(S, x.grid, b, &lo, &hi);
+    uint64_t ou = x.bcnt[3 * (x.grid + b)], on = x.bcnt[3 * (x.grid + b) + 1], op = x.bcnt[3 * (x.grid + b) + 2];
+    const uint64_t end_u = ou + x.bcnt[3 * b], end_n = on + x.bcnt[3 * b + 1];
+    const uint64_t spb = block_steps(S, x.grid);
+    const bool flags = spb * x.grid <= x.steps_cap;
+    uint64_t step = (uint64_t)b * spb;
+    for (uint64_t base = lo; base < hi && (ou < end_u || on < end_n); base += kStep, ++step) {
+        if (flags && *reinterpret_cast<const uint32_t *>(x.sflag + 4 * step) == 0) continue;   // no entries here
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+            uint32_t und = 0, un = 0;
+            if (c < hi) chunk_faults(S, c, &und, &un);
+            uint64_t v[3] = {und ? 1u : 0u, un ? 1u : 0u, (uint64_t)__builtin_popcount(und)};
+            uint64_t ex[3], tot[3];
+            block_scan3(v, ex, tot);
+            if (und) {
+                x.uchunk[ou + ex[0]] = c;
+                x.umask[ou + ex[0]] = und;
+                x.ucum[ou + ex[0]] = op + ex[2];
+            }
+            if (un) {
+                x.nchunk[on + ex[1]] = c;
+                x.nmask[on + ex[1]] = un;
+            }
+            ou += tot[0];
+            on += tot[1];
+            op += tot[2];
+        }
+    }
+}
+
+// first i in [0, n) with key[i] >= k (n if none)
+__device__ __forceinline__ uint64_t lower_bound(const uint64_t *key, uint64_t n, uint64_t k)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (key[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Facts about space offsets [ra, rb) (ra < rb): bytes [ra, rb) of chunk c
+// are the bits of range_mask(c).
+struct Range {
+    uint64_t ca, cb;
+    uint32_t lo_bit, hi_bit;
+    __device__ Range(uint64_t ra, uint64_t rb)
+        : ca(ra >> 4), cb((rb - 1) >> 4), lo_bit((uint32_t)(ra & 15u)), hi_bit((uint32_t)((rb - 1) & 15u)) {}
+    __device__ uint32_t mask(uint64_t c) const
+    {
+        uint32_t m = 0xFFFFu;
+        if (c == ca) m &= (0xFFFFu << lo_bit) & 0xFFFFu;
+        if (c == cb) m &= (2u << hi_bit) - 1u;
+        return m;
+    }
+};
+
+// first faulty byte of the range among list entries [i0, i1) (space offset,
+// or ~0): only the first two entries can hold it, since every entry's mask
+// is non-zero and only the edge chunks are cut
+__device__ __forceinline__ uint64_t first_in(const uint64_t *chunk, const uint32_t *mask, uint64_t i0, uint64_t i1,
+                                             const Range &g)
+{
+    for (uint64_t i = i0; i < i1 && i < i0 + 2; ++i) {
+        const uint32_t bits = mask[i] & g.mask(chunk[i]);
+        if (bits) return 16 * chunk[i] + (uint64_t)__builtin_ctz(bits);
+    }
+    return ~0ull;
+}
+
+// undefined bytes of the range and the first one (space offset, or ~0)
+__device__ __forceinline__ uint64_t undef_in(const ShadowIndex &x, const Range &g, uint64_t *first)
+{
+    const uint64_t nu = x.state[2];
+    const uint64_t i0 = lower_bound(x.uchunk, nu, g.ca), i1 = lower_bound(x.uchunk, nu, g.cb + 1);
+    uint64_t n = x.ucum[i1] - x.ucum[i0];
+    if (i1 > i0) {
+        // the edge chunks' bytes outside the range
+        if (x.uchunk[i0] == g.ca) n -= (uint64_t)__builtin_popcount(x.umask[i0] & ~(0xFFFFu << g.lo_bit) & 0xFFFFu);
+        if (x.uchunk[i1 - 1] == g.cb) n -= (uint64_t)__builtin_popcount(x.umask[i1 - 1] & ~((2u << g.hi_bit) - 1u));
+    }
+    *first = first_in(x.uchunk, x.umask, i0, i1, g);
+    return n;
+}
+
+// the first unaddressable byte of the range (space offset, or ~0)
+__device__ __forceinline__ uint64_t unaddr_in(const ShadowIndex &x, const Range &g)
+{
+    const uint64_t nn = x.state[3];
+    const uint64_t j0 = lower_bound(x.nchunk, nn, g.ca), j1 = lower_bound(x.nchunk, nn, g.cb + 1);
+    return first_in(x.nchunk, x.nmask, j0, j1, g);
+}
+
+__device__ __forceinline__ void take_first(uint64_t *first, uint64_t off, int64_t off0)
+{
+    const uint64_t i = (uint64_t)((int64_t)off - off0);   // record byte index of space offset off
+    *first = i < *first ? i : *first;
+}
+
+__global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, ShadowIndex p, uint64_t *wbsum)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    uint64_t removed = 0;
+    if (a.out && t < a.count) {
+        const Desc d = a.desc[t];
+        const bool src_host = (d.ctl & CTL_SRC_HOST) != 0;
+        const bool has_src = d.v_hi > d.v_lo;
+        const bool dsta = (d.ctl & CTL_DST_A) != 0 && d.d_hi > d.d_lo;
+        // a check without propagation whose spaces have a valid index
+        const bool ok = (d.ctl & CTL_CHECK) && !(d.ctl & CTL_PROP) && d.units > 0 &&
+                        (!has_src || (src_host ? h.state[1] : p.state[1])) && (!dsta || h.state[1]);
+        if (ok) {
+            cg_verdict v = a.out[t];
+            uint64_t first = v.first_bad;
+            if (has_src) {
+                const uint32_t phi = (d.ctl >> CTL_PHI_SHIFT) & 15u;
+                // space offset of the record's byte 0: host region offset, or pool offset
+                const int64_t off0 = src_host ? d.a_src + (int64_t)phi
+                                              : (int64_t)(d.src_sh + phi - a.st->pool);
+                const Range g((uint64_t)(off0 + d.v_lo), (uint64_t)(off0 + d.v_hi));
+                uint64_t fu;
+                const uint64_t undef = undef_in(src_host ? h : p, g, &fu);
+                if (undef) {
+                    v.flags |= CG_SRC_UNDEF;
+                    take_first(&first, fu, off0);
+                }
+                v.undef_bytes += undef;
+                if (src_host) {
+                    const uint64_t fn = unaddr_in(h, g);
+                    if (fn != ~0ull) {
+                        v.flags |= CG_SRC_UNADDR;
+                        take_first(&first, fn, off0);
+                    }
+                }
+            }
+            if (dsta) {
+                const uint32_t psi = (d.ctl >> CTL_PSI_SHIFT) & 15u;
+                const int64_t off0 = d.a_dst + (int64_t)psi;   // host region offset of the destination's byte 0
+                const Range g((uint64_t)(off0 + d.d_lo), (uint64_t)(off0 + d.d_hi));
+                const uint64_t fn = unaddr_in(h, g);
+                if (fn != ~0ull) {
+                    v.flags |= CG_DST_UNADDR;
+                    take_first(&first, fn, off0);
+                }
+            }
+            v.first_bad = first;
+            a.out[t] = v;
+            a.desc[t].units = 0;
+            removed = d.units - 1;   // its weight max(units, 1) becomes 1
+        }
+    }
+    // the block's weight sum as k_classify left it, for the segment plan
+    uint64_t r = removed;
+    for (int k = 32; k >= 1; k >>= 1) r += __shfl_xor(r, k);
+    __shared__ uint64_t wr[kT / 64];
+    if ((threadIdx.x & 63u) == 0) wr[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t all = 0;
+        for (int k = 0; k < kT / 64; ++k) all += wr[k];
+        if (all) wbsum[blockIdx.x] -= all;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sidx_reset, dim3(1), dim3(1), 0, s, h, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s)
+{
+    if (x.space == 0) hipLaunchKernelGGL(k_sidx_count<0>, dim3(x.grid), dim3(kT), 0, s, x, st);
+    else hipLaunchKernelGGL(k_sidx_count<1>, dim3(x.grid), dim3(kT), 0, s, x, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sidx_scan, dim3(1), dim3(1024), 0, s, x, st);
+    hipLaunchKernelGGL(k_sidx_fill, dim3(x.grid), dim3(kT), 0, s, x, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s)
+{
+    const hipError_t e = launch_sidx_count(x, st, s);
+    return e != hipSuccess ? e : launch_sidx_finish(x, st, s);
+}
+
+hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
+                             hipStream_t s)
+{
+    const uint64_t blocks = (ar.count + kT - 1) / kT;
+    hipLaunchKernelGGL(k_sidx_query, dim3((uint32_t)blocks), dim3(kT), 0, s, ar, h, p, wbsum);
+    return hipGetLastError();
+}
+
+}  // namespace xc

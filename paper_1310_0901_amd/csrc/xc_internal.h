@@ -76,6 +76,7 @@ struct DevState {
     Region region;
     uint64_t pool;          // device address of the shadow pool
     uint64_t size_bound;    // no live allocation is larger (within a factor of two)
+    uint64_t pool_len;      // bytes of the pool ever handed out (from its start)
 };
 
 struct FillRange {
@@ -130,30 +131,37 @@ struct BatchArgs {
     // when not null, position t is the pitched 2D record pitch[t] (desc[t] is
     // its row 0; check_transfers_2d), and findings are offset by row * width
     const Pitch *pitch;
-    // when not null, k_classify adds the valid host-source bytes of the batch
-    // here (the host index's cost test, hostindex.hip)
-    uint64_t *host_bytes;
+    // when not null, k_classify adds the batch's valid bytes that a shadow
+    // index would answer: [0] in the host region (host sources, host
+    // destinations of device-to-host records), [1] in the shadow pool (device
+    // sources); the indexes' cost test (shadowindex.hip)
+    uint64_t *index_bytes[2];
 };
 
-// Index of the host region's faulty 16-byte chunks for one check-only batch
-// (hostindex.hip): every chunk holding an undefined byte (V != 0 where A = 1),
-// with its mask and the undefined bytes of all chunks before it, and every
-// chunk holding an unaddressable byte (A = 0), in ascending order.  A
-// host-source record's findings are then two searches per list instead of a
-// scan of its bytes.  Built by `grid` blocks, block b over a contiguous range
-// of chunks; state = {valid host-source bytes of the batch, index valid,
+// Index of one shadow space's faulty 16-byte chunks for a check-only batch
+// (shadowindex.hip).  Space 0 is the host region (V and A bits), space 1 the
+// shadow pool (V only: its addressability is the allocation table's).  The
+// lists hold every chunk with an undefined byte (V != 0 where A = 1), with
+// its mask and the undefined bytes of all chunks before it, and every chunk
+// with an unaddressable byte (A = 0), in ascending order; a record's
+// findings in that space are then two searches per list instead of a scan
+// of its bytes.  Built by `grid` blocks, block b over a contiguous range of
+// chunks; state = {valid bytes of the batch in the space, index valid,
 // undefined-chunk entries, unaddressable-chunk entries}.
-struct HostIndex {
+struct ShadowIndex {
     uint64_t *uchunk;   // [cap_u + 1]: entry n_u holds ~0
     uint32_t *umask;    // [cap_u]
     uint64_t *ucum;     // [cap_u + 1]: entry n_u holds the total
     uint64_t *nchunk;   // [cap_n]
     uint32_t *nmask;    // [cap_n]
-    uint64_t *bcnt;     // [3 * grid]: per block entries (u, n) and undefined bytes, then their offsets
+    uint64_t *bcnt;     // [6 * grid]: per block entries (u, n) and undefined bytes, then their offsets
     uint64_t *state;    // [4]
+    uint8_t *sflag;     // [4 * steps_cap]: wave w of a block step (4,096 chunks) met list entries
+    uint64_t steps_cap;
     uint64_t cap_u, cap_n;
     uint32_t grid;
-    uint32_t ratio;     // build when the batch's valid host-source bytes reach ratio * region length
+    uint32_t space;     // 0 host region, 1 shadow pool
+    uint32_t ratio;     // built when the batch's valid bytes in the space reach ratio * its length
 };
 
 // Cutting a batch's records into source-block segments (segment.hip).
@@ -211,12 +219,16 @@ hipError_t launch_merge_warm(hipStream_t s);
 hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
 // one lane per pitched 2D record: row 0 classified, Pitch, weight rows * upr,
 // verdict before any row is worked (check_transfers_2d)
-// the host index of a check-only batch worked as segments: reset before
-// k_classify, build after it, then answer the host-source records and take
-// them out of the scan (their units to 0, wbsum per classify block adjusted)
-hipError_t launch_hidx_reset(const HostIndex &x, hipStream_t s);
-hipError_t launch_hidx_build(const HostIndex &x, const DevState *st, hipStream_t s);
-hipError_t launch_hidx_query(const BatchArgs &ar, const HostIndex &x, uint64_t *wbsum, hipStream_t s);
+// the shadow indexes of a check-only batch worked as segments: reset before
+// k_classify, build after it, then answer the records whose every space has
+// a valid index and take them out of the scan (units to 0, wbsum per
+// classify block adjusted)
+hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStream_t s);
+hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s);   // count + finish
+hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s);
+hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s);
+hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
+                             hipStream_t s);
 hipError_t launch_classify_2d(const BatchArgs &a, const cg_transfer2d *recs2d, Pitch *pitch, hipStream_t s);
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s);
 hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);

@@ -44,9 +44,9 @@ def host_lds(request, monkeypatch):
     LDS by the scan kernel's own blocks or by a kernel of their own after it,
     or all of them in the persistent scan kernel."""
     p = request.param
-    monkeypatch.setenv("XC_HOST_INDEX", "2" if p.startswith("host-index") else "0")
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2" if p.startswith("host-index") else "0")
     if p == "host-index-overflow":
-        monkeypatch.setenv("XC_HIDX_CAP", "4")
+        monkeypatch.setenv("XC_SIDX_CAP", "4")
     monkeypatch.setenv("XC_HOST_LDS", {"host-lds-after": "2", "scan-only": "0"}.get(p, "1"))
     return p
 
@@ -305,8 +305,8 @@ def test_host_index_edges(X, H, cap, monkeypatch):
     faulty chunk (cap 4096) or overflow (cap 64: the records are scanned)."""
     monkeypatch.setenv("XC_REORDER_MIN", "1")
     monkeypatch.setenv("XC_SEG_MIN_LOG2", "4")
-    monkeypatch.setenv("XC_HOST_INDEX", "2")
-    monkeypatch.setenv("XC_HIDX_CAP", cap)
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2")
+    monkeypatch.setenv("XC_SIDX_CAP", cap)
     rng = np.random.default_rng(61)
     hl = 4000 + 7
     hv = np.zeros(hl, np.uint8)
@@ -337,19 +337,49 @@ def test_host_index_edges(X, H, cap, monkeypatch):
         dw.close()
 
 
-def test_host_index_dense_world(X, H, monkeypatch):
-    """A region with 30 % undefined bytes and 1 % A holes (most chunks are
-    listed): the host index answers every host-to-device record exactly."""
+def faulty_chunks(hv, a):
+    """Chunks of a host region with an undefined byte (V != 0, A = 1), and
+    with an unaddressable byte (A = 0)."""
+    n = (hv.size + 15) // 16 * 16
+    und = np.zeros(n, bool)
+    und[:hv.size] = (hv != 0) & (a == 1)
+    un = np.zeros(n, bool)
+    un[:hv.size] = a == 0
+    return int(und.reshape(-1, 16).any(1).sum()), int(un.reshape(-1, 16).any(1).sum())
+
+
+@pytest.mark.parametrize("world", ["host-fits", "pool-fits", "both-fit"])
+def test_shadow_index_dense_worlds(X, H, world, monkeypatch):
+    """Worlds with 30 % undefined bytes and 1 % A holes, so that most chunks
+    are listed, and list capacities chosen so that only the host region's
+    index fits, only the pool's, or both: every record equals the oracle,
+    whichever of its spaces are indexed."""
     monkeypatch.setenv("XC_REORDER_MIN", "1")
-    monkeypatch.setenv("XC_HOST_INDEX", "2")
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2")
     rng = np.random.default_rng(62)
-    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=200_003, nalloc=6, max_size=100_000, dens=0.3)
+    if world == "pool-fits":
+        hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=400_003, nalloc=4, max_size=20_000, dens=0.3)
+    else:
+        hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=100_003, nalloc=6, max_size=200_000, dens=0.3)
     a = (rng.random(hl) > 0.01).astype(np.uint8)
-    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 2000, max_n=50_000, kinds=(0, 0, 0, 1, 2))
+    hu, hn = faulty_chunks(hv, a)
+    pool_u = sum(int(((v != 0)[: (v.size // 16) * 16].reshape(-1, 16).any(1)).sum()) for v in vs)
+    host = max(hu, hn)
+    if world == "host-fits":
+        assert pool_u > 2 * host
+        cap = (host + pool_u) // 2
+    elif world == "pool-fits":
+        assert host > 2 * pool_u
+        cap = (host + pool_u) // 2
+    else:
+        cap = 1 << 20
+    monkeypatch.setenv("XC_SIDX_CAP", str(cap))
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 2000, max_n=50_000)
     w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
     want = util.oracle_for(w).run(recs)
     dw = H.DeviceWorld(w)
     try:
-        util.assert_verdicts_equal(dw.check(recs, X.CG_CHECK), want, "dense world")
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_EAGER):
+            util.assert_verdicts_equal(dw.check(recs, mode), want, f"{world} mode {mode}")
     finally:
         dw.close()
