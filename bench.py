@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the sources of the profiled kernels: a profile holds while their sha256 (in this order) is unchanged
+KERNEL_SOURCES = ("kernels.hip", "shadowindex.hip")
 METRIC = "shadow GB/s checked (% HBM peak) batched vs plain; transfers/s; p50/p99 check latency"
 
 
@@ -111,8 +113,10 @@ def matching_profile(name, tuning, config):
     if config != 3 or not os.path.exists(path):
         return None, "no profile for this workload"
     prof = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1310_0901_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != prof["kernels_hip_sha256"]:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1310_0901_amd", "csrc", name), "rb").read())
+    if h.hexdigest() != prof.get("kernel_sources_sha256"):
         return None, "kernel changed since the counters were taken"
     if tuning is not None and {k: tuning[k] for k in prof["tuning"]} != prof["tuning"]:
         return None, "launch shape differs from the profiled one"

@@ -182,18 +182,30 @@ __global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState
                 }
             }
         }
-        uint32_t any = 0;
+        // almost every chunk is clean (V all 0, A all 1): the lane's step is
+        // examined chunk by chunk only when it is not, or when it holds the
+        // space's end (bytes past it must not count)
+        uint32_t orv = 0, anda = 0xFFFFu;
 #pragma unroll
         for (uint32_t j = 0; j < kPer; ++j) {
-            const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-            // bytes past the space's end (its last chunk, or none) are clear
-            const uint64_t left = c < hi ? S.len - 16 * c : 0;
-            const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
-            const uint32_t und = nz16(v[j]) & a[j] & live, un = ~a[j] & live;
-            c3[0] += und ? 1u : 0u;
-            c3[1] += un ? 1u : 0u;
-            c3[2] += (uint32_t)__builtin_popcount(und);
-            any |= und | un;
+            orv |= v[j].x | v[j].y | v[j].z | v[j].w;
+            anda &= a[j];
+        }
+        const bool edge = base + kStep > hi || ((S.len & 15u) && base + kStep >= space_chunks(S));
+        uint32_t any = 0;
+        if (orv != 0u || anda != 0xFFFFu || edge) {
+#pragma unroll
+            for (uint32_t j = 0; j < kPer; ++j) {
+                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+                // bytes past the space's end (its last chunk, or none) are clear
+                const uint64_t left = c < hi ? S.len - 16 * c : 0;
+                const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
+                const uint32_t und = nz16(v[j]) & a[j] & live, un = ~a[j] & live;
+                c3[0] += und ? 1u : 0u;
+                c3[1] += un ? 1u : 0u;
+                c3[2] += (uint32_t)__builtin_popcount(und);
+                any |= und | un;
+            }
         }
         if (flags) {
             const uint64_t seen = __ballot(any != 0);
@@ -260,8 +272,39 @@ __global__ void __launch_bounds__(1024) k_sidx_scan(ShadowIndex x, const DevStat
     }
 }
 
+// The entries of one step of block b's range, in chunk order, at the running
+// offsets ou / on / op.
+__device__ __forceinline__ void fill_step(const ShadowIndex &x, const Space &S, uint64_t base, uint64_t hi,
+                                          uint64_t &ou, uint64_t &on, uint64_t &op)
+{
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+        uint32_t und = 0, un = 0;
+        if (c < hi) chunk_faults(S, c, &und, &un);
+        uint64_t v[3] = {und ? 1u : 0u, un ? 1u : 0u, (uint64_t)__builtin_popcount(und)};
+        uint64_t ex[3], tot[3];
+        block_scan3(v, ex, tot);
+        if (und) {
+            x.uchunk[ou + ex[0]] = c;
+            x.umask[ou + ex[0]] = und;
+            x.ucum[ou + ex[0]] = op + ex[2];
+        }
+        if (un) {
+            x.nchunk[on + ex[1]] = c;
+            x.nmask[on + ex[1]] = un;
+        }
+        ou += tot[0];
+        on += tot[1];
+        op += tot[2];
+    }
+}
+
+// With the steps' flags, the block reads 256 of them at a time, one per
+// thread, lists the flagged ones in order, and fills only those.
 __global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState *stp)
 {
+    __shared__ uint32_t list[kT];
+    __shared__ uint32_t nlist;
     if (!x.state[1]) return;
     const Space S = space_of(x, stp);
     const uint32_t b = blockIdx.x;
@@ -269,32 +312,27 @@ __global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState 
     uint64_t lo, hi;
     block_range(S, x.grid, b, &lo, &hi);
     uint64_t ou = x.bcnt[3 * (x.grid + b)], on = x.bcnt[3 * (x.grid + b) + 1], op = x.bcnt[3 * (x.grid + b) + 2];
-    const uint64_t end_u = ou + x.bcnt[3 * b], end_n = on + x.bcnt[3 * b + 1];
     const uint64_t spb = block_steps(S, x.grid);
-    const bool flags = spb * x.grid <= x.steps_cap;
-    uint64_t step = (uint64_t)b * spb;
-    for (uint64_t base = lo; base < hi && (ou < end_u || on < end_n); base += kStep, ++step) {
-        if (flags && *reinterpret_cast<const uint32_t *>(x.sflag + 4 * step) == 0) continue;   // no entries here
-        for (uint32_t j = 0; j < kPer; ++j) {
-            const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-            uint32_t und = 0, un = 0;
-            if (c < hi) chunk_faults(S, c, &und, &un);
-            uint64_t v[3] = {und ? 1u : 0u, un ? 1u : 0u, (uint64_t)__builtin_popcount(und)};
-            uint64_t ex[3], tot[3];
-            block_scan3(v, ex, tot);
-            if (und) {
-                x.uchunk[ou + ex[0]] = c;
-                x.umask[ou + ex[0]] = und;
-                x.ucum[ou + ex[0]] = op + ex[2];
-            }
-            if (un) {
-                x.nchunk[on + ex[1]] = c;
-                x.nmask[on + ex[1]] = un;
-            }
-            ou += tot[0];
-            on += tot[1];
-            op += tot[2];
-        }
+    if (spb * x.grid > x.steps_cap) {
+        // no flags: every step of the range
+        const uint64_t end_u = ou + x.bcnt[3 * b], end_n = on + x.bcnt[3 * b + 1];
+        for (uint64_t base = lo; base < hi && (ou < end_u || on < end_n); base += kStep) fill_step(x, S, base, hi, ou, on, op);
+        return;
+    }
+    const uint64_t nsteps = lo < hi ? (hi - lo + kStep - 1) / kStep : 0;
+    const uint64_t step0 = (uint64_t)b * spb;
+    for (uint64_t g0 = 0; g0 < nsteps; g0 += kT) {
+        const uint64_t g = g0 + threadIdx.x;
+        const uint32_t f = g < nsteps && *reinterpret_cast<const uint32_t *>(x.sflag + 4 * (step0 + g)) != 0;
+        uint64_t v[3] = {f, 0, 0};
+        uint64_t ex[3], tot[3];
+        block_scan3(v, ex, tot);
+        if (f) list[ex[0]] = (uint32_t)threadIdx.x;
+        if (threadIdx.x == 0) nlist = (uint32_t)tot[0];
+        __syncthreads();
+        const uint32_t n = nlist;
+        for (uint32_t k = 0; k < n; ++k) fill_step(x, S, lo + (g0 + list[k]) * kStep, hi, ou, on, op);
+        __syncthreads();   // list and nlist are rewritten next
     }
 }
 
