@@ -817,6 +817,34 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
 }
 
+// After the shadow indexes have answered records (units 0) of a batch in its
+// given order: each record's weight max(units, 1) again, with the block-local
+// prefix and block sums that k_classify leaves.
+__global__ void __launch_bounds__(kClassifyBlock) k_reweigh(BatchArgs a)
+{
+    __shared__ uint64_t wsum[kClassifyBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
+    uint64_t w = 0;
+    if (t < a.count) {
+        const uint64_t u = a.desc[t].units;
+        a.weight[t] = u;
+        w = u ? u : 1;
+    }
+    const uint32_t lane = lane_id(), wid = tid >> 6;
+    uint64_t x = w;
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63u) wsum[wid] = x;
+    __syncthreads();
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
+    if (t < a.count) a.local[t] = off + x - w;
+    if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
+}
+
 // ---------------------------------------------------------------------------
 // pitched 2D records (check_transfers_2d) as positions of their own
 // ---------------------------------------------------------------------------
@@ -1906,6 +1934,13 @@ hipError_t launch_classify(const BatchArgs &a, hipStream_t s)
 {
     const uint64_t blocks = (a.count + kClassifyBlock - 1) / kClassifyBlock;
     hipLaunchKernelGGL(k_classify, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reweigh(const BatchArgs &a, hipStream_t s)
+{
+    const uint64_t blocks = (a.count + kClassifyBlock - 1) / kClassifyBlock;
+    hipLaunchKernelGGL(k_reweigh, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, a);
     return hipGetLastError();
 }
 

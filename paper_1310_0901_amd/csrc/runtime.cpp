@@ -502,7 +502,12 @@ LaunchShape shape_of(cg_ctx *c, const cg_tuning &t)
 
 // A batch worked as source-block segments: k_classify over the records in
 // their given order (ar), then the segments (g) as the positions of the batch.
+// How a batched check is prepared beyond classify and scan: as source-block
+// segments (seg; ar is then the record-level classify's arguments), and/or
+// with the shadow indexes (hidx, pidx; without segments ar is the batch's own
+// arguments).
 struct SegPlan {
+    bool seg;
     BatchArgs ar;
     SegArgs g;
     SortWs *sort;
@@ -529,8 +534,11 @@ hipError_t prepare_stage(const BatchArgs &a, const LaunchShape &sh, hipStream_t 
     if (idx) {
         if ((e = launch_sidx_finish(*sp->pidx, sp->ar.st, s)) != hipSuccess) return e;
         if ((e = launch_sidx_query(sp->ar, *sp->hidx, *sp->pidx, sp->ar.bsum, s)) != hipSuccess) return e;
+        // a batch in its given order: the prefix inputs again, from the units left
+        if (!sp->seg && (e = launch_reweigh(a, s)) != hipSuccess) return e;
     }
-    if (sp && (e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess) return e;
+    if (sp && sp->seg && (e = launch_segments(sp->g, *sp->sort, a, const_cast<uint32_t *>(a.perm), s)) != hipSuccess)
+        return e;
     if ((e = launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s)) != hipSuccess) return e;
     return launch_prefix_tiles(a, s);
 }
@@ -810,19 +818,28 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2,
                          host_last ? 1u : 0u};
         plan.sort = &w->sort;
-        plan.hidx = plan.pidx = nullptr;
-        if (c->shadow_index && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK) {
-            rc = reserve_sidx(c, w);
-            if (rc) return rc;
-            w->hidx.ratio = w->pidx.ratio = c->shadow_index == 2 ? 0u : c->sidx_ratio;
-            plan.hidx = &w->hidx;
-            plan.pidx = &w->pidx;
-            plan.ar.index_bytes[0] = w->hidx.state;
-            plan.ar.index_bytes[1] = w->pidx.state;
-        }
+        plan.seg = true;
         a.perm = w->perm;
         a.lds_meta = host_last ? w->meta : nullptr;
         a.task_pos = c->task_pos;
+        sp = &plan;
+    }
+    // a check without propagation, of more records than one launch takes and
+    // not kept in its order: the shadow indexes answer what they can
+    if (c->shadow_index && (mode & (CG_CHECK | CG_PROPAGATE | CG_PLAIN | CG_KEEP_ORDER)) == CG_CHECK &&
+        count > c->small_max) {
+        rc = reserve_sidx(c, w);
+        if (rc) return rc;
+        w->hidx.ratio = w->pidx.ratio = c->shadow_index == 2 ? 0u : c->sidx_ratio;
+        if (!seg) {
+            plan.seg = false;
+            plan.ar = a;
+        }
+        plan.hidx = &w->hidx;
+        plan.pidx = &w->pidx;
+        plan.ar.index_bytes[0] = w->hidx.state;
+        plan.ar.index_bytes[1] = w->pidx.state;
+        if (!seg) a = plan.ar;
         sp = &plan;
     }
     const LaunchShape sh = shape_of(c, tun);

@@ -229,6 +229,9 @@ hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream
 hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
                              hipStream_t s);
+// the block-local prefix and block sums of max(units, 1) again, after the
+// shadow indexes have answered records of a batch in its given order
+hipError_t launch_reweigh(const BatchArgs &a, hipStream_t s);
 hipError_t launch_classify_2d(const BatchArgs &a, const cg_transfer2d *recs2d, Pitch *pitch, hipStream_t s);
 hipError_t launch_scan_sums(const BatchArgs &a, uint32_t tile_units, uint32_t waves, hipStream_t s);
 hipError_t launch_prefix_tiles(const BatchArgs &a, hipStream_t s);
