@@ -660,6 +660,12 @@ def main():
         "pool_index_pass_ms": None if i_avg_ms is None else round(i_avg_ms, 3),
         "pool_bytes": int(pool_bytes),
     }
+    if i_avg_ms is not None:
+        # what the step reads of the shadow when the indexes answer the batch:
+        # the pool's V bytes and the host region's V and A bytes, once each
+        sb = int(pool_bytes + w.host.length + (w.host.length + 7) // 8)
+        result["shadow_bytes_read_per_step"] = sb
+        result["shadow_read_GBps"] = round(sb / (wall / args.steps) / 1e9, 1)
 
     if not args.no_plain:
         torch.cuda.synchronize(dev)

@@ -197,6 +197,7 @@ struct cg_ctx {
     int shadow_index = 1;                    // shadow indexes of check-only segmented batches: 0 off, 1 when they pay, 2 always
     uint32_t sidx_ratio = 4;                 // one pays from this many of the batch's bytes per byte of its space
     uint64_t sidx_cap = 1ull << 22;          // entries per list of a shadow index
+    uint32_t sidx_blocks_per_cu = 8;         // grid of the index passes
     int host_lds = 1;                        // check-only segments of host sources worked from LDS: 1 in the
                                              // scan kernel's blocks, 2 in a kernel of their own after it, 0 not
     std::map<hipStream_t, StridedWs> strided_ws;   // row expansion of 2D copies, per stream
@@ -752,7 +753,7 @@ int reserve_sidx(cg_ctx *c, Workspace *w)
         x.space = space;
         x.cap_u = c->sidx_cap;
         x.cap_n = space ? 1 : c->sidx_cap;
-        x.grid = (uint32_t)std::max(c->cu_count, 1) * 8u;
+        x.grid = (uint32_t)std::max(c->cu_count, 1) * c->sidx_blocks_per_cu;
         HIPTRY(c, hipMalloc(&x.uchunk, (x.cap_u + 1) * 8));
         HIPTRY(c, hipMalloc(&x.umask, x.cap_u * 4));
         HIPTRY(c, hipMalloc(&x.ucum, (x.cap_u + 1) * 8));
@@ -1084,6 +1085,7 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (const char *e = getenv("XC_PITCHED_2D")) c->pitched_2d = atoi(e) != 0;
     if (const char *e = getenv("XC_SHADOW_INDEX")) c->shadow_index = std::min(std::max(atoi(e), 0), 2);
     if (const char *e = getenv("XC_SIDX_CAP")) c->sidx_cap = std::max<uint64_t>(strtoull(e, nullptr, 0), 1);
+    if (const char *e = getenv("XC_SIDX_BLOCKS")) c->sidx_blocks_per_cu = std::min(std::max(atoi(e), 1), 64);
     if (c->seg_min_log2 < 4 || c->seg_min_log2 > 40) return bail(CG_EINVAL);
     if (!valid_tuning(c->tuning)) return bail(CG_EINVAL);
     c->tuning_prop = c->tuning;

@@ -273,30 +273,43 @@ __global__ void __launch_bounds__(1024) k_sidx_scan(ShadowIndex x, const DevStat
 }
 
 // The entries of one step of block b's range, in chunk order, at the running
-// offsets ou / on / op.
+// offsets ou / on / op: here thread t takes the step's chunks 16 t .. 16 t + 15
+// (consecutive, so that one block scan of the threads' counts orders them).
 __device__ __forceinline__ void fill_step(const ShadowIndex &x, const Space &S, uint64_t base, uint64_t hi,
                                           uint64_t &ou, uint64_t &on, uint64_t &op)
 {
+    const uint64_t c0 = base + (uint64_t)threadIdx.x * kPer;
+    uint32_t und[kPer], un[kPer];
+    uint64_t v[3] = {0, 0, 0};
+#pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-        const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-        uint32_t und = 0, un = 0;
-        if (c < hi) chunk_faults(S, c, &und, &un);
-        uint64_t v[3] = {und ? 1u : 0u, un ? 1u : 0u, (uint64_t)__builtin_popcount(und)};
-        uint64_t ex[3], tot[3];
-        block_scan3(v, ex, tot);
-        if (und) {
-            x.uchunk[ou + ex[0]] = c;
-            x.umask[ou + ex[0]] = und;
-            x.ucum[ou + ex[0]] = op + ex[2];
-        }
-        if (un) {
-            x.nchunk[on + ex[1]] = c;
-            x.nmask[on + ex[1]] = un;
-        }
-        ou += tot[0];
-        on += tot[1];
-        op += tot[2];
+        und[j] = un[j] = 0;
+        if (c0 + j < hi) chunk_faults(S, c0 + j, &und[j], &un[j]);
+        v[0] += und[j] ? 1u : 0u;
+        v[1] += un[j] ? 1u : 0u;
+        v[2] += (uint64_t)__builtin_popcount(und[j]);
     }
+    uint64_t ex[3], tot[3];
+    block_scan3(v, ex, tot);
+    uint64_t iu = ou + ex[0], in = on + ex[1], ip = op + ex[2];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        if (und[j]) {
+            x.uchunk[iu] = c0 + j;
+            x.umask[iu] = und[j];
+            x.ucum[iu] = ip;
+            ++iu;
+            ip += (uint64_t)__builtin_popcount(und[j]);
+        }
+        if (un[j]) {
+            x.nchunk[in] = c0 + j;
+            x.nmask[in] = un[j];
+            ++in;
+        }
+    }
+    ou += tot[0];
+    on += tot[1];
+    op += tot[2];
 }
 
 // With the steps' flags, the block reads 256 of them at a time, one per

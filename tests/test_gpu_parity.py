@@ -383,3 +383,51 @@ def test_shadow_index_dense_worlds(X, H, world, monkeypatch):
             util.assert_verdicts_equal(dw.check(recs, mode), want, f"{world} mode {mode}")
     finally:
         dw.close()
+
+
+def test_shadow_index_after_frees(X, H, monkeypatch):
+    """The indexes are rebuilt from the shadow as it is at each check: after
+    frees, fresh allocations (one in a freed block's pool slot, whose bytes
+    past the new size keep the old shadow), and partial writes, a second
+    batch (with pointers into freed allocations) equals the oracle on the new
+    state, as the first did on the old."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1")
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2")
+    rng = np.random.default_rng(63)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=300_000, nalloc=6, max_size=100_000, dens=0.01)
+    recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 600, max_n=40_000)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, recs)
+    dw = H.DeviceWorld(w, pool_slack=1 << 20)
+    try:
+        util.assert_verdicts_equal(dw.check(recs), util.oracle_for(w).run(recs), "before")
+        # free two allocations; allocate one smaller at the first freed base
+        # (its pool slot may be the freed one), and one past the last
+        freed = [1, 3]
+        for j in freed:
+            X.shadow_free(dw.ctx, int(bases[j]))
+        torch.cuda.synchronize()
+        X.cg_sync(dw.ctx)
+        nb = [int(bases[1]), int(bases[-1]) + int(sizes[-1]) + 4096]
+        ns = [int(sizes[1]) // 2 + 1, 50_000]
+        for b, z in zip(nb, ns):
+            X.shadow_alloc(dw.ctx, b, z)
+        # define the second half of each new allocation
+        nv = []
+        for b, z in zip(nb, ns):
+            X.shadow_set(dw.ctx, b + z // 2, z - z // 2, 0)
+            v = np.full(z, 0xFF, np.uint8)
+            v[z // 2:] = 0
+            nv.append(v)
+        keep = [j for j in range(bases.size) if j not in freed]
+        b2 = np.array(sorted([int(bases[j]) for j in keep] + nb), np.uint64)
+        order = {int(bases[j]): (int(sizes[j]), vs[j]) for j in keep}
+        order.update({b: (z, v) for b, z, v in zip(nb, ns, nv)})
+        s2 = np.array([order[int(b)][0] for b in b2], np.uint64)
+        v2 = [order[int(b)][1] for b in b2]
+        recs2 = np.concatenate([util.random_records(rng, W.HOST_BASE, hl, b2, s2, 500, max_n=40_000),
+                                util.random_records(rng, W.HOST_BASE, hl, bases[freed], sizes[freed], 100,
+                                                    max_n=5_000)])
+        w2 = util.workload_from_arrays(W.HOST_BASE, hv, a, b2, s2, v2, recs2)
+        util.assert_verdicts_equal(dw.check(recs2), util.oracle_for(w2).run(recs2), "after frees")
+    finally:
+        dw.close()
