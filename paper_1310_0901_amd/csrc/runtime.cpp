@@ -330,6 +330,9 @@ int materialize(cg_ctx *c)
     return ctx_end(c);
 }
 
+int issue_fills(cg_ctx *c, const std::vector<FillRange> &rs, bool after_checks);
+void add_fill(std::vector<FillRange> &rs, uint64_t ptr, uint64_t len, uint8_t v);
+
 // Checks that have finished, in issue order; quarantined pool blocks whose
 // readers are all done go back to the allocator.
 void retire(cg_ctx *c, bool wait_all)
@@ -343,10 +346,17 @@ void retire(cg_ctx *c, bool wait_all)
         c->inflight.pop_front();
     }
     if (c->inflight.empty()) c->done_seq = c->check_seq;
+    // released blocks are cleared to 0, so that a stale shadow left in the
+    // pool adds no entries to the pool's shadow index (a new allocation fills
+    // its block first, later on the same stream)
+    std::vector<FillRange> zero;
     while (!c->quarantine.empty() && c->quarantine.front().seq <= c->done_seq) {
-        c->palloc->release(c->quarantine.front().off, c->quarantine.front().size);
+        const Quarantined &q = c->quarantine.front();
+        add_fill(zero, (uint64_t)c->pool + q.off, c->palloc->rounded(q.size), 0);
+        c->palloc->release(q.off, q.size);
         c->quarantine.pop_front();
     }
+    if (!zero.empty()) (void)issue_fills(c, zero, false);   // a failed clear only makes an index longer
 }
 
 // Issue fills of [ptr, ptr + len) with v on the context stream.  Fills of
