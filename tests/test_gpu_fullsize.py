@@ -141,3 +141,67 @@ def test_config4_full_chain(X, H, pieces):
     finally:
         dw.close()
     say(f"config 4 ({pieces} pieces) done in {time.time() - t0:.1f} s")
+
+
+def rows_and_expected(w, r2):
+    """The row records of pitched 2D records (row r reads src + r*spitch and
+    writes dst + r*dpitch, width bytes), the rows' verdicts by interval
+    arithmetic, and one verdict per 2D record by the row-by-row numbering of
+    its bytes (flags OR, smallest r*width + first_bad_r, undefined bytes
+    summed, row 0's avail; no rows: {0, NONE, 0, 0})."""
+    T = r2.size
+    counts = np.where(r2["width"] > 0, r2["rows"], 0).astype(np.int64)
+    rec = np.repeat(np.arange(T), counts)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    r = np.arange(int(counts.sum()), dtype=np.int64) - np.repeat(first, counts)
+    rows = np.zeros(r.size, W.RECORD_DTYPE)
+    rows["src"] = r2["src"][rec] + (r * r2["spitch"][rec].astype(np.int64)).astype(np.uint64)
+    rows["dst"] = r2["dst"][rec] + (r * r2["dpitch"][rec].astype(np.int64)).astype(np.uint64)
+    rows["n"] = r2["width"][rec]
+    rows["kind"] = r2["kind"][rec]
+    f, fb, u, a = intervals.expected(w, rows)
+    out = np.zeros(T, W.VERDICT_DTYPE)
+    flags = np.zeros(T, np.uint32)
+    np.bitwise_or.at(flags, rec, f.astype(np.uint32))
+    none = np.uint64((1 << 64) - 1)
+    cand = np.where(fb != none, (r.astype(np.uint64) * r2["width"][rec]) + fb, none)
+    firsts = np.full(T, none, np.uint64)
+    np.minimum.at(firsts, rec, cand.astype(np.uint64))
+    und = np.zeros(T, np.uint64)
+    np.add.at(und, rec, u.astype(np.uint64))
+    av = np.zeros(T, np.uint64)
+    av[rec[r == 0]] = a[r == 0]
+    out["flags"], out["first_bad"], out["undef_bytes"], out["avail"] = flags, firsts, und, av
+    return out, rows.size
+
+
+def test_config2_as_pitched_rows(X, H):
+    """Configuration 2's copies as pitched 2D records on the no-wait path, at
+    full size: 4 KiB rows back to back (worked as one transfer each), 4,032-byte
+    rows at a 4 KiB pitch (row by row), and, for the first 300 copies,
+    240-byte rows at a 256-byte pitch (several rows per wave iteration).
+    Every record's verdict equals the rows' verdicts by interval arithmetic,
+    combined by the row-by-row numbering of its bytes."""
+    t0 = time.time()
+    w = W.config2()
+    hv, ha = W.host_v(w.host), W.host_a(w.host)
+    dw = H.DeviceWorld(w, host_arrays=(hv, ha))
+    say(f"config 2 set up in {time.time() - t0:.1f} s")
+    try:
+        base = np.zeros(w.count, W.RECORD2D_DTYPE)
+        base["src"], base["dst"], base["kind"] = w.records["src"], w.records["dst"], w.records["kind"]
+        for name, width, pitch, k in (("back to back", 4096, 4096, w.count), ("strided", 4032, 4096, w.count),
+                                      ("short rows", 240, 256, 300)):
+            r2 = base[:k].copy()
+            r2["width"], r2["spitch"], r2["dpitch"] = width, pitch, pitch
+            r2["rows"] = w.records["n"][:k] // pitch
+            want, nrows = rows_and_expected(w, r2)
+            rt = torch.from_numpy(np.ascontiguousarray(r2).view(np.uint8).copy()).to(dw.dev)
+            out = H.verdicts_tensor(k, dw.dev)
+            X.check_transfers_2d(dw.ctx, rt.data_ptr(), k, out.data_ptr(), X.CG_CHECK,
+                                 torch.cuda.current_stream(dw.dev).cuda_stream)
+            torch.cuda.synchronize(dw.dev)
+            util.assert_verdicts_equal(H.verdicts_np(out, k), want, f"config 2 as {name}")
+            say(f"config 2 as {name}: {k} records, {nrows} rows equal ({time.time() - t0:.1f} s)")
+    finally:
+        dw.close()
