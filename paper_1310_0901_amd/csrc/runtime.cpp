@@ -1629,8 +1629,16 @@ int cg_autotune(cg_ctx *c, const cg_transfer *recs_dev, uint64_t count, cg_verdi
     if (rc) { c->timing = was_timing; return rc; }
     HIPTRY(c, hipStreamSynchronize(s));
     c->tused = 0;
+    c->iused = 0;
     Ctl ctl;
     HIPTRY(c, hipMemcpy(&ctl, c->ws[s]->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (ctl.total_units <= count) {
+        // no record left to scan (the shadow indexes answered them, or they
+        // are empty): the launch shape does not matter; keep it
+        c->timing = was_timing;
+        if (best) *best = target;
+        return CG_OK;
+    }
     uint32_t lg = 0;
     while ((1ull << lg) < ctl.total_units) ++lg;
     std::ostringstream key;
