@@ -817,9 +817,9 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
 }
 
-// After the shadow indexes have answered records (units 0) of a batch in its
-// given order: each record's weight max(units, 1) again, with the block-local
-// prefix and block sums that k_classify leaves.
+// After the shadow indexes have answered positions (their weight set to 0)
+// of a batch in its given order: each position's weight max(units, 1) again,
+// with the block-local prefix and block sums that k_classify leaves.
 __global__ void __launch_bounds__(kClassifyBlock) k_reweigh(BatchArgs a)
 {
     __shared__ uint64_t wsum[kClassifyBlock / 64];
@@ -827,8 +827,7 @@ __global__ void __launch_bounds__(kClassifyBlock) k_reweigh(BatchArgs a)
     const uint64_t t = (uint64_t)blockIdx.x * kClassifyBlock + tid;
     uint64_t w = 0;
     if (t < a.count) {
-        const uint64_t u = a.desc[t].units;
-        a.weight[t] = u;
+        const uint64_t u = a.weight[t];
         w = u ? u : 1;
     }
     const uint32_t lane = lane_id(), wid = tid >> 6;
@@ -849,13 +848,6 @@ __global__ void __launch_bounds__(kClassifyBlock) k_reweigh(BatchArgs a)
 // pitched 2D records (check_transfers_2d) as positions of their own
 // ---------------------------------------------------------------------------
 
-// Pitch::uniform: rows follow row 0 (kRowsUniform), and also keep its 16-byte
-// phases, so that every row has row 0's units and upr is that number
-// (kRowsStep); or, in a check without propagation, the rows' sources (and a
-// host destination) lie back to back, so that the record is worked as one
-// transfer of rows * width bytes, whose descriptor is the position's and whose
-// units are upr (kRowsContig): its byte indices are the record's own.
-constexpr uint32_t kRowsUniform = 1u, kRowsStep = 3u, kRowsContig = 7u;
 
 // rows of a 2D record that are worked: every row below index 2^32 that
 // starts below byte 2^62 of the record (its bytes are numbered row by row)
@@ -969,6 +961,14 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
                 P.uniform = kRowsContig;
             }
             units = P.uniform == kRowsContig ? P.upr : rows * P.upr;
+            if (P.uniform == kRowsContig && a.index_bytes[0]) {
+                // one transfer: its valid bytes per shadow space, for the indexes' cost test
+                const uint64_t src = ds.v_hi > ds.v_lo ? (uint64_t)(ds.v_hi - ds.v_lo) : 0;
+                const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? (uint64_t)(ds.d_hi - ds.d_lo) : 0;
+                const uint64_t hb = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst, pb = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
+                if (hb) atomicAdd((unsigned long long *)a.index_bytes[0], (unsigned long long)hb);
+                if (pb) atomicAdd((unsigned long long *)a.index_bytes[1], (unsigned long long)pb);
+            }
             v = uniform ? v0 : cg_verdict{0u, 0u, NONE, 0, v0.avail};
             if (rows < R2.rows) v.flags |= CG_ROWS_LIMIT;
         }

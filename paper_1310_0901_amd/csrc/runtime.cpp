@@ -1385,7 +1385,26 @@ int check_2d_pitched(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, c
     a.pitch = w->pitch;
     const cg_tuning &tun = (mode & CG_PROPAGATE) ? c->tuning_prop : c->tuning;
     const LaunchShape sh = shape_of(c, tun);
+    // a check without propagation: records worked as one transfer each (rows
+    // back to back) are answered by the shadow indexes when they pay
+    const bool idx = c->shadow_index && mode == CG_CHECK;
+    if (idx) {
+        if (capturing && !w->pidx.state)
+            return fail(c, CG_ESTATE, "check_transfers_2d under capture: make one call on this stream first");
+        rc = reserve_sidx(c, w);
+        if (rc) return rc;
+        w->hidx.ratio = w->pidx.ratio = c->shadow_index == 2 ? 0u : c->sidx_ratio;
+        a.index_bytes[0] = w->hidx.state;
+        a.index_bytes[1] = w->pidx.state;
+        HIPTRY(c, launch_sidx_reset(w->hidx, w->pidx, s));
+    }
     HIPTRY(c, launch_classify_2d(a, recs_dev, w->pitch, s));
+    if (idx) {
+        HIPTRY(c, launch_sidx_build(w->hidx, a.st, s));
+        HIPTRY(c, launch_sidx_build(w->pidx, a.st, s));
+        HIPTRY(c, launch_sidx_query(a, w->hidx, w->pidx, a.bsum, s, w->pitch));
+        HIPTRY(c, launch_reweigh(a, s));
+    }
     HIPTRY(c, launch_scan_sums(a, sh.tile_units, sh.grid * (sh.block / 64), s));
     HIPTRY(c, launch_prefix_tiles(a, s));
     if (capturing) {

@@ -418,11 +418,15 @@ __device__ __forceinline__ void take_first(uint64_t *first, uint64_t off, int64_
     *first = i < *first ? i : *first;
 }
 
-__global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, ShadowIndex p, uint64_t *wbsum)
+// With `pitch`, the positions are pitched 2D records: only those worked as
+// one transfer (kRowsContig, whose descriptor is that transfer's) are
+// answered, and their units per row go to 0.
+__global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, ShadowIndex p, uint64_t *wbsum,
+                                                   Pitch *pitch)
 {
     const uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x;
     uint64_t removed = 0;
-    if (a.out && t < a.count) {
+    if (a.out && t < a.count && (!pitch || pitch[t].uniform == kRowsContig)) {
         const Desc d = a.desc[t];
         const bool src_host = (d.ctl & CTL_SRC_HOST) != 0;
         const bool has_src = d.v_hi > d.v_lo;
@@ -467,6 +471,8 @@ __global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, S
             v.first_bad = first;
             a.out[t] = v;
             a.desc[t].units = 0;
+            a.weight[t] = 0;
+            if (pitch) pitch[t].upr = 0;
             removed = d.units - 1;   // its weight max(units, 1) becomes 1
         }
     }
@@ -512,10 +518,10 @@ hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream
 }
 
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
-                             hipStream_t s)
+                             hipStream_t s, Pitch *pitch)
 {
     const uint64_t blocks = (ar.count + kT - 1) / kT;
-    hipLaunchKernelGGL(k_sidx_query, dim3((uint32_t)blocks), dim3(kT), 0, s, ar, h, p, wbsum);
+    hipLaunchKernelGGL(k_sidx_query, dim3((uint32_t)blocks), dim3(kT), 0, s, ar, h, p, wbsum, pitch);
     return hipGetLastError();
 }
 

@@ -102,6 +102,14 @@ struct Pitch {
     uint64_t src, dst, width, rows, spitch, dpitch, upr;
     uint32_t kind, uniform;
 };
+
+// Pitch::uniform: rows follow row 0 (kRowsUniform), and also keep its 16-byte
+// phases, so that every row has row 0's units and upr is that number
+// (kRowsStep); or, in a check without propagation, the rows' sources (and a
+// host destination) lie back to back, so that the record is worked as one
+// transfer of rows * width bytes, whose descriptor is the position's and whose
+// units are upr (kRowsContig): its byte indices are the record's own.
+constexpr uint32_t kRowsUniform = 1u, kRowsStep = 3u, kRowsContig = 7u;
 static_assert(sizeof(Pitch) == 64, "pitched record layout");
 
 struct BatchArgs {
@@ -228,7 +236,7 @@ hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream
 hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
-                             hipStream_t s);
+                             hipStream_t s, Pitch *pitch = nullptr);   // pitch: positions are 2D records
 // the block-local prefix and block sums of max(units, 1) again, after the
 // shadow indexes have answered records of a batch in its given order
 hipError_t launch_reweigh(const BatchArgs &a, hipStream_t s);

@@ -31,6 +31,14 @@ def H():
     return harness
 
 
+@pytest.fixture(params=["index-when-it-pays", "index-always"])
+def index_mode(request, monkeypatch):
+    """Shadow indexes for records worked as one transfer (rows back to back):
+    built when they pay (these small batches: rarely), or for every check."""
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2" if request.param == "index-always" else "1")
+    return request.param
+
+
 def check2d(X, dw, recs2d, mode):
     r = np.ascontiguousarray(recs2d, W.RECORD2D_DTYPE)
     rt = torch.from_numpy(r.view(np.uint8).copy()).to("cuda:0")
@@ -81,7 +89,7 @@ def test_pins(X, H):
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_random_check(X, H, seed):
+def test_random_check(X, H, seed, index_mode):
     rng = np.random.default_rng(700 + seed)
     hl, hv, a, bases, sizes, vs = util.random_world(rng, dens=0.01)
     w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
@@ -166,7 +174,7 @@ def wide_2d(rng, hb, hl, bases, sizes, count):
 
 
 @pytest.mark.parametrize("seed", range(3))
-def test_wide_rows(X, H, seed):
+def test_wide_rows(X, H, seed, index_mode):
     """Rows of 1-9 KiB: check on the no-wait path and the expanded path, both
     against the oracle; then check + propagate of a conflict-free subset on
     the no-wait path with every shadow byte compared."""
@@ -258,7 +266,7 @@ def step_2d(rng, hb, hl, bases, sizes, count):
 
 
 @pytest.mark.parametrize("seed", range(3))
-def test_step_rows(X, H, seed):
+def test_step_rows(X, H, seed, index_mode):
     """Rows at pitches that keep the 16-byte phase, worked with several rows
     per wave iteration: check (host A holes included, so device->host rows
     meet unaddressable destination bytes) against the oracle, on the no-wait
