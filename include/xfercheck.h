@@ -188,6 +188,13 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  *   block order, so that copies reading the same bytes run close together.
  *   Verdicts are the same and are written at the records' own positions
  *   either way; CG_KEEP_ORDER works the batch in the given order.
+ *   A check without propagation of more than 256 records (not CG_PLAIN or
+ *   CG_KEEP_ORDER) that reads its shadow spaces heavily (at least 4 bytes of
+ *   the host region, or of the shadow pool, per byte of it) reads each such
+ *   space once into an index of its faulty 16-byte chunks and answers its
+ *   records from it, with the same verdicts (the first such call on a
+ *   stream allocates the index space: about 170 MB plus one byte per 16 KiB
+ *   of the pool).
  * With CG_PROPAGATE every valid destination byte receives the source's V
  * byte, or 0xFF where the source byte is not valid; overlapping D2D records
  * are not propagated.  All records read the shadow as it was before the
