@@ -961,10 +961,12 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
                 P.uniform = kRowsContig;
             }
             units = P.uniform == kRowsContig ? P.upr : rows * P.upr;
-            if (P.uniform == kRowsContig && a.index_bytes[0]) {
-                // one transfer: its valid bytes per shadow space, for the indexes' cost test
-                const uint64_t src = ds.v_hi > ds.v_lo ? (uint64_t)(ds.v_hi - ds.v_lo) : 0;
-                const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? (uint64_t)(ds.d_hi - ds.d_lo) : 0;
+            if (P.uniform && a.index_bytes[0]) {
+                // the valid bytes read per shadow space, for the indexes' cost
+                // test: one transfer's, or row 0's times the rows
+                const uint64_t nr = P.uniform == kRowsContig ? 1 : rows;
+                const uint64_t src = ds.v_hi > ds.v_lo ? nr * (uint64_t)(ds.v_hi - ds.v_lo) : 0;
+                const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? nr * (uint64_t)(ds.d_hi - ds.d_lo) : 0;
                 const uint64_t hb = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst, pb = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
                 if (hb) atomicAdd((unsigned long long *)a.index_bytes[0], (unsigned long long)hb);
                 if (pb) atomicAdd((unsigned long long *)a.index_bytes[1], (unsigned long long)pb);

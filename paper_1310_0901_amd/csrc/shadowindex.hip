@@ -30,6 +30,9 @@
 //   k_sidx_query   one lane per record: answers the records of a check
 //                  without propagation whose spaces are indexed, and takes
 //                  their units out of the scan
+//   k_sidx_rows    one wave per pitched 2D record whose rows follow row 0:
+//                  the same, with the list entries of its span mapped onto
+//                  its rows
 #include <hip/hip_runtime.h>
 
 #include "xc_internal.h"
@@ -489,6 +492,161 @@ __global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, S
     }
 }
 
+// One side of a pitched record in a shadow space: byte c of row r (r < R,
+// c < w) is space offset S + r q + c and byte r w + c of the record (its
+// bytes are numbered row by row).  Rows may overlap (q < w), even coincide
+// (q = 0): a byte then belongs to several rows.
+struct RowSide {
+    uint64_t S, R, q, w;
+};
+
+// the rows holding the byte at offset o = space offset - S: how many, and the
+// record byte index of its first one (CG_NONE if none)
+__device__ __forceinline__ void byte_rows(const RowSide &x, uint64_t o, uint64_t *n, uint64_t *first)
+{
+    uint64_t lo, hi;
+    if (x.q == 0) {
+        if (o >= x.w) return;
+        lo = 0;
+        hi = x.R - 1;
+    } else {
+        hi = o / x.q;
+        if (hi > x.R - 1) hi = x.R - 1;
+        lo = o < x.w ? 0 : (o - x.w) / x.q + 1;   // the first row whose end passes o
+    }
+    if (lo > hi) return;
+    *n += hi - lo + 1;
+    const uint64_t i = lo * x.w + (o - lo * x.q);
+    *first = i < *first ? i : *first;
+}
+
+// bits [lo, hi) of a 16-bit mask (0 <= lo, both clamped to 16)
+__device__ __forceinline__ uint32_t bit_range(uint64_t lo, uint64_t hi)
+{
+    if (hi > 16) hi = 16;
+    if (lo >= hi) return 0;
+    return ((1u << (uint32_t)hi) - 1u) & ~((1u << (uint32_t)lo) - 1u);
+}
+
+// The bytes of chunk c marked in `sel` that lie in rows of side x: how many
+// (a byte counted once per row holding it) and the first one's record byte
+// index.  Chunks meet at most two rows, and a byte at most one, when
+// q >= max(w, 16): one division per chunk; otherwise byte by byte.
+__device__ __forceinline__ void chunk_rows(const RowSide &x, uint64_t c, uint32_t sel, uint64_t *n, uint64_t *first)
+{
+    const uint64_t b0 = 16 * c;
+    const uint32_t k0 = b0 < x.S ? (uint32_t)(x.S - b0) : 0u;   // bytes below the first row are in none
+    sel &= (0xFFFFu << k0) & 0xFFFFu;
+    if (!sel) return;
+    const uint64_t o0 = b0 + k0 - x.S;   // offset of byte k0
+    if (x.q >= 16 && x.q >= x.w) {
+        const uint64_t r = o0 / x.q, m = o0 - r * x.q;
+        // bytes k0 + j: row r for m + j < q, row r + 1 after
+        uint32_t in = 0;
+        if (r < x.R && m < x.w) in |= bit_range(k0, k0 + (x.w - m));
+        if (r + 1 < x.R && x.q - m < 16) in |= bit_range(k0 + (x.q - m), k0 + (x.q - m) + x.w);
+        const uint32_t hit = sel & in;
+        if (!hit) return;
+        *n += (uint64_t)__builtin_popcount(hit);
+        const uint64_t j = (uint64_t)__builtin_ctz(hit) - k0;
+        const uint64_t i = m + j < x.q ? r * x.w + m + j : (r + 1) * x.w + (m + j - x.q);
+        *first = i < *first ? i : *first;
+        return;
+    }
+    for (uint32_t bits = sel; bits; bits &= bits - 1u) byte_rows(x, o0 + ((uint64_t)__builtin_ctz(bits) - k0), n, first);
+}
+
+// the list entries [i0, i1) against side x, one lane per entry
+__device__ __forceinline__ void walk_rows(const uint64_t *chunk, const uint32_t *mask, uint64_t i0, uint64_t i1,
+                                          const RowSide &x, uint32_t lane, uint64_t *n, uint64_t *first)
+{
+    for (uint64_t i = i0 + lane; i < i1; i += 64) chunk_rows(x, chunk[i], mask[i], n, first);
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v)
+{
+    for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min(uint64_t v)
+{
+    for (int k = 32; k >= 1; k >>= 1) {
+        const uint64_t o = __shfl_xor(v, k);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Pitched positions whose rows follow row 0 (kRowsUniform, kRowsStep: every
+// row whole inside row 0's allocation or the host region) in a check without
+// propagation, one wave per position.  The list entries between the first
+// row's start and the last row's end are mapped onto the rows: undefined
+// bytes counted once per row holding them, the first faulty byte by the
+// record's row-by-row numbering.  A position whose spaces lack a valid index,
+// or whose span holds more entries than a scan of its rows would read
+// chunks (and more than 4,096), is left to the scan.
+__global__ void __launch_bounds__(kT) k_sidx_rows(BatchArgs a, ShadowIndex h, ShadowIndex p, Pitch *pitch)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t t = (uint64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (!a.out || t >= a.count) return;
+    const Pitch P = pitch[t];
+    if (P.uniform != kRowsUniform && P.uniform != kRowsStep) return;
+    const Desc d = a.desc[t];
+    const bool src_host = (d.ctl & CTL_SRC_HOST) != 0;
+    const bool dsta = (d.ctl & CTL_DST_A) != 0 && d.d_hi > d.d_lo;
+    const int64_t w = (int64_t)P.width;
+    // row 0 is valid whole on both sides (its verdict has no flags)
+    const bool ok = (d.ctl & CTL_CHECK) && !(d.ctl & CTL_PROP) && d.units > 0 && P.rows > 0 && d.v_lo == 0 &&
+                    d.v_hi == w && (!dsta || (d.d_lo == 0 && d.d_hi == w)) &&
+                    (src_host ? h.state[1] : p.state[1]) && (!dsta || h.state[1]);
+    if (!ok) return;
+    const ShadowIndex &xs = src_host ? h : p;
+    const uint32_t phi = (d.ctl >> CTL_PHI_SHIFT) & 15u, psi = (d.ctl >> CTL_PSI_SHIFT) & 15u;
+    const RowSide rs{src_host ? (uint64_t)(d.a_src + (int64_t)phi) : d.src_sh + phi - a.st->pool, P.rows, P.spitch,
+                     P.width};
+    const RowSide rd{(uint64_t)(d.a_dst + (int64_t)psi), P.rows, P.dpitch, P.width};
+    // the chunks of each side's span, first row to last
+    const uint64_t sa = rs.S >> 4, sb = (rs.S + (rs.R - 1) * rs.q + rs.w - 1) >> 4;
+    const uint64_t da = rd.S >> 4, db = (rd.S + (rd.R - 1) * rd.q + rd.w - 1) >> 4;
+    // the six list bounds, one lane each: undefined entries of the source span,
+    // unaddressable ones of the host source's and of the host destination's
+    uint64_t bound = 0;
+    if (lane < 2) bound = lower_bound(xs.uchunk, xs.state[2], lane == 0 ? sa : sb + 1);
+    else if (lane < 4 && src_host) bound = lower_bound(h.nchunk, h.state[3], lane == 2 ? sa : sb + 1);
+    else if (lane >= 4 && lane < 6 && dsta) bound = lower_bound(h.nchunk, h.state[3], lane == 4 ? da : db + 1);
+    const uint64_t i0 = __shfl(bound, 0), i1 = __shfl(bound, 1), j0 = __shfl(bound, 2), j1 = __shfl(bound, 3),
+                   k0 = __shfl(bound, 4), k1 = __shfl(bound, 5);
+    const uint64_t entries = (i1 - i0) + (j1 - j0) + (k1 - k0);
+    const uint64_t chunks = P.rows * ((P.width + 15) >> 4) * (dsta ? 2 : 1);
+    if (entries > 4096 && entries > chunks) return;
+    uint64_t undef = 0, fu = CG_NONE, fs = CG_NONE, fd = CG_NONE, unused = 0;
+    walk_rows(xs.uchunk, xs.umask, i0, i1, rs, lane, &undef, &fu);
+    walk_rows(h.nchunk, h.nmask, j0, j1, rs, lane, &unused, &fs);
+    walk_rows(h.nchunk, h.nmask, k0, k1, rd, lane, &unused, &fd);
+    undef = wave_sum(undef);
+    fu = wave_min(fu);
+    fs = wave_min(fs);
+    fd = wave_min(fd);
+    if (lane == 0) {
+        cg_verdict v = a.out[t];
+        if (undef) v.flags |= CG_SRC_UNDEF;
+        if (fs != CG_NONE) v.flags |= CG_SRC_UNADDR;
+        if (fd != CG_NONE) v.flags |= CG_DST_UNADDR;
+        v.undef_bytes += undef;
+        uint64_t first = v.first_bad;
+        first = fu < first ? fu : first;
+        first = fs < first ? fs : first;
+        first = fd < first ? fd : first;
+        v.first_bad = first;
+        a.out[t] = v;
+        a.desc[t].units = 0;
+        a.weight[t] = 0;
+        pitch[t].upr = 0;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStream_t s)
@@ -522,6 +680,10 @@ hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const Sh
 {
     const uint64_t blocks = (ar.count + kT - 1) / kT;
     hipLaunchKernelGGL(k_sidx_query, dim3((uint32_t)blocks), dim3(kT), 0, s, ar, h, p, wbsum, pitch);
+    if (pitch) {
+        const uint64_t wblocks = (ar.count + kT / 64 - 1) / (kT / 64);
+        hipLaunchKernelGGL(k_sidx_rows, dim3((uint32_t)wblocks), dim3(kT), 0, s, ar, h, p, pitch);
+    }
     return hipGetLastError();
 }
 

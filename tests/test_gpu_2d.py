@@ -33,8 +33,9 @@ def H():
 
 @pytest.fixture(params=["index-when-it-pays", "index-always"])
 def index_mode(request, monkeypatch):
-    """Shadow indexes for records worked as one transfer (rows back to back):
-    built when they pay (these small batches: rarely), or for every check."""
+    """Shadow indexes for records whose rows follow row 0 (worked as one
+    transfer, or row by row from the entries of their span): built when they
+    pay (these small batches: rarely), or for every check."""
     monkeypatch.setenv("XC_SHADOW_INDEX", "2" if request.param == "index-always" else "1")
     return request.param
 
@@ -300,6 +301,63 @@ def test_step_rows(X, H, seed, index_mode):
         dw.close()
 
 
+def inside_2d(rng, hb, hl, bases, sizes, count):
+    """2D copies whose rows all lie inside one allocation or the host region
+    on each side (so their rows follow row 0), at pitches that make rows
+    coincide (0), overlap (below the width), sit closer than a chunk (1-15),
+    touch (the width) or leave gaps of any phase; widths of 1-200 bytes."""
+    out = np.zeros(count, W.RECORD2D_DTYPE)
+    i = 0
+    while i < count:
+        kind = int(rng.choice([0, 1, 2]))
+        width = int(rng.integers(1, 200))
+        rows = int(rng.integers(1, 150))
+
+        def pitch():
+            return int(rng.choice([0, int(rng.integers(1, 16)), max(1, width - int(rng.integers(1, 40))), width,
+                                   width + int(rng.integers(1, 40)), 16 * int(rng.integers(1, 20))]))
+        sp, dp = pitch(), pitch()
+        if kind == 2 and rng.random() < 0.5:
+            dp = sp
+
+        def place(host, q):
+            span = (rows - 1) * q + width
+            if host:
+                return hb + int(rng.integers(0, hl - span + 1)) if span <= hl else None
+            j = int(rng.integers(0, bases.size))
+            return int(bases[j]) + int(rng.integers(0, int(sizes[j]) - span + 1)) if span <= int(sizes[j]) else None
+        s_, d_ = place(kind == 0, sp), place(kind == 1, dp)
+        if s_ is None or d_ is None:
+            continue
+        out[i] = (s_, d_, width, rows, sp, dp, kind, (0, 0, 0))
+        i += 1
+    return out
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_rows_from_index(X, H, seed, index_mode):
+    """Records whose rows follow row 0, in worlds dense with undefined and
+    unaddressable bytes: the index maps its entries onto rows that coincide,
+    overlap, sit closer than a chunk or leave gaps; every verdict equals the
+    oracle's (and the expanded path's)."""
+    rng = np.random.default_rng(970 + seed)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=1 << 20, nalloc=8, max_size=1 << 19,
+                                                     dens=[0.05, 0.002, 0.3][seed])
+    a = (rng.random(hl) > [0.01, 1e-3, 0.05][seed]).astype(np.uint8)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    recs = inside_2d(rng, W.HOST_BASE, hl, bases, sizes, 600)
+    want = util.oracle_for(w).run2d(recs)
+    for f in (X.CG_SRC_UNDEF, X.CG_SRC_UNADDR, X.CG_DST_UNADDR):
+        assert (want["flags"] & f).any(), f
+    assert seed == 2 or (want["flags"] == 0).any()
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_PLAIN):
+            util.assert_verdicts_equal(check2d(X, dw, recs, mode), want, f"seed {seed} mode {mode}")
+    finally:
+        dw.close()
+
+
 def test_captured_call_replays(X, H):
     """check_transfers_2d captured in a graph (after one call of that size on
     the stream) and replayed several times, with other eager work and
@@ -337,7 +395,7 @@ def test_captured_call_replays(X, H):
         dw.close()
 
 
-def test_many_rows(X, H):
+def test_many_rows(X, H, index_mode):
     """One record of 200,000 rows and many small ones in one batch."""
     rng = np.random.default_rng(9)
     hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=4 << 20, nalloc=4, max_size=3 << 20, dens=1e-4)
@@ -387,7 +445,7 @@ def test_no_rows_and_errors(X, H):
         dw.close()
 
 
-def test_row_limit(X, H):
+def test_row_limit(X, H, index_mode):
     """The no-wait path works the rows below index 2^32 that start below byte
     2^62 of the copy and flags a record with more rows CG_ROWS_LIMIT; its
     other fields cover the rows worked.  Rows here repeat one row (pitch 0),
