@@ -239,6 +239,10 @@ typedef struct cg_transfer2d {
  * The rows of a record checked are those below index 2^32 that start below
  * byte 2^62 of the copy; a record with more rows gets CG_ROWS_LIMIT in its
  * flags (its other fields cover the rows checked).
+ * In a check without propagation, a record whose rows all lie inside the
+ * first row's allocation (or the host region) is answered from the shadow
+ * indexes when check_transfers would build them for the rows' bytes: its rows
+ * are not read, and its verdict is the same.
  * With CG_PLAIN or CG_DEBUG_CONFLICTS the rows are instead expanded into
  * transfer records (a launch per row, or the host-side conflict check on the
  * rows): that call waits for the stream once, to learn the number of rows, and
