@@ -126,9 +126,11 @@ def matching_profile(name, tuning, config):
 def roofline(tun, config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step, l2_probe_GBps):
     """The dominant kernel's roofline.  When the shadow indexes answer the
     check-only records, that is the shadow pool index's counting pass
-    (k_sidx_count<1>): it reads every V byte of the pool once (its algorithmic
-    bytes: 1 B per pool byte), so HBM bounds it; achieved = pool bytes over
-    its live duration, traffic from its committed counters.  Otherwise it is
+    (k_sidx_count<1>): it reads once each V byte of the pool steps (64 KiB)
+    the batch's records read (its algorithmic bytes: `pool_bytes`, as the
+    library counted them for the timed passes), so HBM bounds it; achieved =
+    those bytes over its live duration, traffic from its committed counters.
+    Otherwise it is
     the scan kernel: the bytes the L2 returns to the L1s per launch (L1 -> L2
     read requests x 128 B, from its counters) over the launch, against the
     L2-resident read probe measured in this run, HBM traffic beside it."""
@@ -139,10 +141,11 @@ def roofline(tun, config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step, l2_probe_G
                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                "algorithmic_bytes_per_launch": int(pool_bytes), "scan_kernel_avg_ms": round(k_avg_ms, 3),
-               "note": "the shadow pool index's counting pass reads each V byte of the pool once (16-byte loads; "
-                       "the pool holds no A bits); achieved = pool bytes over its live duration (HIP events around "
-                       "it on the check's stream); traffic = HBM-side bytes per launch from FETCH_SIZE + WRITE_SIZE, "
-                       "profiles/k_sidx_count_pool_batched-1M_counters.md"}
+               "note": "the shadow pool index's counting pass reads once each V byte of the pool's 64 KiB steps "
+                       "that the batch's records read (16-byte loads; the pool holds no A bits); achieved = those "
+                       "bytes (counted by the library, cg_index_ms) over the pass's live duration (HIP events "
+                       "around it on the check's stream); traffic = HBM-side bytes per launch from FETCH_SIZE + "
+                       "WRITE_SIZE, profiles/k_sidx_count_pool_batched-1M_counters.md"}
         prof, why = matching_profile("k_sidx_count_pool_batched-1M_counters", None, config)
         if prof is not None:
             tb = int(prof["limits"]["traffic_bytes"])
@@ -633,15 +636,17 @@ def main():
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     kms, nk = X.cg_kernel_ms(ctx)
-    ims, ni = X.cg_index_ms(ctx)
+    ims, ni, (host_read, pool_read) = X.cg_index_ms(ctx)
     got = verdicts_np(out_t, T)
     ms_step = wall * 1e3 / args.steps
     value = bytes_step * args.steps / wall / 1e9
     k_avg_ms = kms / max(nk, 1)
     i_avg_ms = ims / ni if ni else None
     pool_bytes = X.cg_stats(ctx)[1]   # allocated once, in one go: the pool's used bytes are its length
+    pass_bytes = pool_read // ni if ni else 0   # what each counting pass of the pool read
     log(f"[bench] batched: {ms_step:.2f} ms/step, {value:.0f} GB/s; scan kernel {k_avg_ms:.2f} ms; pool index "
-        f"pass {i_avg_ms if i_avg_ms is None else round(i_avg_ms, 2)} ms over {pool_bytes / 1e9:.1f} GB")
+        f"pass {i_avg_ms if i_avg_ms is None else round(i_avg_ms, 2)} ms over {pass_bytes / 1e9:.1f} of the "
+        f"pool's {pool_bytes / 1e9:.1f} GB")
 
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -650,9 +655,10 @@ def main():
         "config": {"workload": f"{w.name} (configuration {args.config}): {w.note}",
                    "records": T, "live_allocations": int(w.dev.live_idx.size),
                    "host_region_bytes": int(w.host.length), "transfer_bytes": int(w.records["n"].sum()),
-                   "mode": "check", "path": "batched: classify; indexes of the faulty chunks of the host region and "
-                           "of the shadow pool, read once each, answering the check-only records; source-block "
-                           "segments and the persistent scan kernel for any record left; hipGraph replay",
+                   "mode": "check", "path": "batched: classify (marking the 64 KiB shadow steps the records read); "
+                           "indexes of the faulty chunks of those steps of the host region and of the shadow pool, "
+                           "read once each, answering the check-only records; source-block segments and the "
+                           "persistent scan kernel for any record left; hipGraph replay",
                    "tuning": tun},
         "transfers_per_s": round(T / (wall / args.steps), 1),
         "algorithmic_bytes_per_step": int(bytes_step),
@@ -662,8 +668,10 @@ def main():
     }
     if i_avg_ms is not None:
         # what the step reads of the shadow when the indexes answer the batch:
-        # the pool's V bytes and the host region's V and A bytes, once each
-        sb = int(pool_bytes + w.host.length + (w.host.length + 7) // 8)
+        # the V bytes of the pool steps its records read, and the host
+        # region's V and A bytes of the steps they read, once each
+        sb = int((host_read + pool_read) // args.steps)
+        result["pool_bytes_read_per_pass"] = int(pass_bytes)
         result["shadow_bytes_read_per_step"] = sb
         result["shadow_read_GBps"] = round(sb / (wall / args.steps) / 1e9, 1)
 
@@ -716,7 +724,7 @@ def main():
         result["probe_l2_read"] = l2
         log(f"[bench] probe read {rd:.0f} GB/s, copy {cp:.0f} GB/s (read + write), L2-resident read {l2}")
 
-    result["roofline"] = roofline(tun, args.config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step,
+    result["roofline"] = roofline(tun, args.config, k_avg_ms, i_avg_ms, pass_bytes, bytes_step,
                                   result.get("probe_l2_read", {}).get("GBps"))
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline_legs(w, hv, ha, got, args.cpu_bytes, args.cpu_bytes_one)

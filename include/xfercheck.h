@@ -190,11 +190,12 @@ int shadow_ptr(cg_ctx *ctx, uint64_t dev_addr, uint8_t **v_dev);
  *   either way; CG_KEEP_ORDER works the batch in the given order.
  *   A check without propagation of more than 256 records (not CG_PLAIN or
  *   CG_KEEP_ORDER) that reads its shadow spaces heavily (at least 4 bytes of
- *   the host region, or of the shadow pool, per byte of it) reads each such
- *   space once into an index of its faulty 16-byte chunks and answers its
- *   records from it, with the same verdicts (the first such call on a
- *   stream allocates the index space: about 170 MB plus one byte per 16 KiB
- *   of the pool).
+ *   the host region, or of the shadow pool, per byte of it) reads the 64 KiB
+ *   steps of each such space that its records read, once, into an index of
+ *   their faulty 16-byte chunks and answers its records from it, with the
+ *   same verdicts (the first such call on a stream allocates the index
+ *   space: about 180 MB plus 9 bytes per 64 KiB of the pool).  A host region
+ *   above 64 GiB is not indexed.
  * With CG_PROPAGATE every valid destination byte receives the source's V
  * byte, or 0xFF where the source byte is not valid; overlapping D2D records
  * are not propagated.  All records read the shadow as it was before the
@@ -421,9 +422,14 @@ int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
  * As cg_kernel_ms, for the counting pass of the shadow pool's index (one
  * launch per large check-only batch that builds the index, bracketed by
  * events while timing is on): its summed time in ms since the last call, and
- * the number of timed passes.  Errors: CG_EINVAL, CG_EHIP.
+ * the number of timed passes.  When bytes is not NULL (2 entries), it
+ * receives the shadow bytes the counting passes of the indexes read since the
+ * last such call, timed or not: [0] of the host region (V and A bits), [1] of
+ * the shadow pool (V); that count then restarts.  A pass reads the 64 KiB
+ * steps of V that the batch's records read, not the whole space.  With bytes,
+ * the call waits for the device.  Errors: CG_EINVAL, CG_EHIP.
  */
-int cg_index_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
+int cg_index_ms(cg_ctx *ctx, double *ms, uint64_t *launches, uint64_t *bytes);
 
 /* ---- bandwidth probes (roofline reference) -------------------------------- */
 /* Read `bytes` (multiple of 16) at dev and fold them into *sink_dev (u64). */

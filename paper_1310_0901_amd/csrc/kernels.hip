@@ -756,6 +756,47 @@ __device__ uint64_t classify_rec(const cg_transfer &r, uint32_t mode, const DevS
     return units;
 }
 
+// Marks the steps (2^16 bytes of V) of shadow space k that hold its bytes
+// [lo, hi), for that index's counting pass: bytes before the first 16-aligned
+// step, then 16 marks per store.
+__device__ __forceinline__ void mark_steps(const BatchArgs &a, int k, uint64_t lo, uint64_t hi)
+{
+    uint8_t *m = a.index_mark[k];
+    if (!m || hi <= lo) return;
+    uint64_t s = lo >> kIdxStepShift, e = ((hi - 1) >> kIdxStepShift) + 1;
+    if (e > a.mark_cap[k]) e = a.mark_cap[k];
+    for (; s < e && (s & 15u); ++s) m[s] = 1;
+    for (; s + 16 <= e; s += 16) *reinterpret_cast<uint4 *>(m + s) = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    for (; s < e; ++s) m[s] = 1;
+}
+
+// space offsets of a descriptor's byte 0: of its source (host region or pool)
+// and of a host destination
+__device__ __forceinline__ uint64_t src_space_off(const Desc &ds, const DevState &st)
+{
+    const uint32_t phi = (ds.ctl >> CTL_PHI_SHIFT) & 15u;
+    return (ds.ctl & CTL_SRC_HOST) ? (uint64_t)(ds.a_src + (int64_t)phi) : ds.src_sh + phi - st.pool;
+}
+
+__device__ __forceinline__ uint64_t dst_space_off(const Desc &ds)
+{
+    return (uint64_t)(ds.a_dst + (int64_t)((ds.ctl >> CTL_PSI_SHIFT) & 15u));
+}
+
+// the steps a transfer's index answer reads: its valid source bytes, and a
+// host destination's valid bytes
+__device__ __forceinline__ void mark_desc(const BatchArgs &a, const DevState &st, const Desc &ds)
+{
+    if (ds.v_hi > ds.v_lo) {
+        const uint64_t o = src_space_off(ds, st);
+        mark_steps(a, (ds.ctl & CTL_SRC_HOST) ? 0 : 1, o + (uint64_t)ds.v_lo, o + (uint64_t)ds.v_hi);
+    }
+    if ((ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo) {
+        const uint64_t o = dst_space_off(ds);
+        mark_steps(a, 0, o + (uint64_t)ds.d_lo, o + (uint64_t)ds.d_hi);
+    }
+}
+
 // Record t of a batch: its descriptor and work weight, and its verdict's
 // range-derived fields; returns its number of units (and in sp[0], sp[1] its
 // valid bytes in the host region and in the shadow pool, when sp is given).
@@ -773,6 +814,7 @@ __device__ uint64_t classify_one(const BatchArgs &a, const DevState &st, uint64_
         const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? (uint64_t)(ds.d_hi - ds.d_lo) : 0;
         sp[0] = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst;
         sp[1] = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
+        mark_desc(a, st, ds);
     }
     a.desc[t] = ds;
     a.weight[t] = units;
@@ -895,6 +937,22 @@ __device__ __forceinline__ cg_transfer row_record(const Pitch &P, uint64_t r)
     return cg_transfer{P.src + r * P.spitch, P.dst + r * P.dpitch, P.width, P.kind, 0u};
 }
 
+// The steps the index answer of a record whose rows follow row 0 reads: on
+// each side, the span from the first row's start to the last row's end when
+// it is at most 4 times the rows' bytes (plus 4 steps); a sparser side asks
+// for every step of its space instead, so that marking stays within a
+// fraction of the bytes the rows hold.
+__device__ __forceinline__ void mark_rows(const BatchArgs &a, const DevState &st, const Desc &ds, const Pitch &P)
+{
+    auto side = [&](int k, uint64_t o, uint64_t q) {
+        const uint64_t span = (P.rows - 1) * q + P.width;
+        if (span / 4 <= P.rows * P.width + (4ull << kIdxStepShift)) mark_steps(a, k, o, o + span);
+        else a.index_bytes[k][kIdxAll] = 1;
+    };
+    if (ds.v_hi > ds.v_lo) side((ds.ctl & CTL_SRC_HOST) ? 0 : 1, src_space_off(ds, st), P.spitch);
+    if ((ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo) side(0, dst_space_off(ds), P.dpitch);
+}
+
 // One lane per pitched 2D record: row 0 looked up and classified (its
 // descriptor is the position's), whether every row follows from it, the
 // units (rows * upr) and the verdict before any row is worked: row 0's when
@@ -970,6 +1028,8 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
                 const uint64_t hb = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst, pb = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
                 if (hb) atomicAdd((unsigned long long *)a.index_bytes[0], (unsigned long long)hb);
                 if (pb) atomicAdd((unsigned long long *)a.index_bytes[1], (unsigned long long)pb);
+                if (P.uniform == kRowsContig) mark_desc(a, st, ds);
+                else mark_rows(a, st, ds, P);
             }
             v = uniform ? v0 : cg_verdict{0u, 0u, NONE, 0, v0.avail};
             if (rows < R2.rows) v.flags |= CG_ROWS_LIMIT;

@@ -208,6 +208,7 @@ struct cg_ctx {
     std::vector<TimingPair> tpairs;   // pairs of the last check
     std::vector<TimingPair> ipairs;   // pairs around the pool index's counting pass
     size_t iused = 0;
+    uint64_t *idx_read = nullptr;     // device: bytes the index counting passes read, [0] host region, [1] pool
     size_t tused = 0;
     std::string last_error;
 };
@@ -408,7 +409,8 @@ void free_seg(Workspace *w)
     w->srec = w->perm = nullptr;
     w->seg_cap = 0;
     for (ShadowIndex *x : {&w->hidx, &w->pidx}) {
-        void *hs[] = {x->uchunk, x->umask, x->ucum, x->nchunk, x->nmask, x->bcnt, x->sflag, x->state};
+        void *hs[] = {x->uchunk, x->umask, x->ucum, x->nchunk, x->nmask, x->bcnt, x->sflag, x->state,
+                      x->smark, x->slist, x->mcnt};
         for (void *p : hs)
             if (p) (void)hipFree(p);
         *x = ShadowIndex{};
@@ -539,6 +541,7 @@ hipError_t prepare_stage(const BatchArgs &a, const LaunchShape &sh, hipStream_t 
         if (idx && (e = launch_sidx_reset(*sp->hidx, *sp->pidx, s)) != hipSuccess) return e;
         if ((e = launch_classify(sp->ar, s)) != hipSuccess) return e;
         if (idx && (e = launch_sidx_build(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
+        if (idx && (e = launch_sidx_marks(*sp->pidx, sp->ar.st, s)) != hipSuccess) return e;
         return hipSuccess;
     }
     if (stage == 1) return idx ? launch_sidx_count(*sp->pidx, sp->ar.st, s) : hipSuccess;
@@ -758,6 +761,10 @@ int reserve_segments(cg_ctx *c, Workspace *w, uint64_t count, hipStream_t s)
 int reserve_sidx(cg_ctx *c, Workspace *w)
 {
     if (w->pidx.state) return CG_OK;
+    if (!c->idx_read) {
+        HIPTRY(c, hipMalloc(&c->idx_read, 2 * 8));
+        HIPTRY(c, hipMemset(c->idx_read, 0, 2 * 8));
+    }
     for (uint32_t space : {0u, 1u}) {
         ShadowIndex &x = space ? w->pidx : w->hidx;
         x.space = space;
@@ -770,14 +777,31 @@ int reserve_sidx(cg_ctx *c, Workspace *w)
         HIPTRY(c, hipMalloc(&x.nchunk, x.cap_n * 8));
         HIPTRY(c, hipMalloc(&x.nmask, x.cap_n * 4));
         HIPTRY(c, hipMalloc(&x.bcnt, 6ull * x.grid * 8));
-        // a flag per step of 4,096 chunks (64 KiB) of the pool, or of a host
-        // region of up to 64 GiB; a larger space is filled without them
+        // a mark, a list entry and 4 flags per step of 4,096 chunks (64 KiB) of
+        // the pool, or of a host region of up to 64 GiB; a larger one is not indexed
         const uint64_t len = space ? c->palloc->capacity() : std::max<uint64_t>(c->region.hl, 64ull << 30);
-        x.steps_cap = (len >> 16) + x.grid;
+        x.steps_cap = (len >> kIdxStepShift) + 1;
+        x.mark_grid = (uint32_t)((x.steps_cap + 16383) / 16384);
         HIPTRY(c, hipMalloc(&x.sflag, 4 * x.steps_cap));
-        HIPTRY(c, hipMalloc(&x.state, 4 * 8));
+        HIPTRY(c, hipMalloc(&x.slist, 4 * x.steps_cap));
+        HIPTRY(c, hipMalloc(&x.smark, 16384ull * x.mark_grid));
+        HIPTRY(c, hipMemset(x.smark, 0, 16384ull * x.mark_grid));   // the marking kernels clear what they read
+        HIPTRY(c, hipMalloc(&x.mcnt, 8ull * x.mark_grid));
+        HIPTRY(c, hipMalloc(&x.state, 8 * 8));
+        x.read = c->idx_read + space;
     }
     return CG_OK;
+}
+
+// a batch's classify kernels feed the workspace's indexes: bytes per space and step marks
+void set_index_args(BatchArgs &a, const Workspace *w)
+{
+    const ShadowIndex *xs[2] = {&w->hidx, &w->pidx};
+    for (int k = 0; k < 2; ++k) {
+        a.index_bytes[k] = xs[k]->state;
+        a.index_mark[k] = xs[k]->smark;
+        a.mark_cap[k] = xs[k]->steps_cap;
+    }
 }
 
 // Blocks per record of a small batch, at most: `hint`, or else about 8
@@ -848,8 +872,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         }
         plan.hidx = &w->hidx;
         plan.pidx = &w->pidx;
-        plan.ar.index_bytes[0] = w->hidx.state;
-        plan.ar.index_bytes[1] = w->pidx.state;
+        set_index_args(plan.ar, w);
         if (!seg) a = plan.ar;
         sp = &plan;
     }
@@ -1138,10 +1161,12 @@ int cg_destroy(cg_ctx *c)
         (void)hipFree(w.rowv);
         if (w.h_total) (void)hipHostFree(w.h_total);
     }
-    for (auto &p : c->tpairs) {
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
-    }
+    for (auto *v : {&c->tpairs, &c->ipairs})
+        for (auto &p : *v) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    (void)hipFree(c->idx_read);
     if (c->s) (void)hipStreamDestroy(c->s);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     (void)hipFree(c->pool);
@@ -1394,8 +1419,7 @@ int check_2d_pitched(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, c
         rc = reserve_sidx(c, w);
         if (rc) return rc;
         w->hidx.ratio = w->pidx.ratio = c->shadow_index == 2 ? 0u : c->sidx_ratio;
-        a.index_bytes[0] = w->hidx.state;
-        a.index_bytes[1] = w->pidx.state;
+        set_index_args(a, w);
         HIPTRY(c, launch_sidx_reset(w->hidx, w->pidx, s));
     }
     HIPTRY(c, launch_classify_2d(a, recs_dev, w->pitch, s));
@@ -1612,7 +1636,7 @@ int cg_kernel_ms(cg_ctx *c, double *ms, uint64_t *launches)
     return CG_OK;
 }
 
-int cg_index_ms(cg_ctx *c, double *ms, uint64_t *launches)
+int cg_index_ms(cg_ctx *c, double *ms, uint64_t *launches, uint64_t *bytes)
 {
     if (!c || !ms) return CG_EINVAL;
     double sum = 0;
@@ -1625,6 +1649,15 @@ int cg_index_ms(cg_ctx *c, double *ms, uint64_t *launches)
     *ms = sum;
     if (launches) *launches = c->iused;
     c->iused = 0;
+    if (bytes) {
+        bytes[0] = bytes[1] = 0;
+        if (c->idx_read) {
+            if (hipSetDevice(c->dev) != hipSuccess) return fail(c, CG_EHIP, "hipSetDevice");
+            HIPTRY(c, hipDeviceSynchronize());
+            HIPTRY(c, hipMemcpy(bytes, c->idx_read, 2 * 8, hipMemcpyDeviceToHost));
+            HIPTRY(c, hipMemset(c->idx_read, 0, 2 * 8));
+        }
+    }
     return CG_OK;
 }
 

@@ -20,10 +20,13 @@
 // other is scanned as before.  The facts are exact, so verdicts do not depend
 // on the choice.
 //
-//   k_sidx_reset   one lane: both states = {0, 0, 0, 0}
-//   (k_classify adds the batch's valid bytes per space to state[0])
-//   k_sidx_count   block b over its contiguous range of chunks: list entries
-//                  and undefined bytes
+//   k_sidx_reset   one lane: both states = {0, ...}
+//   (k_classify adds the batch's valid bytes per space to state[0], and
+//   marks the steps of 4,096 chunks that its records read)
+//   k_sidx_mark_count, k_sidx_mark_list
+//                  the marked steps as an ascending list (marks cleared)
+//   k_sidx_count   block b over its contiguous slice of the listed steps:
+//                  list entries and undefined bytes
 //   k_sidx_scan    one block: the blocks' offsets, the totals, validity
 //   k_sidx_fill    block b writes its entries in chunk order (a block with
 //                  none returns at once)
@@ -46,6 +49,9 @@ template <typename T> using gcptr = const __attribute__((address_space(1))) T *;
 constexpr int kT = 256;
 constexpr uint32_t kPer = 16;                          // chunks per thread per step
 constexpr uint64_t kStep = (uint64_t)kT * kPer;        // chunks per block per step
+static_assert(kStep * 16 == (1ull << kIdxStepShift), "a step is the marks' unit");
+constexpr uint32_t kMarkT = 1024;                      // threads of the marking kernels
+constexpr uint64_t kMarkBlock = 16ull * kMarkT;        // marks per block of them (16 per thread)
 
 // one bit per non-zero byte of w (SWAR: no carry crosses a byte)
 __device__ __forceinline__ uint32_t nz4(uint32_t w)
@@ -77,26 +83,22 @@ __device__ __forceinline__ Space space_of(const ShadowIndex &x, const DevState *
 
 __device__ __forceinline__ uint64_t space_chunks(const Space &S) { return (S.len + 15) >> 4; }
 
-// the index is built for this batch: a space, and enough of the batch's bytes in it
+__device__ __forceinline__ uint64_t space_steps(const Space &S) { return (space_chunks(S) + kStep - 1) / kStep; }
+
+// the index is built for this batch: a space whose steps fit the step list,
+// and enough of the batch's bytes in it
 __device__ __forceinline__ bool worth(const ShadowIndex &x, const Space &S)
 {
-    return S.len > 0 && (x.ratio == 0 || x.state[0] / x.ratio >= S.len);
+    return S.len > 0 && space_steps(S) <= x.steps_cap && (x.ratio == 0 || x.state[0] / x.ratio >= S.len);
 }
 
-// steps of kStep chunks per block
-__device__ __forceinline__ uint64_t block_steps(const Space &S, uint32_t grid)
+// positions [p0, p1) of the step list that block b works
+__device__ __forceinline__ void block_slice(const ShadowIndex &x, uint32_t b, uint64_t *p0, uint64_t *p1)
 {
-    const uint64_t n = space_chunks(S);
-    return (n + (uint64_t)grid * kStep - 1) / ((uint64_t)grid * kStep);
-}
-
-// chunks [lo, hi) of block b
-__device__ __forceinline__ void block_range(const Space &S, uint32_t grid, uint32_t b, uint64_t *lo, uint64_t *hi)
-{
-    const uint64_t n = space_chunks(S);
-    const uint64_t span = block_steps(S, grid) * kStep;
-    *lo = (uint64_t)b * span < n ? (uint64_t)b * span : n;
-    *hi = *lo + span < n ? *lo + span : n;
+    const uint64_t m = x.state[kIdxSteps];
+    const uint64_t per = (m + x.grid - 1) / x.grid;
+    *p0 = (uint64_t)b * per < m ? (uint64_t)b * per : m;
+    *p1 = *p0 + per < m ? *p0 + per : m;
 }
 
 // undefined (V != 0, A = 1) and unaddressable (A = 0) bytes of chunk c < the
@@ -140,79 +142,169 @@ __device__ void block_scan3(uint64_t x[3], uint64_t ex[3], uint64_t tot[3])
 
 __global__ void k_sidx_reset(ShadowIndex h, ShadowIndex p)
 {
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 8; ++k) {
         h.state[k] = 0;
         p.state[k] = 0;
     }
 }
 
+// The marks of steps m0 .. m0 + 15 as bits, for a space of `steps` steps
+// (none when the index is not built; every step of the space when the batch
+// asked for all of them).
+__device__ __forceinline__ uint32_t marked16(const ShadowIndex &x, uint64_t m0, uint64_t steps, bool all, u32x4 v)
+{
+    if (m0 >= steps) return 0;
+    const uint32_t live = steps - m0 >= 16 ? 0xFFFFu : (1u << (uint32_t)(steps - m0)) - 1u;
+    return (all ? 0xFFFFu : nz16(v)) & live;
+}
+
+__device__ __forceinline__ uint64_t block_sum(uint64_t v)
+{
+    __shared__ uint64_t ws[kMarkT / 64];
+    for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+    if ((threadIdx.x & 63u) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t all = 0;
+    for (uint32_t q = 0; q < kMarkT / 64; ++q) all += ws[q];
+    __syncthreads();   // ws is reused by the next call
+    return all;
+}
+
+__device__ __forceinline__ u32x4 load_marks(const ShadowIndex &x, uint64_t m0)
+{
+    return *reinterpret_cast<const u32x4 *>(x.smark + m0);
+}
+
+// marked steps among block b's kMarkBlock marks
+__global__ void __launch_bounds__(kMarkT) k_sidx_mark_count(ShadowIndex x, const DevState *stp)
+{
+    const Space S = space_of(x, stp);
+    const uint64_t steps = worth(x, S) ? space_steps(S) : 0;
+    const uint64_t m0 = (uint64_t)blockIdx.x * kMarkBlock + 16ull * threadIdx.x;
+    const bool all = x.state[kIdxAll] != 0;
+    const uint32_t bits = m0 < steps ? marked16(x, m0, steps, all, all ? u32x4{0, 0, 0, 0} : load_marks(x, m0)) : 0u;
+    const uint64_t n = block_sum((uint64_t)__builtin_popcount(bits));
+    if (threadIdx.x == 0) x.mcnt[blockIdx.x] = n;
+}
+
+// Block b lists its marked steps after those of the blocks before it and
+// clears its marks (all of them, listed or not); block 0 writes the list's
+// length.  Each block adds the bytes the counting pass will read for its steps.
+__global__ void __launch_bounds__(kMarkT) k_sidx_mark_list(ShadowIndex x, const DevState *stp)
+{
+    __shared__ uint64_t ws[kMarkT / 64];
+    const Space S = space_of(x, stp);
+    const uint64_t steps = worth(x, S) ? space_steps(S) : 0;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    uint64_t before = 0, total = 0;
+    for (uint32_t k = tid; k < gridDim.x; k += kMarkT) {
+        const uint64_t c = x.mcnt[k];
+        total += c;
+        before += k < blockIdx.x ? c : 0;
+    }
+    before = block_sum(before);
+    total = block_sum(total);
+    const uint64_t m0 = (uint64_t)blockIdx.x * kMarkBlock + 16ull * tid;
+    const u32x4 v = load_marks(x, m0);
+    const uint32_t bits = marked16(x, m0, steps, x.state[kIdxAll] != 0, v);
+    if (v.x | v.y | v.z | v.w) *reinterpret_cast<u32x4 *>(x.smark + m0) = u32x4{0, 0, 0, 0};
+    // block exclusive scan of the threads' marked steps
+    const uint64_t n = (uint64_t)__builtin_popcount(bits);
+    uint64_t inc = n;
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63u) ws[w] = inc;
+    __syncthreads();
+    uint64_t off = before;
+    for (uint32_t q = 0; q < w; ++q) off += ws[q];
+    off += inc - n;
+    // the chunks the counting pass reads for these steps (the space's last step may be short)
+    const uint64_t nch = space_chunks(S);
+    uint64_t chunks = 0;
+    for (uint32_t b = bits; b; b &= b - 1u) {
+        const uint64_t st = m0 + (uint64_t)__builtin_ctz(b);
+        x.slist[off++] = (uint32_t)st;
+        chunks += st * kStep + kStep <= nch ? kStep : nch - st * kStep;
+    }
+    chunks = block_sum(chunks);
+    if (tid == 0) {
+        if (chunks) atomicAdd((unsigned long long *)x.read, (unsigned long long)(chunks * (x.space == 0 ? 18u : 16u)));
+        if (blockIdx.x == 0) x.state[kIdxSteps] = total;
+    }
+}
+
 // (one instance per space, so that a trace tells them apart).  A step's 16
 // chunks per thread are loaded back to back (non-temporal: each byte is read
-// once), then examined; each wave flags the steps where it met a faulty
-// chunk, so that the fill reads only those.
+// once), then examined; each wave flags the listed steps where it met a
+// faulty chunk, so that the fill reads only those.  The steps of the block's
+// slice are read from the list 64 at a time, one per lane.
 template <uint32_t SPACE>
 __global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState *stp)
 {
     const Space S = space_of(SPACE, stp);
     if (!worth(x, S)) return;
-    uint64_t lo, hi;
-    block_range(S, x.grid, blockIdx.x, &lo, &hi);
-    const uint64_t spb = block_steps(S, x.grid);
-    const bool flags = spb * x.grid <= x.steps_cap;
+    uint64_t p0, p1;
+    block_slice(x, blockIdx.x, &p0, &p1);
+    const uint64_t nch = space_chunks(S);
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const gcptr<u32x4> vp = reinterpret_cast<gcptr<u32x4>>(reinterpret_cast<uint64_t>(S.v));
     uint64_t c3[3] = {0, 0, 0};
-    uint64_t step = (uint64_t)blockIdx.x * spb;
-    for (uint64_t base = lo; base < hi; base += kStep, ++step) {
-        u32x4 v[kPer];
-        uint32_t a[kPer];
-        if (base + kStep <= hi) {
+    for (uint64_t g = p0; g < p1; g += 64) {
+        const uint32_t mine = g + lane < p1 ? x.slist[g + lane] : 0u;
+        const uint32_t ng = p1 - g < 64 ? (uint32_t)(p1 - g) : 64u;
+        for (uint32_t k = 0; k < ng; ++k) {
+            const uint64_t base = (uint64_t)__builtin_amdgcn_readlane((int)mine, (int)k) * kStep;
+            const uint64_t hi = base + kStep < nch ? base + kStep : nch;
+            u32x4 v[kPer];
+            uint32_t a[kPer];
+            if (base + kStep <= hi) {
 #pragma unroll
-            for (uint32_t j = 0; j < kPer; ++j) {
-                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-                v[j] = __builtin_nontemporal_load(vp + c);
-                a[j] = SPACE == 0 ? (uint32_t)S.a16[c] : 0xFFFFu;
-            }
-        } else {
-#pragma unroll
-            for (uint32_t j = 0; j < kPer; ++j) {
-                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-                v[j] = u32x4{0u, 0u, 0u, 0u};
-                a[j] = 0xFFFFu;
-                if (c < hi) {
+                for (uint32_t j = 0; j < kPer; ++j) {
+                    const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
                     v[j] = __builtin_nontemporal_load(vp + c);
-                    if (SPACE == 0) a[j] = S.a16[c];
+                    a[j] = SPACE == 0 ? (uint32_t)S.a16[c] : 0xFFFFu;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t j = 0; j < kPer; ++j) {
+                    const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+                    v[j] = u32x4{0u, 0u, 0u, 0u};
+                    a[j] = 0xFFFFu;
+                    if (c < hi) {
+                        v[j] = __builtin_nontemporal_load(vp + c);
+                        if (SPACE == 0) a[j] = S.a16[c];
+                    }
                 }
             }
-        }
-        // almost every chunk is clean (V all 0, A all 1): the lane's step is
-        // examined chunk by chunk only when it is not, or when it holds the
-        // space's end (bytes past it must not count)
-        uint32_t orv = 0, anda = 0xFFFFu;
-#pragma unroll
-        for (uint32_t j = 0; j < kPer; ++j) {
-            orv |= v[j].x | v[j].y | v[j].z | v[j].w;
-            anda &= a[j];
-        }
-        const bool edge = base + kStep > hi || ((S.len & 15u) && base + kStep >= space_chunks(S));
-        uint32_t any = 0;
-        if (orv != 0u || anda != 0xFFFFu || edge) {
+            // almost every chunk is clean (V all 0, A all 1): the lane's step is
+            // examined chunk by chunk only when it is not, or when it holds the
+            // space's end (bytes past it must not count)
+            uint32_t orv = 0, anda = 0xFFFFu;
 #pragma unroll
             for (uint32_t j = 0; j < kPer; ++j) {
-                const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-                // bytes past the space's end (its last chunk, or none) are clear
-                const uint64_t left = c < hi ? S.len - 16 * c : 0;
-                const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
-                const uint32_t und = nz16(v[j]) & a[j] & live, un = ~a[j] & live;
-                c3[0] += und ? 1u : 0u;
-                c3[1] += un ? 1u : 0u;
-                c3[2] += (uint32_t)__builtin_popcount(und);
-                any |= und | un;
+                orv |= v[j].x | v[j].y | v[j].z | v[j].w;
+                anda &= a[j];
             }
-        }
-        if (flags) {
+            const bool edge = base + kStep > hi || ((S.len & 15u) && base + kStep >= nch);
+            uint32_t any = 0;
+            if (orv != 0u || anda != 0xFFFFu || edge) {
+#pragma unroll
+                for (uint32_t j = 0; j < kPer; ++j) {
+                    const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
+                    // bytes past the space's end (its last chunk, or none) are clear
+                    const uint64_t left = c < hi ? S.len - 16 * c : 0;
+                    const uint32_t live = left < 16 ? (1u << left) - 1u : 0xFFFFu;
+                    const uint32_t und = nz16(v[j]) & a[j] & live, un = ~a[j] & live;
+                    c3[0] += und ? 1u : 0u;
+                    c3[1] += un ? 1u : 0u;
+                    c3[2] += (uint32_t)__builtin_popcount(und);
+                    any |= und | un;
+                }
+            }
             const uint64_t seen = __ballot(any != 0);
-            if (lane == 0) x.sflag[4 * step + wave] = seen ? 1u : 0u;
+            if (lane == 0) x.sflag[4 * (g + k) + wave] = seen ? 1u : 0u;
         }
     }
     uint64_t ex[3], tot[3];
@@ -315,7 +407,7 @@ __device__ __forceinline__ void fill_step(const ShadowIndex &x, const Space &S, 
     op += tot[2];
 }
 
-// With the steps' flags, the block reads 256 of them at a time, one per
+// The block reads the flags of its slice 256 steps at a time, one per
 // thread, lists the flagged ones in order, and fills only those.
 __global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState *stp)
 {
@@ -325,21 +417,13 @@ __global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState 
     const Space S = space_of(x, stp);
     const uint32_t b = blockIdx.x;
     if (x.bcnt[3 * b] == 0 && x.bcnt[3 * b + 1] == 0) return;
-    uint64_t lo, hi;
-    block_range(S, x.grid, b, &lo, &hi);
+    uint64_t p0, p1;
+    block_slice(x, b, &p0, &p1);
+    const uint64_t nch = space_chunks(S);
     uint64_t ou = x.bcnt[3 * (x.grid + b)], on = x.bcnt[3 * (x.grid + b) + 1], op = x.bcnt[3 * (x.grid + b) + 2];
-    const uint64_t spb = block_steps(S, x.grid);
-    if (spb * x.grid > x.steps_cap) {
-        // no flags: every step of the range
-        const uint64_t end_u = ou + x.bcnt[3 * b], end_n = on + x.bcnt[3 * b + 1];
-        for (uint64_t base = lo; base < hi && (ou < end_u || on < end_n); base += kStep) fill_step(x, S, base, hi, ou, on, op);
-        return;
-    }
-    const uint64_t nsteps = lo < hi ? (hi - lo + kStep - 1) / kStep : 0;
-    const uint64_t step0 = (uint64_t)b * spb;
-    for (uint64_t g0 = 0; g0 < nsteps; g0 += kT) {
+    for (uint64_t g0 = p0; g0 < p1; g0 += kT) {
         const uint64_t g = g0 + threadIdx.x;
-        const uint32_t f = g < nsteps && *reinterpret_cast<const uint32_t *>(x.sflag + 4 * (step0 + g)) != 0;
+        const uint32_t f = g < p1 && *reinterpret_cast<const uint32_t *>(x.sflag + 4 * g) != 0;
         uint64_t v[3] = {f, 0, 0};
         uint64_t ex[3], tot[3];
         block_scan3(v, ex, tot);
@@ -347,7 +431,10 @@ __global__ void __launch_bounds__(kT) k_sidx_fill(ShadowIndex x, const DevState 
         if (threadIdx.x == 0) nlist = (uint32_t)tot[0];
         __syncthreads();
         const uint32_t n = nlist;
-        for (uint32_t k = 0; k < n; ++k) fill_step(x, S, lo + (g0 + list[k]) * kStep, hi, ou, on, op);
+        for (uint32_t k = 0; k < n; ++k) {
+            const uint64_t base = (uint64_t)x.slist[g0 + list[k]] * kStep;
+            fill_step(x, S, base, base + kStep < nch ? base + kStep : nch, ou, on, op);
+        }
         __syncthreads();   // list and nlist are rewritten next
     }
 }
@@ -669,9 +756,17 @@ hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_sidx_marks(const ShadowIndex &x, const DevState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sidx_mark_count, dim3(x.mark_grid), dim3(kMarkT), 0, s, x, st);
+    hipLaunchKernelGGL(k_sidx_mark_list, dim3(x.mark_grid), dim3(kMarkT), 0, s, x, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s)
 {
-    const hipError_t e = launch_sidx_count(x, st, s);
+    hipError_t e = launch_sidx_marks(x, st, s);
+    if (e == hipSuccess) e = launch_sidx_count(x, st, s);
     return e != hipSuccess ? e : launch_sidx_finish(x, st, s);
 }
 

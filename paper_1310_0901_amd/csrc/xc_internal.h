@@ -144,6 +144,11 @@ struct BatchArgs {
     // destinations of device-to-host records), [1] in the shadow pool (device
     // sources); the indexes' cost test (shadowindex.hip)
     uint64_t *index_bytes[2];
+    // with index_bytes: per space, a byte per step of 4,096 chunks (64 KiB of
+    // V bytes), set to 1 for every step the batch's valid bytes fall in
+    // (mark_cap[k] steps), so that the index's counting pass reads only those
+    uint8_t *index_mark[2];
+    uint64_t mark_cap[2];
 };
 
 // Index of one shadow space's faulty 16-byte chunks for a check-only batch
@@ -153,9 +158,11 @@ struct BatchArgs {
 // its mask and the undefined bytes of all chunks before it, and every chunk
 // with an unaddressable byte (A = 0), in ascending order; a record's
 // findings in that space are then two searches per list instead of a scan
-// of its bytes.  Built by `grid` blocks, block b over a contiguous range of
-// chunks; state = {valid bytes of the batch in the space, index valid,
-// undefined-chunk entries, unaddressable-chunk entries}.
+// of its bytes.  Only the steps of 4,096 chunks that the batch's records
+// read are listed (marked by the classify kernels) and read; the list is cut
+// into `grid` contiguous slices, one per block.  state = {valid bytes of the
+// batch in the space, index valid, undefined-chunk entries,
+// unaddressable-chunk entries, steps listed, every step wanted, 0, 0}.
 struct ShadowIndex {
     uint64_t *uchunk;   // [cap_u + 1]: entry n_u holds ~0
     uint32_t *umask;    // [cap_u]
@@ -163,14 +170,23 @@ struct ShadowIndex {
     uint64_t *nchunk;   // [cap_n]
     uint32_t *nmask;    // [cap_n]
     uint64_t *bcnt;     // [6 * grid]: per block entries (u, n) and undefined bytes, then their offsets
-    uint64_t *state;    // [4]
-    uint8_t *sflag;     // [4 * steps_cap]: wave w of a block step (4,096 chunks) met list entries
-    uint64_t steps_cap;
+    uint64_t *state;    // [8]
+    uint8_t *sflag;     // [4 * steps_cap]: wave w of listed step i (4,096 chunks) met list entries
+    uint8_t *smark;     // [16384 * mark_grid]: steps the batch reads (set by the classify kernels)
+    uint32_t *slist;    // [steps_cap]: the steps listed, ascending
+    uint64_t *mcnt;     // [mark_grid]: marked steps per block of the marking kernels
+    uint64_t *read;     // bytes the counting passes read (V, and A for the host region), accumulated
+    uint64_t steps_cap; // steps of the largest space indexed (a larger one is not)
     uint64_t cap_u, cap_n;
     uint32_t grid;
+    uint32_t mark_grid;
     uint32_t space;     // 0 host region, 1 shadow pool
     uint32_t ratio;     // built when the batch's valid bytes in the space reach ratio * its length
 };
+
+// ShadowIndex::state slots beyond the first four
+constexpr int kIdxSteps = 4, kIdxAll = 5;
+constexpr uint64_t kIdxStepShift = 16;   // a step is 2^16 bytes of V (4,096 chunks)
 
 // Cutting a batch's records into source-block segments (segment.hip).
 // rdesc / wbsum come from k_classify run over the records in their given
@@ -232,7 +248,8 @@ hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
 // a valid index and take them out of the scan (units to 0, wbsum per
 // classify block adjusted)
 hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStream_t s);
-hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s);   // count + finish
+hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s);   // marks + count + finish
+hipError_t launch_sidx_marks(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,

@@ -107,7 +107,7 @@ _PROTOS = {
     "cg_autotune": (I32, [P, P, U64, P, U32, P, ctypes.c_char_p, ctypes.POINTER(cg_tuning)]),
     "cg_timing": (I32, [P, I32]),
     "cg_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double), PU64]),
-    "cg_index_ms": (I32, [P, ctypes.POINTER(ctypes.c_double), PU64]),
+    "cg_index_ms": (I32, [P, ctypes.POINTER(ctypes.c_double), PU64, P]),
     "cg_probe_read": (I32, [P, U64, P, P]),
     "cg_probe_copy": (I32, [P, P, U64, P]),
     "cg_probe_l2": (I32, [P, U64, U32, U32, P, P]),
@@ -294,9 +294,13 @@ def cg_kernel_ms(ctx):
 
 
 def cg_index_ms(ctx):
+    """(summed ms, timed passes, (host region bytes, pool bytes) read by the
+    counting passes) since the last call."""
     ms, n = ctypes.c_double(), ctypes.c_uint64()
-    _chk(ctx, lib().cg_index_ms(ctx, ctypes.byref(ms), ctypes.byref(n)), "cg_index_ms")
-    return ms.value, n.value
+    b = (ctypes.c_uint64 * 2)()
+    _chk(ctx, lib().cg_index_ms(ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.cast(b, ctypes.c_void_p)),
+         "cg_index_ms")
+    return ms.value, n.value, (b[0], b[1])
 
 
 def cg_probe_read(dev, nbytes, sink_dev, stream=0) -> None:

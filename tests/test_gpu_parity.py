@@ -385,6 +385,51 @@ def test_shadow_index_dense_worlds(X, H, world, monkeypatch):
         dw.close()
 
 
+@pytest.mark.parametrize("order", ["segments", "given-order"])
+def test_shadow_index_reads_marked_steps(X, H, order, monkeypatch):
+    """The indexes list and read only the 64 KiB steps of V that the batch's
+    records read: in a world dense with faults whose records each touch a
+    few of its steps, every verdict equals the oracle's, batch after batch
+    (each batch's marks are cleared for the next); a batch confined to one
+    allocation and one host window reads at most those steps (the byte counts
+    of cg_index_ms)."""
+    monkeypatch.setenv("XC_REORDER_MIN", "1" if order == "segments" else str(1 << 40))
+    monkeypatch.setenv("XC_SHADOW_INDEX", "2")
+    rng = np.random.default_rng(64)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=(4 << 20) + 5, nalloc=8, max_size=3 << 20, dens=0.02)
+    a = (rng.random(hl) > 1e-3).astype(np.uint8)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    o = util.oracle_for(w)
+    step = 1 << 16
+    dw = H.DeviceWorld(w)
+    try:
+        X.cg_index_ms(dw.ctx)
+        for k in range(3):
+            recs = util.random_records(rng, W.HOST_BASE, hl, bases, sizes, 1500, max_n=20_000)
+            util.assert_verdicts_equal(dw.check(recs), o.run(recs), f"{order} batch {k}")
+        _, _, (host_read, pool_read) = X.cg_index_ms(dw.ctx)
+        assert 0 < pool_read <= 3 * (int(sizes.sum()) + len(sizes) * step)
+        assert 0 < host_read <= 3 * (hl + step) * 18 // 16
+        # one allocation and one host window of 100 KiB
+        j = int(np.argmax(sizes))
+        x0 = int(rng.integers(0, hl - 100_000))
+        recs = np.zeros(1000, W.RECORD_DTYPE)
+        for i in range(recs.size):
+            n = int(rng.integers(1, 5000))
+            if i % 2:
+                recs[i] = (W.HOST_BASE + x0 + int(rng.integers(0, 100_000 - n)), int(bases[j]) +
+                           int(rng.integers(0, int(sizes[j]) - n)), n, X.CG_H2D, 0)
+            else:
+                recs[i] = (int(bases[j]) + int(rng.integers(0, int(sizes[j]) - n)),
+                           W.HOST_BASE + x0 + int(rng.integers(0, 100_000 - n)), n, X.CG_D2H, 0)
+        util.assert_verdicts_equal(dw.check(recs), o.run(recs), f"{order} confined batch")
+        _, _, (host_read, pool_read) = X.cg_index_ms(dw.ctx)
+        assert 0 < pool_read <= (int(sizes[j]) // step + 2) * step, (pool_read, int(sizes[j]))
+        assert 0 < host_read <= (100_000 // step + 2) * step * 18 // 16, host_read
+    finally:
+        dw.close()
+
+
 def test_shadow_index_after_frees(X, H, monkeypatch):
     """The indexes are rebuilt from the shadow as it is at each check: after
     frees, fresh allocations (one in a freed block's pool slot, whose bytes
