@@ -17,8 +17,9 @@
 // 16 * ceil(W / count), W the sum of the records' work weights (units, at
 // least 1).  A record of L source bytes spans at most L / B + 2 blocks, so a
 // batch has at most 3 * count segments: the positions the caller provides.
-// Records that read no source byte (or have no units) stay one segment, with
-// key 0.
+// Records with units that read no source byte stay one segment, with key 0;
+// records without units (nothing to scan: their verdicts are complete, as
+// for those the shadow indexes answered) have none.
 //
 //   k_seg_plan    one block: W, then log2 B
 //   k_seg_count   one lane per record: segments, block-local prefix
@@ -56,6 +57,7 @@ __device__ __forceinline__ uint64_t seg_a0(const Desc &d)
 
 __device__ __forceinline__ uint64_t seg_count(const Desc &d, uint32_t lb)
 {
+    if (d.units == 0) return 0;
     if (!seg_split(d)) return 1;
     const uint64_t a0 = seg_a0(d), a1 = a0 + 16u * (d.units - 1);
     return (a1 >> lb) - (a0 >> lb) + 1;
@@ -172,22 +174,30 @@ __global__ void __launch_bounds__(kT) k_seg_first(SegArgs g)
     if (r < g.count) g.first[r] += g.sbsum[blockIdx.x];
 }
 
+// The record holding segment q < ns: the last r with first[r] <= q (first[]
+// does not decrease, and a record without segments shares its first with the
+// records after it up to the next one that has some).
+__device__ __forceinline__ uint64_t seg_record(const SegArgs &g, uint64_t q)
+{
+    uint64_t lo = 0, hi = g.count - 1;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (g.first[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(kT) k_seg_keys(SegArgs g, uint64_t *keys, uint32_t *vals, uint64_t *parts)
 {
     __shared__ uint64_t part[kT / 64];
     const uint64_t ns = g.meta[0];
     const uint32_t lb = (uint32_t)g.meta[1];
     const uint64_t q = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    const uint64_t key0 = seg_key(g.rdesc[0], lb, 0, g.host_last);   // segment 0 is record 0's first
     uint64_t x = 0;
     if (q < ns) {
-        // the record holding segment q: the last r with first[r] <= q (every
-        // record has at least one segment, so first[] strictly increases)
-        uint64_t lo = 0, hi = g.count - 1;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi + 1) >> 1;
-            if (g.first[mid] <= q) lo = mid; else hi = mid - 1;
-        }
+        const uint64_t r0 = seg_record(g, 0);
+        const uint64_t key0 = seg_key(g.rdesc[r0], lb, 0, g.host_last);   // segment 0's
+        const uint64_t lo = seg_record(g, q);
         const uint64_t key = seg_key(g.rdesc[lo], lb, q - g.first[lo], g.host_last);
         keys[q] = key;
         vals[q] = (uint32_t)q;
@@ -229,14 +239,17 @@ __global__ void __launch_bounds__(kT) k_seg_layout(SegArgs g, const uint32_t *va
             host = g.host_last && seg_host(d);
             // the first host-source position (they sort last)
             if (host && (p == 0 || !seg_host(g.rdesc[g.srec[sorted[p - 1]]]))) g.meta[2] = p;
+            desc[p] = o;
+            perm[p] = r;
         }
-        desc[p] = o;
-        perm[p] = r;
+        // (the positions past the segments weigh 0: no unit reaches them, so
+        // their descriptor and record are never read)
         weight[p] = o.units;
-        // a segment weighs its units (at least 1); the empty positions past
-        // the segments, and with host_last the host-source ones (worked by
-        // k_host_lds), weigh 0, so no unit of the scan kernel reaches them
-        w = p < ns && !host ? (o.units ? o.units : 1) : 0;
+        // a segment weighs its units (at least 1: records without units have
+        // no segment); the empty positions past the segments, and with
+        // host_last the host-source ones (worked by k_host_lds), weigh 0, so
+        // no unit of the scan kernel reaches them
+        w = p < ns && !host ? o.units : 0;
     }
     uint64_t tot;
     const uint64_t ex = block_excl(w, &tot);
