@@ -590,7 +590,9 @@ int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, con
 int find_graph(cg_ctx *c, Workspace *w, const BatchArgs &a, const SegPlan *sp, const LaunchShape &sh,
                const cg_tuning &tun, bool split, hipStream_t s, GraphEntry **out)
 {
-    const uint32_t mode = (a.mode & 3u) | (a.perm ? 4u : 0u);
+    // (the segment keys' width follows the shadow's addresses, which a new
+    // host region may change)
+    const uint32_t mode = (a.mode & 3u) | (a.perm ? 4u : 0u) | (sp && sp->seg && sp->g.key_bytes == 8 ? 8u : 0u);
     for (auto &g : w->graphs)
         if (g.st == a.st && g.recs == a.recs && g.count == a.count && g.mode == mode && same_tuning(g.tun, tun) &&
             g.split == split && g.out == a.out) {
@@ -850,8 +852,13 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         plan.ar.ctl = nullptr;
         // check-only: the host-source segments sort last and are worked from LDS
         const bool host_last = c->host_lds && (mode & (CG_CHECK | CG_PROPAGATE)) == CG_CHECK;
+        // the segments' block indices (shadow address >> log2 B, B >= 2^seg_min_log2)
+        // fit 31 bits, and the keys 4 bytes, when the shadow's highest address does
+        const uint64_t top = std::max<uint64_t>((uint64_t)c->pool + c->palloc->capacity(),
+                                                (uint64_t)c->region.v + c->region.hl);
+        const uint32_t key_bytes = (top >> c->seg_min_log2) < (1ull << 31) ? 4u : 8u;
         plan.g = SegArgs{w->rdesc, count, npos, w->rbsum, w->sfirst, w->sbsum, w->srec, w->meta, c->seg_min_log2,
-                         host_last ? 1u : 0u};
+                         host_last ? 1u : 0u, key_bytes};
         plan.sort = &w->sort;
         plan.seg = true;
         a.perm = w->perm;

@@ -66,11 +66,13 @@ __device__ __forceinline__ uint64_t seg_count(const Desc &d, uint32_t lb)
 // a segment of a record whose source is the host region
 __device__ __forceinline__ bool seg_host(const Desc &d) { return seg_split(d) && (d.ctl & CTL_SRC_HOST); }
 
-// the block of segment j; with host_last, host-source segments after all others
-__device__ __forceinline__ uint64_t seg_key(const Desc &d, uint32_t lb, uint64_t j, uint32_t host_last)
+// the block of segment j; with host_last, host-source segments after all
+// others (the key's top bit: bit 31 of 4-byte keys, else bit 63)
+__device__ __forceinline__ uint64_t seg_key(const SegArgs &g, const Desc &d, uint32_t lb, uint64_t j)
 {
     if (!seg_split(d)) return 0ull;
-    return ((seg_a0(d) >> lb) + j) | (host_last && (d.ctl & CTL_SRC_HOST) ? 1ull << 63 : 0ull);
+    const uint64_t top = g.key_bytes == 4 ? 1ull << 31 : 1ull << 63;
+    return ((seg_a0(d) >> lb) + j) | (g.host_last && (d.ctl & CTL_SRC_HOST) ? top : 0ull);
 }
 
 // units [u0, u1) of segment j
@@ -196,9 +198,9 @@ __global__ void __launch_bounds__(kT) k_seg_keys(SegArgs g, uint64_t *keys, uint
     uint64_t x = 0;
     if (q < ns) {
         const uint64_t r0 = seg_record(g, 0);
-        const uint64_t key0 = seg_key(g.rdesc[r0], lb, 0, g.host_last);   // segment 0's
+        const uint64_t key0 = seg_key(g, g.rdesc[r0], lb, 0);   // segment 0's
         const uint64_t lo = seg_record(g, q);
-        const uint64_t key = seg_key(g.rdesc[lo], lb, q - g.first[lo], g.host_last);
+        const uint64_t key = seg_key(g, g.rdesc[lo], lb, q - g.first[lo]);
         keys[q] = key;
         vals[q] = (uint32_t)q;
         g.srec[q] = (uint32_t)lo;
@@ -271,7 +273,7 @@ hipError_t launch_segments(const SegArgs &g, SortWs &sort, const BatchArgs &ap, 
     hipLaunchKernelGGL(k_seg_keys, dim3((uint32_t)nbp), dim3(kT), 0, s, g, sort.keys[0], sort.vals[0], sort.parts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = sort_pairs(sort, g.npos, s, g.meta)) != hipSuccess) return e;
+    if ((e = sort_pairs(sort, g.npos, s, g.meta, (int)g.key_bytes)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_layout, dim3((uint32_t)nbp), dim3(kT), 0, s, g, sort.vals[0], sort.vals[1], sort.mask,
                        ap.desc, perm, ap.weight, ap.local, ap.bsum);
     return hipGetLastError();

@@ -202,6 +202,7 @@ struct SegArgs {
     uint64_t *meta;         // [0] segments, [1] log2 of the block size, [2] first host-source position
     uint32_t min_log2;      // smallest block size, log2
     uint32_t host_last;     // host-source segments sort after the others and weigh 0: k_host_lds works them
+    uint32_t key_bytes;     // 4 when every block index is below 2^31 (the host bit is then bit 31), else 8
 };
 
 // Per record of a batch worked by k_small: the findings of its blocks so
