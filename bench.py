@@ -123,34 +123,35 @@ def matching_profile(name, tuning, config):
     return prof, None
 
 
-def roofline(tun, config, k_avg_ms, i_avg_ms, pool_bytes, bytes_step, l2_probe_GBps):
+def roofline(tun, config, k_avg_ms, i_avg_ms, pass_bytes, bytes_step, l2_probe_GBps):
     """The dominant kernel's roofline.  When the shadow indexes answer the
-    check-only records, that is the shadow pool index's counting pass
-    (k_sidx_count<1>): it reads once each V byte of the pool steps (64 KiB)
-    the batch's records read (its algorithmic bytes: `pool_bytes`, as the
-    library counted them for the timed passes), so HBM bounds it; achieved =
-    those bytes over its live duration, traffic from its committed counters.
-    Otherwise it is
-    the scan kernel: the bytes the L2 returns to the L1s per launch (L1 -> L2
-    read requests x 128 B, from its counters) over the launch, against the
+    check-only records, that is the indexes' counting pass (k_sidx_count, one
+    launch over both spaces): it reads once each V byte (and the host
+    region's A bits) of the 64 KiB steps the batch's records read (its
+    algorithmic bytes: `pass_bytes`, as the library counted them for the
+    timed passes), so HBM bounds it; achieved = those bytes over its live
+    duration, traffic from its committed counters.  Otherwise it is the scan
+    kernel: the bytes the L2 returns to the L1s per launch (L1 -> L2 read
+    requests x 128 B, from its counters) over the launch, against the
     L2-resident read probe measured in this run, HBM traffic beside it."""
     if i_avg_ms and i_avg_ms >= k_avg_ms:
         t = i_avg_ms / 1e3
-        achieved = pool_bytes / t / 1e9
-        out = {"kernel": "k_sidx_count<1>", "kernel_avg_ms": round(i_avg_ms, 3), "bound": "hbm",
+        achieved = pass_bytes / t / 1e9
+        out = {"kernel": "k_sidx_count", "kernel_avg_ms": round(i_avg_ms, 3), "bound": "hbm",
                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-               "algorithmic_bytes_per_launch": int(pool_bytes), "scan_kernel_avg_ms": round(k_avg_ms, 3),
-               "note": "the shadow pool index's counting pass reads once each V byte of the pool's 64 KiB steps "
-                       "that the batch's records read (16-byte loads; the pool holds no A bits); achieved = those "
-                       "bytes (counted by the library, cg_index_ms) over the pass's live duration (HIP events "
-                       "around it on the check's stream); traffic = HBM-side bytes per launch from FETCH_SIZE + "
-                       "WRITE_SIZE, profiles/k_sidx_count_pool_batched-1M_counters.md"}
-        prof, why = matching_profile("k_sidx_count_pool_batched-1M_counters", None, config)
+               "algorithmic_bytes_per_launch": int(pass_bytes), "scan_kernel_avg_ms": round(k_avg_ms, 3),
+               "note": "the shadow indexes' counting pass reads once each V byte of the 64 KiB steps of the host "
+                       "region and of the pool that the batch's records read, and the host region's A bits of "
+                       "them (16-byte V loads, 2-byte A loads); achieved = those bytes (counted by the library, "
+                       "cg_index_ms) over the pass's live duration (HIP events around it on the check's stream); "
+                       "traffic = HBM-side bytes per launch from FETCH_SIZE + WRITE_SIZE, "
+                       "profiles/k_sidx_count_batched-1M_counters.md"}
+        prof, why = matching_profile("k_sidx_count_batched-1M_counters", None, config)
         if prof is not None:
             tb = int(prof["limits"]["traffic_bytes"])
             out.update(traffic=tb, hbm_traffic_GBps=round(tb / t / 1e9, 1),
-                       traffic_over_algorithmic=round(tb / pool_bytes, 4))
+                       traffic_over_algorithmic=round(tb / pass_bytes, 4))
         else:
             out["traffic_note"] = why
         return out
@@ -643,10 +644,10 @@ def main():
     k_avg_ms = kms / max(nk, 1)
     i_avg_ms = ims / ni if ni else None
     pool_bytes = X.cg_stats(ctx)[1]   # allocated once, in one go: the pool's used bytes are its length
-    pass_bytes = pool_read // ni if ni else 0   # what each counting pass of the pool read
-    log(f"[bench] batched: {ms_step:.2f} ms/step, {value:.0f} GB/s; scan kernel {k_avg_ms:.2f} ms; pool index "
-        f"pass {i_avg_ms if i_avg_ms is None else round(i_avg_ms, 2)} ms over {pass_bytes / 1e9:.1f} of the "
-        f"pool's {pool_bytes / 1e9:.1f} GB")
+    pass_bytes = (host_read + pool_read) // ni if ni else 0   # what each counting pass read (both spaces)
+    log(f"[bench] batched: {ms_step:.2f} ms/step, {value:.0f} GB/s; scan kernel {k_avg_ms:.2f} ms; index counting "
+        f"pass {i_avg_ms if i_avg_ms is None else round(i_avg_ms, 2)} ms over {pass_bytes / 1e9:.1f} GB (pool: "
+        f"{pool_read // max(ni, 1) / 1e9:.1f} of {pool_bytes / 1e9:.1f} GB)")
 
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -663,7 +664,7 @@ def main():
         "transfers_per_s": round(T / (wall / args.steps), 1),
         "algorithmic_bytes_per_step": int(bytes_step),
         "scan_kernel_ms": round(k_avg_ms, 3),
-        "pool_index_pass_ms": None if i_avg_ms is None else round(i_avg_ms, 3),
+        "index_pass_ms": None if i_avg_ms is None else round(i_avg_ms, 3),
         "pool_bytes": int(pool_bytes),
     }
     if i_avg_ms is not None:
@@ -671,7 +672,8 @@ def main():
         # the V bytes of the pool steps its records read, and the host
         # region's V and A bytes of the steps they read, once each
         sb = int((host_read + pool_read) // args.steps)
-        result["pool_bytes_read_per_pass"] = int(pass_bytes)
+        result["index_pass_bytes"] = int(pass_bytes)
+        result["pool_bytes_read_per_pass"] = int(pool_read // max(ni, 1))
         result["shadow_bytes_read_per_step"] = sb
         result["shadow_read_GBps"] = round(sb / (wall / args.steps) / 1e9, 1)
 

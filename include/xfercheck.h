@@ -419,10 +419,11 @@ int cg_timing(cg_ctx *ctx, int enable);
 int cg_kernel_ms(cg_ctx *ctx, double *ms, uint64_t *launches);
 
 /*
- * As cg_kernel_ms, for the counting pass of the shadow pool's index (one
- * launch per large check-only batch that builds the index, bracketed by
- * events while timing is on): its summed time in ms since the last call, and
- * the number of timed passes.  When bytes is not NULL (2 entries), it
+ * As cg_kernel_ms, for the counting pass of the shadow indexes (one launch
+ * over the host region's and the pool's listed steps per large check-only
+ * batch that uses the indexes, bracketed by events while timing is on): its
+ * summed time in ms since the last call, and the number of timed passes.
+ * When bytes is not NULL (2 entries), it
  * receives the shadow bytes the counting passes of the indexes read since the
  * last such call, timed or not: [0] of the host region (V and A bits), [1] of
  * the shadow pool (V); that count then restarts.  A pass reads the 64 KiB

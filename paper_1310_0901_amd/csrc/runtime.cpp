@@ -60,7 +60,7 @@ struct GraphEntry {
     bool split;
     // whole check (or, split for timing: the preparation, the scan kernel);
     // a split check with shadow indexes has its preparation in three parts,
-    // the pool index's counting pass alone in the middle one
+    // the indexes' counting pass alone in the middle one
     hipGraph_t graph, graph2, graph3, graph4;
     hipGraphExec_t exec, exec2, exec3, exec4;
 };
@@ -206,7 +206,7 @@ struct cg_ctx {
     // timing
     bool timing = false;
     std::vector<TimingPair> tpairs;   // pairs of the last check
-    std::vector<TimingPair> ipairs;   // pairs around the pool index's counting pass
+    std::vector<TimingPair> ipairs;   // pairs around the indexes' counting pass
     size_t iused = 0;
     uint64_t *idx_read = nullptr;     // device: bytes the index counting passes read, [0] host region, [1] pool
     size_t tused = 0;
@@ -529,9 +529,10 @@ struct SegPlan {
     const ShadowIndex *hidx, *pidx;
 };
 
-// The preparation of a batched check, in three stages around the shadow pool
-// index's counting pass (stage 1, empty without indexes), so that timing can
-// bracket that pass.
+// The preparation of a batched check, in three stages around the shadow
+// indexes' counting pass (stage 1, empty without indexes: one launch over the
+// host region's and the pool's listed steps), so that timing can bracket that
+// pass.
 hipError_t prepare_stage(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, const SegPlan *sp, int stage)
 {
     hipError_t e;
@@ -540,12 +541,13 @@ hipError_t prepare_stage(const BatchArgs &a, const LaunchShape &sh, hipStream_t 
         if (!sp) return launch_classify(a, s);
         if (idx && (e = launch_sidx_reset(*sp->hidx, *sp->pidx, s)) != hipSuccess) return e;
         if ((e = launch_classify(sp->ar, s)) != hipSuccess) return e;
-        if (idx && (e = launch_sidx_build(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
+        if (idx && (e = launch_sidx_marks(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
         if (idx && (e = launch_sidx_marks(*sp->pidx, sp->ar.st, s)) != hipSuccess) return e;
         return hipSuccess;
     }
-    if (stage == 1) return idx ? launch_sidx_count(*sp->pidx, sp->ar.st, s) : hipSuccess;
+    if (stage == 1) return idx ? launch_sidx_count(*sp->hidx, *sp->pidx, sp->ar.st, s) : hipSuccess;
     if (idx) {
+        if ((e = launch_sidx_finish(*sp->hidx, sp->ar.st, s)) != hipSuccess) return e;
         if ((e = launch_sidx_finish(*sp->pidx, sp->ar.st, s)) != hipSuccess) return e;
         if ((e = launch_sidx_query(sp->ar, *sp->hidx, *sp->pidx, sp->ar.bsum, s)) != hipSuccess) return e;
         // a batch in its given order: the prefix inputs again, from the units left
@@ -566,7 +568,7 @@ hipError_t enqueue_prepare(const BatchArgs &a, const LaunchShape &sh, hipStream_
 }
 
 // The whole check; with tp, events around the scan kernel, and with ip
-// around the pool index's counting pass.
+// around the indexes' counting pass.
 hipError_t enqueue_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t s, TimingPair *tp,
                            const SegPlan *sp, TimingPair *ip = nullptr)
 {
@@ -956,7 +958,7 @@ int capture(cg_ctx *c, hipGraph_t *g, hipGraphExec_t *x, const BatchArgs &a, con
 {
     HIPTRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     // 0: all; 1: the preparation; 2: the scan kernel; 3, 4, 5: the
-    // preparation's stages 0, 1 (the pool index's counting pass), 2
+    // preparation's stages 0, 1 (the indexes' counting pass), 2
     hipError_t e = part == 0 ? enqueue_batched(a, sh, c->cap, nullptr, sp)
                  : part == 1 ? enqueue_prepare(a, sh, c->cap, sp)
                  : part == 2 ? launch_batched(a, sh, c->cap)
@@ -1431,8 +1433,7 @@ int check_2d_pitched(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, c
     }
     HIPTRY(c, launch_classify_2d(a, recs_dev, w->pitch, s));
     if (idx) {
-        HIPTRY(c, launch_sidx_build(w->hidx, a.st, s));
-        HIPTRY(c, launch_sidx_build(w->pidx, a.st, s));
+        HIPTRY(c, launch_sidx_build(w->hidx, w->pidx, a.st, s));
         HIPTRY(c, launch_sidx_query(a, w->hidx, w->pidx, a.bsum, s, w->pitch));
         HIPTRY(c, launch_reweigh(a, s));
     }

@@ -25,8 +25,9 @@
 //   marks the steps of 4,096 chunks that its records read)
 //   k_sidx_mark_count, k_sidx_mark_list
 //                  the marked steps as an ascending list (marks cleared)
-//   k_sidx_count   block b over its contiguous slice of the listed steps:
-//                  list entries and undefined bytes
+//   k_sidx_count   block b over its contiguous slice of the listed steps of
+//                  the host region, then of the pool: list entries and
+//                  undefined bytes
 //   k_sidx_scan    one block: the blocks' offsets, the totals, validity
 //   k_sidx_fill    block b writes its entries in chunk order (a block with
 //                  none returns at once)
@@ -235,16 +236,16 @@ __global__ void __launch_bounds__(kMarkT) k_sidx_mark_list(ShadowIndex x, const 
     }
 }
 
-// (one instance per space, so that a trace tells them apart).  A step's 16
-// chunks per thread are loaded back to back (non-temporal: each byte is read
-// once), then examined; each wave flags the listed steps where it met a
-// faulty chunk, so that the fill reads only those.  The steps of the block's
-// slice are read from the list 64 at a time, one per lane.
-template <uint32_t SPACE>
-__global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState *stp)
+// The counting pass of one index over block b's slice of its listed steps
+// (nothing when the index is not built).  A step's 16 chunks per thread are
+// loaded back to back (non-temporal: each byte is read once), then examined;
+// each wave flags the listed steps where it met a faulty chunk, so that the
+// fill reads only those.  The steps of the slice are read from the list 64 at
+// a time, one per lane.
+__device__ __forceinline__ void count_slice(const ShadowIndex &x, const Space &S)
 {
-    const Space S = space_of(SPACE, stp);
     if (!worth(x, S)) return;
+    const bool has_a = S.a16 != nullptr;   // the host region's A bits
     uint64_t p0, p1;
     block_slice(x, blockIdx.x, &p0, &p1);
     const uint64_t nch = space_chunks(S);
@@ -261,11 +262,9 @@ __global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState
             uint32_t a[kPer];
             if (base + kStep <= hi) {
 #pragma unroll
-                for (uint32_t j = 0; j < kPer; ++j) {
-                    const uint64_t c = base + (uint64_t)j * kT + threadIdx.x;
-                    v[j] = __builtin_nontemporal_load(vp + c);
-                    a[j] = SPACE == 0 ? (uint32_t)S.a16[c] : 0xFFFFu;
-                }
+                for (uint32_t j = 0; j < kPer; ++j) v[j] = __builtin_nontemporal_load(vp + base + (uint64_t)j * kT + threadIdx.x);
+#pragma unroll
+                for (uint32_t j = 0; j < kPer; ++j) a[j] = has_a ? (uint32_t)S.a16[base + (uint64_t)j * kT + threadIdx.x] : 0xFFFFu;
             } else {
 #pragma unroll
                 for (uint32_t j = 0; j < kPer; ++j) {
@@ -274,7 +273,7 @@ __global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState
                     a[j] = 0xFFFFu;
                     if (c < hi) {
                         v[j] = __builtin_nontemporal_load(vp + c);
-                        if (SPACE == 0) a[j] = S.a16[c];
+                        if (has_a) a[j] = S.a16[c];
                     }
                 }
             }
@@ -311,6 +310,15 @@ __global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex x, const DevState
     block_scan3(c3, ex, tot);
     if (threadIdx.x == 0)
         for (int k = 0; k < 3; ++k) x.bcnt[3 * blockIdx.x + k] = tot[k];
+}
+
+// Both indexes' counting passes in one launch: each block counts its slice of
+// the host region's listed steps, then its slice of the pool's, so that the
+// shorter pass leaves no tail of its own (both indexes have the same grid).
+__global__ void __launch_bounds__(kT) k_sidx_count(ShadowIndex h, ShadowIndex p, const DevState *stp)
+{
+#pragma nounroll
+    for (uint32_t k = 0; k < 2; ++k) count_slice(k ? p : h, space_of(k, stp));
 }
 
 // offsets of the blocks' entries into [3 grid, 6 grid) of bcnt
@@ -742,10 +750,9 @@ hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s)
+hipError_t launch_sidx_count(const ShadowIndex &h, const ShadowIndex &p, const DevState *st, hipStream_t s)
 {
-    if (x.space == 0) hipLaunchKernelGGL(k_sidx_count<0>, dim3(x.grid), dim3(kT), 0, s, x, st);
-    else hipLaunchKernelGGL(k_sidx_count<1>, dim3(x.grid), dim3(kT), 0, s, x, st);
+    hipLaunchKernelGGL(k_sidx_count, dim3(h.grid), dim3(kT), 0, s, h, p, st);
     return hipGetLastError();
 }
 
@@ -763,11 +770,13 @@ hipError_t launch_sidx_marks(const ShadowIndex &x, const DevState *st, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s)
+hipError_t launch_sidx_build(const ShadowIndex &h, const ShadowIndex &p, const DevState *st, hipStream_t s)
 {
-    hipError_t e = launch_sidx_marks(x, st, s);
-    if (e == hipSuccess) e = launch_sidx_count(x, st, s);
-    return e != hipSuccess ? e : launch_sidx_finish(x, st, s);
+    hipError_t e = launch_sidx_marks(h, st, s);
+    if (e == hipSuccess) e = launch_sidx_marks(p, st, s);
+    if (e == hipSuccess) e = launch_sidx_count(h, p, st, s);
+    if (e == hipSuccess) e = launch_sidx_finish(h, st, s);
+    return e != hipSuccess ? e : launch_sidx_finish(p, st, s);
 }
 
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,

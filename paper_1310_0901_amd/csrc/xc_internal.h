@@ -249,9 +249,10 @@ hipError_t launch_classify(const BatchArgs &a, hipStream_t s);
 // a valid index and take them out of the scan (units to 0, wbsum per
 // classify block adjusted)
 hipError_t launch_sidx_reset(const ShadowIndex &h, const ShadowIndex &p, hipStream_t s);
-hipError_t launch_sidx_build(const ShadowIndex &x, const DevState *st, hipStream_t s);   // marks + count + finish
+// both indexes: marks, counting pass, finish
+hipError_t launch_sidx_build(const ShadowIndex &h, const ShadowIndex &p, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_marks(const ShadowIndex &x, const DevState *st, hipStream_t s);
-hipError_t launch_sidx_count(const ShadowIndex &x, const DevState *st, hipStream_t s);
+hipError_t launch_sidx_count(const ShadowIndex &h, const ShadowIndex &p, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_finish(const ShadowIndex &x, const DevState *st, hipStream_t s);
 hipError_t launch_sidx_query(const BatchArgs &ar, const ShadowIndex &h, const ShadowIndex &p, uint64_t *wbsum,
                              hipStream_t s, Pitch *pitch = nullptr);   // pitch: positions are 2D records

@@ -358,6 +358,47 @@ def test_rows_from_index(X, H, seed, index_mode):
         dw.close()
 
 
+def test_sparse_rows_from_index(X, H, index_mode):
+    """Rows far apart (a pitch of up to 1 MiB for rows of 1-64 bytes): the
+    span from the first row to the last is many times the rows' bytes, so
+    the index reads every step of the space for them instead of the steps of
+    their span; mixed in one batch with records whose spans are marked step
+    by step.  Every verdict equals the oracle's."""
+    rng = np.random.default_rng(990)
+    hl, hv, a, bases, sizes, vs = util.random_world(rng, hl=24 << 20, nalloc=4, max_size=12 << 20, dens=0.002)
+    a = (rng.random(hl) > 1e-4).astype(np.uint8)
+    w = util.workload_from_arrays(W.HOST_BASE, hv, a, bases, sizes, vs, np.zeros(0, W.RECORD_DTYPE))
+    recs = np.zeros(400, W.RECORD2D_DTYPE)
+    i = 0
+    while i < recs.size:
+        kind = int(rng.choice([0, 1, 2]))
+        width = int(rng.integers(1, 65))
+        rows = int(rng.integers(2, 12))
+        sp, dp = (int(rng.choice([int(rng.integers(256 << 10, 1 << 20)), width + int(rng.integers(0, 48))]))
+                  for _ in range(2))
+
+        def place(host, q):
+            span = (rows - 1) * q + width
+            if host:
+                return W.HOST_BASE + int(rng.integers(0, hl - span + 1)) if span <= hl else None
+            j = int(rng.integers(0, bases.size))
+            return int(bases[j]) + int(rng.integers(0, int(sizes[j]) - span + 1)) if span <= int(sizes[j]) else None
+        s_, d_ = place(kind == 0, sp), place(kind == 1, dp)
+        if s_ is None or d_ is None:
+            continue
+        recs[i] = (s_, d_, width, rows, sp, dp, kind, (0, 0, 0))
+        i += 1
+    assert ((recs["spitch"] >= 256 << 10) | (recs["dpitch"] >= 256 << 10)).sum() > 100
+    want = util.oracle_for(w).run2d(recs)
+    assert (want["flags"] != 0).any() and (want["flags"] == 0).any()
+    dw = H.DeviceWorld(w)
+    try:
+        for mode in (X.CG_CHECK, X.CG_CHECK | X.CG_PLAIN):
+            util.assert_verdicts_equal(check2d(X, dw, recs, mode), want, f"mode {mode}")
+    finally:
+        dw.close()
+
+
 def test_captured_call_replays(X, H):
     """check_transfers_2d captured in a graph (after one call of that size on
     the stream) and replayed several times, with other eager work and
