@@ -1817,7 +1817,6 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t
 // of its own classification and the findings of all blocks -- and puts the
 // accumulator back to its starting state {NONE, 0, 0, 0}, so that the next
 // call needs no clearing.
-constexpr uint64_t kSmallUnits = 8192;
 
 template <int U, bool NT, bool PROP>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PROP ? 1 : 3)))
@@ -1921,6 +1920,16 @@ __global__ void __launch_bounds__(256) k_small_reset(SmallAcc *acc, uint64_t n)
 // ---------------------------------------------------------------------------
 // shadow fills and bandwidth probes
 // ---------------------------------------------------------------------------
+// A small upload from coherent host memory: one block copies n 8-byte words
+// with system-scope loads (they observe the host's latest writes); for the
+// few kilobytes of a table delta, a context state or fill ranges, a launch
+// waits less than a DMA copy.
+__global__ void __launch_bounds__(256) k_upload(const uint64_t *src, uint64_t *dst, uint64_t n)
+{
+    for (uint64_t i = threadIdx.x; i < n; i += 256)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(256) k_fill(const FillRange *ranges, uint64_t k)
 {
     for (uint64_t i = blockIdx.x; i < k; i += gridDim.x) {
@@ -2126,6 +2135,14 @@ hipError_t launch_pointers(const DevState *st, const uint64_t *ptrs, uint64_t co
 {
     const uint64_t blocks = (count + kClassifyBlock - 1) / kClassifyBlock;
     hipLaunchKernelGGL(k_pointers, dim3((uint32_t)blocks), dim3(kClassifyBlock), 0, s, st, ptrs, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_upload(const void *src, void *dst, uint64_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, static_cast<const uint64_t *>(src),
+                       static_cast<uint64_t *>(dst), bytes / 8);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ namespace {
 
 constexpr uint64_t kFillPiece = 1ull << 20;   // bytes per fill range
 constexpr uint64_t kFillCap = 1ull << 13;     // ranges per fill launch
+constexpr uint64_t kDeltaWords = 4096;        // a table delta this small is uploaded by a kernel
 constexpr int kFillSlots = 8;                 // staging ring for fill ranges
 constexpr uint64_t kTilesCap = 1ull << 22;    // tile-start entries per workspace
 constexpr int kPooledEvents = 16;             // completion events made at set-up
@@ -80,7 +81,7 @@ struct Workspace {
     uint32_t *tile_start = nullptr;
     Ctl *ctl = nullptr;
     uint64_t *h_weight = nullptr;   // pinned copy of weights (plain path)
-    uint64_t ctx_seen = ~0ull;      // ctx_seq when this stream last waited for ev_ctx (2D path)
+    uint64_t ctx_seen = ~0ull;      // ctx_seq when this stream last waited for ev_ctx
     SmallAcc *small = nullptr;      // small_max accumulators of the one-launch path (k_small)
     Pitch *pitch = nullptr;         // per position of a pitched 2D batch (allocated on first use)
     uint64_t pitch_cap = 0;
@@ -166,8 +167,12 @@ struct cg_ctx {
     uint8_t *m_keep = nullptr;
     uint32_t *m_loc = nullptr;
     uint64_t *m_bsum = nullptr, *m_boff = nullptr;
-    uint64_t *h_stage = nullptr;   // pinned staging for table uploads and deltas
-    DevState *h_state = nullptr;
+    uint64_t *h_stage = nullptr;   // pinned staging for table uploads and large deltas
+    // coherent host staging that small uploads read from the device (k_upload):
+    // a table delta of up to kDeltaWords words and the context state; m_* are
+    // the device's addresses of the same memory
+    uint64_t *h_delta = nullptr, *m_delta = nullptr;
+    DevState *h_state = nullptr, *m_state = nullptr;
     hipEvent_t ev_stage = nullptr;
     bool stage_busy = false;
     uint64_t versions_made = 0, merges = 0, full_uploads = 0;
@@ -180,7 +185,7 @@ struct cg_ctx {
     Region region{0, 0, nullptr, nullptr};
     // fills: a ring of staging buffers so that a new fill rarely waits for
     // the copy of an earlier one
-    FillRange *d_fill = nullptr, *h_fill = nullptr;
+    FillRange *d_fill = nullptr, *h_fill = nullptr, *m_fill = nullptr;   // h_fill coherent, m_fill its device address
     hipEvent_t ev_fill[kFillSlots] = {};
     bool fill_busy[kFillSlots] = {};
     int fill_next = 0;
@@ -284,6 +289,9 @@ int materialize(cg_ctx *c)
         }
         c->full_uploads++;
     } else {
+        const uint64_t words = nd + 3 * ni;
+        const bool small = words <= kDeltaWords;
+        if (small) hs = c->h_delta;
         uint64_t *hd = hs, *hib = hd + nd, *hie = hib + ni, *hio = hie + ni;
         size_t k = 0;
         for (uint64_t b : c->pend_del) hd[k++] = b;
@@ -294,8 +302,8 @@ int materialize(cg_ctx *c)
             hio[k] = kv.second.off;
             ++k;
         }
-        if (nd + 3 * ni)
-            HIPTRY(c, hipMemcpyAsync(c->d_delta, hs, (nd + 3 * ni) * 8, hipMemcpyHostToDevice, c->s));
+        if (small) HIPTRY(c, launch_upload(c->m_delta, c->d_delta, words * 8, c->s));
+        else HIPTRY(c, hipMemcpyAsync(c->d_delta, hs, words * 8, hipMemcpyHostToDevice, c->s));
         MergeArgs m{};
         m.old_base = ov.tab; m.old_end = ov.tab + M; m.old_off = ov.tab + 2 * M; m.n_old = ov.n;
         m.del = c->d_delta; m.n_del = nd;
@@ -319,7 +327,7 @@ int materialize(cg_ctx *c)
     st.pool = (uint64_t)c->pool;
     st.size_bound = c->table.size_bound();
     st.pool_len = c->palloc->high();
-    HIPTRY(c, hipMemcpyAsync(nv.st, c->h_state, sizeof(DevState), hipMemcpyHostToDevice, c->s));
+    HIPTRY(c, launch_upload(c->m_state, nv.st, sizeof(DevState), c->s));
     HIPTRY(c, hipEventRecord(c->ev_stage, c->s));
     c->stage_busy = true;
     nv.n = n;
@@ -380,7 +388,7 @@ int issue_fills(cg_ctx *c, const std::vector<FillRange> &rs, bool after_checks)
         FillRange *h = c->h_fill + f * kFillCap, *d = c->d_fill + f * kFillCap;
         size_t k = 0;
         for (; i < rs.size() && k < kFillCap; ++i) h[k++] = rs[i];
-        HIPTRY(c, hipMemcpyAsync(d, h, k * sizeof(FillRange), hipMemcpyHostToDevice, c->s));
+        HIPTRY(c, launch_upload(c->m_fill + f * kFillCap, d, k * sizeof(FillRange), c->s));
         HIPTRY(c, launch_fill(d, k, c->s));
         HIPTRY(c, hipEventRecord(c->ev_fill[f], c->s));
         c->fill_busy[f] = true;
@@ -830,7 +838,12 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     if (rc) return rc;
     rc = materialize(c);
     if (rc) return rc;
-    HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+    // the stream waits once for each new state of the context (a table
+    // version, fills): later work on it is ordered after that wait
+    if (w->ctx_seen != c->ctx_seq) {
+        HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+        w->ctx_seen = c->ctx_seq;
+    }
     if ((mode & CG_DEBUG_CONFLICTS) && (mode & CG_PROPAGATE)) {
         rc = debug_conflicts(c, recs, count, s);
         if (rc) return rc;
@@ -1101,9 +1114,16 @@ int cg_create(cg_ctx **out, int hip_device, uint64_t shadow_pool_bytes, uint64_t
     if (hipMalloc(&c->m_boff, (max_allocs / 256 + 2) * 8) != hipSuccess) return bail(CG_ENOMEM);
     if (hipHostMalloc(&c->h_stage, (3 * max_allocs + kMaxTop) * 8, hipHostMallocDefault) != hipSuccess)
         return bail(CG_ENOMEM);
-    if (hipHostMalloc(&c->h_state, sizeof(DevState), hipHostMallocDefault) != hipSuccess) return bail(CG_ENOMEM);
+    const unsigned coh = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc(&c->h_state, sizeof(DevState), coh) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->m_state, c->h_state, 0) != hipSuccess)
+        return bail(CG_ENOMEM);
+    if (hipHostMalloc(&c->h_delta, kDeltaWords * 8, coh) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->m_delta, c->h_delta, 0) != hipSuccess)
+        return bail(CG_ENOMEM);
     if (hipMalloc(&c->d_fill, kFillSlots * kFillCap * sizeof(FillRange)) != hipSuccess) return bail(CG_ENOMEM);
-    if (hipHostMalloc(&c->h_fill, kFillSlots * kFillCap * sizeof(FillRange), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(&c->h_fill, kFillSlots * kFillCap * sizeof(FillRange), coh) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->m_fill, c->h_fill, 0) != hipSuccess)
         return bail(CG_ENOMEM);
     if (hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess) return bail(CG_EHIP);
     for (auto &e : c->ev_fill)
@@ -1195,6 +1215,7 @@ int cg_destroy(cg_ctx *c)
     (void)hipFree(c->d_fill);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_delta) (void)hipHostFree(c->h_delta);
     if (c->h_fill) (void)hipHostFree(c->h_fill);
     if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
     for (auto e : c->ev_fill)
@@ -1841,6 +1862,11 @@ struct Slot {
     hipStream_t s = nullptr;
     cg_transfer *d_recs = nullptr, *h_recs = nullptr;
     cg_verdict *d_out = nullptr, *h_out = nullptr;
+    // the device's addresses of h_recs / h_out (coherent host memory): a
+    // micro-batch worked in one launch reads its records and writes its
+    // verdicts there, with no copy on either side
+    cg_transfer *m_recs = nullptr;
+    cg_verdict *m_out = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
     uint64_t bytes = 0;
@@ -1908,8 +1934,10 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
         if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
             hipMalloc(&sl.d_recs, B * sizeof(cg_transfer)) != hipSuccess ||
             hipMalloc(&sl.d_out, B * sizeof(cg_verdict)) != hipSuccess ||
-            hipHostMalloc(&sl.h_recs, B * sizeof(cg_transfer), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&sl.h_out, B * sizeof(cg_verdict), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&sl.h_recs, B * sizeof(cg_transfer), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostMalloc(&sl.h_out, B * sizeof(cg_verdict), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer((void **)&sl.m_recs, sl.h_recs, 0) != hipSuccess ||
+            hipHostGetDevicePointer((void **)&sl.m_out, sl.h_out, 0) != hipSuccess ||
             hipEventCreate(&sl.done) != hipSuccess)
             return bail(fail(c, CG_ENOMEM, "serve: slot buffers"));
         for (uint32_t k = 0; k < B; ++k) sl.h_recs[k] = cg_transfer{0, 0, 0, 0xFFFFFFFFu, 0};
@@ -2029,13 +2057,29 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
             // launch take their own count
             const bool one_launch = !cfg->plain && B <= c->small_max;
             const uint32_t count = cfg->plain || one_launch ? cnt : B;
-            hipError_t e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
-            if (e1 != hipSuccess) { rc = hip_fail(c, "serve: records upload", e1); break; }
-            // micro-batches keep their order (their graphs are captured before the clock starts)
-            rc = run_check(c, sl.d_recs, count, sl.d_out, CG_CHECK | CG_KEEP_ORDER | (cfg->plain ? CG_PLAIN : 0u),
-                           sl.s, tun);
-            if (rc) break;
-            e1 = hipMemcpyAsync(sl.h_out, sl.d_out, cnt * sizeof(cg_verdict), hipMemcpyDeviceToHost, sl.s);
+            hipError_t e1 = hipSuccess;
+            if (one_launch) {
+                // the launch reads the records from, and writes the verdicts
+                // to, the slot's coherent host memory, with as many blocks per
+                // record as the largest of them uses
+                uint32_t bpr = 1;
+                for (uint32_t q = 0; q < cnt; ++q) {
+                    const cg_transfer &r = sl.h_recs[q];
+                    const uint64_t most = r.kind <= CG_D2D && r.n ? r.n / 16 + 2 : 1;
+                    const uint64_t nb = (most + kSmallUnits - 1) / kSmallUnits;
+                    bpr = nb > bpr ? (uint32_t)std::min<uint64_t>(nb, 1u << 20) : bpr;
+                }
+                rc = run_check(c, sl.m_recs, count, sl.m_out, CG_CHECK | CG_KEEP_ORDER, sl.s, tun, bpr);
+                if (rc) break;
+            } else {
+                e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
+                if (e1 != hipSuccess) { rc = hip_fail(c, "serve: records upload", e1); break; }
+                // micro-batches keep their order (their graphs are captured before the clock starts)
+                rc = run_check(c, sl.d_recs, count, sl.d_out, CG_CHECK | CG_KEEP_ORDER | (cfg->plain ? CG_PLAIN : 0u),
+                               sl.s, tun);
+                if (rc) break;
+                e1 = hipMemcpyAsync(sl.h_out, sl.d_out, cnt * sizeof(cg_verdict), hipMemcpyDeviceToHost, sl.s);
+            }
             if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);
             if (e1 != hipSuccess) { rc = hip_fail(c, "serve: verdict download", e1); break; }
             sl.busy = true;

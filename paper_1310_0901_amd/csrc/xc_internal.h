@@ -78,6 +78,7 @@ struct DevState {
     uint64_t size_bound;    // no live allocation is larger (within a factor of two)
     uint64_t pool_len;      // bytes of the pool ever handed out (from its start)
 };
+static_assert(sizeof(DevState) % 8 == 0, "uploaded in 8-byte words");
 
 struct FillRange {
     uint64_t ptr, len;
@@ -88,6 +89,7 @@ constexpr int kMaxTop = 1024;        // LDS-staged top level of the table
 constexpr uint64_t kMinTile = 1024;  // smallest work tile, in 16-byte units
 constexpr int kClassifyBlock = 256;  // records per classify block
 constexpr uint64_t kScanLimit = 1ull << 62;  // byte indices scanned per record
+constexpr uint64_t kSmallUnits = 8192;       // units per block of a record in a one-launch batch (k_small)
 
 // A pitched 2D record worked as one position (check_transfers_2d): row r is
 // the transfer {src + r*spitch, dst + r*dpitch, width, kind}, its units are
@@ -267,6 +269,8 @@ hipError_t launch_batched(const BatchArgs &a, const LaunchShape &sh, hipStream_t
 hipError_t launch_plain(const BatchArgs &a, uint64_t rec, uint64_t units, const LaunchShape &sh,
                         hipStream_t s);
 hipError_t launch_fill(const FillRange *ranges_dev, uint64_t k, hipStream_t s);
+// `bytes` (a multiple of 8) from coherent host memory (its device address) to device memory
+hipError_t launch_upload(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 // a batch of a.count records in one launch of a.count * bpr blocks of sh.block threads
 hipError_t launch_small(const BatchArgs &a, SmallAcc *acc, uint32_t bpr, const LaunchShape &sh, hipStream_t s);
 hipError_t launch_small_reset(SmallAcc *acc, uint64_t n, hipStream_t s);

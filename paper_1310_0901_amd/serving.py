@@ -60,6 +60,10 @@ def summarise(sw: W.ServeWorkload, res: np.ndarray, st) -> dict:
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "mean_ms": round(float(lat.mean()), 4),
         "max_ms": round(float(lat.max()), 4),
+        # where the latency goes: arrival to issue (the host loop, waiting
+        # for a free slot), issue to completion on the GPU
+        "p50_wait_ms": round(float(np.percentile((res["t_admit"] - res["t_arrive"]) * 1e3, 50)), 4),
+        "p50_gpu_ms": round(float(np.percentile((res["t_done"] - res["t_admit"]) * 1e3, 50)), 4),
         "batches": int(st.batches), "mean_batch": round(st.mean_batch, 2),
         "events_applied": int(st.events), "table_versions": int(st.table_versions),
         "max_inflight_GB": round(st.max_inflight_bytes / 1e9, 3),
