@@ -828,8 +828,10 @@ uint32_t small_bpr(const cg_ctx *c, uint64_t count, const LaunchShape &sh, uint3
     return (uint32_t)bpr;
 }
 
+// With `after`, a one-launch batch records that event right after its launch,
+// before the bookkeeping events (a caller timing the batch's completion).
 int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *out, uint32_t mode,
-              hipStream_t s, const cg_tuning &tun, uint32_t bpr = 0)
+              hipStream_t s, const cg_tuning &tun, uint32_t bpr = 0, hipEvent_t after = nullptr)
 {
     Workspace *w;
     const bool seg = segmented(c, count, mode);
@@ -905,6 +907,7 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
         if (tp) HIPTRY(c, hipEventRecord(tp->a, s));
         HIPTRY(c, launch_small(a, w->small, small_bpr(c, count, sh, bpr), sh, s));
         if (tp) HIPTRY(c, hipEventRecord(tp->b, s));
+        if (after) HIPTRY(c, hipEventRecord(after, s));
     } else if (mode & CG_PLAIN) {
         HIPTRY(c, launch_classify(a, s));
         HIPTRY(c, hipMemcpyAsync(w->h_weight, w->weight, count * 8, hipMemcpyDeviceToHost, s));
@@ -2069,7 +2072,8 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
                     const uint64_t nb = (most + kSmallUnits - 1) / kSmallUnits;
                     bpr = nb > bpr ? (uint32_t)std::min<uint64_t>(nb, 1u << 20) : bpr;
                 }
-                rc = run_check(c, sl.m_recs, count, sl.m_out, CG_CHECK | CG_KEEP_ORDER, sl.s, tun, bpr);
+                // its completion event right behind the launch
+                rc = run_check(c, sl.m_recs, count, sl.m_out, CG_CHECK | CG_KEEP_ORDER, sl.s, tun, bpr, sl.done);
                 if (rc) break;
             } else {
                 e1 = hipMemcpyAsync(sl.d_recs, sl.h_recs, count * sizeof(cg_transfer), hipMemcpyHostToDevice, sl.s);
@@ -2079,8 +2083,8 @@ extern "C" int cg_serve_run(cg_ctx *c, const cg_serve_event *ev, uint64_t n, con
                                sl.s, tun);
                 if (rc) break;
                 e1 = hipMemcpyAsync(sl.h_out, sl.d_out, cnt * sizeof(cg_verdict), hipMemcpyDeviceToHost, sl.s);
+                if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);
             }
-            if (e1 == hipSuccess) e1 = hipEventRecord(sl.done, sl.s);
             if (e1 != hipSuccess) { rc = hip_fail(c, "serve: verdict download", e1); break; }
             sl.busy = true;
             sl.bytes = bytes;
