@@ -826,6 +826,7 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
 {
     __shared__ uint64_t top[kMaxTop];
     __shared__ uint64_t wsum[kClassifyBlock / 64];
+    __shared__ uint64_t isum[2][kClassifyBlock / 64];
     const uint32_t tid = threadIdx.x;
     const DevState st = *a.st;
     for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
@@ -838,11 +839,12 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     }
     const uint32_t lane = lane_id(), wid = tid >> 6;
     if (a.index_bytes[0]) {
-        // the batch's valid bytes per shadow space (the shadow indexes' cost test)
+        // the batch's valid bytes per shadow space (the shadow indexes' cost
+        // test): wave sums here, one atomic per block below
         for (int k = 0; k < 2; ++k) {
             uint64_t x = sp[k];
             for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-            if (lane == 0 && x) atomicAdd((unsigned long long *)a.index_bytes[k], (unsigned long long)x);
+            if (lane == 0) isum[k][wid] = x;
         }
     }
     // block exclusive scan of w
@@ -857,6 +859,12 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify(BatchArgs a)
     for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
     if (t < a.count) a.local[t] = off + x - w;
     if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
+    if (a.index_bytes[0] && tid == 0)
+        for (int k = 0; k < 2; ++k) {
+            uint64_t b = 0;
+            for (uint32_t q = 0; q < kClassifyBlock / 64; ++q) b += isum[k][q];
+            if (b) atomicAdd((unsigned long long *)a.index_bytes[k], (unsigned long long)b);
+        }
 }
 
 // After the shadow indexes have answered positions (their weight set to 0)
@@ -967,6 +975,8 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
 {
     __shared__ uint64_t top[kMaxTop];
     __shared__ uint64_t wsum[kClassifyBlock / 64];
+    __shared__ uint64_t isum[2][kClassifyBlock / 64];
+    uint64_t ib[2] = {0, 0};   // this record's valid bytes per shadow space (the indexes' cost test)
     const uint32_t tid = threadIdx.x;
     const DevState st = *a.st;
     for (uint32_t k = tid; k < st.table.ntop; k += kClassifyBlock) top[k] = st.table.top[k];
@@ -1025,9 +1035,8 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
                 const uint64_t nr = P.uniform == kRowsContig ? 1 : rows;
                 const uint64_t src = ds.v_hi > ds.v_lo ? nr * (uint64_t)(ds.v_hi - ds.v_lo) : 0;
                 const uint64_t dst = (ds.ctl & CTL_DST_A) && ds.d_hi > ds.d_lo ? nr * (uint64_t)(ds.d_hi - ds.d_lo) : 0;
-                const uint64_t hb = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst, pb = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
-                if (hb) atomicAdd((unsigned long long *)a.index_bytes[0], (unsigned long long)hb);
-                if (pb) atomicAdd((unsigned long long *)a.index_bytes[1], (unsigned long long)pb);
+                ib[0] = ((ds.ctl & CTL_SRC_HOST) ? src : 0) + dst;
+                ib[1] = (ds.ctl & CTL_SRC_HOST) ? 0 : src;
                 if (P.uniform == kRowsContig) mark_desc(a, st, ds);
                 else mark_rows(a, st, ds, P);
             }
@@ -1041,6 +1050,12 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
         w = units ? units : 1;
     }
     const uint32_t lane = lane_id(), wid = tid >> 6;
+    if (a.index_bytes[0])
+        for (int k = 0; k < 2; ++k) {
+            uint64_t y = ib[k];
+            for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d);
+            if (lane == 0) isum[k][wid] = y;
+        }
     uint64_t x = w;
     for (uint32_t d = 1; d < 64u; d <<= 1) {
         const uint64_t y = __shfl_up(x, d);
@@ -1052,6 +1067,13 @@ __global__ void __launch_bounds__(kClassifyBlock) k_classify_2d(BatchArgs a, con
     for (uint32_t k = 0; k < wid; ++k) off += wsum[k];
     if (t < a.count) a.local[t] = off + x - w;
     if (tid == kClassifyBlock - 1) a.bsum[blockIdx.x] = off + x;
+    // one atomic per block and space for the cost test
+    if (a.index_bytes[0] && tid == 0)
+        for (int k = 0; k < 2; ++k) {
+            uint64_t b = 0;
+            for (uint32_t q = 0; q < kClassifyBlock / 64; ++q) b += isum[k][q];
+            if (b) atomicAdd((unsigned long long *)a.index_bytes[k], (unsigned long long)b);
+        }
 }
 
 // Row r's descriptor when the rows are uniform: row 0's shifted by the
