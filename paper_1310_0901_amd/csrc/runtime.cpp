@@ -253,6 +253,15 @@ int ctx_end(cg_ctx *c)
     return CG_OK;
 }
 
+// Stream s waits for the context's latest state (a table version, fills).
+// Every check waits: a stream handle may be a destroyed stream's, reused.
+int wait_ctx(cg_ctx *c, Workspace *w, hipStream_t s)
+{
+    HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
+    w->ctx_seen = c->ctx_seq;
+    return CG_OK;
+}
+
 // Make a new table version if allocations, frees or the host region changed
 // since the current one.  The new version goes to the next buffer of the ring
 // after the checks that last read that buffer have finished; it is either a
@@ -840,12 +849,8 @@ int run_check(cg_ctx *c, const cg_transfer *recs, uint64_t count, cg_verdict *ou
     if (rc) return rc;
     rc = materialize(c);
     if (rc) return rc;
-    // the stream waits once for each new state of the context (a table
-    // version, fills): later work on it is ordered after that wait
-    if (w->ctx_seen != c->ctx_seq) {
-        HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
-        w->ctx_seen = c->ctx_seq;
-    }
+    rc = wait_ctx(c, w, s);
+    if (rc) return rc;
     if ((mode & CG_DEBUG_CONFLICTS) && (mode & CG_PROPAGATE)) {
         rc = debug_conflicts(c, recs, count, s);
         if (rc) return rc;
@@ -1436,8 +1441,8 @@ int check_2d_pitched(cg_ctx *c, const cg_transfer2d *recs_dev, uint64_t count, c
     } else {
         rc = materialize(c);
         if (rc) return rc;
-        HIPTRY(c, hipStreamWaitEvent(s, c->ev_ctx, 0));
-        w->ctx_seen = c->ctx_seq;
+        rc = wait_ctx(c, w, s);
+        if (rc) return rc;
     }
     BatchArgs a = make_args(c, w, nullptr, count, out_dev, mode);
     a.pitch = w->pitch;
