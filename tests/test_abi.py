@@ -72,3 +72,14 @@ def test_preload_wraps_the_hip_calls():
               "hipMemsetD32Async", "hipMemcpy2D", "hipMemcpy2DAsync", "hipMemcpy3D", "hipMemcpy3DAsync",
               "hipLaunchKernel", "hipDeviceSynchronize", "hipStreamSynchronize"):
         assert f in names, f
+
+
+def test_library_loads_beside_torch():
+    """The tests, the smoke run and the benchmark load the library after
+    torch, whose own HIP runtime then resolves the library's HIP symbols: it
+    must need no symbol version that runtime lacks."""
+    import subprocess
+    import sys
+    code = "import torch\nfrom paper_1310_0901_amd import xfercheck as X\nX.lib()\nprint('loaded')"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "loaded" in r.stdout, r.stderr[-2000:]
