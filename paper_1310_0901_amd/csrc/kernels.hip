@@ -11,7 +11,12 @@
 //   k_classify     one lane per record: decode, interval lookup in the
 //                  sorted allocation table (top level staged in LDS),
 //                  range-derived verdict fields, scan descriptor, work weight,
-//                  block-local exclusive scan of the weights;
+//                  block-local exclusive scan of the weights; for a check the
+//                  shadow indexes may answer, the valid bytes per shadow space
+//                  and the marks of the 64 KiB shadow steps they fall in;
+//   (shadowindex.hip) large check-only batches: indexes of the faulty chunks
+//                  of those steps, which answer the records whose spaces they
+//                  cover (their units leave the scan);
 //   (segment.hip)  large batches only: every record's units cut at blocks of
 //                  source memory, the pieces sorted by block and laid out as
 //                  the batch's positions (descriptors, weights, block-local

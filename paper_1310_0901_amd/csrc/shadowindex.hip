@@ -7,12 +7,14 @@
 // undefined (V != 0 where A = 1), the first undefined one and the first
 // unaddressable one (A = 0, host sources only); for the valid bytes of a host
 // destination, the first unaddressable one.  The ranges themselves were
-// judged by k_classify's lookups.  Here each shadow space the batch reads
-// heavily is read once into two sorted lists: the chunks holding an undefined
-// byte, with its mask and the undefined bytes of all chunks before it, and
-// the chunks holding an unaddressable byte, with its mask.  A record's facts
-// then come from two binary searches per list and the masks of its edge
-// chunks.  The spaces are the host region (V and A bits) and the shadow pool
+// judged by k_classify's lookups.  Here the parts of each shadow space the
+// batch reads heavily (its steps of 4,096 chunks that some record reads) are
+// read once into two sorted lists: the chunks holding an undefined byte, with
+// its mask and the undefined bytes of all chunks before it, and the chunks
+// holding an unaddressable byte, with its mask.  A record's facts then come
+// from two binary searches per list and the masks of its edge chunks: its
+// range lies inside listed steps, so the entries between its searches are
+// all of its faulty chunks.  The spaces are the host region (V and A bits) and the shadow pool
 // (V only; addressability there is the allocation table's).  An index is
 // built when the batch's valid bytes in its space reach `ratio` times the
 // space's length, and is valid when both lists fit their capacity; a record
