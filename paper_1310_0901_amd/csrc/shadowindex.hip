@@ -490,10 +490,44 @@ __device__ __forceinline__ uint64_t first_in(const uint64_t *chunk, const uint32
 }
 
 // undefined bytes of the range and the first one (space offset, or ~0)
-__device__ __forceinline__ uint64_t undef_in(const ShadowIndex &x, const Range &g, uint64_t *first)
+// A list's chunk indices with every stride-th of them (samples) in LDS, for a
+// two-level search: the samples first, then at most stride - 1 entries in
+// global memory.
+constexpr uint32_t kSamp = 256;   // samples per list
+
+struct Sampled {
+    const uint64_t *chunk;
+    uint64_t n, stride, ns;
+    const uint64_t *s;   // LDS: chunk[i * stride], i < ns
+};
+
+// the block fills s (kSamp entries) for a list of n entries (none when the
+// index is not valid); every thread of the block calls it
+__device__ __forceinline__ Sampled sample_list(uint64_t *s, const uint64_t *chunk, uint64_t n, bool valid)
 {
-    const uint64_t nu = x.state[2];
-    const uint64_t i0 = lower_bound(x.uchunk, nu, g.ca), i1 = lower_bound(x.uchunk, nu, g.cb + 1);
+    if (!valid) n = 0;
+    const uint64_t st = n <= kSamp ? 1 : (n + kSamp - 1) / kSamp;
+    const uint64_t m = (n + st - 1) / st;
+    for (uint64_t i = threadIdx.x; i < m; i += kT) s[i] = chunk[i * st];
+    return Sampled{chunk, n, st, m, s};
+}
+
+// lower_bound over the sampled list
+__device__ __forceinline__ uint64_t lower_bound(const Sampled &x, uint64_t k)
+{
+    uint64_t lo = 0, hi = x.ns;   // the first sample >= k
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (x.s[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    // the entries after sample lo - 1 (< k) up to sample lo (>= k), or the list's end
+    const uint64_t a = lo == 0 ? 0 : (lo - 1) * x.stride + 1, b = lo < x.ns ? lo * x.stride : x.n;
+    return a + lower_bound(x.chunk + a, b - a, k);
+}
+
+__device__ __forceinline__ uint64_t undef_in(const ShadowIndex &x, const Sampled &su, const Range &g, uint64_t *first)
+{
+    const uint64_t i0 = lower_bound(su, g.ca), i1 = lower_bound(su, g.cb + 1);
     uint64_t n = x.ucum[i1] - x.ucum[i0];
     if (i1 > i0) {
         // the edge chunks' bytes outside the range
@@ -505,10 +539,9 @@ __device__ __forceinline__ uint64_t undef_in(const ShadowIndex &x, const Range &
 }
 
 // the first unaddressable byte of the range (space offset, or ~0)
-__device__ __forceinline__ uint64_t unaddr_in(const ShadowIndex &x, const Range &g)
+__device__ __forceinline__ uint64_t unaddr_in(const ShadowIndex &x, const Sampled &sn, const Range &g)
 {
-    const uint64_t nn = x.state[3];
-    const uint64_t j0 = lower_bound(x.nchunk, nn, g.ca), j1 = lower_bound(x.nchunk, nn, g.cb + 1);
+    const uint64_t j0 = lower_bound(sn, g.ca), j1 = lower_bound(sn, g.cb + 1);
     return first_in(x.nchunk, x.nmask, j0, j1, g);
 }
 
@@ -524,6 +557,13 @@ __device__ __forceinline__ void take_first(uint64_t *first, uint64_t off, int64_
 __global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, ShadowIndex p, uint64_t *wbsum,
                                                    Pitch *pitch)
 {
+    __shared__ uint64_t samp[3][kSamp];
+    // the lists' samples: the host region's undefined and unaddressable
+    // chunks, the pool's undefined chunks
+    const Sampled hu = sample_list(samp[0], h.uchunk, h.state[2], h.state[1] != 0);
+    const Sampled hn = sample_list(samp[1], h.nchunk, h.state[3], h.state[1] != 0);
+    const Sampled pu = sample_list(samp[2], p.uchunk, p.state[2], p.state[1] != 0);
+    __syncthreads();
     const uint64_t t = (uint64_t)blockIdx.x * kT + threadIdx.x;
     uint64_t removed = 0;
     if (a.out && t < a.count && (!pitch || pitch[t].uniform == kRowsContig)) {
@@ -544,14 +584,14 @@ __global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, S
                                               : (int64_t)(d.src_sh + phi - a.st->pool);
                 const Range g((uint64_t)(off0 + d.v_lo), (uint64_t)(off0 + d.v_hi));
                 uint64_t fu;
-                const uint64_t undef = undef_in(src_host ? h : p, g, &fu);
+                const uint64_t undef = src_host ? undef_in(h, hu, g, &fu) : undef_in(p, pu, g, &fu);
                 if (undef) {
                     v.flags |= CG_SRC_UNDEF;
                     take_first(&first, fu, off0);
                 }
                 v.undef_bytes += undef;
                 if (src_host) {
-                    const uint64_t fn = unaddr_in(h, g);
+                    const uint64_t fn = unaddr_in(h, hn, g);
                     if (fn != ~0ull) {
                         v.flags |= CG_SRC_UNADDR;
                         take_first(&first, fn, off0);
@@ -562,7 +602,7 @@ __global__ void __launch_bounds__(kT) k_sidx_query(BatchArgs a, ShadowIndex h, S
                 const uint32_t psi = (d.ctl >> CTL_PSI_SHIFT) & 15u;
                 const int64_t off0 = d.a_dst + (int64_t)psi;   // host region offset of the destination's byte 0
                 const Range g((uint64_t)(off0 + d.d_lo), (uint64_t)(off0 + d.d_hi));
-                const uint64_t fn = unaddr_in(h, g);
+                const uint64_t fn = unaddr_in(h, hn, g);
                 if (fn != ~0ull) {
                     v.flags |= CG_DST_UNADDR;
                     take_first(&first, fn, off0);
