@@ -1834,8 +1834,9 @@ __global__ void __launch_bounds__(512) k_plain(BatchArgs a, uint64_t t, uint64_t
 // A batch of few records in one launch, up to `bpr` blocks per record.  The
 // blocks a record uses follow from its byte count alone (at most one per
 // kSmallUnits units), so that every block of the record agrees on them and
-// the unused ones leave after one load.  Block b of record t: wave 0 looks up
-// the record's device pointers and classifies it; the record's units are
+// the unused ones leave after one load.  Block b of record t: waves 0 and 1
+// look up the record's source and destination pointers side by side, one
+// lane classifies it; the record's units are
 // split evenly over its blocks, and a block's share over its waves (the
 // wave-uniform loop).  A record of one block gets its whole verdict from that
 // block.  Otherwise a block that finds something merges it into the record's
@@ -1854,6 +1855,7 @@ k_small(BatchArgs a, SmallAcc *acc, uint32_t bpr)
     __shared__ uint64_t su;
     __shared__ uint64_t wfirst[8], wund[8];
     __shared__ uint32_t wfl[8];
+    __shared__ int64_t sj[2];   // the source's and the destination's allocation (-1: none)
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint64_t t = blockIdx.x / bpr;
     const uint32_t b = blockIdx.x % bpr;
@@ -1864,16 +1866,20 @@ k_small(BatchArgs a, SmallAcc *acc, uint32_t bpr)
     const uint32_t nb = want < bpr ? (uint32_t)want : bpr;   // blocks of this record, at least 1
     if (b >= nb) return;
     const DevState *st = a.st;
-    if (wid == 0) {
-        const int64_t js = dev_src(r) ? table_lookup_wave(st->table, r.src) : -1;
-        const int64_t jd = dev_dst(r) ? table_lookup_wave(st->table, r.dst) : -1;
-        if (lane == 0) {
-            Desc ds;
-            cg_verdict v;
-            su = classify_rec(r, a.mode, *st, js, jd, ds, v);
-            sd = ds;
-            sv = v;
-        }
+    if (wid < 2) {
+        // the source's lookup on wave 0, the destination's on wave 1, side by side
+        const bool src = wid == 0;
+        int64_t j = -1;
+        if (src ? dev_src(r) : dev_dst(r)) j = table_lookup_wave(st->table, src ? r.src : r.dst);
+        if (lane == 0) sj[wid] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Desc ds;
+        cg_verdict v;
+        su = classify_rec(r, a.mode, *st, sj[0], sj[1], ds, v);
+        sd = ds;
+        sv = v;
     }
     __syncthreads();
     const uint64_t units = su;
