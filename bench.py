@@ -613,9 +613,11 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t_setup = time.perf_counter()
+    if args.config not in (1, 2, 3):
+        raise SystemExit("--config takes 1, 2 or 3 (one batch per step); configuration 4 (a propagation chain) and "
+                         "configuration 5 (serving) run as legs of the default benchmark (--leg propagation, "
+                         "--leg serving)")
     w = W.full_config(args.config)
-    if args.config == 4:
-        raise SystemExit("configuration 4 is a propagation chain; use the tests")
     log(f"[bench] workload {w.name}: {w.count} records, {w.dev.live_idx.size} live allocations")
     hv, ha = W.host_v(w.host), W.host_a(w.host)
     dw = DeviceWorld(w, host_arrays=(hv, ha))
