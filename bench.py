@@ -609,14 +609,14 @@ def main():
     from paper_1310_0901_amd import workloads as W, xfercheck as X
     from paper_1310_0901_amd.harness import DeviceWorld, records_tensor, verdicts_tensor, verdicts_np
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    t_setup = time.perf_counter()
     if args.config not in (1, 2, 3):
         raise SystemExit("--config takes 1, 2 or 3 (one batch per step); configuration 4 (a propagation chain) and "
                          "configuration 5 (serving) run as legs of the default benchmark (--leg propagation, "
                          "--leg serving)")
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t_setup = time.perf_counter()
     w = W.full_config(args.config)
     log(f"[bench] workload {w.name}: {w.count} records, {w.dev.live_idx.size} live allocations")
     hv, ha = W.host_v(w.host), W.host_a(w.host)
